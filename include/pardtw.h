@@ -1,0 +1,181 @@
+/*
+ * pardtw.h -- C ABI of libpardtw.so: exact Parallelized Diagonal DTW (ParDTW)
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Yang, Shaw & Tsai, "A Study of Parallelizable Alternatives to Dynamic
+ * Time Warping for Aligning Long Sequences". Given two feature sequences the
+ * library returns the optimal DTW alignment path (a sequence of coordinate
+ * pairs) and its cost (problem statement: Sec. I; outputs: Sec. VI-D).
+ *
+ *   cost     C[i,j] = 1 - <x_i, y_j> / (|x_i| |y_j|)   (cosine distance, Sec. IV)
+ *   DP       steps (1,1), (1,2), (2,1) with weights 2, 3, 3 (Sec. V); the weight
+ *            multiplies the cost of the cell a step lands on; D[0,0] = C[0,0];
+ *            D[i,j] = min(D[i-1,j-1] + 2C, D[i-1,j-2] + 3C, D[i-2,j-1] + 3C)
+ *   codes    0 = (1,1), 1 = (1,2), 2 = (2,1), 3 = origin / unreachable; an exact
+ *            tie goes to the lowest code. Four codes = the paper's 2-bit
+ *            transition types (Sec. VI-D).
+ *   result   D[N-1, M-1] and the path from (0,0) to (N-1,M-1), exactly DTW's
+ *            (Sec. II-D: ParDTW changes the order of work, not the result).
+ *
+ * Conventions. X is N x d (rows i, the query), Y is M x d (columns j, the
+ * reference); both row-major FP32. Sizes are int64, coordinates int32. Every
+ * pointer argument named "device" must point to GPU memory owned by the caller;
+ * the library allocates no memory in these calls (plans are the only
+ * library-owned objects and are created ahead of time). All calls are
+ * asynchronous on the given stream and never synchronise it.
+ *
+ * Errors. The return value reports host-side argument validation and launch
+ * errors only. Per-pair outcomes are written to a device int32 status:
+ * PARDTW_PAIR_OK, or PARDTW_PAIR_INFEASIBLE when no legal path exists
+ * (M-1 > 2(N-1) or N-1 > 2(M-1)); an infeasible pair gets total = +inf and
+ * path_len = 0.
+ */
+#ifndef PARDTW_H
+#define PARDTW_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PARDTW_OK = 0,
+    PARDTW_ERR_INVALID_ARG = 1, /* null pointer, non-positive or overflowing size */
+    PARDTW_ERR_WORKSPACE = 2,   /* workspace missing or smaller than required */
+    PARDTW_ERR_HIP = 3,         /* a HIP runtime call or kernel launch failed */
+    PARDTW_ERR_UNSUPPORTED = 4  /* combination not implemented (e.g. bad layout) */
+} pardtw_status;
+
+typedef enum {
+    PARDTW_PREC_F32 = 0,  /* FP32 features, FP32 MFMA products, FP32 accumulation */
+    PARDTW_PREC_BF16 = 1  /* features rounded to BF16 for the MFMA GEMM, FP32 accumulation */
+} pardtw_prec;
+
+typedef enum {
+    /* Row-major N x M: C[i*M + j]. */
+    PARDTW_LAYOUT_ROW = 0,
+    /* Column panels of 64: panel p = j / 64 holds columns [64p, 64p+64) for all
+     * rows, contiguous: C[(p*N + i)*64 + (j - 64p)], P = ceil(M/64) panels. The
+     * unused columns of the last panel are padding. This is the layout the DP
+     * streams with fully sequential 256-byte rows per wavefront. */
+    PARDTW_LAYOUT_PANEL = 1
+} pardtw_layout;
+
+#define PARDTW_PAIR_OK 0
+#define PARDTW_PAIR_INFEASIBLE 1
+
+/* Number of floats a cost buffer of the given layout occupies (0 on bad args). */
+size_t pardtw_cost_elems(int64_t n, int64_t m, pardtw_layout layout);
+
+/* Bytes of the backtrace buffer written by pardtw_dp (0 on bad args). The
+ * layout is the DP's own: 64-column panels, and within a panel 8-row groups
+ * where each column's 8 codes are 8 consecutive bytes:
+ *   byte((i,j)) = ((p*G + i/8)*64 + (j%64))*8 + i%8,  p = j/64, G = ceil(N/8).
+ * pardtw_bp_unpack converts it to a plain row-major N x M int8 matrix. */
+size_t pardtw_bp_bytes(int64_t n, int64_t m);
+
+/* Bytes of device workspace pardtw_dp needs (0 on bad args). The workspace
+ * carries boundary columns between column panels and a launch counter. Zero it
+ * once before its first use; afterwards it can be reused by any number of
+ * pardtw_dp calls (of any size that fits) issued one after another on one
+ * stream. Calls that overlap in time must not share a workspace. */
+size_t pardtw_dp_workspace_bytes(int64_t n, int64_t m);
+
+/* a1 + a2: pairwise cosine-distance matrix (Sec. IV) as an MFMA GEMM.
+ *   X [device, n*d FP32], Y [device, m*d FP32]: row-major features.
+ *   prec: PARDTW_PREC_F32 or PARDTW_PREC_BF16 (BF16 operands, FP32 accumulate;
+ *         the norms are taken from the same BF16-rounded values).
+ *   layout: PARDTW_LAYOUT_ROW or PARDTW_LAYOUT_PANEL.
+ *   C [device, pardtw_cost_elems(n,m,layout) floats]: overwritten. A frame of
+ *   zero norm is treated as the zero vector, so its cost is 1. */
+pardtw_status pardtw_cost(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
+                          pardtw_prec prec, pardtw_layout layout, float* C, hipStream_t stream);
+
+/* a3: the accumulated-cost dynamic program (Sec. II-D, Sec. III-B), swept as a
+ * staircase wavefront: every 64-column panel advances one row per step and
+ * each panel trails its left neighbour by a few rows, so all cells whose
+ * predecessors are final are computed concurrently. Keeps only the last two
+ * rows of D per panel on chip and writes one code byte per cell.
+ *   C [device]: cost in the given layout (FP32; costs are not clamped).
+ *   bp [device, pardtw_bp_bytes(n,m) bytes]: codes, layout as documented above.
+ *   total [device, 1 float]: D[n-1, m-1] in FP32 (+inf if infeasible).
+ *   pair_status [device, 1 int32]: PARDTW_PAIR_OK / PARDTW_PAIR_INFEASIBLE.
+ *   workspace [device, >= pardtw_dp_workspace_bytes(n,m)], see above.
+ * Per-cell arithmetic (fixed for bit-identical results across schedules):
+ *   cand_r = fmaf(w_r, C[i,j], D_pred_r) in FP32; the winner is chosen by
+ *   strict less-than in the order r = 0, 1, 2. */
+pardtw_status pardtw_dp(const float* C, pardtw_layout layout, int64_t n, int64_t m, uint8_t* bp,
+                        float* total, int32_t* pair_status, void* workspace, size_t workspace_bytes,
+                        hipStream_t stream);
+
+/* pardtw_dp with an explicit schedule: panels_per_workgroup in {1, 2, 4}
+ * consecutive 64-column panels share one workgroup (their boundary columns
+ * pass through LDS); 0 picks it from the problem size. Every schedule gives
+ * bit-identical results; the batched planner times them to choose. */
+pardtw_status pardtw_dp_ex(const float* C, pardtw_layout layout, int64_t n, int64_t m, uint8_t* bp,
+                           float* total, int32_t* pair_status, void* workspace, size_t workspace_bytes,
+                           int32_t panels_per_workgroup, hipStream_t stream);
+
+/* a4: backtrace (Sec. II-D, Sec. VI-C) from (n-1, m-1) along the codes.
+ *   bp [device]: codes written by pardtw_dp for the same (n, m).
+ *   pair_status [device, 1 int32]: as written by pardtw_dp.
+ *   path [device, 2*min(n,m) int32]: (i, j) pairs in forward order, from (0,0).
+ *   path_len [device, 1 int32]: number of pairs written (0 if infeasible). */
+pardtw_status pardtw_backtrace(const uint8_t* bp, int64_t n, int64_t m, const int32_t* pair_status,
+                               int32_t* path, int32_t* path_len, hipStream_t stream);
+
+/* Inspection helper: the DP's backtrace buffer as a row-major n x m int8
+ * matrix out [device, n*m bytes]. */
+pardtw_status pardtw_bp_unpack(const uint8_t* bp, int64_t n, int64_t m, int8_t* out,
+                               hipStream_t stream);
+
+/* a6: gradient of g * J with the optimal path held fixed (the paper motivates
+ * backpropagating through the optimal alignment path, Sec. I):
+ *   J = sum over path cells (i,j) of w_ij * C[i,j], w = 1 at (0,0), else the
+ *   weight of the step that lands on (i,j);
+ *   dC/dx = -(v - <u,v> u)/|x|,  dC/dy = -(u - <u,v> v)/|y|,  u = x/|x|, v = y/|y|.
+ *   X, Y [device FP32], path/path_len [device] from pardtw_backtrace,
+ *   g_total [device, 1 float]: upstream gradient dL/dJ.
+ *   dX [device, n*d FP32], dY [device, m*d FP32]: overwritten; rows and
+ *   columns the path skips are zero, and an infeasible pair gives zeros. */
+pardtw_status pardtw_path_grad(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
+                               const int32_t* path, const int32_t* path_len, const float* g_total,
+                               float* dX, float* dY, hipStream_t stream);
+
+/* ---- a5: batched form -----------------------------------------------------
+ * A plan fixes the pair lengths of a batch and chooses, by measuring, the
+ * schedule of the persistent DP (panels per workgroup, work order). Features of
+ * pair b live at X_packed + x_off[b]*d and Y_packed + y_off[b]*d with x_off,
+ * y_off the exclusive prefix sums of n_b, m_b. Path of pair b: 2*min(n_b,m_b)
+ * int32 starting at paths_packed + 2*path_off[b], path_off the prefix sum of
+ * min(n_b, m_b). pardtw_align_batch makes no allocation and no host sync, so it
+ * can be captured in a hipGraph. */
+typedef struct pardtw_plan pardtw_plan;
+
+pardtw_status pardtw_plan_create(int32_t batch, const int64_t* n_host, const int64_t* m_host,
+                                 int64_t d, pardtw_prec prec, pardtw_plan** plan);
+size_t pardtw_plan_workspace_bytes(const pardtw_plan* plan);
+int64_t pardtw_plan_path_capacity(const pardtw_plan* plan); /* sum of min(n_b, m_b) */
+void pardtw_plan_destroy(pardtw_plan* plan);
+
+pardtw_status pardtw_align_batch(const pardtw_plan* plan, const float* X_packed, const float* Y_packed,
+                                 void* workspace, size_t workspace_bytes, float* totals,
+                                 int32_t* paths_packed, int32_t* path_len, int32_t* pair_status,
+                                 hipStream_t stream);
+
+/* Batched twin of pardtw_path_grad over the plan's pairs (g_totals: batch floats). */
+pardtw_status pardtw_path_grad_batch(const pardtw_plan* plan, const float* X_packed,
+                                     const float* Y_packed, const int32_t* paths_packed,
+                                     const int32_t* path_len, const float* g_totals, float* dX_packed,
+                                     float* dY_packed, hipStream_t stream);
+
+const char* pardtw_status_string(pardtw_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PARDTW_H */

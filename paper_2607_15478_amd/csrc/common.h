@@ -1,0 +1,52 @@
+// Internal definitions shared by the libpardtw HIP sources (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pardtw.h"
+
+namespace pardtw {
+
+constexpr int kLanes = 64;        // wavefront width on CDNA4; one lane per column
+constexpr int kPanel = 64;        // columns per panel (= kLanes)
+constexpr int kBpRows = 8;        // rows per packed backtrace group (8 code bytes per lane)
+
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t num_panels(int64_t m) { return ceil_div(m, kPanel); }
+__host__ __device__ inline int64_t bp_groups(int64_t n) { return ceil_div(n, kBpRows); }
+
+// Byte offset of cell (i, j) inside the backtrace buffer.
+__host__ __device__ inline int64_t bp_offset(int64_t n, int64_t i, int64_t j) {
+    const int64_t p = j / kPanel;
+    return ((p * bp_groups(n) + i / kBpRows) * kLanes + (j % kPanel)) * kBpRows + (i % kBpRows);
+}
+
+// Sizes must stay representable: cells counted in int64, coordinates in int32.
+inline bool valid_sizes(int64_t n, int64_t m) {
+    return n > 0 && m > 0 && n < (int64_t(1) << 31) && m < (int64_t(1) << 31) &&
+           n <= (int64_t(1) << 62) / m;
+}
+
+inline bool pair_feasible(int64_t n, int64_t m) {
+    return (m - 1) <= 2 * (n - 1) && (n - 1) <= 2 * (m - 1);
+}
+
+// Device workspace header of the DP (followed by boundary records).
+struct DpWsHeader {
+    uint32_t epoch;   // launch counter; boundary records carry it as a tag
+    uint32_t ticket;  // work-queue head for the persistent DP
+    uint32_t pad[62];
+};
+static_assert(sizeof(DpWsHeader) == 256, "header keeps records 256-byte aligned");
+
+#define PARDTW_HIP_TRY(expr)                                  \
+    do {                                                      \
+        if ((expr) != hipSuccess) return PARDTW_ERR_HIP;      \
+    } while (0)
+
+inline pardtw_status launch_status() {
+    return hipGetLastError() == hipSuccess ? PARDTW_OK : PARDTW_ERR_HIP;
+}
+
+}  // namespace pardtw

@@ -1,0 +1,186 @@
+"""Thin Python binding of libpardtw.so (declared in include/pardtw.h).
+
+Argument marshalling only: every step of the alignment runs in the library's
+HIP kernels. PyTorch supplies device memory and the current stream. The
+library must have been built (``python -m paper_2607_15478_amd.build``);
+importing this module without it raises, there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpardtw.so")
+
+PARDTW_OK = 0
+PAIR_OK = 0
+PAIR_INFEASIBLE = 1
+PREC_F32 = 0
+PREC_BF16 = 1
+LAYOUT_ROW = 0
+LAYOUT_PANEL = 1
+
+STATUS_NAMES = {0: "OK", 1: "ERR_INVALID_ARG", 2: "ERR_WORKSPACE", 3: "ERR_HIP", 4: "ERR_UNSUPPORTED"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2607_15478_amd.build` first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_SZ = ctypes.c_size_t
+_E = ctypes.c_int
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_lib_cost_elems = _sig("pardtw_cost_elems", _SZ, [_I64, _I64, _E])
+_lib_bp_bytes = _sig("pardtw_bp_bytes", _SZ, [_I64, _I64])
+_lib_dp_ws = _sig("pardtw_dp_workspace_bytes", _SZ, [_I64, _I64])
+_lib_cost = _sig("pardtw_cost", _E, [_P, _P, _I64, _I64, _I64, _E, _E, _P, _P])
+_lib_dp = _sig("pardtw_dp", _E, [_P, _E, _I64, _I64, _P, _P, _P, _P, _SZ, _P])
+_lib_dp_ex = _sig("pardtw_dp_ex", _E, [_P, _E, _I64, _I64, _P, _P, _P, _P, _SZ, _I32, _P])
+_lib_bt = _sig("pardtw_backtrace", _E, [_P, _I64, _I64, _P, _P, _P, _P])
+_lib_unpack = _sig("pardtw_bp_unpack", _E, [_P, _I64, _I64, _P, _P])
+_lib_grad = _sig("pardtw_path_grad", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P])
+_lib_plan_create = _sig("pardtw_plan_create", _E, [_I32, _P, _P, _I64, _E, ctypes.POINTER(_P)])
+_lib_plan_ws = _sig("pardtw_plan_workspace_bytes", _SZ, [_P])
+_lib_plan_cap = _sig("pardtw_plan_path_capacity", _I64, [_P])
+_lib_plan_destroy = _sig("pardtw_plan_destroy", None, [_P])
+_lib_align_batch = _sig("pardtw_align_batch", _E, [_P, _P, _P, _P, _SZ, _P, _P, _P, _P, _P])
+_lib_grad_batch = _sig("pardtw_path_grad_batch", _E, [_P, _P, _P, _P, _P, _P, _P, _P, _P])
+_lib_status_string = _sig("pardtw_status_string", ctypes.c_char_p, [_E])
+
+
+class PardtwError(RuntimeError):
+    pass
+
+
+def _check(rc: int, what: str):
+    if rc != PARDTW_OK:
+        msg = _lib_status_string(rc).decode()
+        raise PardtwError(f"{what}: {STATUS_NAMES.get(rc, rc)} ({msg})")
+
+
+def _stream(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+def _dev_f32(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    return t
+
+
+# ---- sizes ------------------------------------------------------------------
+def pardtw_cost_elems(n: int, m: int, layout: int = LAYOUT_PANEL) -> int:
+    return int(_lib_cost_elems(n, m, layout))
+
+
+def pardtw_bp_bytes(n: int, m: int) -> int:
+    return int(_lib_bp_bytes(n, m))
+
+
+def pardtw_dp_workspace_bytes(n: int, m: int) -> int:
+    return int(_lib_dp_ws(n, m))
+
+
+# ---- the four steps of the hot path -----------------------------------------
+def pardtw_cost(X: torch.Tensor, Y: torch.Tensor, C: torch.Tensor, prec: int = PREC_F32,
+                layout: int = LAYOUT_PANEL, stream=None) -> torch.Tensor:
+    _dev_f32(X, "X"), _dev_f32(Y, "Y"), _dev_f32(C, "C")
+    n, d = X.shape
+    m, d2 = Y.shape
+    if d2 != d:
+        raise ValueError("X and Y feature dimensions differ")
+    if C.numel() < pardtw_cost_elems(n, m, layout):
+        raise ValueError("C is too small for this layout")
+    _check(_lib_cost(_ptr(X), _ptr(Y), n, m, d, prec, layout, _ptr(C), _stream(stream)), "pardtw_cost")
+    return C
+
+
+def pardtw_dp(C: torch.Tensor, n: int, m: int, bp: torch.Tensor, total: torch.Tensor, status: torch.Tensor,
+              workspace: torch.Tensor, layout: int = LAYOUT_PANEL, stream=None, panels_per_workgroup=None):
+    _dev_f32(C, "C")
+    if C.numel() < pardtw_cost_elems(n, m, layout):
+        raise ValueError("C is too small for this layout")
+    if bp.dtype != torch.uint8 or bp.numel() < pardtw_bp_bytes(n, m):
+        raise ValueError("bp must be a uint8 tensor of pardtw_bp_bytes(n, m) bytes")
+    if total.dtype != torch.float32 or status.dtype != torch.int32:
+        raise ValueError("total must be float32 and status int32")
+    ws_bytes = workspace.numel() * workspace.element_size()
+    if panels_per_workgroup is None:
+        _check(_lib_dp(_ptr(C), layout, n, m, _ptr(bp), _ptr(total), _ptr(status), _ptr(workspace), ws_bytes,
+                       _stream(stream)), "pardtw_dp")
+    else:
+        _check(_lib_dp_ex(_ptr(C), layout, n, m, _ptr(bp), _ptr(total), _ptr(status), _ptr(workspace), ws_bytes,
+                          int(panels_per_workgroup), _stream(stream)), "pardtw_dp_ex")
+
+
+def pardtw_backtrace(bp: torch.Tensor, n: int, m: int, status: torch.Tensor, path: torch.Tensor,
+                     path_len: torch.Tensor, stream=None):
+    if path.dtype != torch.int32 or path.numel() < 2 * min(n, m):
+        raise ValueError("path must be int32 with room for 2*min(n, m) entries")
+    _check(_lib_bt(_ptr(bp), n, m, _ptr(status), _ptr(path), _ptr(path_len), _stream(stream)),
+           "pardtw_backtrace")
+
+
+def pardtw_bp_unpack(bp: torch.Tensor, n: int, m: int, out: Optional[torch.Tensor] = None, stream=None):
+    if out is None:
+        out = torch.empty((n, m), dtype=torch.int8, device=bp.device)
+    _check(_lib_unpack(_ptr(bp), n, m, _ptr(out), _stream(stream)), "pardtw_bp_unpack")
+    return out
+
+
+def pardtw_path_grad(X, Y, path, path_len, g_total, dX, dY, stream=None):
+    n, d = X.shape
+    m = Y.shape[0]
+    _check(_lib_grad(_ptr(X), _ptr(Y), n, m, d, _ptr(path), _ptr(path_len), _ptr(g_total), _ptr(dX), _ptr(dY),
+                     _stream(stream)), "pardtw_path_grad")
+
+
+# ---- convenience: buffers + the whole path for one pair ---------------------
+class Workspace:
+    """Device buffers for one (n, m) alignment, reusable across calls."""
+
+    def __init__(self, n: int, m: int, device="cuda", layout: int = LAYOUT_PANEL):
+        self.n, self.m, self.layout = n, m, layout
+        self.C = torch.empty(pardtw_cost_elems(n, m, layout), dtype=torch.float32, device=device)
+        self.bp = torch.empty(pardtw_bp_bytes(n, m), dtype=torch.uint8, device=device)
+        self.ws = torch.zeros(pardtw_dp_workspace_bytes(n, m), dtype=torch.uint8, device=device)
+        self.total = torch.empty(1, dtype=torch.float32, device=device)
+        self.status = torch.empty(1, dtype=torch.int32, device=device)
+        self.path = torch.empty((min(n, m), 2), dtype=torch.int32, device=device)
+        self.path_len = torch.empty(1, dtype=torch.int32, device=device)
+
+
+def align_into(X: torch.Tensor, Y: torch.Tensor, w: Workspace, prec: int = PREC_F32, stream=None):
+    """cost -> dp -> backtrace on the given stream, results left in w."""
+    n, m = X.shape[0], Y.shape[0]
+    pardtw_cost(X, Y, w.C, prec, w.layout, stream)
+    pardtw_dp(w.C, n, m, w.bp, w.total, w.status, w.ws, w.layout, stream)
+    pardtw_backtrace(w.bp, n, m, w.status, w.path, w.path_len, stream)
+    return w
+
+
+def align(X: torch.Tensor, Y: torch.Tensor, prec: int = PREC_F32, layout: int = LAYOUT_PANEL):
+    """Exact DTW of two feature sequences on the GPU: (total, path (L,2) int32, status)."""
+    w = Workspace(X.shape[0], Y.shape[0], X.device, layout)
+    align_into(X, Y, w, prec)
+    L = int(w.path_len.item())
+    return float(w.total.item()), w.path[:L].clone(), int(w.status.item())

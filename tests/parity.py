@@ -1,0 +1,112 @@
+"""Path and backtrace parity checks between the GPU results and the oracle.
+
+Rules (restating the parity contract of the build):
+
+* a GPU path must be legal: start (0,0), end (N-1,M-1), every step in
+  {(1,1), (1,2), (2,1)};
+* walking the GPU path backward, the step taken into each cell must equal the
+  oracle's backtrace code at that cell, unless the two candidate totals are a
+  declared near-tie: |cand_r - cand_r'| < 1e-6 * max(|cand_r|, |cand_r'|, 1),
+  evaluated on the oracle's FP64 candidates;
+* the FP32 total must be within 1e-5 relative of the oracle's FP64 total;
+* the GPU path re-scored in FP64 must not exceed J* (1 + 1e-6) + 1e-9.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+STEPS = ((1, 1), (1, 2), (2, 1))
+TIE_REL = 1e-6
+TOTAL_REL = 1e-5
+
+
+def step_codes(path: np.ndarray) -> np.ndarray:
+    d = np.diff(path.astype(np.int64), axis=0)
+    codes = np.full(len(d), -1, dtype=np.int64)
+    for c, (di, dj) in enumerate(STEPS):
+        codes[(d[:, 0] == di) & (d[:, 1] == dj)] = c
+    return codes
+
+
+def check_legal(path: np.ndarray, n: int, m: int):
+    assert path.ndim == 2 and path.shape[1] == 2 and len(path) >= 1
+    assert tuple(path[0]) == (0, 0), "path must start at (0,0)"
+    assert tuple(path[-1]) == (n - 1, m - 1), "path must end at (N-1,M-1)"
+    codes = step_codes(path)
+    assert np.all(codes >= 0), "illegal step in path"
+    assert len(path) <= min(n, m)
+
+
+def is_tie(cand: np.ndarray, r: int, r2: int) -> bool:
+    a, b = float(cand[r]), float(cand[r2])
+    if not (np.isfinite(a) and np.isfinite(b)):
+        return False
+    return abs(a - b) < TIE_REL * max(abs(a), abs(b), 1.0)
+
+
+def audit_path(path: np.ndarray, oracle_bp: np.ndarray, cand_at):
+    """Compare the GPU path's steps with the oracle's codes.
+
+    cand_at(cells (k,2)) -> (k,3) FP64 candidate totals. Returns the number of
+    declared near-ties; raises AssertionError on a real mismatch."""
+    codes = step_codes(path)
+    cells = path[1:]
+    ocodes = oracle_bp[cells[:, 0], cells[:, 1]].astype(np.int64)
+    diff = np.nonzero(ocodes != codes)[0]
+    if len(diff) == 0:
+        return 0
+    cands = cand_at(cells[diff])
+    for q, k in enumerate(diff):
+        r_gpu, r_or = int(codes[k]), int(ocodes[k])
+        assert 0 <= r_or <= 2, f"GPU path enters cell {tuple(cells[k])} that the oracle marks unreachable"
+        assert is_tie(cands[q], r_or, r_gpu), (
+            f"step mismatch at {tuple(cells[k])}: gpu {r_gpu} oracle {r_or}, candidates {cands[q]}")
+    return len(diff)
+
+
+def audit_bp_matrix(gpu_bp: np.ndarray, oracle_bp: np.ndarray, D: np.ndarray, C: np.ndarray):
+    """Full backtrace-matrix parity: every differing cell must be a declared tie
+    of the oracle's FP64 candidates (computed from the full D). Returns the
+    number of tie cells."""
+    diff = np.argwhere(gpu_bp != oracle_bp)
+    for i, j in diff:
+        cand = np.full(3, np.inf)
+        for r, (di, dj) in enumerate(STEPS):
+            if i - di >= 0 and j - dj >= 0:
+                cand[r] = D[i - di, j - dj] + (2.0 if r == 0 else 3.0) * float(C[i, j])
+        assert 0 <= gpu_bp[i, j] <= 2 and 0 <= oracle_bp[i, j] <= 2, (
+            f"code mismatch at {(i, j)} involving an unreachable cell: gpu {gpu_bp[i, j]} oracle {oracle_bp[i, j]}")
+        assert is_tie(cand, int(oracle_bp[i, j]), int(gpu_bp[i, j])), (
+            f"code mismatch at {(i, j)}: gpu {gpu_bp[i, j]} oracle {oracle_bp[i, j]} candidates {cand}")
+    return len(diff)
+
+
+def check_total(gpu_total: float, oracle_total: float):
+    if not np.isfinite(oracle_total):
+        assert not np.isfinite(gpu_total)
+        return
+    assert abs(gpu_total - oracle_total) <= TOTAL_REL * abs(oracle_total) + 1e-6, (gpu_total, oracle_total)
+
+
+def to_panel(C: np.ndarray) -> np.ndarray:
+    """Row-major (n, m) cost to the 64-column panel layout (flat)."""
+    n, m = C.shape
+    P = -(-m // 64)
+    out = np.zeros((P, n, 64), dtype=C.dtype)
+    for p in range(P):
+        w = min(64, m - 64 * p)
+        out[p, :, :w] = C[:, 64 * p:64 * p + w]
+    return out.reshape(-1)
+
+
+def from_panel(flat: np.ndarray, n: int, m: int) -> np.ndarray:
+    P = -(-m // 64)
+    a = flat[: P * n * 64].reshape(P, n, 64)
+    return np.concatenate([a[p] for p in range(P)], axis=1)[:, :m]
+
+
+def bf16_round(a: np.ndarray) -> np.ndarray:
+    """Round FP32 values to the nearest BF16 (ties to even), returned as FP32."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32)

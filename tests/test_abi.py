@@ -1,0 +1,70 @@
+"""The C-ABI library loads on the CPU host and exports every declared symbol;
+host-side argument validation and size helpers work without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pardtw.h")
+LIB = os.path.join(ROOT, "paper_2607_15478_amd", "libpardtw.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pardtw_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2607_15478_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 14
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_size_helpers(lib):
+    I = ctypes.c_int64
+    lib.pardtw_cost_elems.restype = ctypes.c_size_t
+    lib.pardtw_cost_elems.argtypes = [I, I, ctypes.c_int]
+    lib.pardtw_bp_bytes.restype = ctypes.c_size_t
+    lib.pardtw_bp_bytes.argtypes = [I, I]
+    lib.pardtw_dp_workspace_bytes.restype = ctypes.c_size_t
+    lib.pardtw_dp_workspace_bytes.argtypes = [I, I]
+    n, m = 50000, 60000
+    P = -(-m // 64)
+    assert lib.pardtw_cost_elems(n, m, 0) == n * m
+    assert lib.pardtw_cost_elems(n, m, 1) == P * n * 64
+    assert lib.pardtw_bp_bytes(n, m) == P * (-(-n // 8)) * 64 * 8
+    assert lib.pardtw_dp_workspace_bytes(n, m) == 256 + P * n * 16
+    assert lib.pardtw_cost_elems(0, 5, 0) == 0
+    assert lib.pardtw_bp_bytes(-1, 5) == 0
+    assert lib.pardtw_cost_elems(3, 5, 7) == 0
+
+
+def test_validation_without_gpu(lib):
+    I = ctypes.c_int64
+    P = ctypes.c_void_p
+    lib.pardtw_dp.restype = ctypes.c_int
+    lib.pardtw_dp.argtypes = [P, ctypes.c_int, I, I, P, P, P, P, ctypes.c_size_t, P]
+    fake = ctypes.c_void_p(0x1000)
+    # null cost pointer
+    assert lib.pardtw_dp(None, 1, 10, 10, fake, fake, fake, fake, 1 << 20, None) == 1
+    # bad sizes
+    assert lib.pardtw_dp(fake, 1, 0, 10, fake, fake, fake, fake, 1 << 20, None) == 1
+    # bad layout
+    assert lib.pardtw_dp(fake, 9, 10, 10, fake, fake, fake, fake, 1 << 20, None) == 4
+    # workspace too small
+    assert lib.pardtw_dp(fake, 1, 10, 10, fake, fake, fake, fake, 16, None) == 2
+    lib.pardtw_status_string.restype = ctypes.c_char_p
+    lib.pardtw_status_string.argtypes = [ctypes.c_int]
+    assert lib.pardtw_status_string(2) == b"workspace missing or too small"
