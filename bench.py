@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Benchmark: exact ParDTW on one MI355X, 50000 x 60000 chroma-like pair.
+
+One step = the whole hot path for one pair with inputs resident in HBM:
+  cosine-cost MFMA GEMM (panel layout) -> staircase-wavefront DP -> backtrace.
+Prints one JSON line with GCUPS (N*M cells / step time), pairs/s, the DP
+kernel's roofline figures (algorithmic bytes / measured kernel time against
+the 8 TB/s HBM peak), an oracle CPU baseline on a bounded sample, and the
+result of validating the GPU path against the FP64 oracle (full sweep, run on
+a host thread while the GPU is timed).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+DP_BYTES_PER_CELL = 5  # 4 B cost read + 1 B backtrace code written
+WORKLOAD = "pair_50000x60000_d12"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--no-validate", action="store_true", help="skip the full oracle path check")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the baseline sample")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "dp_traffic.json"))
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0,
+                    help="also run a plain device copy of this size (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU only; a multi-GPU run is not supported "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2607_15478_amd import synth
+    from paper_2607_15478_amd import pardtw as pd
+
+    dev = torch.device("cuda:0")
+    spec = synth.WORKLOADS[args.workload]
+    assert spec["kind"] == "pair"
+    print(f"[bench] generating {args.workload}", file=sys.stderr, flush=True)
+    X, Y = synth.make_workload(args.workload)
+    n, m, d = X.shape[0], Y.shape[0], X.shape[1]
+    cells = n * m
+
+    # ---- validation oracle on a host thread (full FP64 sweep) ----
+    val = {}
+
+    def run_oracle():
+        import oracle
+        t0 = time.perf_counter()
+        J, BP = oracle.dtw_features(X, Y)
+        val["J"], val["BP"], val["secs"] = J, BP, time.perf_counter() - t0
+
+    th = None
+    if not args.no_validate:
+        th = threading.Thread(target=run_oracle, daemon=True)
+        th.start()
+
+    Xd = torch.from_numpy(X).to(dev)
+    Yd = torch.from_numpy(Y).to(dev)
+    w = pd.Workspace(n, m, dev, pd.LAYOUT_PANEL)
+    stream = torch.cuda.current_stream()
+
+    calib = None
+    if args.calib_copy_gib > 0:
+        nb = int(args.calib_copy_gib * (1 << 30))
+        src = torch.empty(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        calib = {"bytes_each_way": nb}
+        del src, dst
+
+    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        pd.align_into(Xd, Yd, w)
+    torch.cuda.synchronize()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        e = evs[s]
+        e[0].record(stream)
+        pd.pardtw_cost(Xd, Yd, w.C, pd.PREC_F32, pd.LAYOUT_PANEL)
+        e[1].record(stream)
+        pd.pardtw_dp(w.C, n, m, w.bp, w.total, w.status, w.ws, pd.LAYOUT_PANEL)
+        e[2].record(stream)
+        pd.pardtw_backtrace(w.bp, n, m, w.status, w.path, w.path_len)
+        e[3].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stage_ms = np.array([[e[k].elapsed_time(e[k + 1]) for k in range(3)] for e in evs])
+    cost_ms, dp_ms, bt_ms = stage_ms.mean(0)
+    ms_per_step = wall * 1e3 / args.steps
+    gcups = cells / (ms_per_step * 1e-3) / 1e9
+    print(f"[bench] step {ms_per_step:.3f} ms (cost {cost_ms:.3f}, dp {dp_ms:.3f}, backtrace {bt_ms:.3f})",
+          file=sys.stderr, flush=True)
+
+    total = float(w.total.item())
+    L = int(w.path_len.item())
+    path = w.path[:L].cpu().numpy()
+
+    dp_achieved = DP_BYTES_PER_CELL * cells / (dp_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            tj = json.load(open(args.traffic_json))
+            if tj.get("workload") == args.workload:
+                traffic = tj.get("bytes_per_launch")
+        except (OSError, ValueError):
+            traffic = None
+    roofline = {"bound": "hbm", "achieved": round(dp_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dp_achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "dp_kernel", "algorithmic_bytes_per_launch": DP_BYTES_PER_CELL * cells,
+                "kernel_ms": round(float(dp_ms), 4)}
+
+    # ---- validation against the oracle ----
+    validation = None
+    if th is not None:
+        print("[bench] waiting for the oracle sweep", file=sys.stderr, flush=True)
+        th.join()
+        from tests import parity
+        import oracle
+        ok = True
+        ties = -1
+        msg = "ok"
+        try:
+            parity.check_legal(path, n, m)
+            parity.check_total(total, val["J"])
+            ties = parity.audit_path(path, val["BP"], lambda c: oracle.probe(c, X=X, Y=Y)[0])
+        except AssertionError as exc:  # report, do not hide
+            ok, msg = False, str(exc)[:300]
+        validation = {"path_match": ok, "declared_ties": ties, "oracle_total": val["J"], "gpu_total": total,
+                      "path_len": L, "oracle_secs": round(val["secs"], 2), "detail": msg}
+        del val["BP"]
+
+    # ---- CPU baseline: the oracle on a bounded leading block of the same pair ----
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        rate_guess = 6e7  # cells/s of the single-thread FP64 oracle
+        side = float(np.sqrt(args.cpu_seconds * rate_guess / cells))
+        ns, ms_ = max(64, int(n * side)), max(64, int(m * side))
+        ns, ms_ = min(ns, n), min(ms_, m)
+        t1 = time.perf_counter()
+        oracle.dtw_features(X[:ns], Y[:ms_])
+        dt = time.perf_counter() - t1
+        cpu = {"value": round(ns * ms_ / dt / 1e9, 5), "unit": "GCUPS", "cores": 1, "kind": "oracle",
+               "sample": f"leading {ns}x{ms_} block of the {n}x{m} pair: FP64 cost rows + DP + int8 "
+                         f"backtrace matrix, single thread, {dt:.1f} s"}
+
+    out = {
+        "metric": "DP cells/sec (GCUPS) + aligned pairs/sec at oracle path match, 1 MI355X",
+        "value": round(gcups, 2),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": m, "d": d, "cells": cells, "layout": "panel64",
+                   "pairs_per_s": round(1e3 / ms_per_step, 3),
+                   "stage_ms": {"cost": round(float(cost_ms), 4), "dp": round(float(dp_ms), 4),
+                                "backtrace": round(float(bt_ms), 4)}},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "validation": validation,
+    }
+    if calib:
+        out["calibration_copy"] = calib
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

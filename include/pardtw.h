@@ -57,10 +57,12 @@ typedef enum {
 typedef enum {
     /* Row-major N x M: C[i*M + j]. */
     PARDTW_LAYOUT_ROW = 0,
-    /* Column panels of 64: panel p = j / 64 holds columns [64p, 64p+64) for all
-     * rows, contiguous: C[(p*N + i)*64 + (j - 64p)], P = ceil(M/64) panels. The
-     * unused columns of the last panel are padding. This is the layout the DP
-     * streams with fully sequential 256-byte rows per wavefront. */
+    /* Column panels of 64 columns, each cut into groups of 8 rows; inside a
+     * group the 8 values of one column are contiguous:
+     *   C[((p*G + i/8)*64 + (j - 64p))*8 + i%8],  p = j/64, G = ceil(N/8),
+     * P = ceil(M/64) panels, P*G*512 floats. Columns past M and rows past N are
+     * padding. A wavefront of the DP reads one 8-row chunk of its panel as 2 KB
+     * of contiguous memory, 32 bytes per lane. */
     PARDTW_LAYOUT_PANEL = 1
 } pardtw_layout;
 
@@ -70,9 +72,8 @@ typedef enum {
 /* Number of floats a cost buffer of the given layout occupies (0 on bad args). */
 size_t pardtw_cost_elems(int64_t n, int64_t m, pardtw_layout layout);
 
-/* Bytes of the backtrace buffer written by pardtw_dp (0 on bad args). The
- * layout is the DP's own: 64-column panels, and within a panel 8-row groups
- * where each column's 8 codes are 8 consecutive bytes:
+/* Bytes of the backtrace buffer written by pardtw_dp (0 on bad args). It has
+ * the panel layout above with one code byte per cell:
  *   byte((i,j)) = ((p*G + i/8)*64 + (j%64))*8 + i%8,  p = j/64, G = ceil(N/8).
  * pardtw_bp_unpack converts it to a plain row-major N x M int8 matrix. */
 size_t pardtw_bp_bytes(int64_t n, int64_t m);

@@ -8,7 +8,7 @@
 // v_mfma_f32_16x16x32_bf16 for BF16 operands (FP32 accumulate in both). The
 // inverse norms of the tile's 64 rows and 64 columns are computed in the same
 // workgroup into LDS. The tile is written either into the DP's panel layout
-// (64 rows x 256 bytes, one contiguous 16 KB block) or row-major.
+// (one contiguous 16 KB block) or row-major.
 //
 // With D = 12 the kernel does 24 flop per 4-byte output, far below the MFMA
 // ridge point, so it is bound by HBM writes; the MFMA keeps the arithmetic off
@@ -102,22 +102,37 @@ __global__ __launch_bounds__(kThreads) void cost_kernel(const float* __restrict_
     }
     __syncthreads();
 
-    // output layout of a 16x16 block: lane holds column lane%16 of rows 4*(lane/16) + r
+    // Output of a 16x16 block: lane holds column lane%16 of rows 4*(lane/16) + r,
+    // r = 0..3. Those four rows lie in one 8-row group, and the panel layout
+    // keeps a column's 8 rows of a group contiguous, so each lane writes one
+    // 16-byte vector per block and a wave's store covers 1 KB without holes.
+    const int tr0 = wave * 16 + 4 * (lane >> 4);  // first of the lane's 4 tile rows
+    const int64_t ib = i0 + tr0;
+    if constexpr (PANEL) {
+        const int64_t G = bp_groups(n);
+        if (ib / kBpRows < G) {
+            float* dst = C + ((p * G + ib / kBpRows) * kPanel) * kBpRows + (ib % kBpRows);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int tr = wave * 16 + 4 * (lane >> 4) + r;  // row within the tile
-        const int64_t i = i0 + tr;
-        if (i >= n) continue;
-        const float sx = rx[tr];
+            for (int b = 0; b < 4; ++b) {
+                const int cc = b * 16 + (lane & 15);
+                const float sy = ry[cc];
+                f32x4 v;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int cc = b * 16 + (lane & 15);
-            const float v = 1.0f - (acc[b][r] * sx) * ry[cc];
-            if constexpr (PANEL) {
-                __builtin_nontemporal_store(v, C + (p * n + i) * kPanel + cc);
-            } else {
+                for (int r = 0; r < 4; ++r) v[r] = 1.0f - (acc[b][r] * rx[tr0 + r]) * sy;
+                __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(dst + cc * kBpRows));
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t i = ib + r;
+            if (i >= n) continue;
+            const float sx = rx[tr0 + r];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int cc = b * 16 + (lane & 15);
                 const int64_t j = j0 + cc;
-                if (j < m) __builtin_nontemporal_store(v, C + i * m + j);
+                if (j < m) __builtin_nontemporal_store(1.0f - (acc[b][r] * sx) * ry[cc], C + i * m + j);
             }
         }
     }
@@ -146,7 +161,8 @@ pardtw_status cost_launch(const float* X, const float* Y, int64_t n, int64_t m, 
 extern "C" size_t pardtw_cost_elems(int64_t n, int64_t m, pardtw_layout layout) {
     if (!pardtw::valid_sizes(n, m)) return 0;
     if (layout == PARDTW_LAYOUT_ROW) return size_t(n) * size_t(m);
-    if (layout == PARDTW_LAYOUT_PANEL) return size_t(pardtw::num_panels(m)) * size_t(n) * pardtw::kPanel;
+    if (layout == PARDTW_LAYOUT_PANEL)
+        return size_t(pardtw::num_panels(m)) * size_t(pardtw::bp_groups(n)) * pardtw::kPanel * pardtw::kBpRows;
     return 0;
 }
 

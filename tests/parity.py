@@ -89,20 +89,20 @@ def check_total(gpu_total: float, oracle_total: float):
 
 
 def to_panel(C: np.ndarray) -> np.ndarray:
-    """Row-major (n, m) cost to the 64-column panel layout (flat)."""
+    """Row-major (n, m) cost to the panel layout (flat): 64-column panels,
+    8-row groups, a column's 8 rows of a group contiguous."""
     n, m = C.shape
-    P = -(-m // 64)
-    out = np.zeros((P, n, 64), dtype=C.dtype)
-    for p in range(P):
-        w = min(64, m - 64 * p)
-        out[p, :, :w] = C[:, 64 * p:64 * p + w]
-    return out.reshape(-1)
+    P, G = -(-m // 64), -(-n // 8)
+    pad = np.zeros((G * 8, P * 64), dtype=C.dtype)
+    pad[:n, :m] = C
+    # [G*8, P*64] -> [P, G, 64, 8]
+    return pad.reshape(G, 8, P, 64).transpose(2, 0, 3, 1).reshape(-1).copy()
 
 
 def from_panel(flat: np.ndarray, n: int, m: int) -> np.ndarray:
-    P = -(-m // 64)
-    a = flat[: P * n * 64].reshape(P, n, 64)
-    return np.concatenate([a[p] for p in range(P)], axis=1)[:, :m]
+    P, G = -(-m // 64), -(-n // 8)
+    a = flat[: P * G * 512].reshape(P, G, 64, 8)
+    return a.transpose(1, 3, 0, 2).reshape(G * 8, P * 64)[:n, :m]
 
 
 def bf16_round(a: np.ndarray) -> np.ndarray:
