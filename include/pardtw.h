@@ -57,12 +57,13 @@ typedef enum {
 typedef enum {
     /* Row-major N x M: C[i*M + j]. */
     PARDTW_LAYOUT_ROW = 0,
-    /* Column panels of 64 columns, each cut into groups of 8 rows; inside a
-     * group the 8 values of one column are contiguous:
-     *   C[((p*G + i/8)*64 + (j - 64p))*8 + i%8],  p = j/64, G = ceil(N/8),
-     * P = ceil(M/64) panels, P*G*512 floats. Columns past M and rows past N are
-     * padding. A wavefront of the DP reads one 8-row chunk of its panel as 2 KB
-     * of contiguous memory, 32 bytes per lane. */
+    /* Column panels of 64 columns, each cut into groups of 8 rows; a group
+     * stores rows 0-3 of its 64 columns, then rows 4-7, each column's 4 rows
+     * contiguous:
+     *   C[((p*G + i/8)*2 + (i%8)/4)*256 + (j - 64p)*4 + i%4],
+     *   p = j/64, G = ceil(N/8), P = ceil(M/64) panels, P*G*512 floats.
+     * Columns past M and rows past N are padding. A wavefront of the DP reads
+     * one 8-row chunk of its panel with two 1 KB contiguous loads. */
     PARDTW_LAYOUT_PANEL = 1
 } pardtw_layout;
 
@@ -72,8 +73,8 @@ typedef enum {
 /* Number of floats a cost buffer of the given layout occupies (0 on bad args). */
 size_t pardtw_cost_elems(int64_t n, int64_t m, pardtw_layout layout);
 
-/* Bytes of the backtrace buffer written by pardtw_dp (0 on bad args). It has
- * the panel layout above with one code byte per cell:
+/* Bytes of the backtrace buffer written by pardtw_dp (0 on bad args). Codes
+ * use 64-column panels and 8-row groups with a column's 8 codes contiguous:
  *   byte((i,j)) = ((p*G + i/8)*64 + (j%64))*8 + i%8,  p = j/64, G = ceil(N/8).
  * pardtw_bp_unpack converts it to a plain row-major N x M int8 matrix. */
 size_t pardtw_bp_bytes(int64_t n, int64_t m);
@@ -112,7 +113,7 @@ pardtw_status pardtw_dp(const float* C, pardtw_layout layout, int64_t n, int64_t
                         float* total, int32_t* pair_status, void* workspace, size_t workspace_bytes,
                         hipStream_t stream);
 
-/* pardtw_dp with an explicit schedule: panels_per_workgroup in {1, 2, 4}
+/* pardtw_dp with an explicit schedule: panels_per_workgroup in {1, 2, 4, 8}
  * consecutive 64-column panels share one workgroup (their boundary columns
  * pass through LDS); 0 picks it from the problem size. Every schedule gives
  * bit-identical results; the batched planner times them to choose. */

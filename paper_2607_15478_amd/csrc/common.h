@@ -34,11 +34,12 @@ inline bool pair_feasible(int64_t n, int64_t m) {
 
 // Device workspace header of the DP (followed by boundary records).
 struct DpWsHeader {
-    uint32_t epoch;   // launch counter; boundary records carry it as a tag
-    uint32_t ticket;  // work-queue head for the persistent DP
+    uint32_t epoch;    // launch counter; boundary records carry it as a tag
+    uint32_t ticket;   // work-queue head for the persistent DP
     uint32_t pad[62];
+    uint64_t sink[64]; // target of the DP's stores for chunks past the end
 };
-static_assert(sizeof(DpWsHeader) == 256, "header keeps records 256-byte aligned");
+static_assert(sizeof(DpWsHeader) == 768, "header keeps records 256-byte aligned");
 
 #define PARDTW_HIP_TRY(expr)                                  \
     do {                                                      \

@@ -103,15 +103,16 @@ __global__ __launch_bounds__(kThreads) void cost_kernel(const float* __restrict_
     __syncthreads();
 
     // Output of a 16x16 block: lane holds column lane%16 of rows 4*(lane/16) + r,
-    // r = 0..3. Those four rows lie in one 8-row group, and the panel layout
-    // keeps a column's 8 rows of a group contiguous, so each lane writes one
-    // 16-byte vector per block and a wave's store covers 1 KB without holes.
+    // r = 0..3. In the panel layout those four rows of one column are 16
+    // contiguous bytes (a half-group), so each lane writes one 16-byte vector
+    // per block and the 16 lanes of a row quad cover 256 contiguous bytes.
     const int tr0 = wave * 16 + 4 * (lane >> 4);  // first of the lane's 4 tile rows
     const int64_t ib = i0 + tr0;
     if constexpr (PANEL) {
         const int64_t G = bp_groups(n);
         if (ib / kBpRows < G) {
-            float* dst = C + ((p * G + ib / kBpRows) * kPanel) * kBpRows + (ib % kBpRows);
+            const int64_t half = (p * G + ib / kBpRows) * 2 + (ib % kBpRows) / 4;
+            float* dst = C + half * (kPanel * 4);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int cc = b * 16 + (lane & 15);
@@ -119,7 +120,7 @@ __global__ __launch_bounds__(kThreads) void cost_kernel(const float* __restrict_
                 f32x4 v;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) v[r] = 1.0f - (acc[b][r] * rx[tr0 + r]) * sy;
-                __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(dst + cc * kBpRows));
+                __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(dst + cc * 4));
             }
         }
     } else {

@@ -27,9 +27,9 @@
 // progress whatever the number of resident workgroups.
 //
 // Memory traffic per cell: 4 bytes of cost read and 1 byte of backtrace code
-// written. In the panel layout a lane reads its column's 8 costs of a chunk
-// as two 16-byte loads and writes its 8 codes as one 8-byte store; a wave's
-// chunk is 2 KB of contiguous cost and 512 contiguous bytes of codes.
+// written. In the panel layout a wave reads a chunk's 2 KB of cost with two
+// loads of 1 KB contiguous each (16 bytes per lane) and writes its 512 bytes
+// of codes with one store (8 bytes per lane).
 #include "common.h"
 
 namespace pardtw {
@@ -38,15 +38,15 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kChunk = kBpRows;  // rows per synchronisation chunk (= packed group)
-constexpr int kRing = 16;        // LDS ring depth, in chunks
+constexpr int kRing = 32;        // LDS ring depth, in chunks
 constexpr int kPfPanel = 8;      // cost prefetch distance in chunks, panel layout
 constexpr int kPfRow = 4;        // the same for the row-major layout (8 loads per chunk)
-constexpr int kHelperWin = 4;    // chunks polled per helper round trip (64 lanes)
-constexpr int kMaxNW = 4;
+constexpr int kHelperWin = 16;   // chunks polled per helper round trip (4 records per lane)
+constexpr int kMaxNW = 8;
 
 struct DpShared {
     int super;
-    int prog[kMaxNW + 1];  // ring w: chunks published by its producer
+    int prog[kMaxNW + 1][2];  // ring w: chunks published by its producer (two copies, see below)
     int cons[kMaxNW + 1];  // ring w: chunks released by its consumer
     // ring[w][slot][c][r] = D[8k + r][64p - 2 + c] for chunk k, slot = k % kRing
     float ring[kMaxNW + 1][kRing][2][kChunk];
@@ -81,109 +81,228 @@ struct DpArgs {
     int S;          // number of panel groups (= ceil(P / NW))
 };
 
-enum { kOutNone = 0, kOutLocal = 1, kOutGlobal = 2 };
-
+// Loads chunk k of panel p into cb. Every call issues the same loads: when
+// `real` is false (a chunk whose result is known without its costs, or one
+// past the end) the loads read the panel's first chunk instead, which stays
+// cached; each panel uses its own, so these reads spread over the caches. Unconditional loads keep the compiler's count of outstanding
+// memory operations exact, so the prefetch ring really stays kPf chunks deep.
 template <bool PANEL>
-__device__ __attribute__((always_inline)) inline void load_chunk(const DpArgs& a, int p, int lane, int64_t k, float (&cb)[kChunk]) {
+__device__ __attribute__((always_inline)) inline void load_chunk(const DpArgs& a, int p, int lane, int k, bool real,
+                                                                 float (&cb)[kChunk]) {
     if constexpr (PANEL) {
-        const f32x4* src = reinterpret_cast<const f32x4*>(a.C + ((int64_t(p) * a.G + k) * kLanes + lane) * kChunk);
+        // rows 0-3 of the chunk for all 64 columns, then rows 4-7: each load
+        // instruction reads 1 KB of contiguous memory
+        const int64_t off = (int64_t(p) * a.G + (real ? k : 0)) * (kLanes * kChunk);
+        const f32x4* src = reinterpret_cast<const f32x4*>(a.C + off) + lane;
         const f32x4 v0 = __builtin_nontemporal_load(src);
-        const f32x4 v1 = __builtin_nontemporal_load(src + 1);
+        const f32x4 v1 = __builtin_nontemporal_load(src + kLanes);
         cb[0] = v0[0]; cb[1] = v0[1]; cb[2] = v0[2]; cb[3] = v0[3];
         cb[4] = v1[0]; cb[5] = v1[1]; cb[6] = v1[2]; cb[7] = v1[3];
     } else {
+        // padding lanes and rows read element 0; their results are never used
         const int64_t j = int64_t(p) * kPanel + lane;
         const bool colv = j < a.m;
 #pragma unroll
         for (int r = 0; r < kChunk; ++r) {
-            const int64_t i = k * kChunk + r;
-            cb[r] = (colv && i < a.n) ? __builtin_nontemporal_load(a.C + i * a.m + j) : 0.0f;
+            const int64_t i = int64_t(k) * kChunk + r;
+            const int64_t off = (real && colv && i < a.n) ? i * a.m + j : 0;
+            cb[r] = __builtin_nontemporal_load(a.C + off);
         }
     }
 }
 
-template <int NW, bool PANEL, bool HAVE_LEFT, int OUT>
-__device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs& a, DpShared& sh, int wave, int p, uint32_t epoch) {
+// Cells reachable from (0,0) by the three steps are exactly those with
+// j <= 2i and i <= 2j. For chunk k of panel p (rows 8k..8k+7, columns
+// jlo..jhi = 64p..64p+63) every cell is unreachable when jlo > 2(8k+7) or
+// 8k > 2 jhi: then D = +inf and code 3 everywhere and the chunk's result is
+// known without reading its costs. Every cell is reachable when jhi <= 16k and
+// 8k+7 <= 2 jlo: then no cell can see three infinite candidates and the
+// per-cell unreachable test is not needed. Both sets are ranges of k,
+// computed once per panel.
+struct ChunkRanges {
+    int lo, hi;    // chunks with at least one reachable cell: [lo, hi]
+    int flo, fhi;  // chunks with only reachable cells: [flo, fhi]
+};
+
+__device__ inline ChunkRanges chunk_ranges(int p, int64_t G) {
+    const int64_t jlo = int64_t(p) * kPanel, jhi = jlo + kPanel - 1;
+    ChunkRanges r;
+    const int64_t lo = jlo <= 14 ? 0 : (jlo - 14 + 15) / 16;  // first k with 16k + 14 >= jlo
+    const int64_t hi = jhi / 4;                                // last k with 8k <= 2 jhi
+    const int64_t flo = (jhi + 15) / 16;                       // first k with 16k >= jhi
+    const int64_t fhi = (2 * jlo - 7) < 0 ? -1 : (2 * jlo - 7) / 8;  // last k with 8k + 7 <= 2 jlo
+    auto clampk = [&](int64_t v) { return int(v < -1 ? -1 : (v > G ? G : v)); };
+    r.lo = clampk(lo);
+    r.hi = clampk(hi);
+    r.flo = clampk(flo);
+    r.fhi = clampk(fhi);
+    return r;
+}
+
+enum { kChunkSkip = 0, kChunkFast = 1, kChunkFull = 2 };
+
+__device__ inline int chunk_class(int k, const ChunkRanges& r) {
+    if (k < r.lo || k > r.hi) return kChunkSkip;
+    if (k >= r.flo && k <= r.fhi) return kChunkFast;
+    return kChunkFull;
+}
+
+// One 8-row chunk of a panel. `lv0/lv1` hold the left boundary columns
+// D[i0+r][64p-2] / D[i0+r][64p-1]; e0/e1 the same for row i0-1.
+template <bool CHECK_INF>
+__device__ __attribute__((always_inline)) inline void dp_rows(const float (&cb)[kChunk], const float (&lv0)[kChunk],
+                                                              const float (&lv1)[kChunk], float e0, float e1,
+                                                              float& d1, float& s1p, uint32_t& lo, uint32_t& hi,
+                                                              float (&best_r)[kChunk]) {
+    const float kInf = __builtin_inff();
+    lo = 0;
+    hi = 0;
+#pragma unroll
+    for (int r = 0; r < kChunk; ++r) {
+        const float c = cb[r];
+        const float s1 = shift_in(d1, r == 0 ? e1 : lv1[r - 1]);  // D[i-1][j-1]
+        const float s2 = shift_in(s1, r == 0 ? e0 : lv0[r - 1]);  // D[i-1][j-2]
+        const float c0 = __builtin_fmaf(2.0f, c, s1);
+        const float c1 = __builtin_fmaf(3.0f, c, s2);
+        const float c2 = __builtin_fmaf(3.0f, c, s1p);
+        const float best = __builtin_fminf(__builtin_fminf(c0, c1), c2);
+        uint32_t code = (c1 == best) ? 1u : 2u;
+        code = (c0 == best) ? 0u : code;
+        if constexpr (CHECK_INF) code = (best == kInf) ? 3u : code;
+        if (r < 4) lo |= code << (8 * r); else hi |= code << (8 * (r - 4));
+        d1 = best;
+        s1p = s1;
+        best_r[r] = best;
+    }
+}
+
+// A compute wave owns panel p. Its role flags (a left neighbour to read, a
+// right neighbour to feed) are runtime values made opaque to the optimiser, so
+// every role runs the same instructions: the unrolled chunk loop is large and
+// several roles sharing one instruction cache would otherwise evict each
+// other.
+template <bool PANEL>
+__device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs& a, DpShared& sh, int wave, int p,
+                                                                   bool have_left, bool have_out) {
     const int lane = threadIdx.x & 63;
-    const int64_t G = a.G;  // chunks per panel (rows padded to a multiple of 8)
+    const int G = int(a.G);  // chunks per panel (rows padded to a multiple of 8)
+    const ChunkRanges cr = chunk_ranges(p, a.G);
     const float kInf = __builtin_inff();
     const int bcol = lane - (kLanes - 2);  // 0 / 1 on the two boundary lanes
-    float* rin = &sh.ring[wave][0][0][0];
-    float* rout = &sh.ring[wave + 1][0][0][0];
-    uint64_t* rec_out = a.rec + (size_t(p) * size_t(G) * kChunk) * 2;
     uint64_t* bp_out = reinterpret_cast<uint64_t*>(a.bp) + int64_t(p) * G * kLanes + lane;
+    const float* rin = &sh.ring[wave][0][0][0];
+    float* rout = &sh.ring[wave + 1][0][0][0];
+    int flags = __builtin_amdgcn_readfirstlane((have_left ? 1 : 0) | (have_out ? 2 : 0));
 
     constexpr int kPf = PANEL ? kPfPanel : kPfRow;
+    static_assert(kPf % 2 == 0, "boundary buffers alternate between even and odd chunks");
     float cbuf[kPf][kChunk];
 #pragma unroll
     for (int u = 0; u < kPf; ++u)
-        if (u < G) load_chunk<PANEL>(a, p, lane, u, cbuf[u]);
+        load_chunk<PANEL>(a, p, lane, u, u < G && chunk_class(u, cr) != kChunkSkip, cbuf[u]);
 
     // D[i-1][j] and D[i-2][j-1]. The origin is produced by the general rule
     // through a virtual D[-2][-1] = -2 C[0][0]: fma(3, C00, -2 C00) = C00
     // exactly, and that value is used by no other cell.
     float d1 = kInf;
     float s1p = (p == 0 && lane == 0) ? -2.0f * cbuf[0][0] : kInf;
-    // left boundary D[i-1][64p-2], D[i-1][64p-1] for the first row of the chunk
+    // left boundary D[i0-1][64p-2], D[i0-1][64p-1] for the first row of a chunk
     float e0 = kInf, e1 = kInf;
-    int prog_seen = 0, cons_seen = 0;
-    const int64_t last = G - 1;
+    const int last = G - 1;
     const int rlast = int((a.n - 1) % kChunk);
     float dlast = kInf;
+    int cons_seen = 0;
 
-    for (int64_t k0 = 0; k0 < G; k0 += kPf) {
+    // Boundary columns of chunk k arrive in registers one chunk ahead: while a
+    // wave computes chunk k, the LDS reads of chunk k+1 are in flight, and the
+    // producer's progress counter is read asynchronously one chunk before it
+    // is tested. A consumer therefore trails its producer by two chunks and,
+    // in steady state, never waits on LDS latency.
+    float lvA0[kChunk], lvA1[kChunk], lvB0[kChunk], lvB1[kChunk];
+#pragma unroll
+    for (int r = 0; r < kChunk; ++r) { lvA0[r] = kInf; lvA1[r] = kInf; lvB0[r] = kInf; lvB1[r] = kInf; }
+    int prog_seen = 0, pv = 0;
+    if (have_left) {
+        while ((prog_seen = lds_get(&sh.prog[wave][0])) <= 0) __builtin_amdgcn_s_sleep(1);
+        compiler_order();
+        const f32x4* src = reinterpret_cast<const f32x4*>(rin);
+        const f32x4 x0 = src[0], x1 = src[1], y0 = src[2], y1 = src[3];
+        lvA0[0] = x0[0]; lvA0[1] = x0[1]; lvA0[2] = x0[2]; lvA0[3] = x0[3];
+        lvA0[4] = x1[0]; lvA0[5] = x1[1]; lvA0[6] = x1[2]; lvA0[7] = x1[3];
+        lvA1[0] = y0[0]; lvA1[1] = y0[1]; lvA1[2] = y0[2]; lvA1[3] = y0[3];
+        lvA1[4] = y1[0]; lvA1[5] = y1[1]; lvA1[6] = y1[2]; lvA1[7] = y1[3];
+        compiler_order();
+        if (lane == 0) lds_put(&sh.cons[wave], 1);
+        pv = lds_get(&sh.prog[wave][lane & 1]);
+    }
+
+    // The unrolled body has no early exit: chunks past the end of the panel
+    // (at most kPf - 1) run as known chunks whose code store goes to a sink.
+    // Every path then issues the same memory operations, which keeps the
+    // compiler's outstanding-load counts exact across the loop back edge.
+    for (int k0 = 0; k0 < G; k0 += kPf) {
 #pragma unroll
         for (int u = 0; u < kPf; ++u) {
-            const int64_t k = k0 + u;
-            if (k >= G) break;
-            const int slot = int(k % kRing);
+            const int k = k0 + u;
+            const bool inside = k < G;
+            asm volatile("" : "+s"(flags));
+            const int slot = k % kRing;
+            float(&cur0)[kChunk] = (u & 1) ? lvB0 : lvA0;
+            float(&cur1)[kChunk] = (u & 1) ? lvB1 : lvA1;
+            float(&nxt0)[kChunk] = (u & 1) ? lvA0 : lvB0;
+            float(&nxt1)[kChunk] = (u & 1) ? lvA1 : lvB1;
 
-            float lv0[kChunk], lv1[kChunk];
-            if constexpr (HAVE_LEFT) {
-                if (prog_seen <= k) {
-                    int v;
-                    while ((v = lds_get(&sh.prog[wave])) <= k) __builtin_amdgcn_s_sleep(1);
-                    prog_seen = v;
+            if ((flags & 1) && k + 1 < G) {
+                while (prog_seen <= k + 1) {
+                    __builtin_amdgcn_s_sleep(1);
+                    prog_seen = lds_get(&sh.prog[wave][0]);
                 }
                 compiler_order();
-                const f32x4* src = reinterpret_cast<const f32x4*>(rin + slot * 2 * kChunk);
-                const f32x4 a0 = src[0], a1 = src[1], b0 = src[2], b1 = src[3];
-                lv0[0] = a0[0]; lv0[1] = a0[1]; lv0[2] = a0[2]; lv0[3] = a0[3];
-                lv0[4] = a1[0]; lv0[5] = a1[1]; lv0[6] = a1[2]; lv0[7] = a1[3];
-                lv1[0] = b0[0]; lv1[1] = b0[1]; lv1[2] = b0[2]; lv1[3] = b0[3];
-                lv1[4] = b1[0]; lv1[5] = b1[1]; lv1[6] = b1[2]; lv1[7] = b1[3];
+                const f32x4* src = reinterpret_cast<const f32x4*>(rin + ((k + 1) % kRing) * 2 * kChunk);
+                const f32x4 x0 = src[0], x1 = src[1], y0 = src[2], y1 = src[3];
+                nxt0[0] = x0[0]; nxt0[1] = x0[1]; nxt0[2] = x0[2]; nxt0[3] = x0[3];
+                nxt0[4] = x1[0]; nxt0[5] = x1[1]; nxt0[6] = x1[2]; nxt0[7] = x1[3];
+                nxt1[0] = y0[0]; nxt1[1] = y0[1]; nxt1[2] = y0[2]; nxt1[3] = y0[3];
+                nxt1[4] = y1[0]; nxt1[5] = y1[1]; nxt1[6] = y1[2]; nxt1[7] = y1[3];
                 compiler_order();
-                if (lane == 0) lds_put(&sh.cons[wave], int(k + 1));
-            } else {
-#pragma unroll
-                for (int r = 0; r < kChunk; ++r) { lv0[r] = kInf; lv1[r] = kInf; }
+                if (lane == 0) lds_put(&sh.cons[wave], k + 2);
+                // read per lane from one of two identical copies, so the value
+                // stays in a vector register and is not waited for until the
+                // end of the chunk
+                pv = lds_get(&sh.prog[wave][lane & 1]);
             }
 
-            uint32_t lo = 0, hi = 0;
+            const int cls = inside ? chunk_class(k, cr) : kChunkSkip;
+            uint32_t lo, hi;
             float best_r[kChunk];
+            if (cls == kChunkFast) {
+                dp_rows<false>(cbuf[u], cur0, cur1, e0, e1, d1, s1p, lo, hi, best_r);
+            } else if (cls == kChunkFull) {
+                dp_rows<true>(cbuf[u], cur0, cur1, e0, e1, d1, s1p, lo, hi, best_r);
+                if (p == 0 && k == 0) lo = (lane == 0) ? ((lo & ~0xffu) | 3u) : lo;  // the origin's code
+            } else {
+                lo = hi = 0x03030303u;
+                d1 = kInf;
+                s1p = kInf;
 #pragma unroll
-            for (int r = 0; r < kChunk; ++r) {
-                const float c = cbuf[u][r];
-                const float s1 = shift_in(d1, r == 0 ? e1 : lv1[r - 1]);  // D[i-1][j-1]
-                const float s2 = shift_in(s1, r == 0 ? e0 : lv0[r - 1]);  // D[i-1][j-2]
-                const float c0 = __builtin_fmaf(2.0f, c, s1);
-                const float c1 = __builtin_fmaf(3.0f, c, s2);
-                const float c2 = __builtin_fmaf(3.0f, c, s1p);
-                const float best = __builtin_fminf(__builtin_fminf(c0, c1), c2);
-                uint32_t code = (c1 == best) ? 1u : 2u;
-                code = (c0 == best) ? 0u : code;
-                code = (best == kInf) ? 3u : code;
-                if (r < 4) lo |= code << (8 * r); else hi |= code << (8 * (r - 4));
-                d1 = best;
-                s1p = s1;
-                best_r[r] = best;
+                for (int r = 0; r < kChunk; ++r) best_r[r] = kInf;
             }
-            e0 = lv0[kChunk - 1];
-            e1 = lv1[kChunk - 1];
-            if (p == 0 && k == 0) lo = (lane == 0) ? ((lo & ~0xffu) | 3u) : lo;  // the origin's code
-            __builtin_nontemporal_store(uint64_t(lo) | (uint64_t(hi) << 32), bp_out + k * kLanes);
+            e0 = cur0[kChunk - 1];
+            e1 = cur1[kChunk - 1];
 
-            if constexpr (OUT == kOutLocal) {
+            __builtin_nontemporal_store(uint64_t(lo) | (uint64_t(hi) << 32),
+                                        inside ? bp_out + int64_t(k) * kLanes : a.hdr->sink + lane);
+
+            // LDS operations complete in issue order. Drain this chunk's reads
+            // (issued a whole chunk ago, so already done) before issuing the
+            // ring writes below, so that no later wait queues behind fresh writes.
+            __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+            if (flags & 1) {
+                const int pv0 = __builtin_amdgcn_readfirstlane(pv);
+                prog_seen = pv0 > prog_seen ? pv0 : prog_seen;
+            }
+
+            if ((flags & 2) && inside) {
                 if (cons_seen < k + 1 - kRing) {
                     int v;
                     while ((v = lds_get(&sh.cons[wave + 1])) < k + 1 - kRing) __builtin_amdgcn_s_sleep(1);
@@ -196,23 +315,15 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
                     dst[1] = f32x4{best_r[4], best_r[5], best_r[6], best_r[7]};
                 }
                 compiler_order();
-                if (lane == 0) lds_put(&sh.prog[wave + 1], int(k + 1));
-            } else if constexpr (OUT == kOutGlobal) {
-                if (bcol >= 0) {
-#pragma unroll
-                    for (int r = 0; r < kChunk; ++r) {
-                        const uint64_t v = (uint64_t(epoch) << 32) | uint64_t(__float_as_uint(best_r[r]));
-                        __hip_atomic_store(rec_out + (k * kChunk + r) * 2 + bcol, v, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                }
+                if (lane < 2) lds_put(&sh.prog[wave + 1][lane], k + 1);
             }
             if (k == last) {
 #pragma unroll
                 for (int r = 0; r < kChunk; ++r) dlast = (r == rlast) ? best_r[r] : dlast;
             }
 
-            if (k + kPf < G) load_chunk<PANEL>(a, p, lane, k + kPf, cbuf[u]);
+            const int kn = k + kPf;
+            load_chunk<PANEL>(a, p, lane, kn, kn < G && chunk_class(kn, cr) != kChunkSkip, cbuf[u]);
         }
     }
     if (int64_t(p) * kPanel + lane == a.m - 1) {
@@ -221,31 +332,39 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
     }
 }
 
-// Helper wave: copies the boundary columns of panel pl (the last panel of the
+// Input helper: copies the boundary columns of panel pl (the last panel of the
 // previous group, computed by another workgroup) from the global records into
-// LDS ring 0. Each poll covers up to kHelperWin chunks (16 records each) and
-// publishes every leading chunk whose epoch tags are all present.
-__device__ __attribute__((always_inline)) inline void helper_wave(const DpArgs& a, DpShared& sh, int pl, uint32_t epoch) {
+// LDS ring 0. One poll reads kHelperWin chunks (16 records each, four per
+// lane) and publishes every leading chunk whose epoch tags are all present, so
+// a single memory round trip can hand over 128 rows.
+__device__ __attribute__((always_inline)) inline void in_helper(const DpArgs& a, DpShared& sh, int pl,
+                                                                uint32_t epoch) {
+    constexpr int kPer = kHelperWin * 16 / kLanes;  // records per lane per poll
     const int lane = threadIdx.x & 63;
     const int64_t G = a.G;
     const uint64_t* rec = a.rec + (size_t(pl) * size_t(G) * kChunk) * 2;
     float* ring = &sh.ring[0][0][0][0];
-    const int q = lane >> 4;           // chunk within the poll window
-    const int row = (lane & 15) >> 1;  // row within that chunk
-    const int col = lane & 1;
     int cons_seen = 0;
     for (int64_t k = 0; k < G;) {
-        const int64_t kq = k + q;
-        const bool want = kq < G;
-        uint64_t v = 0;
-        bool ok = true;
-        if (want) {
-            v = __hip_atomic_load(rec + (kq * kChunk + row) * 2 + col, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ok = uint32_t(v >> 32) == epoch;
+        uint64_t v[kPer];
+        uint64_t good[kPer];
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+            const int e = lane + kLanes * t;  // record within the window
+            const int64_t kq = k + (e >> 4);
+            bool ok = true;
+            v[t] = 0;
+            if (kq < G) {
+                v[t] = __hip_atomic_load(rec + (kq * kChunk + ((e & 15) >> 1)) * 2 + (e & 1), __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+                ok = uint32_t(v[t] >> 32) == epoch;
+            }
+            good[t] = __builtin_amdgcn_ballot_w64(ok);
         }
-        const uint64_t good = __builtin_amdgcn_ballot_w64(ok);
         int ready = 0;
-        while (ready < kHelperWin && ((good >> (16 * ready)) & 0xffffull) == 0xffffull && k + ready < G) ++ready;
+        while (ready < kHelperWin && k + ready < G &&
+               ((good[ready >> 2] >> (16 * (ready & 3))) & 0xffffull) == 0xffffull)
+            ++ready;
         if (ready == 0) {
             __builtin_amdgcn_s_sleep(2);
             continue;
@@ -256,37 +375,62 @@ __device__ __attribute__((always_inline)) inline void helper_wave(const DpArgs& 
             cons_seen = c;
         }
         compiler_order();
-        if (q < ready) ring[((int(kq % kRing)) * 2 + col) * kChunk + row] = __uint_as_float(uint32_t(v));
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+            const int e = lane + kLanes * t;
+            if ((e >> 4) < ready) {
+                const int64_t kq = k + (e >> 4);
+                ring[(int(kq % kRing) * 2 + (e & 1)) * kChunk + ((e & 15) >> 1)] = __uint_as_float(uint32_t(v[t]));
+            }
+        }
         compiler_order();
-        if (lane == 0) lds_put(&sh.prog[0], int(k + ready));
+        if (lane < 2) lds_put(&sh.prog[0][lane], int(k + ready));
         k += ready;
     }
 }
 
-template <int NW, bool PANEL>
-__device__ __attribute__((always_inline)) inline void run_compute(const DpArgs& a, DpShared& sh, int wave, int p, uint32_t epoch) {
-    const bool left = p > 0;
-    const int out = (p + 1 >= a.P) ? kOutNone : (wave < NW - 1 ? kOutLocal : kOutGlobal);
-    if (left) {
-        if (out == kOutLocal) compute_wave<NW, PANEL, true, kOutLocal>(a, sh, wave, p, epoch);
-        else if (out == kOutGlobal) compute_wave<NW, PANEL, true, kOutGlobal>(a, sh, wave, p, epoch);
-        else compute_wave<NW, PANEL, true, kOutNone>(a, sh, wave, p, epoch);
-    } else {
-        if (out == kOutLocal) compute_wave<NW, PANEL, false, kOutLocal>(a, sh, wave, p, epoch);
-        else if (out == kOutGlobal) compute_wave<NW, PANEL, false, kOutGlobal>(a, sh, wave, p, epoch);
-        else compute_wave<NW, PANEL, false, kOutNone>(a, sh, wave, p, epoch);
+// Output helper: forwards the boundary columns that the last compute wave of
+// the group (panel pl) leaves in LDS ring NW to the global records, up to four
+// chunks (64 records, one per lane) per store. Keeping these agent-scope
+// stores off the compute waves keeps their memory counter free of slow writes.
+__device__ __attribute__((always_inline)) inline void out_helper(const DpArgs& a, DpShared& sh, int ring_idx,
+                                                                 int pl, uint32_t epoch) {
+    const int lane = threadIdx.x & 63;
+    const int64_t G = a.G;
+    uint64_t* rec = a.rec + (size_t(pl) * size_t(G) * kChunk) * 2;
+    const float* ring = &sh.ring[ring_idx][0][0][0];
+    const int q = lane >> 4, row = (lane & 15) >> 1, col = lane & 1;
+    int prog_seen = 0;
+    for (int64_t k = 0; k < G;) {
+        if (prog_seen <= k) {
+            int v;
+            while ((v = lds_get(&sh.prog[ring_idx][0])) <= k) __builtin_amdgcn_s_sleep(1);
+            prog_seen = v;
+        }
+        const int avail = int(prog_seen - k) < 4 ? int(prog_seen - k) : 4;
+        compiler_order();
+        float val = 0.0f;
+        if (q < avail) val = ring[(int((k + q) % kRing) * 2 + col) * kChunk + row];
+        compiler_order();
+        if (lane == 0) lds_put(&sh.cons[ring_idx], int(k + avail));
+        if (q < avail) {
+            const uint64_t v = (uint64_t(epoch) << 32) | uint64_t(__float_as_uint(val));
+            __hip_atomic_store(rec + ((k + q) * kChunk + row) * 2 + col, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        k += avail;
     }
 }
 
+// Workgroup: NW compute waves, then the input helper and the output helper.
 template <int NW, bool PANEL>
-__global__ __launch_bounds__(kLanes*(NW + 1)) void dp_kernel(DpArgs a) {
+__global__ __launch_bounds__(kLanes*(NW + 2)) void dp_kernel(DpArgs a) {
     __shared__ DpShared sh;
-    const int wave = threadIdx.x / kLanes;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);
     const uint32_t epoch = __hip_atomic_load(&a.hdr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (;;) {
         if (threadIdx.x == 0) {
             sh.super = int(atomicAdd(&a.hdr->ticket, 1u));
-            for (int w = 0; w <= NW; ++w) { sh.prog[w] = 0; sh.cons[w] = 0; }
+            for (int w = 0; w <= NW; ++w) { sh.prog[w][0] = 0; sh.prog[w][1] = 0; sh.cons[w] = 0; }
         }
         __syncthreads();
         const int q = sh.super;
@@ -294,9 +438,12 @@ __global__ __launch_bounds__(kLanes*(NW + 1)) void dp_kernel(DpArgs a) {
         const int p0 = q * NW;
         if (wave < NW) {
             const int p = p0 + wave;
-            if (p < a.P) run_compute<NW, PANEL>(a, sh, wave, p, epoch);
-        } else if (p0 > 0) {
-            helper_wave(a, sh, p0 - 1, epoch);
+            if (p < a.P) compute_wave<PANEL>(a, sh, wave, p, p > 0, p + 1 < a.P);
+        } else if (wave == NW) {
+            if (p0 > 0) in_helper(a, sh, p0 - 1, epoch);
+        } else {
+            // the group's last panel feeds the next group when one exists
+            if (p0 + NW < a.P) out_helper(a, sh, NW, p0 + NW - 1, epoch);
         }
         __syncthreads();
     }
@@ -308,17 +455,17 @@ __global__ void dp_prepare(DpWsHeader* hdr) {
 }
 
 int choose_nw(int P) {
-    // One compute wave per SIMD: prefer 4 panels per workgroup while that still
-    // gives most CUs a workgroup, fall back to fewer for narrow problems.
-    if (P >= 4 * 200) return 4;
-    if (P >= 2 * 200) return 2;
+    // Four panels per workgroup (one compute wave per SIMD) measured fastest
+    // from 188 panels (12000 columns) up; tiny problems keep fewer.
+    if (P >= 4) return 4;
+    if (P >= 2) return 2;
     return 1;
 }
 
 template <int NW>
 void launch_nw(const DpArgs& a, bool panel, int grid, hipStream_t stream) {
-    if (panel) dp_kernel<NW, true><<<grid, kLanes * (NW + 1), 0, stream>>>(a);
-    else dp_kernel<NW, false><<<grid, kLanes * (NW + 1), 0, stream>>>(a);
+    if (panel) dp_kernel<NW, true><<<grid, kLanes * (NW + 2), 0, stream>>>(a);
+    else dp_kernel<NW, false><<<grid, kLanes * (NW + 2), 0, stream>>>(a);
 }
 
 }  // namespace
@@ -345,13 +492,16 @@ pardtw_status dp_launch(const float* C, pardtw_layout layout, int64_t n, int64_t
     int dev = 0, cus = 0;
     PARDTW_HIP_TRY(hipGetDevice(&dev));
     PARDTW_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int grid = a.S < cus ? a.S : cus;
+    // about four compute waves per CU (one per SIMD)
+    const int per_cu = nw >= 4 ? 1 : 4 / nw;
+    const int grid = a.S < cus * per_cu ? a.S : cus * per_cu;
     const bool panel = layout == PARDTW_LAYOUT_PANEL;
     dp_prepare<<<1, 1, 0, stream>>>(a.hdr);
     switch (nw) {
         case 1: launch_nw<1>(a, panel, grid, stream); break;
         case 2: launch_nw<2>(a, panel, grid, stream); break;
         case 4: launch_nw<4>(a, panel, grid, stream); break;
+        case 8: launch_nw<8>(a, panel, grid, stream); break;
         default: return PARDTW_ERR_UNSUPPORTED;
     }
     return launch_status();
@@ -384,7 +534,7 @@ extern "C" pardtw_status pardtw_dp_ex(const float* C, pardtw_layout layout, int6
     if (!C || !bp || !total || !pair_status || !pardtw::valid_sizes(n, m)) return PARDTW_ERR_INVALID_ARG;
     if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL) return PARDTW_ERR_UNSUPPORTED;
     if (panels_per_workgroup != 0 && panels_per_workgroup != 1 && panels_per_workgroup != 2 &&
-        panels_per_workgroup != 4)
+        panels_per_workgroup != 4 && panels_per_workgroup != 8)
         return PARDTW_ERR_INVALID_ARG;
     if (!workspace || workspace_bytes < pardtw::dp_workspace_bytes_impl(n, m)) return PARDTW_ERR_WORKSPACE;
     return pardtw::dp_launch(C, layout, n, m, bp, total, pair_status, workspace, panels_per_workgroup, stream);

@@ -90,19 +90,20 @@ def check_total(gpu_total: float, oracle_total: float):
 
 def to_panel(C: np.ndarray) -> np.ndarray:
     """Row-major (n, m) cost to the panel layout (flat): 64-column panels,
-    8-row groups, a column's 8 rows of a group contiguous."""
+    8-row groups; a group holds rows 0-3 of its 64 columns, then rows 4-7,
+    with each column's 4 rows contiguous."""
     n, m = C.shape
     P, G = -(-m // 64), -(-n // 8)
     pad = np.zeros((G * 8, P * 64), dtype=C.dtype)
     pad[:n, :m] = C
-    # [G*8, P*64] -> [P, G, 64, 8]
-    return pad.reshape(G, 8, P, 64).transpose(2, 0, 3, 1).reshape(-1).copy()
+    # [G, 2, 4, P, 64] -> [P, G, 2, 64, 4]
+    return pad.reshape(G, 2, 4, P, 64).transpose(3, 0, 1, 4, 2).reshape(-1).copy()
 
 
 def from_panel(flat: np.ndarray, n: int, m: int) -> np.ndarray:
     P, G = -(-m // 64), -(-n // 8)
-    a = flat[: P * G * 512].reshape(P, G, 64, 8)
-    return a.transpose(1, 3, 0, 2).reshape(G * 8, P * 64)[:n, :m]
+    a = flat[: P * G * 512].reshape(P, G, 2, 64, 4)
+    return a.transpose(1, 2, 4, 0, 3).reshape(G * 8, P * 64)[:n, :m]
 
 
 def bf16_round(a: np.ndarray) -> np.ndarray:
