@@ -12,6 +12,7 @@ a host thread while the GPU is timed).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -123,18 +124,24 @@ def main():
     path = w.path[:L].cpu().numpy()
 
     dp_achieved = DP_BYTES_PER_CELL * cells / (dp_ms * 1e-3) / 1e9
+    # Measured HBM bytes of one DP launch (scaled FETCH_SIZE + WRITE_SIZE counters), valid only while the
+    # DP source is the one the counters were taken on.
     traffic = None
     if os.path.exists(args.traffic_json):
         try:
             tj = json.load(open(args.traffic_json))
-            if tj.get("workload") == args.workload:
+            src = open(os.path.join(ROOT, "paper_2607_15478_amd", "csrc", "dp.hip"), "rb").read()
+            if tj.get("workload") == args.workload and tj.get("dp_source_sha256") == hashlib.sha256(src).hexdigest():
                 traffic = tj.get("bytes_per_launch")
         except (OSError, ValueError):
             traffic = None
     roofline = {"bound": "hbm", "achieved": round(dp_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dp_achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "dp_kernel", "algorithmic_bytes_per_launch": DP_BYTES_PER_CELL * cells,
-                "kernel_ms": round(float(dp_ms), 4)}
+                "bytes_per_cell": DP_BYTES_PER_CELL, "kernel_ms": round(float(dp_ms), 4)}
+    if traffic:
+        # the kernel reads no cost for chunks the step set cannot reach, so it moves fewer bytes than 5 B/cell
+        roofline["moved_GBps"] = round(traffic / (dp_ms * 1e-3) / 1e9, 1)
 
     # ---- validation against the oracle ----
     validation = None
@@ -160,7 +167,11 @@ def main():
     cpu = None
     if not args.no_cpu:
         import oracle
-        rate_guess = 6e7  # cells/s of the single-thread FP64 oracle
+        # size the sample from a short timing probe of the same oracle call
+        pn, pm = min(n, 2000), min(m, 2400)
+        tp = time.perf_counter()
+        oracle.dtw_features(X[:pn], Y[:pm])
+        rate_guess = pn * pm / max(time.perf_counter() - tp, 1e-3)
         side = float(np.sqrt(args.cpu_seconds * rate_guess / cells))
         ns, ms_ = max(64, int(n * side)), max(64, int(m * side))
         ns, ms_ = min(ns, n), min(ms_, m)
