@@ -1,91 +1,318 @@
 // a4: backtrace of the optimal path (Sec. II-D keeps the full backtrace
 // matrix; the path is recovered from (N-1, M-1) once the sweep is done).
 //
-// The walk is inherently serial. One wavefront walks it; the codes it needs
-// are staged through LDS in windows of two adjacent 64-column panels x 64 rows
-// (8 KB, read as contiguous 512-byte row groups of the DP's backtrace layout),
-// since every step moves 1-2 rows and 1-2 columns up-left and so stays inside
-// the current window for at least 32 steps.
+// The walk is serial, so it is built for latency on one workgroup:
+//
+// * Loaders (waves 1..kLoaders). Every step moves 1-2 rows and 1-2 columns, so
+//   from a cell (i, j) the path's cells in a column panel p satisfy
+//   ceil(dj/2) <= di <= 2 dj, which bounds the rows it can touch there. When
+//   the walker enters panel q it asks for panel q - (kSlots - 1); a loader
+//   copies exactly those rows' 8-row groups (contiguous in the DP's backtrace
+//   layout) into a ring of LDS slots (slot = panel mod kSlots), compacting the
+//   codes to 2 bits on the way: a slot holds one 16-bit word per (group,
+//   column) with row r of the group in bits 2r..2r+1. Loader w serves every
+//   kLoaders-th request, so several requests are in flight at once.
+// * Walker (wave 0). From the current cell (i, j), lane b holds column j - b
+//   and the codes of rows i-31..i in two registers (row i - a in bits
+//   30-2a..31-2a of the first for a < 16, of the second as a - 16 otherwise),
+//   read with five 16-bit LDS loads. The steps that stay in those 32 rows are
+//   resolved with scalar reads of the registers (v_readlane) and scalar
+//   arithmetic; within 32 rows a path moves at most 62 columns, so the row
+//   limit is the only exit test. The cells it passes are written by the lanes
+//   in parallel: lane t finds its offset from the start cell by counting the
+//   double steps among the first t steps (popcount).
+// * The path is written from the back of the output (the walk runs backward)
+//   and shifted to the front by the whole workgroup at the end.
 #include "common.h"
 
 namespace pardtw {
 namespace {
 
-constexpr int kWinGroups = 8;  // 8 groups of 8 rows = 64 rows per window
+constexpr int kSlots = 8;                    // LDS ring of column panels
+constexpr int kSlotGroups = 128;             // 8-row groups per slot
+constexpr int kSlotBytes = kSlotGroups * kPanel * 2;  // 16 KB of 2-bit codes
+constexpr int kGroupBytes = kLanes * kBpRows;          // 512 bytes per group in the DP's layout
+constexpr int kLoaders = 7;
+constexpr int kThreads = kLanes * (1 + kLoaders);
+constexpr int kUnitBytes = kLanes * 16;      // one 16-byte load per lane: 1 KB = two groups
+constexpr int kBatch = 16;                   // units in flight per loader wave
 
-__global__ __launch_bounds__(64) void backtrace_kernel(const uint2* __restrict__ bp, int64_t n, int64_t m,
-                                                       const int32_t* __restrict__ status, int32_t* path,
-                                                       int32_t* path_len) {
-    __shared__ uint2 win[2][kWinGroups][kLanes];
-    __shared__ int64_t st[3];  // i, j, steps written
+struct BtShared {
+    uint8_t slot[kSlots][kSlotBytes];
+    int req_panel[kSlots];   // request ring (request r in entry r % kSlots)
+    int req_glo[kSlots];
+    int req_ng[kSlots];
+    int slot_glo[kSlots];    // first group held by each slot
+    int req_count;           // requests issued by the walker
+    int loaded[kSlots];      // requests completed per slot
+    int done;                // walker finished
+    int len;                 // cells on the path (0 on failure)
+};
+
+__device__ inline int lds_load_acquire(int* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ inline void lds_store_release(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Rows of panel p that a path from (i, j) can touch, as 8-row groups.
+__device__ inline void panel_groups(int i, int j, int p, int& glo, int& ng) {
+    const int djmax = j - p * kPanel;
+    const int djmin = max(0, j - (p * kPanel + kPanel - 1));
+    // clamped at row 0: from a cell the step set cannot reach (only on corrupt
+    // codes) the range may be empty, and one group is still requested
+    const int rlo = max(0, i - 2 * djmax);
+    const int rhi = max(0, i - (djmin + 1) / 2);
+    glo = rlo / kBpRows;
+    // at most 101 groups for a panel kSlots - 1 = 7 panels ahead
+    ng = min(rhi / kBpRows - glo + 1, kSlotGroups);
+}
+
+// Eight 2-bit codes (one byte each, values 0..3) to 16 bits.
+__device__ inline uint32_t compact8(uint32_t lo, uint32_t hi) {
+    uint32_t x = lo & 0x03030303u, y = hi & 0x03030303u;
+    x = (x | (x >> 6)) & 0x000F000Fu;
+    y = (y | (y >> 6)) & 0x000F000Fu;
+    x = (x | (x >> 12)) & 0xFFu;
+    y = (y | (y >> 12)) & 0xFFu;
+    return x | (y << 8);
+}
+
+// Steps through one 16-row half of the window: packed holds row a0 + a' of
+// the window in bits 30-2a'; off = 30 - 2a' on entry. Returns when the path
+// leaves the half (off < 0). codes receives each step's code at bits 2k.
+__device__ inline void resolve_fast(uint32_t packed, int& off, int& b, uint32_t& codes, int& k) {
+    do {
+        const uint32_t w = __builtin_amdgcn_readlane(packed, b);
+        const uint32_t c = (w >> off) & 3u;
+        codes |= c << (2 * k);
+        ++k;
+        off -= 2 + int(c & 2u);
+        b += 1 + int(c & 1u);
+    } while (off >= 0);
+}
+
+// Walker: returns the path length (0 if the codes do not lead to the origin).
+__device__ int walk(BtShared& sh, int n, int m, int P, int32_t* path) {
     const int lane = threadIdx.x;
-    const int64_t cap = n < m ? n : m;
-    if (*status != PARDTW_PAIR_OK) {
-        if (lane == 0) *path_len = 0;
+    const int cap = n < m ? n : m;
+    int i = n - 1, j = m - 1, len = 0;
+    int nreq = 0;
+    auto request = [&](int p) {
+        int glo, ng;
+        panel_groups(i, j, p, glo, ng);
+        const int e = nreq % kSlots;
+        if (lane == 0) {
+            sh.req_panel[e] = p;
+            sh.req_glo[e] = glo;
+            sh.req_ng[e] = ng;
+            sh.slot_glo[p % kSlots] = glo;
+        }
+        ++nreq;
+        if (lane == 0) lds_store_release(&sh.req_count, nreq);
+    };
+    auto wait_panel = [&](int p) {
+        const int target = ((P - 1 - p) / kSlots) + 1;
+        while (lds_load_acquire(&sh.loaded[p % kSlots]) < target) __builtin_amdgcn_s_sleep(1);
+        return sh.slot_glo[p % kSlots];
+    };
+    // On entering panel q the ring holds q .. q-(kSlots-2) and receives
+    // q-(kSlots-1); the start enters panel P-1.
+    for (int k = 0; k < kSlots && P - 1 - k >= 0; ++k) request(P - 1 - k);
+    int cur_q = P - 1;
+    int glo0 = wait_panel(cur_q), glo1 = 0;
+    bool have1 = false;  // panel cur_q - 1 checked ready
+
+    const uint8_t* lds = &sh.slot[0][0];
+    for (;;) {
+        const int q0 = j / kPanel;
+        if (q0 != cur_q) {  // entered panel q0 (panels are entered in decreasing order)
+            cur_q = q0;
+            if (q0 - (kSlots - 1) >= 0) request(q0 - (kSlots - 1));
+            glo0 = have1 ? glo1 : wait_panel(q0);
+            have1 = false;
+        }
+        if (!have1 && q0 > 0 && j - (kLanes - 1) < q0 * kPanel) {
+            glo1 = wait_panel(q0 - 1);
+            have1 = true;
+        }
+
+        // lane b: column j - b, rows i-31..i from the five groups from gr on
+        uint32_t packed0, packed1;
+        {
+            const int col = j - lane;
+            const int p = col >> 6;  // q0 or q0 - 1 (negative columns give junk)
+            const int glo = p == q0 ? glo0 : glo1;
+            const uint8_t* base = lds + (p & (kSlots - 1)) * kSlotBytes + (col & (kPanel - 1)) * 2;
+            const int gr = (i - 31) >> 3;  // floor, may be negative near row 0
+            uint32_t w[5];
+#pragma unroll
+            for (int t = 0; t < 5; ++t) {
+                const int lg = min(max(gr + t - glo, 0), kSlotGroups - 1);  // junk outside the slot
+                w[t] = *reinterpret_cast<const uint16_t*>(base + lg * (kPanel * 2));
+            }
+            // row r is at bits 2(r - 8 gr) of w0 | w1 << 16 | ... ; s = i - 8 gr is in [31, 38]
+            const int s2 = 2 * (i - 8 * gr);
+            const uint64_t lo = uint64_t(w[0]) | (uint64_t(w[1]) << 16) | (uint64_t(w[2]) << 32) | (uint64_t(w[3]) << 48);
+            const uint64_t hi = uint64_t(w[1]) | (uint64_t(w[2]) << 16) | (uint64_t(w[3]) << 32) | (uint64_t(w[4]) << 48);
+            packed0 = uint32_t(hi >> (s2 - 46));  // rows i .. i-15
+            packed1 = uint32_t(lo >> (s2 - 62));  // rows i-16 .. i-31
+        }
+
+        // Resolve the steps inside the window (uniform scalar loops). Bit 1 of
+        // a code says the step takes two rows, bit 0 two columns, so the unused
+        // code 3 reads as an illegal (2, 2) step and is caught after the loops.
+        int off = 30, b = 0, k0 = 0, k1 = 0;
+        uint32_t codes0 = 0, codes1 = 0;  // codes of the steps taken in each half
+        bool origin = false;
+        int a;
+        if (i >= 33 && j >= 66) {
+            // no cell of the window can be the origin or lie outside the matrix
+            resolve_fast(packed0, off, b, codes0, k0);
+            off += 32;
+            resolve_fast(packed1, off, b, codes1, k1);
+            a = (62 - off) >> 1;
+        } else {
+            // near the first row or column: one 16-row half, every step checked
+            const int ij = i + j;
+            for (;;) {
+                a = (30 - off) >> 1;
+                if (a + b == ij) { origin = true; break; }  // a <= i and b <= j here
+                const uint32_t w = __builtin_amdgcn_readlane(packed0, b);
+                const uint32_t c = (w >> off) & 3u;
+                codes0 |= c << (2 * k0);
+                ++k0;
+                off -= 2 + int(c & 2u);
+                b += 1 + int(c & 1u);
+                if ((30 - off) >> 1 > i || b > j) return 0;  // left the matrix
+                if (off < 0) { a = (30 - off) >> 1; break; }
+            }
+        }
+        if (((codes0 & (codes0 >> 1)) | (codes1 & (codes1 >> 1))) & 0x55555555u) return 0;  // code 3
+        const int cnt = k0 + k1 + (origin ? 1 : 0);
+        if (len + cnt > cap) return 0;
+        if (lane < cnt) {
+            // offsets after the first `lane` steps
+            const int t0 = min(lane, k0), t1 = lane - t0;
+            const uint64_t m0 = (uint64_t(1) << (2 * t0)) - 1, m1 = (uint64_t(1) << (2 * t1)) - 1;
+            const uint64_t c0 = codes0, c1 = codes1;
+            const int da = lane + __builtin_popcountll(c0 & m0 & 0xAAAAAAAAull) +
+                           __builtin_popcountll(c1 & m1 & 0xAAAAAAAAull);
+            const int db = lane + __builtin_popcountll(c0 & m0 & 0x55555555ull) +
+                           __builtin_popcountll(c1 & m1 & 0x55555555ull);
+            const int64_t pos = int64_t(cap) - 1 - (len + lane);
+            path[2 * pos] = i - da;
+            path[2 * pos + 1] = j - db;
+        }
+        len += cnt;
+        if (origin) return len;
+        i -= a;
+        j -= b;
+    }
+}
+
+// Loader wave w: serves requests w, w + kLoaders, ... (each alone), compacting
+// the codes of each (group, column) to 16 bits.
+__device__ void load_panels(BtShared& sh, const uint8_t* bp, int64_t G, int w) {
+    const int lane = threadIdx.x & (kLanes - 1);
+    for (int r = w;; r += kLoaders) {
+        while (lds_load_acquire(&sh.req_count) <= r) {
+            if (lds_load_acquire(&sh.done)) return;
+            __builtin_amdgcn_s_sleep(2);
+        }
+        const int e = r % kSlots;
+        const int p = sh.req_panel[e];
+        const int glo = sh.req_glo[e];
+        const int bytes = sh.req_ng[e] * kGroupBytes;
+        const int units = (bytes + kUnitBytes - 1) / kUnitBytes;
+        const uint8_t* src = bp + (int64_t(p) * G + glo) * kGroupBytes;
+        uint8_t* dst = sh.slot[p % kSlots];
+        for (int u0 = 0; u0 < units; u0 += kBatch) {
+            uint4 buf[kBatch];
+#pragma unroll
+            for (int t = 0; t < kBatch; ++t) {
+                const int off = (u0 + t) * kUnitBytes + lane * 16;
+                const int offc = off < bytes ? off : bytes - 16;  // stays inside the requested groups
+                buf[t] = *reinterpret_cast<const uint4*>(src + offc);
+            }
+#pragma unroll
+            for (int t = 0; t < kBatch; ++t) {
+                const int off = (u0 + t) * kUnitBytes + lane * 16;
+                if (off < bytes) {
+                    // 16 bytes = columns c, c+1 of group lg, 8 codes each
+                    const int lg = off / kGroupBytes;
+                    const int c = (off % kGroupBytes) / kBpRows;
+                    const uint32_t pair = compact8(buf[t].x, buf[t].y) | (compact8(buf[t].z, buf[t].w) << 16);
+                    *reinterpret_cast<uint32_t*>(dst + lg * (kPanel * 2) + c * 2) = pair;
+                }
+            }
+        }
+        if (lane == 0) __hip_atomic_fetch_add(&sh.loaded[p % kSlots], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
+// Moves path entries [base, base + len) to [0, len) in place: each batch is
+// read completely before it is written, and later batches read only entries
+// at or above the ones this batch writes.
+__device__ void shift_path(int32_t* path, int64_t base, int64_t len) {
+    constexpr int kPer = 8;
+    int2* pp = reinterpret_cast<int2*>(path);
+    for (int64_t q0 = 0; q0 < len; q0 += int64_t(kThreads) * kPer) {
+        int2 v[kPer];
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+            const int64_t q = q0 + t * kThreads + threadIdx.x;
+            if (q < len) v[t] = pp[base + q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+            const int64_t q = q0 + t * kThreads + threadIdx.x;
+            if (q < len) pp[q] = v[t];
+        }
+        __syncthreads();
+    }
+}
+
+__device__ void backtrace_pair(BtShared& sh, const uint8_t* bp, int n, int m, int pair_status, int32_t* path,
+                               int32_t* path_len) {
+    const int tid = threadIdx.x;
+    if (pair_status != PARDTW_PAIR_OK) {
+        if (tid == 0) *path_len = 0;
         return;
     }
-    const int64_t G = bp_groups(n);
-    int64_t i = n - 1, j = m - 1, len = 0;
-    bool done = false;
-    while (!done) {
-        const int64_t pa = j / kPanel;
-        const int64_t ghi = i / kBpRows;
-        const int64_t g0 = ghi >= kWinGroups - 1 ? ghi - (kWinGroups - 1) : 0;
-        for (int pp = 0; pp < 2; ++pp) {
-            const int64_t pan = pa - pp;
-            if (pan < 0) break;
-            for (int gg = 0; gg < kWinGroups; ++gg) {
-                const int64_t g = g0 + gg;
-                if (g >= G) break;
-                win[pp][gg][lane] = bp[(pan * G + g) * kLanes + lane];
-            }
-        }
-        __syncthreads();
-        if (lane == 0) {
-            const int64_t rlo = g0 * kBpRows;
-            const int64_t clo = (pa > 0 ? pa - 1 : 0) * kPanel;
-            for (;;) {
-                // record (i, j) at the back of the buffer; reversed at the end
-                const int64_t pos = cap - 1 - len;
-                path[2 * pos] = int32_t(i);
-                path[2 * pos + 1] = int32_t(j);
-                ++len;
-                if (i == 0 && j == 0) { done = true; break; }
-                const int pp = int(pa - j / kPanel);
-                const uint2 w = win[pp][(i / kBpRows) - g0][j % kPanel];
-                const int t = int(i % kBpRows);
-                const uint32_t word = t < 4 ? w.x : w.y;
-                const uint32_t code = (word >> (8 * (t & 3))) & 0xffu;
-                if (code > 2 || len >= cap) { len = 0; done = true; break; }  // corrupt input: no path
-                i -= (code == 2) ? 2 : 1;
-                j -= (code == 1) ? 2 : 1;
-                if (i < rlo || j < clo) break;
-            }
-            st[0] = i; st[1] = j; st[2] = len + (done ? (int64_t(1) << 40) : 0);
-        }
-        __syncthreads();
-        i = st[0];
-        j = st[1];
-        len = st[2] & ((int64_t(1) << 40) - 1);
-        done = (st[2] >> 40) != 0;
-        __syncthreads();
+    if (tid < kSlots) sh.loaded[tid] = 0;
+    if (tid == 0) {
+        sh.req_count = 0;
+        sh.done = 0;
+        sh.len = 0;
     }
-    // The walk filled [cap-len, cap) from the back, so the buffer already holds
-    // the path in forward order there: shift it down to start at entry 0.
-    const int64_t base = cap - len;
-    __threadfence();
     __syncthreads();
-    if (base > 0) {
-        for (int64_t q0 = 0; q0 < len; q0 += kLanes) {
-            const int64_t q = q0 + lane;
-            int32_t v0 = 0, v1 = 0;
-            if (q < len) { v0 = path[2 * (base + q)]; v1 = path[2 * (base + q) + 1]; }
-            __syncthreads();
-            if (q < len) { path[2 * q] = v0; path[2 * q + 1] = v1; }
-            __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int P = int(num_panels(m));
+    if (wave == 0) {
+        const int len = walk(sh, n, m, P, path);
+        if (tid == 0) {
+            sh.len = len;
+            lds_store_release(&sh.done, 1);
         }
+    } else {
+        load_panels(sh, bp, bp_groups(n), wave - 1);
     }
-    if (lane == 0) *path_len = int32_t(len);
+    __syncthreads();
+    const int len = sh.len;
+    const int cap = n < m ? n : m;
+    __threadfence_block();
+    shift_path(path, int64_t(cap) - len, len);
+    if (tid == 0) *path_len = len;
+}
+
+__global__ __launch_bounds__(kThreads) void backtrace_kernel(const uint8_t* __restrict__ bp, int64_t n, int64_t m,
+                                                             const int32_t* __restrict__ status, int32_t* path,
+                                                             int32_t* path_len) {
+    __shared__ BtShared sh;
+    backtrace_pair(sh, bp, int(n), int(m), *status, path, path_len);
 }
 
 __global__ void bp_unpack_kernel(const uint8_t* __restrict__ bp, int64_t n, int64_t m, int8_t* __restrict__ out) {
@@ -101,8 +328,8 @@ __global__ void bp_unpack_kernel(const uint8_t* __restrict__ bp, int64_t n, int6
 extern "C" pardtw_status pardtw_backtrace(const uint8_t* bp, int64_t n, int64_t m, const int32_t* pair_status,
                                           int32_t* path, int32_t* path_len, hipStream_t stream) {
     if (!bp || !pair_status || !path || !path_len || !pardtw::valid_sizes(n, m)) return PARDTW_ERR_INVALID_ARG;
-    pardtw::backtrace_kernel<<<1, 64, 0, stream>>>(reinterpret_cast<const uint2*>(bp), n, m, pair_status, path,
-                                                   path_len);
+    if (reinterpret_cast<uintptr_t>(path) % 8 != 0) return PARDTW_ERR_INVALID_ARG;
+    pardtw::backtrace_kernel<<<1, pardtw::kThreads, 0, stream>>>(bp, n, m, pair_status, path, path_len);
     return pardtw::launch_status();
 }
 

@@ -111,3 +111,51 @@ def bf16_round(a: np.ndarray) -> np.ndarray:
     u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
     r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
     return r.astype(np.uint32).view(np.float32)
+
+
+def to_bp_layout(B: np.ndarray) -> np.ndarray:
+    """Row-major (n, m) int8 codes to the DP's backtrace layout (flat uint8):
+    64-column panels, 8-row groups, a column's 8 codes contiguous."""
+    n, m = B.shape
+    P, G = -(-m // 64), -(-n // 8)
+    pad = np.full((G * 8, P * 64), 3, dtype=np.uint8)
+    pad[:n, :m] = B
+    # [G, 8, P, 64] -> [P, G, 64, 8]
+    return pad.reshape(G, 8, P, 64).transpose(2, 0, 3, 1).reshape(-1).copy()
+
+
+def random_path(n: int, m: int, rng: np.random.Generator, mean_run: float = 50.0) -> np.ndarray:
+    """A random legal path from (0,0) to (n-1,m-1) made of runs of one
+    preferred step (so it also holds long stretches at slope 1/2 and 2)."""
+    steps = ((1, 1), (1, 2), (2, 1))
+
+    def ok(ri, rj):
+        return (ri == 0 and rj == 0) or (ri >= 1 and rj >= 1 and rj <= 2 * ri and ri <= 2 * rj)
+
+    i = j = 0
+    out = [(0, 0)]
+    pref, run = 0, 0
+    while (i, j) != (n - 1, m - 1):
+        if run <= 0:
+            pref, run = int(rng.integers(0, 3)), int(rng.geometric(1.0 / mean_run))
+        run -= 1
+        order = [pref] + [int(s) for s in rng.permutation(3) if s != pref]
+        for s in order:
+            di, dj = steps[s]
+            if ok(n - 1 - i - di, m - 1 - j - dj):
+                i, j = i + di, j + dj
+                break
+        else:  # pragma: no cover - a feasible remainder always admits a step
+            raise AssertionError("no legal step")
+        out.append((i, j))
+    return np.array(out, dtype=np.int32)
+
+
+def bp_with_path(n: int, m: int, path: np.ndarray, rng: np.random.Generator) -> np.ndarray:
+    """Random codes everywhere, the path's own step codes on its cells, 3 at
+    the origin."""
+    B = rng.integers(0, 4, size=(n, m), dtype=np.uint8)
+    codes = step_codes(path)
+    B[path[1:, 0], path[1:, 1]] = codes.astype(np.uint8)
+    B[0, 0] = 3
+    return B
