@@ -148,13 +148,29 @@ pardtw_status pardtw_path_grad(const float* X, const float* Y, int64_t n, int64_
                                float* dX, float* dY, hipStream_t stream);
 
 /* ---- a5: batched form -----------------------------------------------------
- * A plan fixes the pair lengths of a batch and chooses, by measuring, the
- * schedule of the persistent DP (panels per workgroup, work order). Features of
- * pair b live at X_packed + x_off[b]*d and Y_packed + y_off[b]*d with x_off,
- * y_off the exclusive prefix sums of n_b, m_b. Path of pair b: 2*min(n_b,m_b)
- * int32 starting at paths_packed + 2*path_off[b], path_off the prefix sum of
- * min(n_b, m_b). pardtw_align_batch makes no allocation and no host sync, so it
- * can be captured in a hipGraph. */
+ * Many independent pairs of uneven lengths aligned together (the problem of
+ * Sec. III for each pair). A plan fixes the pair lengths: pair b has n_b rows
+ * of X and m_b rows of Y, all with d features. Host data is read only during
+ * pardtw_plan_create; the plan owns small device tables (pair descriptors,
+ * work lists) and is the only object the library allocates.
+ *
+ * Packed buffers (device, caller-owned):
+ *   X_packed: sum n_b rows of d FP32; pair b starts at row x_off[b], the
+ *             exclusive prefix sum of n_b. Y_packed likewise with m_b.
+ *   paths_packed: 2 * pardtw_plan_path_capacity int32, 8-byte aligned; pair b
+ *             writes its (i, j) pairs in forward order from entry 2*p_off[b],
+ *             p_off the exclusive prefix sum of min(n_b, m_b).
+ *   totals (FP32), path_len and pair_status (int32): one entry per pair.
+ *   workspace: pardtw_plan_workspace_bytes bytes, 256-byte aligned, zeroed
+ *             once before first use (it holds the cost panels, the codes and
+ *             the DP's boundary records of every pair).
+ * An infeasible pair gets status PARDTW_PAIR_INFEASIBLE, total +inf and
+ * path_len 0, and no work.
+ *
+ * pardtw_align_batch runs cost -> DP -> backtrace for the whole batch: the DP
+ * of all pairs is one persistent launch over (pair, panel group) items. It
+ * makes no allocation, copy or host synchronisation, so it can be captured in
+ * a hipGraph. Calls sharing a workspace must not overlap in time. */
 typedef struct pardtw_plan pardtw_plan;
 
 pardtw_status pardtw_plan_create(int32_t batch, const int64_t* n_host, const int64_t* m_host,
@@ -168,7 +184,31 @@ pardtw_status pardtw_align_batch(const pardtw_plan* plan, const float* X_packed,
                                  int32_t* paths_packed, int32_t* path_len, int32_t* pair_status,
                                  hipStream_t stream);
 
-/* Batched twin of pardtw_path_grad over the plan's pairs (g_totals: batch floats). */
+/* Schedules of the batched DP: panels per workgroup (1, 2, 4, 8), item order
+ * (0 = breadth: group 0 of every pair by decreasing size, then group 1, ...;
+ * 1 = depth: all groups of the largest pair first) and resident workgroups.
+ * Every schedule computes bit-identical results; only the speed differs.
+ * pardtw_plan_schedule describes schedule `index` (-1 = the selected one). */
+int32_t pardtw_plan_num_schedules(const pardtw_plan* plan);
+pardtw_status pardtw_plan_schedule(const pardtw_plan* plan, int32_t index, int32_t* panels_per_workgroup,
+                                   int32_t* order, int32_t* workgroups);
+int32_t pardtw_plan_selected(const pardtw_plan* plan);
+pardtw_status pardtw_plan_select(pardtw_plan* plan, int32_t index);
+
+/* Autotuner: computes the batch's costs once, times the DP of every schedule
+ * on them (one warm-up, then `reps` launches, HIP events on `stream`) and
+ * selects the fastest; *best_ms (may be NULL) receives its time per launch.
+ * Synchronises the stream, so it is not capturable; totals, codes and
+ * statuses are left as written by the last schedule tried. */
+pardtw_status pardtw_plan_autotune(pardtw_plan* plan, const float* X_packed, const float* Y_packed,
+                                   void* workspace, size_t workspace_bytes, float* totals,
+                                   int32_t* paths_packed, int32_t* path_len, int32_t* pair_status,
+                                   int32_t reps, float* best_ms, hipStream_t stream);
+
+/* Batched twin of pardtw_path_grad over the plan's pairs, reading the paths
+ * written by pardtw_align_batch. g_totals: one FP32 per pair. dX_packed /
+ * dY_packed: shaped like X_packed / Y_packed, overwritten (zeros for skipped
+ * rows and infeasible pairs). */
 pardtw_status pardtw_path_grad_batch(const pardtw_plan* plan, const float* X_packed,
                                      const float* Y_packed, const int32_t* paths_packed,
                                      const int32_t* path_len, const float* g_totals, float* dX_packed,

@@ -23,7 +23,7 @@
 //   double steps among the first t steps (popcount).
 // * The path is written from the back of the output (the walk runs backward)
 //   and shifted to the front by the whole workgroup at the end.
-#include "common.h"
+#include "batch.h"
 
 namespace pardtw {
 namespace {
@@ -315,6 +315,18 @@ __global__ __launch_bounds__(kThreads) void backtrace_kernel(const uint8_t* __re
     backtrace_pair(sh, bp, int(n), int(m), *status, path, path_len);
 }
 
+// Batched form: workgroup b walks pair b (infeasible pairs just get length 0).
+__global__ __launch_bounds__(kThreads) void backtrace_batch_kernel(const BatchPair* __restrict__ pairs,
+                                                                   const uint8_t* __restrict__ bpbase,
+                                                                   const int32_t* __restrict__ status,
+                                                                   int32_t* paths, int32_t* path_len) {
+    __shared__ BtShared sh;
+    const int b = blockIdx.x;
+    const BatchPair q = pairs[b];
+    const int st = q.feasible ? status[b] : int(PARDTW_PAIR_INFEASIBLE);
+    backtrace_pair(sh, bpbase + q.bp_off, int(q.n), int(q.m), st, paths + 2 * q.path_off, path_len + b);
+}
+
 __global__ void bp_unpack_kernel(const uint8_t* __restrict__ bp, int64_t n, int64_t m, int8_t* __restrict__ out) {
     const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (idx >= n * m) return;
@@ -323,6 +335,14 @@ __global__ void bp_unpack_kernel(const uint8_t* __restrict__ bp, int64_t n, int6
 }
 
 }  // namespace
+
+pardtw_status backtrace_batch_launch(const BatchPair* pairs, int32_t batch, const uint8_t* bpbase,
+                                     const int32_t* status, int32_t* paths, int32_t* path_len, hipStream_t stream) {
+    if (batch <= 0) return PARDTW_OK;
+    backtrace_batch_kernel<<<unsigned(batch), kThreads, 0, stream>>>(pairs, bpbase, status, paths, path_len);
+    return launch_status();
+}
+
 }  // namespace pardtw
 
 extern "C" pardtw_status pardtw_backtrace(const uint8_t* bp, int64_t n, int64_t m, const int32_t* pair_status,

@@ -1,0 +1,50 @@
+// Internal definitions of the batched form: the per-pair descriptor that the
+// plan keeps in device memory and the batch launchers of each kernel.
+#pragma once
+
+#include "common.h"
+
+namespace pardtw {
+
+// One pair of a batch. Offsets are element offsets from the caller's packed
+// features (rows), the plan's workspace regions (floats / bytes / records) and
+// the packed path buffer (int32 pairs).
+struct BatchPair {
+    int64_t n, m;
+    int64_t x_off, y_off;  // first row of the pair in X_packed / Y_packed
+    int64_t c_off;         // first float of the pair's cost panels
+    int64_t bp_off;        // first byte of the pair's codes
+    int64_t rec_off;       // first boundary record (uint64) of the pair
+    int64_t path_off;      // first (i, j) entry of the pair's path
+    int64_t G;             // 8-row groups
+    int64_t tile0;         // first cost tile of the pair in the batch numbering
+    int32_t P;             // column panels
+    int32_t feasible;      // the step set can reach (n-1, m-1)
+};
+
+// Work item of the persistent batched DP: panel group q of pair b.
+struct DpItem {
+    int32_t pair;
+    int32_t group;
+};
+
+pardtw_status cost_batch_launch(const BatchPair* pairs, const int32_t* tile_pair, int64_t tiles, const float* X,
+                                const float* Y, int64_t d, pardtw_prec prec, float* Cbase, hipStream_t stream);
+
+// Sweeps every item with one persistent launch; hdr/rec as in the single-pair
+// DP (one header for the batch, records at each pair's rec_off).
+pardtw_status dp_batch_launch(const BatchPair* pairs, const DpItem* items, int32_t nitems, int nw, int grid,
+                              const float* Cbase, uint8_t* bpbase, float* totals, int32_t* status, void* dp_ws,
+                              hipStream_t stream);
+
+pardtw_status backtrace_batch_launch(const BatchPair* pairs, int32_t batch, const uint8_t* bpbase,
+                                     const int32_t* status, int32_t* paths, int32_t* path_len, hipStream_t stream);
+
+pardtw_status grad_batch_launch(const BatchPair* pairs, int32_t batch, int64_t max_cap, int64_t d, const float* X,
+                                const float* Y, const int32_t* paths, const int32_t* path_len, const float* g,
+                                float* dX, int64_t dX_count, float* dY, int64_t dY_count, hipStream_t stream);
+
+size_t dp_header_bytes();
+size_t dp_record_bytes(int64_t n, int64_t m);  // boundary records of one pair
+
+}  // namespace pardtw

@@ -1,24 +1,330 @@
-// a5: batched form (placeholder until the persistent batched scheduler lands).
-#include "common.h"
+// a5: batched form. A plan fixes the pair lengths of a batch, lays out one
+// workspace for all of them, and holds in device memory what every kernel of
+// the batch needs (pair descriptors, the cost tiles' pair table and the DP's
+// work lists for each candidate schedule), so that pardtw_align_batch issues
+// only kernel launches: no allocation, copy or host synchronisation, and it
+// can be captured in a hipGraph.
+//
+// The DP of all pairs runs as one persistent launch drawing (pair, panel
+// group) items from one ticket. A schedule fixes the panels per workgroup
+// (1, 2, 4 or 8), the order of the items (breadth: group 0 of every pair, then
+// group 1, ...; depth: every group of the largest pair, then the next) and the
+// number of resident workgroups; pardtw_plan_autotune times each schedule on
+// the caller's data and keeps the fastest.
+#include <algorithm>
+#include <cmath>
+#include <new>
+#include <numeric>
+#include <vector>
 
-struct pardtw_plan {
-    int32_t batch;
+#include "batch.h"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Schedule {
+    int nw;          // panels per workgroup
+    int order;       // 0 breadth, 1 depth
+    int grid_mul;    // resident workgroups per CU, relative to the NW default
+    int32_t nitems;
+    int64_t items_at;  // first item in the plan's item array
 };
 
+__global__ void batch_init_kernel(const pardtw::BatchPair* __restrict__ pairs, int32_t batch, float* totals,
+                                  int32_t* status, int32_t* path_len) {
+    const int b = int(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= batch || pairs[b].feasible) return;
+    totals[b] = __builtin_inff();
+    status[b] = PARDTW_PAIR_INFEASIBLE;
+    path_len[b] = 0;
+}
+
+}  // namespace
+
+struct pardtw_plan {
+    int32_t batch = 0;
+    int64_t d = 0;
+    pardtw_prec prec = PARDTW_PREC_F32;
+    int device = 0;
+    int cus = 1;
+    std::vector<pardtw::BatchPair> pairs;
+    pardtw::BatchPair* pairs_dev = nullptr;
+    int32_t* tile_pair_dev = nullptr;
+    int64_t tiles = 0;
+    pardtw::DpItem* items_dev = nullptr;
+    std::vector<Schedule> scheds;
+    int chosen = 0;
+    size_t off_c = 0, off_bp = 0, off_dp = 0, ws_bytes = 0;
+    int64_t path_capacity = 0, max_cap = 0, x_rows = 0, y_rows = 0;
+
+    ~pardtw_plan() {
+        if (pairs_dev) (void)hipFree(pairs_dev);
+        if (tile_pair_dev) (void)hipFree(tile_pair_dev);
+        if (items_dev) (void)hipFree(items_dev);
+    }
+};
+
+namespace {
+
+int grid_for(const pardtw_plan& pl, const Schedule& s) {
+    const int per_cu = s.nw >= 4 ? 1 : 4 / s.nw;
+    return pl.cus * per_cu * s.grid_mul;
+}
+
+// Work list of one schedule: items of each pair in increasing group order.
+std::vector<pardtw::DpItem> make_items(const pardtw_plan& pl, int nw, int order) {
+    std::vector<int> rank;
+    for (int b = 0; b < pl.batch; ++b)
+        if (pl.pairs[b].feasible) rank.push_back(b);
+    std::stable_sort(rank.begin(), rank.end(), [&](int x, int y) {
+        return pl.pairs[x].n * pl.pairs[x].m > pl.pairs[y].n * pl.pairs[y].m;
+    });
+    std::vector<pardtw::DpItem> items;
+    if (order == 1) {
+        for (int b : rank) {
+            const int S = int(pardtw::ceil_div(pl.pairs[b].P, nw));
+            for (int q = 0; q < S; ++q) items.push_back({b, q});
+        }
+    } else {
+        int smax = 0;
+        for (int b : rank) smax = std::max(smax, int(pardtw::ceil_div(pl.pairs[b].P, nw)));
+        for (int q = 0; q < smax; ++q)
+            for (int b : rank)
+                if (q < pardtw::ceil_div(pl.pairs[b].P, nw)) items.push_back({b, q});
+    }
+    return items;
+}
+
+pardtw_status run_dp(const pardtw_plan& pl, const Schedule& s, char* ws, float* totals, int32_t* status,
+                     hipStream_t stream) {
+    return pardtw::dp_batch_launch(pl.pairs_dev, pl.items_dev + s.items_at, s.nitems, s.nw, grid_for(pl, s),
+                                   reinterpret_cast<const float*>(ws + pl.off_c),
+                                   reinterpret_cast<uint8_t*>(ws + pl.off_bp), totals, status, ws + pl.off_dp,
+                                   stream);
+}
+
+bool aligned(const void* p, size_t a) { return reinterpret_cast<uintptr_t>(p) % a == 0; }
+
+pardtw_status check_call(const pardtw_plan* plan, const float* X, const float* Y, void* ws, size_t ws_bytes,
+                         float* totals, int32_t* paths, int32_t* path_len, int32_t* status) {
+    if (!plan || !X || !Y || !ws || !totals || !paths || !path_len || !status) return PARDTW_ERR_INVALID_ARG;
+    if (!aligned(ws, kAlign) || !aligned(paths, 8)) return PARDTW_ERR_INVALID_ARG;
+    if (ws_bytes < plan->ws_bytes) return PARDTW_ERR_WORKSPACE;
+    return PARDTW_OK;
+}
+
+}  // namespace
+
 extern "C" pardtw_status pardtw_plan_create(int32_t batch, const int64_t* n_host, const int64_t* m_host, int64_t d,
-                                            pardtw_prec prec, pardtw_plan** plan) {
-    (void)batch; (void)n_host; (void)m_host; (void)d; (void)prec;
-    if (plan) *plan = nullptr;
-    return PARDTW_ERR_UNSUPPORTED;
+                                            pardtw_prec prec, pardtw_plan** plan_out) {
+    if (!plan_out) return PARDTW_ERR_INVALID_ARG;
+    *plan_out = nullptr;
+    if (batch <= 0 || !n_host || !m_host || d <= 0 || d > (int64_t(1) << 20)) return PARDTW_ERR_INVALID_ARG;
+    if (prec != PARDTW_PREC_F32 && prec != PARDTW_PREC_BF16) return PARDTW_ERR_UNSUPPORTED;
+    for (int b = 0; b < batch; ++b)
+        if (!pardtw::valid_sizes(n_host[b], m_host[b])) return PARDTW_ERR_INVALID_ARG;
+
+    pardtw_plan* pl = new (std::nothrow) pardtw_plan;
+    if (!pl) return PARDTW_ERR_HIP;
+    pl->batch = batch;
+    pl->d = d;
+    pl->prec = prec;
+    if (hipGetDevice(&pl->device) != hipSuccess ||
+        hipDeviceGetAttribute(&pl->cus, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess) {
+        delete pl;
+        return PARDTW_ERR_HIP;
+    }
+
+    // descriptors and the workspace layout: cost panels | codes | DP header + records
+    pl->pairs.resize(batch);
+    size_t c_floats = 0, bp_bytes = 0, rec_bytes = 0;
+    int64_t xr = 0, yr = 0, po = 0, tiles = 0;
+    for (int b = 0; b < batch; ++b) {
+        pardtw::BatchPair& q = pl->pairs[b];
+        const int64_t n = n_host[b], m = m_host[b];
+        q.n = n;
+        q.m = m;
+        q.x_off = xr;
+        q.y_off = yr;
+        q.path_off = po;
+        q.G = pardtw::bp_groups(n);
+        q.P = int32_t(pardtw::num_panels(m));
+        q.feasible = pardtw::pair_feasible(n, m) ? 1 : 0;
+        q.c_off = int64_t(c_floats);
+        q.bp_off = int64_t(bp_bytes);
+        q.rec_off = int64_t(rec_bytes / sizeof(uint64_t));
+        q.tile0 = tiles;
+        if (q.feasible) {
+            const size_t cells = size_t(q.P) * size_t(q.G) * pardtw::kPanel * pardtw::kBpRows;
+            c_floats += cells;  // multiples of 512: keeps every pair 256-byte aligned
+            bp_bytes += cells;
+            rec_bytes += pardtw::dp_record_bytes(n, m);
+            tiles += int64_t(q.P) * pardtw::ceil_div(n, 64);
+        }
+        const int64_t cap = std::min(n, m);
+        xr += n;
+        yr += m;
+        po += cap;
+        pl->max_cap = std::max(pl->max_cap, cap);
+    }
+    pl->x_rows = xr;
+    pl->y_rows = yr;
+    pl->path_capacity = po;
+    pl->tiles = tiles;
+    pl->off_c = 0;
+    pl->off_bp = align_up(c_floats * sizeof(float));
+    pl->off_dp = pl->off_bp + align_up(bp_bytes);
+    pl->ws_bytes = pl->off_dp + align_up(pardtw::dp_header_bytes() + rec_bytes);
+
+    // tile -> pair table of the batched cost kernel
+    std::vector<int32_t> tile_pair(size_t(std::max<int64_t>(tiles, 1)));
+    for (int b = 0; b < batch; ++b) {
+        const pardtw::BatchPair& q = pl->pairs[b];
+        if (!q.feasible) continue;
+        const int64_t t = int64_t(q.P) * pardtw::ceil_div(q.n, 64);
+        std::fill(tile_pair.begin() + q.tile0, tile_pair.begin() + q.tile0 + t, b);
+    }
+
+    // candidate schedules and their work lists
+    std::vector<pardtw::DpItem> all_items;
+    const int nws[4] = {1, 2, 4, 8};
+    for (int nw : nws) {
+        for (int order = 0; order < 2; ++order) {
+            const std::vector<pardtw::DpItem> it = make_items(*pl, nw, order);
+            const int64_t at = int64_t(all_items.size());
+            all_items.insert(all_items.end(), it.begin(), it.end());
+            for (int gm = 1; gm <= 2; ++gm) pl->scheds.push_back({nw, order, gm, int32_t(it.size()), at});
+        }
+    }
+    // default: four panels per workgroup, breadth order, one workgroup per CU
+    pl->chosen = 0;
+    for (size_t s = 0; s < pl->scheds.size(); ++s)
+        if (pl->scheds[s].nw == 4 && pl->scheds[s].order == 0 && pl->scheds[s].grid_mul == 1) pl->chosen = int(s);
+    if (all_items.empty()) all_items.push_back({0, 0});
+
+    bool ok = hipMalloc(&pl->pairs_dev, sizeof(pardtw::BatchPair) * batch) == hipSuccess &&
+              hipMalloc(&pl->tile_pair_dev, sizeof(int32_t) * tile_pair.size()) == hipSuccess &&
+              hipMalloc(&pl->items_dev, sizeof(pardtw::DpItem) * all_items.size()) == hipSuccess;
+    ok = ok && hipMemcpy(pl->pairs_dev, pl->pairs.data(), sizeof(pardtw::BatchPair) * batch,
+                         hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(pl->tile_pair_dev, tile_pair.data(), sizeof(int32_t) * tile_pair.size(),
+                         hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(pl->items_dev, all_items.data(), sizeof(pardtw::DpItem) * all_items.size(),
+                         hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok) {
+        delete pl;
+        return PARDTW_ERR_HIP;
+    }
+    *plan_out = pl;
+    return PARDTW_OK;
 }
-extern "C" size_t pardtw_plan_workspace_bytes(const pardtw_plan* plan) { (void)plan; return 0; }
-extern "C" int64_t pardtw_plan_path_capacity(const pardtw_plan* plan) { (void)plan; return 0; }
+
+extern "C" size_t pardtw_plan_workspace_bytes(const pardtw_plan* plan) { return plan ? plan->ws_bytes : 0; }
+
+extern "C" int64_t pardtw_plan_path_capacity(const pardtw_plan* plan) { return plan ? plan->path_capacity : 0; }
+
 extern "C" void pardtw_plan_destroy(pardtw_plan* plan) { delete plan; }
-extern "C" pardtw_status pardtw_align_batch(const pardtw_plan*, const float*, const float*, void*, size_t, float*,
-                                            int32_t*, int32_t*, int32_t*, hipStream_t) {
-    return PARDTW_ERR_UNSUPPORTED;
+
+extern "C" int32_t pardtw_plan_num_schedules(const pardtw_plan* plan) {
+    return plan ? int32_t(plan->scheds.size()) : 0;
 }
-extern "C" pardtw_status pardtw_path_grad_batch(const pardtw_plan*, const float*, const float*, const int32_t*,
-                                                const int32_t*, const float*, float*, float*, hipStream_t) {
-    return PARDTW_ERR_UNSUPPORTED;
+
+extern "C" pardtw_status pardtw_plan_schedule(const pardtw_plan* plan, int32_t index, int32_t* panels_per_workgroup,
+                                              int32_t* order, int32_t* workgroups) {
+    if (!plan || index < -1 || index >= int32_t(plan->scheds.size())) return PARDTW_ERR_INVALID_ARG;
+    const Schedule& s = plan->scheds[index < 0 ? plan->chosen : index];
+    if (panels_per_workgroup) *panels_per_workgroup = s.nw;
+    if (order) *order = s.order;
+    if (workgroups) *workgroups = std::min(grid_for(*plan, s), std::max(s.nitems, 1));
+    return PARDTW_OK;
+}
+
+extern "C" int32_t pardtw_plan_selected(const pardtw_plan* plan) { return plan ? plan->chosen : -1; }
+
+extern "C" pardtw_status pardtw_plan_select(pardtw_plan* plan, int32_t index) {
+    if (!plan || index < 0 || index >= int32_t(plan->scheds.size())) return PARDTW_ERR_INVALID_ARG;
+    plan->chosen = index;
+    return PARDTW_OK;
+}
+
+extern "C" pardtw_status pardtw_align_batch(const pardtw_plan* plan, const float* X_packed, const float* Y_packed,
+                                            void* workspace, size_t workspace_bytes, float* totals,
+                                            int32_t* paths_packed, int32_t* path_len, int32_t* pair_status,
+                                            hipStream_t stream) {
+    pardtw_status st = check_call(plan, X_packed, Y_packed, workspace, workspace_bytes, totals, paths_packed,
+                                  path_len, pair_status);
+    if (st != PARDTW_OK) return st;
+    char* ws = static_cast<char*>(workspace);
+    batch_init_kernel<<<unsigned(pardtw::ceil_div(plan->batch, 256)), 256, 0, stream>>>(
+        plan->pairs_dev, plan->batch, totals, pair_status, path_len);
+    if ((st = pardtw::launch_status()) != PARDTW_OK) return st;
+    st = pardtw::cost_batch_launch(plan->pairs_dev, plan->tile_pair_dev, plan->tiles, X_packed, Y_packed, plan->d,
+                                   plan->prec, reinterpret_cast<float*>(ws + plan->off_c), stream);
+    if (st != PARDTW_OK) return st;
+    st = run_dp(*plan, plan->scheds[plan->chosen], ws, totals, pair_status, stream);
+    if (st != PARDTW_OK) return st;
+    return pardtw::backtrace_batch_launch(plan->pairs_dev, plan->batch,
+                                          reinterpret_cast<const uint8_t*>(ws + plan->off_bp), pair_status,
+                                          paths_packed, path_len, stream);
+}
+
+extern "C" pardtw_status pardtw_plan_autotune(pardtw_plan* plan, const float* X_packed, const float* Y_packed,
+                                              void* workspace, size_t workspace_bytes, float* totals,
+                                              int32_t* paths_packed, int32_t* path_len, int32_t* pair_status,
+                                              int32_t reps, float* best_ms, hipStream_t stream) {
+    pardtw_status st = check_call(plan, X_packed, Y_packed, workspace, workspace_bytes, totals, paths_packed,
+                                  path_len, pair_status);
+    if (st != PARDTW_OK) return st;
+    if (reps < 1) reps = 1;
+    char* ws = static_cast<char*>(workspace);
+    // the costs do not depend on the schedule: compute them once
+    st = pardtw::cost_batch_launch(plan->pairs_dev, plan->tile_pair_dev, plan->tiles, X_packed, Y_packed, plan->d,
+                                   plan->prec, reinterpret_cast<float*>(ws + plan->off_c), stream);
+    if (st != PARDTW_OK) return st;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return PARDTW_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return PARDTW_ERR_HIP;
+    }
+    float best = INFINITY;
+    int best_s = plan->chosen;
+    for (size_t s = 0; s < plan->scheds.size() && st == PARDTW_OK; ++s) {
+        const Schedule& sc = plan->scheds[s];
+        st = run_dp(*plan, sc, ws, totals, pair_status, stream);  // warm-up
+        if (st != PARDTW_OK) break;
+        if (hipEventRecord(e0, stream) != hipSuccess) { st = PARDTW_ERR_HIP; break; }
+        for (int r = 0; r < reps && st == PARDTW_OK; ++r) st = run_dp(*plan, sc, ws, totals, pair_status, stream);
+        if (st != PARDTW_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = PARDTW_ERR_HIP;
+            break;
+        }
+        ms /= float(reps);
+        if (ms < best) {
+            best = ms;
+            best_s = int(s);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != PARDTW_OK) return st;
+    plan->chosen = best_s;
+    if (best_ms) *best_ms = best;
+    return PARDTW_OK;
+}
+
+extern "C" pardtw_status pardtw_path_grad_batch(const pardtw_plan* plan, const float* X_packed,
+                                                const float* Y_packed, const int32_t* paths_packed,
+                                                const int32_t* path_len, const float* g_totals, float* dX_packed,
+                                                float* dY_packed, hipStream_t stream) {
+    if (!plan || !X_packed || !Y_packed || !paths_packed || !path_len || !g_totals || !dX_packed || !dY_packed)
+        return PARDTW_ERR_INVALID_ARG;
+    return pardtw::grad_batch_launch(plan->pairs_dev, plan->batch, plan->max_cap, plan->d, X_packed, Y_packed,
+                                     paths_packed, path_len, g_totals, dX_packed, plan->x_rows * plan->d,
+                                     dY_packed, plan->y_rows * plan->d, stream);
 }

@@ -13,7 +13,7 @@
 // With D = 12 the kernel does 24 flop per 4-byte output, far below the MFMA
 // ridge point, so it is bound by HBM writes; the MFMA keeps the arithmetic off
 // the VALU so the stores stream at full rate.
-#include "common.h"
+#include "batch.h"
 
 namespace pardtw {
 namespace {
@@ -40,16 +40,15 @@ __device__ inline float inv_norm(const float* row, int64_t d) {
     return s > 0.0f ? 1.0f / __builtin_sqrtf(s) : 0.0f;
 }
 
+// One 64-row x 64-column tile: rows [i0, i0+64) of column panel p.
 template <bool BF16, bool PANEL>
-__global__ __launch_bounds__(kThreads) void cost_kernel(const float* __restrict__ X, const float* __restrict__ Y,
-                                                        int64_t n, int64_t m, int64_t d, float* __restrict__ C) {
-    __shared__ float rx[kTileM];
-    __shared__ float ry[kPanel];
+__device__ __attribute__((always_inline)) inline void cost_tile(const float* __restrict__ X,
+                                                                const float* __restrict__ Y, int64_t n, int64_t m,
+                                                                int64_t d, float* __restrict__ C, int64_t p,
+                                                                int64_t i0, float (&rx)[kTileM], float (&ry)[kPanel]) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int64_t p = blockIdx.x;                 // column panel
-    const int64_t i0 = int64_t(blockIdx.y) * kTileM;  // first row of the tile
     const int64_t j0 = p * kPanel;
 
     if (tid < kTileM) {
@@ -139,7 +138,44 @@ __global__ __launch_bounds__(kThreads) void cost_kernel(const float* __restrict_
     }
 }
 
+template <bool BF16, bool PANEL>
+__global__ __launch_bounds__(kThreads) void cost_kernel(const float* __restrict__ X, const float* __restrict__ Y,
+                                                        int64_t n, int64_t m, int64_t d, float* __restrict__ C) {
+    __shared__ float rx[kTileM];
+    __shared__ float ry[kPanel];
+    cost_tile<BF16, PANEL>(X, Y, n, m, d, C, blockIdx.x, int64_t(blockIdx.y) * kTileM, rx, ry);
+}
+
+// Batched form: block t is tile t of the batch; tile_pair[t] names its pair,
+// whose tiles are numbered panel-major from pairs[b].tile0.
+template <bool BF16>
+__global__ __launch_bounds__(kThreads) void cost_batch_kernel(const BatchPair* __restrict__ pairs,
+                                                              const int32_t* __restrict__ tile_pair,
+                                                              const float* __restrict__ X,
+                                                              const float* __restrict__ Y, int64_t d,
+                                                              float* __restrict__ Cbase) {
+    __shared__ float rx[kTileM];
+    __shared__ float ry[kPanel];
+    const int64_t t = blockIdx.x;
+    const BatchPair q = pairs[tile_pair[t]];
+    const int64_t local = t - q.tile0;
+    const int64_t tiles_m = ceil_div(q.n, kTileM);
+    cost_tile<BF16, true>(X + q.x_off * d, Y + q.y_off * d, q.n, q.m, d, Cbase + q.c_off, local / tiles_m,
+                          (local % tiles_m) * kTileM, rx, ry);
+}
+
 }  // namespace
+
+pardtw_status cost_batch_launch(const BatchPair* pairs, const int32_t* tile_pair, int64_t tiles, const float* X,
+                                const float* Y, int64_t d, pardtw_prec prec, float* Cbase, hipStream_t stream) {
+    if (tiles <= 0) return PARDTW_OK;
+    if (tiles > 0x7fffffff) return PARDTW_ERR_UNSUPPORTED;
+    if (prec == PARDTW_PREC_F32)
+        cost_batch_kernel<false><<<unsigned(tiles), kThreads, 0, stream>>>(pairs, tile_pair, X, Y, d, Cbase);
+    else
+        cost_batch_kernel<true><<<unsigned(tiles), kThreads, 0, stream>>>(pairs, tile_pair, X, Y, d, Cbase);
+    return launch_status();
+}
 
 pardtw_status cost_launch(const float* X, const float* Y, int64_t n, int64_t m, int64_t d, pardtw_prec prec,
                           pardtw_layout layout, float* C, hipStream_t stream) {

@@ -30,7 +30,7 @@
 // written. In the panel layout a wave reads a chunk's 2 KB of cost with two
 // loads of 1 KB contiguous each (16 bytes per lane) and writes its 512 bytes
 // of codes with one store (8 bytes per lane).
-#include "common.h"
+#include "batch.h"
 
 namespace pardtw {
 namespace {
@@ -421,30 +421,85 @@ __device__ __attribute__((always_inline)) inline void out_helper(const DpArgs& a
     }
 }
 
-// Workgroup: NW compute waves, then the input helper and the output helper.
+// Panel group q (panels q*NW .. q*NW+NW-1) of one pair: NW compute waves, then
+// the input helper and the output helper.
+template <int NW, bool PANEL>
+__device__ __attribute__((always_inline)) inline void run_group(const DpArgs& a, DpShared& sh, int wave, int q,
+                                                                uint32_t epoch) {
+    const int p0 = q * NW;
+    if (wave < NW) {
+        const int p = p0 + wave;
+        if (p < a.P) compute_wave<PANEL>(a, sh, wave, p, p > 0, p + 1 < a.P);
+    } else if (wave == NW) {
+        if (p0 > 0) in_helper(a, sh, p0 - 1, epoch);
+    } else {
+        // the group's last panel feeds the next group when one exists
+        if (p0 + NW < a.P) out_helper(a, sh, NW, p0 + NW - 1, epoch);
+    }
+}
+
+// Takes the next ticket and resets the group's LDS handoff counters.
+template <int NW>
+__device__ inline int next_ticket(DpShared& sh, DpWsHeader* hdr) {
+    if (threadIdx.x == 0) {
+        sh.super = int(atomicAdd(&hdr->ticket, 1u));
+        for (int w = 0; w <= NW; ++w) { sh.prog[w][0] = 0; sh.prog[w][1] = 0; sh.cons[w] = 0; }
+    }
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(sh.super);
+}
+
 template <int NW, bool PANEL>
 __global__ __launch_bounds__(kLanes*(NW + 2)) void dp_kernel(DpArgs a) {
     __shared__ DpShared sh;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);
     const uint32_t epoch = __hip_atomic_load(&a.hdr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (;;) {
-        if (threadIdx.x == 0) {
-            sh.super = int(atomicAdd(&a.hdr->ticket, 1u));
-            for (int w = 0; w <= NW; ++w) { sh.prog[w][0] = 0; sh.prog[w][1] = 0; sh.cons[w] = 0; }
-        }
-        __syncthreads();
-        const int q = sh.super;
+        const int q = next_ticket<NW>(sh, a.hdr);
         if (q >= a.S) break;
-        const int p0 = q * NW;
-        if (wave < NW) {
-            const int p = p0 + wave;
-            if (p < a.P) compute_wave<PANEL>(a, sh, wave, p, p > 0, p + 1 < a.P);
-        } else if (wave == NW) {
-            if (p0 > 0) in_helper(a, sh, p0 - 1, epoch);
-        } else {
-            // the group's last panel feeds the next group when one exists
-            if (p0 + NW < a.P) out_helper(a, sh, NW, p0 + NW - 1, epoch);
-        }
+        run_group<NW, PANEL>(a, sh, wave, q, epoch);
+        __syncthreads();
+    }
+}
+
+// Batched form: one persistent launch over the items of every pair. Items of
+// one pair appear in increasing group order in the list, so a group again only
+// waits on lower tickets.
+struct DpBatchArgs {
+    const BatchPair* pairs;
+    const DpItem* items;
+    int32_t nitems;
+    const float* C;
+    uint8_t* bp;
+    float* totals;
+    int32_t* status;
+    DpWsHeader* hdr;
+    uint64_t* rec;
+};
+
+template <int NW>
+__global__ __launch_bounds__(kLanes*(NW + 2)) void dp_batch_kernel(DpBatchArgs ba) {
+    __shared__ DpShared sh;
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);
+    const uint32_t epoch = __hip_atomic_load(&ba.hdr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        const int t = next_ticket<NW>(sh, ba.hdr);
+        if (t >= ba.nitems) break;
+        const DpItem it = ba.items[t];
+        const BatchPair q = ba.pairs[it.pair];
+        DpArgs a;
+        a.C = ba.C + q.c_off;
+        a.bp = ba.bp + q.bp_off;
+        a.total = ba.totals + it.pair;
+        a.status = ba.status + it.pair;
+        a.hdr = ba.hdr;
+        a.rec = ba.rec + q.rec_off;
+        a.n = q.n;
+        a.m = q.m;
+        a.G = q.G;
+        a.P = q.P;
+        a.S = int(ceil_div(q.P, NW));
+        run_group<NW, true>(a, sh, wave, it.group, epoch);
         __syncthreads();
     }
 }
@@ -468,10 +523,45 @@ void launch_nw(const DpArgs& a, bool panel, int grid, hipStream_t stream) {
     else dp_kernel<NW, false><<<grid, kLanes * (NW + 2), 0, stream>>>(a);
 }
 
+template <int NW>
+void launch_batch_nw(const DpBatchArgs& a, int grid, hipStream_t stream) {
+    dp_batch_kernel<NW><<<grid, kLanes * (NW + 2), 0, stream>>>(a);
+}
+
 }  // namespace
 
-size_t dp_workspace_bytes_impl(int64_t n, int64_t m) {
-    return sizeof(DpWsHeader) + size_t(num_panels(m)) * size_t(bp_groups(n)) * kChunk * 2 * sizeof(uint64_t);
+size_t dp_header_bytes() { return sizeof(DpWsHeader); }
+
+size_t dp_record_bytes(int64_t n, int64_t m) {
+    return size_t(num_panels(m)) * size_t(bp_groups(n)) * kChunk * 2 * sizeof(uint64_t);
+}
+
+size_t dp_workspace_bytes_impl(int64_t n, int64_t m) { return sizeof(DpWsHeader) + dp_record_bytes(n, m); }
+
+pardtw_status dp_batch_launch(const BatchPair* pairs, const DpItem* items, int32_t nitems, int nw, int grid,
+                              const float* Cbase, uint8_t* bpbase, float* totals, int32_t* status, void* dp_ws,
+                              hipStream_t stream) {
+    DpBatchArgs a;
+    a.pairs = pairs;
+    a.items = items;
+    a.nitems = nitems;
+    a.C = Cbase;
+    a.bp = bpbase;
+    a.totals = totals;
+    a.status = status;
+    a.hdr = reinterpret_cast<DpWsHeader*>(dp_ws);
+    a.rec = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(dp_ws) + sizeof(DpWsHeader));
+    dp_prepare<<<1, 1, 0, stream>>>(a.hdr);
+    if (nitems <= 0) return launch_status();
+    if (grid > nitems) grid = nitems;
+    switch (nw) {
+        case 1: launch_batch_nw<1>(a, grid, stream); break;
+        case 2: launch_batch_nw<2>(a, grid, stream); break;
+        case 4: launch_batch_nw<4>(a, grid, stream); break;
+        case 8: launch_batch_nw<8>(a, grid, stream); break;
+        default: return PARDTW_ERR_UNSUPPORTED;
+    }
+    return launch_status();
 }
 
 pardtw_status dp_launch(const float* C, pardtw_layout layout, int64_t n, int64_t m, uint8_t* bp,

@@ -8,7 +8,7 @@
 // Every step advances both coordinates, so a row or column appears at most
 // once on a path: each path cell owns its output rows and no atomics are
 // needed. One wavefront per path cell, lanes over the feature dimension.
-#include "common.h"
+#include "batch.h"
 
 namespace pardtw {
 namespace {
@@ -68,17 +68,14 @@ __device__ void grad_cell(const GradPair& q, int64_t l, int64_t d, int lane) {
     }
 }
 
-// grid.x covers path cells (one wave each, 4 waves per block), grid.y pairs.
-__global__ __launch_bounds__(256) void grad_kernel(const GradPair* __restrict__ pairs, GradPair single, int64_t d) {
-    const GradPair q = pairs ? pairs[blockIdx.y] : single;
+// grid.x covers path cells (one wave each, 4 waves per block).
+__global__ __launch_bounds__(256) void grad_kernel(GradPair q, int64_t d) {
     const int lane = threadIdx.x & 63;
     const int64_t len = *q.path_len;
     const int64_t waves = int64_t(gridDim.x) * (blockDim.x / kLanes);
     for (int64_t l = int64_t(blockIdx.x) * (blockDim.x / kLanes) + (threadIdx.x >> 6); l < len; l += waves)
         grad_cell(q, l, d, lane);
 }
-
-}  // namespace
 
 pardtw_status grad_launch_single(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
                                  const int32_t* path, const int32_t* path_len, const float* g, float* dX,
@@ -88,28 +85,40 @@ pardtw_status grad_launch_single(const float* X, const float* Y, int64_t n, int6
     GradPair q{X, Y, path, path_len, g, dX, dY, n, m, n < m ? n : m};
     const int64_t cap = q.cap;
     const unsigned blocks = unsigned(ceil_div(cap, 4) < 4096 ? ceil_div(cap, 4) : 4096);
-    grad_kernel<<<dim3(blocks, 1), 256, 0, stream>>>(nullptr, q, d);
+    grad_kernel<<<dim3(blocks, 1), 256, 0, stream>>>(q, d);
     return launch_status();
 }
 
-// Batched form: pairs[] describes every pair (device array built by the plan).
-pardtw_status grad_launch_batch(const void* pairs_dev, int batch, int64_t max_cap, int64_t d, float* dX,
-                                int64_t dX_count, float* dY, int64_t dY_count, hipStream_t stream) {
+// Batched form: grid.y = pair; the plan's descriptors give each pair's rows
+// in the packed features and its path, so the launch needs no per-call setup.
+__global__ __launch_bounds__(256) void grad_batch_kernel(const BatchPair* __restrict__ pairs, const float* X,
+                                                         const float* Y, const int32_t* paths,
+                                                         const int32_t* path_len, const float* g, float* dX,
+                                                         float* dY, int64_t d) {
+    const int b = blockIdx.y;
+    const BatchPair pr = pairs[b];
+    if (!pr.feasible) return;
+    GradPair q{X + pr.x_off * d, Y + pr.y_off * d, paths + 2 * pr.path_off, path_len + b, g + b,
+               dX + pr.x_off * d, dY + pr.y_off * d, pr.n, pr.m, pr.n < pr.m ? pr.n : pr.m};
+    const int lane = threadIdx.x & 63;
+    const int64_t len = *q.path_len;
+    const int64_t waves = int64_t(gridDim.x) * (blockDim.x / kLanes);
+    for (int64_t l = int64_t(blockIdx.x) * (blockDim.x / kLanes) + (threadIdx.x >> 6); l < len; l += waves)
+        grad_cell(q, l, d, lane);
+}
+
+}  // namespace
+
+pardtw_status grad_batch_launch(const BatchPair* pairs, int32_t batch, int64_t max_cap, int64_t d, const float* X,
+                                const float* Y, const int32_t* paths, const int32_t* path_len, const float* g,
+                                float* dX, int64_t dX_count, float* dY, int64_t dY_count, hipStream_t stream) {
     zero_kernel<<<2048, 256, 0, stream>>>(dX, dX_count);
     zero_kernel<<<2048, 256, 0, stream>>>(dY, dY_count);
-    GradPair none{};
+    if (batch <= 0 || max_cap <= 0) return launch_status();
     const unsigned blocks = unsigned(ceil_div(max_cap, 4) < 1024 ? ceil_div(max_cap, 4) : 1024);
-    grad_kernel<<<dim3(blocks, unsigned(batch)), 256, 0, stream>>>(reinterpret_cast<const GradPair*>(pairs_dev),
-                                                                    none, d);
+    grad_batch_kernel<<<dim3(blocks, unsigned(batch)), 256, 0, stream>>>(pairs, X, Y, paths, path_len, g, dX, dY,
+                                                                          d);
     return launch_status();
-}
-
-size_t grad_pair_desc_bytes() { return sizeof(GradPair); }
-
-void grad_fill_desc(void* dst, const float* X, const float* Y, const int32_t* path, const int32_t* path_len,
-                    const float* g, float* dX, float* dY, int64_t n, int64_t m) {
-    GradPair q{X, Y, path, path_len, g, dX, dY, n, m, n < m ? n : m};
-    *reinterpret_cast<GradPair*>(dst) = q;
 }
 
 }  // namespace pardtw

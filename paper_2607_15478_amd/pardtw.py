@@ -59,6 +59,11 @@ _lib_plan_cap = _sig("pardtw_plan_path_capacity", _I64, [_P])
 _lib_plan_destroy = _sig("pardtw_plan_destroy", None, [_P])
 _lib_align_batch = _sig("pardtw_align_batch", _E, [_P, _P, _P, _P, _SZ, _P, _P, _P, _P, _P])
 _lib_grad_batch = _sig("pardtw_path_grad_batch", _E, [_P, _P, _P, _P, _P, _P, _P, _P, _P])
+_lib_plan_nsched = _sig("pardtw_plan_num_schedules", _I32, [_P])
+_lib_plan_sched = _sig("pardtw_plan_schedule", _E, [_P, _I32, _P, _P, _P])
+_lib_plan_selected = _sig("pardtw_plan_selected", _I32, [_P])
+_lib_plan_select = _sig("pardtw_plan_select", _E, [_P, _I32])
+_lib_plan_autotune = _sig("pardtw_plan_autotune", _E, [_P, _P, _P, _P, _SZ, _P, _P, _P, _P, _I32, _P, _P])
 _lib_status_string = _sig("pardtw_status_string", ctypes.c_char_p, [_E])
 
 
@@ -184,3 +189,99 @@ def align(X: torch.Tensor, Y: torch.Tensor, prec: int = PREC_F32, layout: int = 
     align_into(X, Y, w, prec)
     L = int(w.path_len.item())
     return float(w.total.item()), w.path[:L].clone(), int(w.status.item())
+
+
+# ---- batched form -----------------------------------------------------------
+class Plan:
+    """A batch of pairs with fixed lengths (pardtw_plan_create). Buffers are
+    packed as the C header describes; `buffers()` allocates a matching set."""
+
+    def __init__(self, ns, ms, d: int, prec: int = PREC_F32):
+        ns = [int(v) for v in ns]
+        ms = [int(v) for v in ms]
+        if len(ns) != len(ms) or not ns:
+            raise ValueError("ns and ms must be non-empty and of equal length")
+        self.ns, self.ms, self.d, self.prec = ns, ms, int(d), prec
+        self.batch = len(ns)
+        n_arr = (ctypes.c_int64 * self.batch)(*ns)
+        m_arr = (ctypes.c_int64 * self.batch)(*ms)
+        h = _P()
+        _check(_lib_plan_create(self.batch, n_arr, m_arr, self.d, prec, ctypes.byref(h)), "pardtw_plan_create")
+        self._h = h
+        self.workspace_bytes = int(_lib_plan_ws(h))
+        self.path_capacity = int(_lib_plan_cap(h))
+        self.x_off = [0] * self.batch
+        self.y_off = [0] * self.batch
+        self.p_off = [0] * self.batch
+        xo = yo = po = 0
+        for b in range(self.batch):
+            self.x_off[b], self.y_off[b], self.p_off[b] = xo, yo, po
+            xo += ns[b]
+            yo += ms[b]
+            po += min(ns[b], ms[b])
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib_plan_destroy(h)
+            self._h = None
+
+    def buffers(self, device="cuda"):
+        """Output and workspace tensors for this plan (workspace zeroed)."""
+        return dict(
+            workspace=torch.zeros(self.workspace_bytes, dtype=torch.uint8, device=device),
+            totals=torch.empty(self.batch, dtype=torch.float32, device=device),
+            paths=torch.empty((self.path_capacity, 2), dtype=torch.int32, device=device),
+            path_len=torch.empty(self.batch, dtype=torch.int32, device=device),
+            status=torch.empty(self.batch, dtype=torch.int32, device=device),
+        )
+
+    def _args(self, Xp, Yp, buf):
+        _dev_f32(Xp, "X_packed"), _dev_f32(Yp, "Y_packed")
+        if Xp.shape != (sum(self.ns), self.d) or Yp.shape != (sum(self.ms), self.d):
+            raise ValueError("packed features do not match the plan")
+        ws = buf["workspace"]
+        return (_ptr(Xp), _ptr(Yp), _ptr(ws), ws.numel() * ws.element_size(), _ptr(buf["totals"]),
+                _ptr(buf["paths"]), _ptr(buf["path_len"]), _ptr(buf["status"]))
+
+    def align(self, Xp: torch.Tensor, Yp: torch.Tensor, buf: dict, stream=None):
+        _check(_lib_align_batch(self._h, *self._args(Xp, Yp, buf), _stream(stream)), "pardtw_align_batch")
+
+    def autotune(self, Xp: torch.Tensor, Yp: torch.Tensor, buf: dict, reps: int = 2, stream=None) -> float:
+        best = ctypes.c_float(0.0)
+        _check(_lib_plan_autotune(self._h, *self._args(Xp, Yp, buf), int(reps), ctypes.byref(best),
+                                  _stream(stream)), "pardtw_plan_autotune")
+        return float(best.value)
+
+    @property
+    def num_schedules(self) -> int:
+        return int(_lib_plan_nsched(self._h))
+
+    def schedule(self, index: int = -1):
+        nw, order, wg = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib_plan_sched(self._h, int(index), ctypes.byref(nw), ctypes.byref(order), ctypes.byref(wg)),
+               "pardtw_plan_schedule")
+        return dict(panels_per_workgroup=nw.value, order=("breadth", "depth")[order.value], workgroups=wg.value)
+
+    @property
+    def selected(self) -> int:
+        return int(_lib_plan_selected(self._h))
+
+    def select(self, index: int):
+        _check(_lib_plan_select(self._h, int(index)), "pardtw_plan_select")
+
+    def path(self, buf: dict, b: int) -> torch.Tensor:
+        L = int(buf["path_len"][b].item())
+        return buf["paths"][self.p_off[b]: self.p_off[b] + L]
+
+    def path_grad(self, Xp, Yp, buf, g_totals, dXp, dYp, stream=None):
+        _check(_lib_grad_batch(self._h, _ptr(Xp), _ptr(Yp), _ptr(buf["paths"]), _ptr(buf["path_len"]),
+                               _ptr(g_totals), _ptr(dXp), _ptr(dYp), _stream(stream)), "pardtw_path_grad_batch")
+
+
+def pack(pairs, device="cuda"):
+    """[(X_b, Y_b)] numpy pairs -> (X_packed, Y_packed) device tensors."""
+    import numpy as np
+    Xp = torch.from_numpy(np.ascontiguousarray(np.concatenate([p[0] for p in pairs]), dtype=np.float32)).to(device)
+    Yp = torch.from_numpy(np.ascontiguousarray(np.concatenate([p[1] for p in pairs]), dtype=np.float32)).to(device)
+    return Xp, Yp

@@ -176,6 +176,9 @@ WORKLOADS = {
     "pair_10000x12000_d12": dict(kind="pair", seed=2, n=10000, m=12000, d=12, lo=0.8, hi=1.25),
     "pair_50000x60000_d12": dict(kind="pair", seed=3, n=50000, m=60000, d=12, lo=0.7, hi=1.4),
     "batch256_500to8000_d12": dict(kind="chroma_batch", seed=4, count=256, lo=500, hi=8000, d=12),
+    # the same draw with infeasible pairs' m redrawn, so every pair is aligned
+    "batch256_500to8000_d12_feasible": dict(kind="chroma_batch", seed=4, count=256, lo=500, hi=8000, d=12,
+                                            redraw_infeasible=True),
     "batch32_2000to4000_d128": dict(kind="gaussian_batch", seed=5, count=32, lo=2000, hi=4000, d=128),
 }
 
@@ -186,5 +189,5 @@ def make_workload(name: str):
     if w["kind"] == "pair":
         return chroma_pair(w["seed"], w["n"], w["m"], w["d"], w["lo"], w["hi"])
     if w["kind"] == "chroma_batch":
-        return chroma_batch(w["seed"], w["count"], w["lo"], w["hi"], w["d"])
+        return chroma_batch(w["seed"], w["count"], w["lo"], w["hi"], w["d"], w.get("redraw_infeasible", False))
     return gaussian_batch(w["seed"], w["count"], w["lo"], w["hi"], w["d"])
