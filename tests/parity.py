@@ -159,3 +159,13 @@ def bp_with_path(n: int, m: int, path: np.ndarray, rng: np.random.Generator) -> 
     B[path[1:, 0], path[1:, 1]] = codes.astype(np.uint8)
     B[0, 0] = 3
     return B
+
+
+def path_deviation(path_a: np.ndarray, path_b: np.ndarray, n: int):
+    """Mean and max over X-frames i of |j_A(i) - j_B(i)|, each path's j taken
+    at its cell in row i, linearly interpolated over rows the path skips."""
+    rows = np.arange(n, dtype=np.float64)
+    ja = np.interp(rows, path_a[:, 0].astype(np.float64), path_a[:, 1].astype(np.float64))
+    jb = np.interp(rows, path_b[:, 0].astype(np.float64), path_b[:, 1].astype(np.float64))
+    dev = np.abs(ja - jb)
+    return float(dev.mean()), float(dev.max())
