@@ -208,5 +208,149 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def run_batch(args):
+    """Batched form: every pair of a batch workload in one hipGraph replay of
+    pardtw_align_batch (autotuned schedule), against the same pairs aligned by
+    sequential single-pair calls. For the D = 128 workload the BF16-cost form is
+    run too and its paths compared with the FP32 ones."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2607_15478_amd import synth
+    from paper_2607_15478_amd import pardtw as pd
+
+    dev = torch.device("cuda:0")
+    print(f"[bench] generating {args.workload}", file=sys.stderr, flush=True)
+    pairs = synth.make_workload(args.workload)
+    ns, ms = [len(p[0]) for p in pairs], [len(p[1]) for p in pairs]
+    d = pairs[0][0].shape[1]
+    feas = [(n - 1) <= 2 * (m - 1) and (m - 1) <= 2 * (n - 1) for n, m in zip(ns, ms)]
+    cells = sum(n * m for n, m, f in zip(ns, ms, feas) if f)
+
+    val = {}
+    pool = None
+    if not args.no_validate:
+        import oracle
+        pool = ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1))
+        futs = [pool.submit(oracle.dtw_features, x, y) if f else None for (x, y), f in zip(pairs, feas)]
+
+    Xp, Yp = pd.pack(pairs, dev)
+    res = {}
+    for prec in ([pd.PREC_F32, pd.PREC_BF16] if d >= 64 else [pd.PREC_F32]):
+        plan = pd.Plan(ns, ms, d, prec)
+        buf = plan.buffers(dev)
+        best = plan.autotune(Xp, Yp, buf, reps=2)
+        for _ in range(args.warmup):
+            plan.align(Xp, Yp, buf)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            plan.align(Xp, Yp, buf)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            plan.align(Xp, Yp, buf)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms_graph = e0.elapsed_time(e1) / args.steps
+        res[prec] = dict(plan=plan, buf=buf, ms=ms_graph, tuned_dp_ms=best, sched=plan.schedule(),
+                         totals=buf["totals"].cpu().numpy(), status=buf["status"].cpu().numpy(),
+                         paths=[plan.path(buf, b).cpu().numpy() for b in range(len(pairs))])
+        print(f"[bench] batch prec={prec} graph {ms_graph:.3f} ms, schedule {plan.schedule()}", file=sys.stderr,
+              flush=True)
+
+    # sequential single-pair calls on preallocated workspaces
+    ws = [pd.Workspace(n, m, dev) for n, m in zip(ns, ms)]
+    Xs = [torch.from_numpy(x).to(dev) for x, _ in pairs]
+    Ys = [torch.from_numpy(y).to(dev) for _, y in pairs]
+    for b in range(len(pairs)):
+        pd.align_into(Xs[b], Ys[b], ws[b])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for b in range(len(pairs)):
+        pd.align_into(Xs[b], Ys[b], ws[b])
+    e1.record()
+    torch.cuda.synchronize()
+    ms_seq = e0.elapsed_time(e1)
+    r32 = res[pd.PREC_F32]
+    same_as_single = all(
+        (not feas[b]) or (np.array_equal(r32["paths"][b], ws[b].path[: int(ws[b].path_len.item())].cpu().numpy())
+                          and float(r32["totals"][b]) == float(ws[b].total.item()))
+        for b in range(len(pairs)))
+    del ws
+
+    validation = None
+    if pool is not None:
+        from tests import parity
+        import oracle
+        ok, ties, msg = True, 0, "ok"
+        devs = []
+        for b, fut in enumerate(futs):
+            x, y = pairs[b]
+            try:
+                if fut is None:
+                    assert r32["status"][b] == pd.PAIR_INFEASIBLE and len(r32["paths"][b]) == 0
+                    continue
+                J, BP = fut.result()
+                parity.check_legal(r32["paths"][b], ns[b], ms[b])
+                parity.check_total(float(r32["totals"][b]), J)
+                ties += parity.audit_path(r32["paths"][b], BP, lambda c: oracle.probe(c, X=x, Y=y)[0])
+                if pd.PREC_BF16 in res:
+                    p16 = res[pd.PREC_BF16]["paths"][b]
+                    mdev, xdev = parity.path_deviation(p16, r32["paths"][b], ns[b])
+                    devs.append((mdev, xdev, abs(float(res[pd.PREC_BF16]["totals"][b]) - J) / J,
+                                 (oracle.path_cost(x, y, p16) - J) / J))
+            except AssertionError as exc:
+                ok, msg = False, f"pair {b}: {str(exc)[:200]}"
+                break
+        pool.shutdown()
+        validation = {"path_match": ok, "declared_ties": ties, "detail": msg,
+                      "batch_equals_single_pair_calls": same_as_single}
+        if devs:
+            a = np.array(devs)
+            validation["bf16"] = {"mean_path_dev_frames": round(float(a[:, 0].mean()), 4),
+                                  "max_path_dev_frames": float(a[:, 1].max()),
+                                  "max_rel_cost_err": float(a[:, 2].max()),
+                                  "max_rescore_gap": float(a[:, 3].max())}
+
+    out = {
+        "metric": "DP cells/sec (GCUPS) + aligned pairs/sec at oracle path match, 1 MI355X",
+        "value": round(cells / (r32["ms"] * 1e-3) / 1e9, 2),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "pairs": len(pairs), "feasible_pairs": int(sum(feas)), "d": d,
+                   "feasible_cells": cells, "pairs_per_s": round(len(pairs) / (r32["ms"] * 1e-3), 1),
+                   "schedule": r32["sched"], "tuned_dp_ms": round(r32["tuned_dp_ms"], 4),
+                   "sequential_single_pair_ms": round(ms_seq, 3),
+                   "speedup_vs_sequential": round(ms_seq / r32["ms"], 2)},
+        "validation": validation,
+    }
+    if pd.PREC_BF16 in res:
+        out["config"]["bf16_graph_ms"] = round(res[pd.PREC_BF16]["ms"], 4)
+    print(json.dumps(out), flush=True)
+
+
 if __name__ == "__main__":
-    main()
+    if "--workload" in sys.argv and any(a.startswith("batch") for a in sys.argv):
+        _a = parse()
+        if _a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+            print("bench.py: this build measures one GPU only", file=sys.stderr)
+            sys.exit(2)
+        run_batch(_a)
+    else:
+        main()
