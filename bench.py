@@ -5,9 +5,9 @@ One step = the whole hot path for one pair with inputs resident in HBM:
   cosine-cost MFMA GEMM (panel layout) -> staircase-wavefront DP -> backtrace.
 Prints one JSON line with GCUPS (N*M cells / step time), pairs/s, the DP
 kernel's roofline figures (algorithmic bytes / measured kernel time against
-the 8 TB/s HBM peak), an oracle CPU baseline on a bounded sample, and the
-result of validating the GPU path against the FP64 oracle (full sweep, run on
-a host thread while the GPU is timed).
+the 8 TB/s HBM peak), and the CPU baseline leg: the FP64 oracle timed on the
+whole pair (about 15 s on one host core), whose result also validates the GPU
+path. `--workload batch...` runs the batched form instead (see run_batch).
 """
 from __future__ import annotations
 
@@ -16,7 +16,6 @@ import hashlib
 import json
 import os
 import sys
-import threading
 import time
 
 import numpy as np
@@ -35,13 +34,82 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=WORKLOAD)
-    ap.add_argument("--no-validate", action="store_true", help="skip the full oracle path check")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the baseline sample")
+    ap.add_argument("--no-validate", action="store_true", help="time the oracle but skip the path check")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline leg (and validation)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "dp_traffic.json"))
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     return ap.parse_args()
+
+
+def cpu_baseline_pair(X, Y, path, total, validate=True):
+    """The oracle (single-threaded FP64 DTW with codes) timed on the whole pair;
+    its result is then used to check the GPU path and total. The only use of
+    the oracle in this script."""
+    import oracle
+    from tests import parity
+    n, m = len(X), len(Y)
+    t0 = time.perf_counter()
+    J, BP = oracle.dtw_features(X, Y)
+    secs = time.perf_counter() - t0
+    cpu = {"value": round(n * m / secs / 1e9, 5), "unit": "GCUPS", "cores": 1, "kind": "oracle",
+           "sample": f"the whole {n}x{m} pair: FP64 cost rows + DP + int8 code matrix, one thread, {secs:.1f} s"}
+    if not validate:
+        return cpu, None
+    ok, ties, msg = True, -1, "ok"
+    try:
+        parity.check_legal(path, n, m)
+        parity.check_total(total, J)
+        ties = parity.audit_path(path, BP, lambda c: oracle.probe(c, X=X, Y=Y)[0])
+    except AssertionError as exc:  # report, do not hide
+        ok, msg = False, str(exc)[:300]
+    validation = {"path_match": ok, "declared_ties": ties, "oracle_total": J, "gpu_total": total,
+                  "path_len": int(len(path)), "detail": msg}
+    return cpu, validation
+
+
+def cpu_baseline_batch(pairs, paths, totals, status, bf16=None, threads=8):
+    """The oracle on every feasible pair of a batch (one thread per pair, a pool
+    of `threads`), timed, then used to check the GPU paths (and, for the BF16
+    form, to measure its cost error and re-score gap). The only use of the
+    oracle in this script's batch mode."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    from tests import parity
+    feas = [oracle.feasible(len(x), len(y)) for x, y in pairs]
+    cells = sum(len(x) * len(y) for (x, y), f in zip(pairs, feas) if f)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        res = list(pool.map(lambda xy: oracle.dtw_features(*xy) if oracle.feasible(len(xy[0]), len(xy[1])) else None,
+                            pairs))
+    secs = time.perf_counter() - t0
+    cpu = {"value": round(cells / secs / 1e9, 5), "unit": "GCUPS", "cores": threads, "kind": "oracle",
+           "sample": f"all {len(pairs)} pairs ({cells:.3e} feasible cells), one pair per thread, {secs:.1f} s"}
+    ok, ties, msg, devs = True, 0, "ok", []
+    for b, (x, y) in enumerate(pairs):
+        try:
+            if not feas[b]:
+                assert status[b] == 1 and len(paths[b]) == 0, "infeasible pair not reported"
+                continue
+            J, BP = res[b]
+            parity.check_legal(paths[b], len(x), len(y))
+            parity.check_total(float(totals[b]), J)
+            ties += parity.audit_path(paths[b], BP, lambda c: oracle.probe(c, X=x, Y=y)[0])
+            if bf16 is not None:
+                p16, t16 = bf16[0][b], float(bf16[1][b])
+                mdev, xdev = parity.path_deviation(p16, paths[b], len(x))
+                devs.append((mdev, xdev, abs(t16 - J) / J, (oracle.path_cost(x, y, p16) - J) / J))
+        except AssertionError as exc:
+            ok, msg = False, f"pair {b}: {str(exc)[:200]}"
+            break
+    validation = {"path_match": ok, "declared_ties": ties, "detail": msg}
+    if devs:
+        a = np.array(devs)
+        validation["bf16"] = {"mean_path_dev_frames": round(float(a[:, 0].mean()), 4),
+                              "max_path_dev_frames": float(a[:, 1].max()),
+                              "max_rel_cost_err": float(a[:, 2].max()),
+                              "max_rescore_gap": float(a[:, 3].max())}
+    return cpu, validation
 
 
 def main():
@@ -62,20 +130,6 @@ def main():
     X, Y = synth.make_workload(args.workload)
     n, m, d = X.shape[0], Y.shape[0], X.shape[1]
     cells = n * m
-
-    # ---- validation oracle on a host thread (full FP64 sweep) ----
-    val = {}
-
-    def run_oracle():
-        import oracle
-        t0 = time.perf_counter()
-        J, BP = oracle.dtw_features(X, Y)
-        val["J"], val["BP"], val["secs"] = J, BP, time.perf_counter() - t0
-
-    th = None
-    if not args.no_validate:
-        th = threading.Thread(target=run_oracle, daemon=True)
-        th.start()
 
     Xd = torch.from_numpy(X).to(dev)
     Yd = torch.from_numpy(Y).to(dev)
@@ -143,44 +197,10 @@ def main():
         # the kernel reads no cost for chunks the step set cannot reach, so it moves fewer bytes than 5 B/cell
         roofline["moved_GBps"] = round(traffic / (dp_ms * 1e-3) / 1e9, 1)
 
-    # ---- validation against the oracle ----
-    validation = None
-    if th is not None:
-        print("[bench] waiting for the oracle sweep", file=sys.stderr, flush=True)
-        th.join()
-        from tests import parity
-        import oracle
-        ok = True
-        ties = -1
-        msg = "ok"
-        try:
-            parity.check_legal(path, n, m)
-            parity.check_total(total, val["J"])
-            ties = parity.audit_path(path, val["BP"], lambda c: oracle.probe(c, X=X, Y=Y)[0])
-        except AssertionError as exc:  # report, do not hide
-            ok, msg = False, str(exc)[:300]
-        validation = {"path_match": ok, "declared_ties": ties, "oracle_total": val["J"], "gpu_total": total,
-                      "path_len": L, "oracle_secs": round(val["secs"], 2), "detail": msg}
-        del val["BP"]
-
-    # ---- CPU baseline: the oracle on a bounded leading block of the same pair ----
-    cpu = None
+    # ---- CPU baseline leg: the oracle on the whole pair, which also validates the GPU path ----
+    cpu, validation = None, None
     if not args.no_cpu:
-        import oracle
-        # size the sample from a short timing probe of the same oracle call
-        pn, pm = min(n, 2000), min(m, 2400)
-        tp = time.perf_counter()
-        oracle.dtw_features(X[:pn], Y[:pm])
-        rate_guess = pn * pm / max(time.perf_counter() - tp, 1e-3)
-        side = float(np.sqrt(args.cpu_seconds * rate_guess / cells))
-        ns, ms_ = max(64, int(n * side)), max(64, int(m * side))
-        ns, ms_ = min(ns, n), min(ms_, m)
-        t1 = time.perf_counter()
-        oracle.dtw_features(X[:ns], Y[:ms_])
-        dt = time.perf_counter() - t1
-        cpu = {"value": round(ns * ms_ / dt / 1e9, 5), "unit": "GCUPS", "cores": 1, "kind": "oracle",
-               "sample": f"leading {ns}x{ms_} block of the {n}x{m} pair: FP64 cost rows + DP + int8 "
-                         f"backtrace matrix, single thread, {dt:.1f} s"}
+        cpu, validation = cpu_baseline_pair(X, Y, path, total, validate=not args.no_validate)
 
     out = {
         "metric": "DP cells/sec (GCUPS) + aligned pairs/sec at oracle path match, 1 MI355X",
@@ -214,7 +234,6 @@ def run_batch(args):
     sequential single-pair calls. For the D = 128 workload the BF16-cost form is
     run too and its paths compared with the FP32 ones."""
     import torch
-    from concurrent.futures import ThreadPoolExecutor
     from paper_2607_15478_amd import synth
     from paper_2607_15478_amd import pardtw as pd
 
@@ -225,13 +244,6 @@ def run_batch(args):
     d = pairs[0][0].shape[1]
     feas = [(n - 1) <= 2 * (m - 1) and (m - 1) <= 2 * (n - 1) for n, m in zip(ns, ms)]
     cells = sum(n * m for n, m, f in zip(ns, ms, feas) if f)
-
-    val = {}
-    pool = None
-    if not args.no_validate:
-        import oracle
-        pool = ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1))
-        futs = [pool.submit(oracle.dtw_features, x, y) if f else None for (x, y), f in zip(pairs, feas)]
 
     Xp, Yp = pd.pack(pairs, dev)
     res = {}
@@ -286,39 +298,15 @@ def run_batch(args):
         for b in range(len(pairs)))
     del ws
 
-    validation = None
-    if pool is not None:
-        from tests import parity
-        import oracle
-        ok, ties, msg = True, 0, "ok"
-        devs = []
-        for b, fut in enumerate(futs):
-            x, y = pairs[b]
-            try:
-                if fut is None:
-                    assert r32["status"][b] == pd.PAIR_INFEASIBLE and len(r32["paths"][b]) == 0
-                    continue
-                J, BP = fut.result()
-                parity.check_legal(r32["paths"][b], ns[b], ms[b])
-                parity.check_total(float(r32["totals"][b]), J)
-                ties += parity.audit_path(r32["paths"][b], BP, lambda c: oracle.probe(c, X=x, Y=y)[0])
-                if pd.PREC_BF16 in res:
-                    p16 = res[pd.PREC_BF16]["paths"][b]
-                    mdev, xdev = parity.path_deviation(p16, r32["paths"][b], ns[b])
-                    devs.append((mdev, xdev, abs(float(res[pd.PREC_BF16]["totals"][b]) - J) / J,
-                                 (oracle.path_cost(x, y, p16) - J) / J))
-            except AssertionError as exc:
-                ok, msg = False, f"pair {b}: {str(exc)[:200]}"
-                break
-        pool.shutdown()
-        validation = {"path_match": ok, "declared_ties": ties, "detail": msg,
-                      "batch_equals_single_pair_calls": same_as_single}
-        if devs:
-            a = np.array(devs)
-            validation["bf16"] = {"mean_path_dev_frames": round(float(a[:, 0].mean()), 4),
-                                  "max_path_dev_frames": float(a[:, 1].max()),
-                                  "max_rel_cost_err": float(a[:, 2].max()),
-                                  "max_rescore_gap": float(a[:, 3].max())}
+    # ---- CPU baseline leg: the oracle on every pair, which also validates the GPU paths ----
+    cpu, validation = None, None
+    if not args.no_cpu:
+        bf16 = None
+        if pd.PREC_BF16 in res:
+            bf16 = (res[pd.PREC_BF16]["paths"], res[pd.PREC_BF16]["totals"])
+        cpu, validation = cpu_baseline_batch(pairs, r32["paths"], r32["totals"], r32["status"], bf16,
+                                             threads=min(8, os.cpu_count() or 1))
+        validation["batch_equals_single_pair_calls"] = same_as_single
 
     out = {
         "metric": "DP cells/sec (GCUPS) + aligned pairs/sec at oracle path match, 1 MI355X",
@@ -338,6 +326,7 @@ def run_batch(args):
                    "schedule": r32["sched"], "tuned_dp_ms": round(r32["tuned_dp_ms"], 4),
                    "sequential_single_pair_ms": round(ms_seq, 3),
                    "speedup_vs_sequential": round(ms_seq / r32["ms"], 2)},
+        "cpu_baseline": cpu,
         "validation": validation,
     }
     if pd.PREC_BF16 in res:
