@@ -50,6 +50,10 @@ struct DpShared {
     int cons[kMaxNW + 1];  // ring w: chunks released by its consumer
     // ring[w][slot][c][r] = D[8k + r][64p - 2 + c] for chunk k, slot = k % kRing
     float ring[kMaxNW + 1][kRing][2][kChunk];
+    // Lanes that have nothing to hand over write here instead, so the handoff
+    // stores run on the full wave without masking the execution mask.
+    f32x4 fsink[kMaxNW][kLanes][2];
+    int isink[kMaxNW][kLanes];
 };
 
 __device__ inline int lds_get(const int* p) {
@@ -223,7 +227,7 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
     for (int r = 0; r < kChunk; ++r) { lvA0[r] = kInf; lvA1[r] = kInf; lvB0[r] = kInf; lvB1[r] = kInf; }
     int prog_seen = 0, pv = 0;
     if (have_left) {
-        while ((prog_seen = lds_get(&sh.prog[wave][0])) <= 0) __builtin_amdgcn_s_sleep(1);
+        while ((prog_seen = lds_get(&sh.prog[wave][0])) <= 0) {}
         compiler_order();
         const f32x4* src = reinterpret_cast<const f32x4*>(rin);
         const f32x4 x0 = src[0], x1 = src[1], y0 = src[2], y1 = src[3];
@@ -253,10 +257,10 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
             float(&nxt1)[kChunk] = (u & 1) ? lvA1 : lvB1;
 
             if ((flags & 1) && k + 1 < G) {
-                while (prog_seen <= k + 1) {
-                    __builtin_amdgcn_s_sleep(1);
-                    prog_seen = lds_get(&sh.prog[wave][0]);
-                }
+                // Compute waves own their SIMD, so a consumer that caught up spins
+                // on the counter without sleeping: each late wake-up would be
+                // lost time it could never win back, adding up along the chain.
+                while (prog_seen <= k + 1) prog_seen = lds_get(&sh.prog[wave][0]);
                 compiler_order();
                 const f32x4* src = reinterpret_cast<const f32x4*>(rin + ((k + 1) % kRing) * 2 * kChunk);
                 const f32x4 x0 = src[0], x1 = src[1], y0 = src[2], y1 = src[3];
@@ -265,7 +269,7 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
                 nxt1[0] = y0[0]; nxt1[1] = y0[1]; nxt1[2] = y0[2]; nxt1[3] = y0[3];
                 nxt1[4] = y1[0]; nxt1[5] = y1[1]; nxt1[6] = y1[2]; nxt1[7] = y1[3];
                 compiler_order();
-                if (lane == 0) lds_put(&sh.cons[wave], k + 2);
+                lds_put(lane == 0 ? &sh.cons[wave] : &sh.isink[wave][lane], k + 2);
                 // read per lane from one of two identical copies, so the value
                 // stays in a vector register and is not waited for until the
                 // end of the chunk
@@ -305,17 +309,18 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
             if ((flags & 2) && inside) {
                 if (cons_seen < k + 1 - kRing) {
                     int v;
-                    while ((v = lds_get(&sh.cons[wave + 1])) < k + 1 - kRing) __builtin_amdgcn_s_sleep(1);
+                    while ((v = lds_get(&sh.cons[wave + 1])) < k + 1 - kRing) {}
                     cons_seen = v;
                 }
                 compiler_order();
-                if (bcol >= 0) {
-                    f32x4* dst = reinterpret_cast<f32x4*>(rout + (slot * 2 + bcol) * kChunk);
+                {
+                    f32x4* dst = bcol >= 0 ? reinterpret_cast<f32x4*>(rout + (slot * 2 + bcol) * kChunk)
+                                           : &sh.fsink[wave][lane][0];
                     dst[0] = f32x4{best_r[0], best_r[1], best_r[2], best_r[3]};
                     dst[1] = f32x4{best_r[4], best_r[5], best_r[6], best_r[7]};
                 }
                 compiler_order();
-                if (lane < 2) lds_put(&sh.prog[wave + 1][lane], k + 1);
+                lds_put(lane < 2 ? &sh.prog[wave + 1][lane] : &sh.isink[wave][lane], k + 1);
             }
             if (k == last) {
 #pragma unroll
