@@ -17,7 +17,7 @@ struct BatchPair {
     int64_t rec_off;       // first boundary record (uint64) of the pair
     int64_t path_off;      // first (i, j) entry of the pair's path
     int64_t G;             // 8-row groups
-    int64_t tile0;         // first cost tile of the pair in the batch numbering
+    int64_t tile0;         // first cost workgroup of the pair in the batch numbering
     int32_t P;             // column panels
     int32_t feasible;      // the step set can reach (n-1, m-1)
 };
@@ -27,6 +27,9 @@ struct DpItem {
     int32_t pair;
     int32_t group;
 };
+
+// Workgroups of the cost kernel for one (n, m) pair (panels x row-tile blocks).
+int64_t cost_blocks(int64_t n, int64_t m);
 
 pardtw_status cost_batch_launch(const BatchPair* pairs, const int32_t* tile_pair, int64_t tiles, const float* X,
                                 const float* Y, int64_t d, pardtw_prec prec, float* Cbase, hipStream_t stream);

@@ -161,7 +161,7 @@ extern "C" pardtw_status pardtw_plan_create(int32_t batch, const int64_t* n_host
             c_floats += cells;  // multiples of 512: keeps every pair 256-byte aligned
             bp_bytes += cells;
             rec_bytes += pardtw::dp_record_bytes(n, m);
-            tiles += int64_t(q.P) * pardtw::ceil_div(n, 64);
+            tiles += pardtw::cost_blocks(n, m);
         }
         const int64_t cap = std::min(n, m);
         xr += n;
@@ -178,12 +178,12 @@ extern "C" pardtw_status pardtw_plan_create(int32_t batch, const int64_t* n_host
     pl->off_dp = pl->off_bp + align_up(bp_bytes);
     pl->ws_bytes = pl->off_dp + align_up(pardtw::dp_header_bytes() + rec_bytes);
 
-    // tile -> pair table of the batched cost kernel
+    // cost block -> pair table of the batched cost kernel
     std::vector<int32_t> tile_pair(size_t(std::max<int64_t>(tiles, 1)));
     for (int b = 0; b < batch; ++b) {
         const pardtw::BatchPair& q = pl->pairs[b];
         if (!q.feasible) continue;
-        const int64_t t = int64_t(q.P) * pardtw::ceil_div(q.n, 64);
+        const int64_t t = pardtw::cost_blocks(q.n, q.m);
         std::fill(tile_pair.begin() + q.tile0, tile_pair.begin() + q.tile0 + t, b);
     }
 

@@ -2,17 +2,24 @@
 //
 //   C[i,j] = 1 - (<x_i, y_j> * rx_i) * ry_j,   rx_i = 1/|x_i| (0 for a zero frame)
 //
-// One workgroup computes a 64-row x 64-column tile, i.e. 64 rows of one column
-// panel. Each of its four waves owns 16 rows and issues 16x16 MFMA blocks over
-// the feature dimension: v_mfma_f32_16x16x4_f32 for FP32 operands,
-// v_mfma_f32_16x16x32_bf16 for BF16 operands (FP32 accumulate in both). The
-// inverse norms of the tile's 64 rows and 64 columns are computed in the same
-// workgroup into LDS. The tile is written either into the DP's panel layout
-// (one contiguous 16 KB block) or row-major.
+// A workgroup of four waves sweeps kTilesPerBlock tiles of 64 rows x 64
+// columns down one column panel; each wave owns 16 rows of a tile and issues
+// 16x16 MFMA blocks over the feature dimension: v_mfma_f32_16x16x4_f32 for
+// FP32 operands, v_mfma_f32_16x16x32_bf16 for BF16 operands (FP32 accumulate
+// in both).
 //
-// With D = 12 the kernel does 24 flop per 4-byte output, far below the MFMA
-// ridge point, so it is bound by HBM writes; the MFMA keeps the arithmetic off
-// the VALU so the stores stream at full rate.
+// Operands: the MFMA sums over all features, so how they are split between
+// the four 16-lane groups and the steps is free; each path picks the split its
+// loads like (see the tile functions). The squared operands summed over the
+// four groups (two cross-lane xors) give every lane the norm of its row and of
+// its columns, so the inverse norms come out of the operand registers with no
+// extra loads and no workgroup barrier. For d <= 16 (FP32) a workgroup keeps
+// its panel's column operands in registers for its whole sweep.
+//
+// The tile is written either into the DP's panel layout (rows 0-3 then 4-7 of
+// each 8-row group, 16 contiguous bytes per column: one 16-byte store per lane
+// per 16x16 block) or row-major. With D = 12 the kernel does 24 flop per
+// 4-byte output, far below the MFMA ridge point: it is bound by HBM writes.
 #include "batch.h"
 
 namespace pardtw {
@@ -23,90 +30,53 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kTileM = 64;
 constexpr int kThreads = 256;
+constexpr int kTilesPerBlock = 8;  // row tiles swept by one workgroup
 
-template <bool BF16>
-__device__ inline float operand(float v) {
-    if constexpr (BF16) return float(__bf16(v));
-    return v;
+__device__ inline float sum_groups(float v) {
+    // lanes l, l^16, l^32, l^48 hold the four quarters of one row / column
+    v += __shfl_xor(v, 16, 64);
+    return v + __shfl_xor(v, 32, 64);
 }
 
-template <bool BF16>
-__device__ inline float inv_norm(const float* row, int64_t d) {
-    float s = 0.0f;
-    for (int64_t k = 0; k < d; ++k) {
-        const float v = operand<BF16>(row[k]);
-        s = __builtin_fmaf(v, v, s);
-    }
-    return s > 0.0f ? 1.0f / __builtin_sqrtf(s) : 0.0f;
-}
+__device__ inline float inv_from_sq(float s) { return s > 0.0f ? 1.0f / __builtin_sqrtf(s) : 0.0f; }
 
-// One 64-row x 64-column tile: rows [i0, i0+64) of column panel p.
-template <bool BF16, bool PANEL>
-__device__ __attribute__((always_inline)) inline void cost_tile(const float* __restrict__ X,
-                                                                const float* __restrict__ Y, int64_t n, int64_t m,
-                                                                int64_t d, float* __restrict__ C, int64_t p,
-                                                                int64_t i0, float (&rx)[kTileM], float (&ry)[kPanel]) {
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int64_t j0 = p * kPanel;
-
-    if (tid < kTileM) {
-        const int64_t i = i0 + tid;
-        rx[tid] = i < n ? inv_norm<BF16>(X + i * d, d) : 0.0f;
-    } else if (tid < kTileM + kPanel) {
-        const int64_t j = j0 + (tid - kTileM);
-        ry[tid - kTileM] = j < m ? inv_norm<BF16>(Y + j * d, d) : 0.0f;
-    }
-
-    // MFMA operand coordinates: A row = lane%16, B column = lane%16, K group = lane/16
-    const int64_t arow = i0 + wave * 16 + (lane & 15);
-    const bool arow_ok = arow < n;
-    const int kg = lane >> 4;
-    f32x4 acc[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-
-    if constexpr (!BF16) {
-        for (int64_t k0 = 0; k0 < d; k0 += 4) {
-            const int64_t k = k0 + kg;
-            const float av = (arow_ok && k < d) ? X[arow * d + k] : 0.0f;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int64_t col = j0 + b * 16 + (lane & 15);
-                const float bv = (col < m && k < d) ? Y[col * d + k] : 0.0f;
-                acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[b], 0, 0, 0);
-            }
-        }
+// Eight consecutive features k0..k0+7 of one row (zeros past d), rounded to BF16.
+template <bool VEC>
+__device__ inline bf16x8 load8_bf16(const float* __restrict__ row, bool ok, int64_t k0, int64_t d, float& sq) {
+    float v[8];
+    if (VEC && ok && k0 + 8 <= d) {
+        const f32x4 a = *reinterpret_cast<const f32x4*>(row + k0);
+        const f32x4 b = *reinterpret_cast<const f32x4*>(row + k0 + 4);
+        v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
+        v[4] = b[0]; v[5] = b[1]; v[6] = b[2]; v[7] = b[3];
     } else {
-        for (int64_t k0 = 0; k0 < d; k0 += 32) {
-            bf16x8 av;
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int64_t k = k0 + kg * 8 + e;
-                av[e] = __bf16((arow_ok && k < d) ? X[arow * d + k] : 0.0f);
-            }
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int64_t col = j0 + b * 16 + (lane & 15);
-                bf16x8 bv;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const int64_t k = k0 + kg * 8 + e;
-                    bv[e] = __bf16((col < m && k < d) ? Y[col * d + k] : 0.0f);
-                }
-                acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[b], 0, 0, 0);
-            }
-        }
+        for (int e = 0; e < 8; ++e) v[e] = (ok && k0 + e < d) ? row[k0 + e] : 0.0f;
     }
-    __syncthreads();
+    bf16x8 out;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        out[e] = __bf16(v[e]);
+        const float r = float(out[e]);
+        sq = __builtin_fmaf(r, r, sq);
+    }
+    return out;
+}
 
-    // Output of a 16x16 block: lane holds column lane%16 of rows 4*(lane/16) + r,
-    // r = 0..3. In the panel layout those four rows of one column are 16
-    // contiguous bytes (a half-group), so each lane writes one 16-byte vector
-    // per block and the 16 lanes of a row quad cover 256 contiguous bytes.
-    const int tr0 = wave * 16 + 4 * (lane >> 4);  // first of the lane's 4 tile rows
-    const int64_t ib = i0 + tr0;
+// Epilogue of a 64-row x 64-column tile: acc[b] holds rows 4*(lane/16) + r of
+// column b*16 + lane%16 within the wave's 16 rows; rxl is the inverse norm of
+// row lane%16, ry[b] that of column b*16 + lane%16.
+template <bool PANEL>
+__device__ __attribute__((always_inline)) inline void store_tile(const f32x4 (&acc)[4], float rxl,
+                                                                 const float (&ry)[4], int64_t n, int64_t m,
+                                                                 float* __restrict__ C, int64_t p, int64_t i0) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int tr0 = 4 * (lane >> 4);  // first of the lane's 4 rows within the wave's 16
+    float rx[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rx[r] = __shfl(rxl, tr0 + r, 64);
+    const int64_t ib = i0 + wave * 16 + tr0;
     if constexpr (PANEL) {
         const int64_t G = bp_groups(n);
         if (ib / kBpRows < G) {
@@ -115,10 +85,9 @@ __device__ __attribute__((always_inline)) inline void cost_tile(const float* __r
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int cc = b * 16 + (lane & 15);
-                const float sy = ry[cc];
                 f32x4 v;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = 1.0f - (acc[b][r] * rx[tr0 + r]) * sy;
+                for (int r = 0; r < 4; ++r) v[r] = 1.0f - (acc[b][r] * rx[r]) * ry[b];
                 __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(dst + cc * 4));
             }
         }
@@ -127,68 +96,233 @@ __device__ __attribute__((always_inline)) inline void cost_tile(const float* __r
         for (int r = 0; r < 4; ++r) {
             const int64_t i = ib + r;
             if (i >= n) continue;
-            const float sx = rx[tr0 + r];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const int cc = b * 16 + (lane & 15);
-                const int64_t j = j0 + cc;
-                if (j < m) __builtin_nontemporal_store(1.0f - (acc[b][r] * sx) * ry[cc], C + i * m + j);
+                const int64_t j = p * kPanel + b * 16 + (lane & 15);
+                if (j < m) __builtin_nontemporal_store(1.0f - (acc[b][r] * rx[r]) * ry[b], C + i * m + j);
             }
         }
     }
 }
 
-template <bool BF16, bool PANEL>
-__global__ __launch_bounds__(kThreads) void cost_kernel(const float* __restrict__ X, const float* __restrict__ Y,
-                                                        int64_t n, int64_t m, int64_t d, float* __restrict__ C) {
-    __shared__ float rx[kTileM];
-    __shared__ float ry[kPanel];
-    cost_tile<BF16, PANEL>(X, Y, n, m, d, C, blockIdx.x, int64_t(blockIdx.y) * kTileM, rx, ry);
+// FP32, d <= 16: feature k = 4t + g (g = lane/16) at MFMA step t. The panel's
+// column operands and their inverse norms stay in registers for the whole
+// sweep of the workgroup; each tile loads only its rows.
+template <bool PANEL>
+__device__ __attribute__((always_inline)) inline void sweep_f32_small(const float* __restrict__ X,
+                                                                      const float* __restrict__ Y, int64_t n,
+                                                                      int64_t m, int64_t d, float* __restrict__ C,
+                                                                      int64_t p, int64_t t0, int tiles) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    float bv[4][4], ry[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int64_t col = p * kPanel + b * 16 + (lane & 15);
+        float sq = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t k = 4 * t + g;
+            bv[b][t] = (col < m && k < d) ? Y[col * d + k] : 0.0f;
+            sq = __builtin_fmaf(bv[b][t], bv[b][t], sq);
+        }
+        ry[b] = inv_from_sq(sum_groups(sq));
+    }
+    for (int u = 0; u < tiles; ++u) {
+        const int64_t i0 = (t0 + u) * kTileM;
+        if (i0 >= n) break;
+        const int64_t arow = i0 + wave * 16 + (lane & 15);
+        float av[4], sa = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t k = 4 * t + g;
+            av[t] = (arow < n && k < d) ? X[arow * d + k] : 0.0f;
+            sa = __builtin_fmaf(av[t], av[t], sa);
+        }
+        f32x4 acc[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            acc[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (4 * t < d) acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], bv[b][t], acc[b], 0, 0, 0);
+        }
+        store_tile<PANEL>(acc, inv_from_sq(sum_groups(sa)), ry, n, m, C, p, i0);
+    }
 }
 
-// Batched form: block t is tile t of the batch; tile_pair[t] names its pair,
-// whose tiles are numbered panel-major from pairs[b].tile0.
-template <bool BF16>
+// Any d. FP32: with VEC, lane group g takes the contiguous features
+// [g*L, g*L + L), L = ceil(d/16)*4, four per 16-byte load; otherwise feature
+// k = 4t + g at step t (neighbouring lanes read neighbouring features). BF16:
+// group g takes [g*L, g*L + L), L = ceil(d/32)*8, eight per step.
+template <bool BF16, bool PANEL, bool VEC>
+__device__ __attribute__((always_inline)) inline void cost_tile(const float* __restrict__ X,
+                                                                const float* __restrict__ Y, int64_t n, int64_t m,
+                                                                int64_t d, float* __restrict__ C, int64_t p,
+                                                                int64_t i0) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int64_t arow = i0 + wave * 16 + (lane & 15);
+    const bool arow_ok = arow < n;
+    const float* xrow = X + (arow_ok ? arow : 0) * d;
+    const float* yrow[4];
+    bool bok[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int64_t col = p * kPanel + b * 16 + (lane & 15);
+        bok[b] = col < m;
+        yrow[b] = Y + (bok[b] ? col : 0) * d;
+    }
+
+    f32x4 acc[4];
+    float sa = 0.0f, sb[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        acc[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        sb[b] = 0.0f;
+    }
+    if constexpr (!BF16 && VEC) {
+        const int64_t L = (d + 15) / 16 * 4;
+        for (int64_t t = 0; t < L; t += 4) {
+            const int64_t k0 = g * L + t;
+            f32x4 a = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            if (arow_ok && k0 < d) a = *reinterpret_cast<const f32x4*>(xrow + k0);  // d % 4 == 0: whole vector
+            f32x4 bb[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                bb[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                if (bok[b] && k0 < d) bb[b] = *reinterpret_cast<const f32x4*>(yrow[b] + k0);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                sa = __builtin_fmaf(a[e], a[e], sa);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    sb[b] = __builtin_fmaf(bb[b][e], bb[b][e], sb[b]);
+                    acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], bb[b][e], acc[b], 0, 0, 0);
+                }
+            }
+        }
+    } else if constexpr (!BF16) {
+        const int64_t T = (d + 3) / 4;
+        for (int64_t t = 0; t < T; ++t) {
+            const int64_t k = 4 * t + g;
+            const float av = (arow_ok && k < d) ? xrow[k] : 0.0f;
+            sa = __builtin_fmaf(av, av, sa);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const float bv = (bok[b] && k < d) ? yrow[b][k] : 0.0f;
+                sb[b] = __builtin_fmaf(bv, bv, sb[b]);
+                acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc[b], 0, 0, 0);
+            }
+        }
+    } else {
+        const int64_t L = (d + 31) / 32 * 8;
+        for (int64_t t = 0; t < L; t += 8) {
+            const int64_t k0 = g * L + t;
+            const bf16x8 av = load8_bf16<VEC>(xrow, arow_ok, k0, d, sa);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const bf16x8 bv = load8_bf16<VEC>(yrow[b], bok[b], k0, d, sb[b]);
+                acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[b], 0, 0, 0);
+            }
+        }
+    }
+    float ry[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) ry[b] = inv_from_sq(sum_groups(sb[b]));
+    store_tile<PANEL>(acc, inv_from_sq(sum_groups(sa)), ry, n, m, C, p, i0);
+}
+
+// A workgroup's sweep: tiles t0 .. t0 + kTilesPerBlock - 1 of panel p.
+template <bool BF16, bool PANEL, bool VEC>
+__device__ __attribute__((always_inline)) inline void sweep(const float* __restrict__ X,
+                                                            const float* __restrict__ Y, int64_t n, int64_t m,
+                                                            int64_t d, float* __restrict__ C, int64_t p, int64_t t0) {
+    if (!BF16 && d <= 16) {
+        sweep_f32_small<PANEL>(X, Y, n, m, d, C, p, t0, kTilesPerBlock);
+        return;
+    }
+    for (int u = 0; u < kTilesPerBlock; ++u) {
+        const int64_t i0 = (t0 + u) * kTileM;
+        if (i0 >= n) break;
+        cost_tile<BF16, PANEL, VEC>(X, Y, n, m, d, C, p, i0);
+    }
+}
+
+template <bool BF16, bool PANEL, bool VEC>
+__global__ __launch_bounds__(kThreads) void cost_kernel(const float* __restrict__ X, const float* __restrict__ Y,
+                                                        int64_t n, int64_t m, int64_t d, float* __restrict__ C) {
+    sweep<BF16, PANEL, VEC>(X, Y, n, m, d, C, blockIdx.x, int64_t(blockIdx.y) * kTilesPerBlock);
+}
+
+// Batched form: block t is block t of the batch's numbering; tile_pair[t]
+// names its pair, whose blocks are numbered panel-major from pairs[b].tile0.
+template <bool BF16, bool VEC>
 __global__ __launch_bounds__(kThreads) void cost_batch_kernel(const BatchPair* __restrict__ pairs,
                                                               const int32_t* __restrict__ tile_pair,
                                                               const float* __restrict__ X,
                                                               const float* __restrict__ Y, int64_t d,
                                                               float* __restrict__ Cbase) {
-    __shared__ float rx[kTileM];
-    __shared__ float ry[kPanel];
     const int64_t t = blockIdx.x;
     const BatchPair q = pairs[tile_pair[t]];
     const int64_t local = t - q.tile0;
-    const int64_t tiles_m = ceil_div(q.n, kTileM);
-    cost_tile<BF16, true>(X + q.x_off * d, Y + q.y_off * d, q.n, q.m, d, Cbase + q.c_off, local / tiles_m,
-                          (local % tiles_m) * kTileM, rx, ry);
+    const int64_t rows_blk = ceil_div(ceil_div(q.n, kTileM), kTilesPerBlock);
+    const int64_t p = local / rows_blk;
+    const int64_t t0 = (local % rows_blk) * kTilesPerBlock;
+    sweep<BF16, true, VEC>(X + q.x_off * d, Y + q.y_off * d, q.n, q.m, d, Cbase + q.c_off, p, t0);
+}
+
+bool vec_ok(const float* X, const float* Y, int64_t d) {
+    return d % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0 && reinterpret_cast<uintptr_t>(Y) % 16 == 0;
 }
 
 }  // namespace
+
+int64_t cost_blocks(int64_t n, int64_t m) {
+    return num_panels(m) * ceil_div(ceil_div(n, kTileM), kTilesPerBlock);
+}
 
 pardtw_status cost_batch_launch(const BatchPair* pairs, const int32_t* tile_pair, int64_t tiles, const float* X,
                                 const float* Y, int64_t d, pardtw_prec prec, float* Cbase, hipStream_t stream) {
     if (tiles <= 0) return PARDTW_OK;
     if (tiles > 0x7fffffff) return PARDTW_ERR_UNSUPPORTED;
-    if (prec == PARDTW_PREC_F32)
-        cost_batch_kernel<false><<<unsigned(tiles), kThreads, 0, stream>>>(pairs, tile_pair, X, Y, d, Cbase);
-    else
-        cost_batch_kernel<true><<<unsigned(tiles), kThreads, 0, stream>>>(pairs, tile_pair, X, Y, d, Cbase);
+    // packed pairs start at row offsets that keep 16-byte alignment when d % 4 == 0
+    const bool vec = vec_ok(X, Y, d);
+    const unsigned grid = unsigned(tiles);
+    if (prec == PARDTW_PREC_F32 && vec && d % 16 == 0) {
+        cost_batch_kernel<false, true><<<grid, kThreads, 0, stream>>>(pairs, tile_pair, X, Y, d, Cbase);
+    } else if (prec == PARDTW_PREC_F32) {
+        cost_batch_kernel<false, false><<<grid, kThreads, 0, stream>>>(pairs, tile_pair, X, Y, d, Cbase);
+    } else if (vec) {
+        cost_batch_kernel<true, true><<<grid, kThreads, 0, stream>>>(pairs, tile_pair, X, Y, d, Cbase);
+    } else {
+        cost_batch_kernel<true, false><<<grid, kThreads, 0, stream>>>(pairs, tile_pair, X, Y, d, Cbase);
+    }
     return launch_status();
 }
 
 pardtw_status cost_launch(const float* X, const float* Y, int64_t n, int64_t m, int64_t d, pardtw_prec prec,
                           pardtw_layout layout, float* C, hipStream_t stream) {
-    const int64_t tiles_m = ceil_div(n, kTileM);
-    if (tiles_m > 65535) return PARDTW_ERR_UNSUPPORTED;
-    dim3 grid(unsigned(num_panels(m)), unsigned(tiles_m));
+    const int64_t rows_blk = ceil_div(ceil_div(n, kTileM), kTilesPerBlock);
+    if (rows_blk > 65535 || num_panels(m) > 0x7fffffff) return PARDTW_ERR_UNSUPPORTED;
+    dim3 grid(unsigned(num_panels(m)), unsigned(rows_blk));
     const bool panel = layout == PARDTW_LAYOUT_PANEL;
-    if (prec == PARDTW_PREC_F32) {
-        if (panel) cost_kernel<false, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
-        else cost_kernel<false, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
+    const bool vec = vec_ok(X, Y, d);
+    if (prec == PARDTW_PREC_F32 && vec && d % 16 == 0) {
+        if (panel) cost_kernel<false, true, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
+        else cost_kernel<false, false, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
+    } else if (prec == PARDTW_PREC_F32) {
+        if (panel) cost_kernel<false, true, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
+        else cost_kernel<false, false, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
+    } else if (vec) {
+        if (panel) cost_kernel<true, true, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
+        else cost_kernel<true, false, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
     } else {
-        if (panel) cost_kernel<true, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
-        else cost_kernel<true, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
+        if (panel) cost_kernel<true, true, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
+        else cost_kernel<true, false, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
     }
     return launch_status();
 }
