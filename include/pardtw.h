@@ -64,7 +64,15 @@ typedef enum {
      *   p = j/64, G = ceil(N/8), P = ceil(M/64) panels, P*G*512 floats.
      * Columns past M and rows past N are padding. A wavefront of the DP reads
      * one 8-row chunk of its panel with two 1 KB contiguous loads. */
-    PARDTW_LAYOUT_PANEL = 1
+    PARDTW_LAYOUT_PANEL = 1,
+    /* The panel layout with only the 8-row groups that pardtw_dp reads: a
+     * group of panel p is written when it holds a cell reachable from (0,0)
+     * with the step set (j <= 2i and i <= 2j, Sec. V), i.e. for
+     *   max(0, ceil((64p - 14)/16)) <= i/8 <= floor((64p + 63)/4).
+     * Other groups are left untouched (about half of a 5:6 pair). Same size
+     * and element placement as PARDTW_LAYOUT_PANEL; pardtw_dp treats the two
+     * alike. */
+    PARDTW_LAYOUT_PANEL_REACHABLE = 2
 } pardtw_layout;
 
 #define PARDTW_PAIR_OK 0
@@ -90,7 +98,7 @@ size_t pardtw_dp_workspace_bytes(int64_t n, int64_t m);
  *   X [device, n*d FP32], Y [device, m*d FP32]: row-major features.
  *   prec: PARDTW_PREC_F32 or PARDTW_PREC_BF16 (BF16 operands, FP32 accumulate;
  *         the norms are taken from the same BF16-rounded values).
- *   layout: PARDTW_LAYOUT_ROW or PARDTW_LAYOUT_PANEL.
+ *   layout: PARDTW_LAYOUT_ROW, PARDTW_LAYOUT_PANEL or PARDTW_LAYOUT_PANEL_REACHABLE.
  *   C [device, pardtw_cost_elems(n,m,layout) floats]: overwritten. A frame of
  *   zero norm is treated as the zero vector, so its cost is 1. */
 pardtw_status pardtw_cost(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,

@@ -28,6 +28,17 @@ inline bool valid_sizes(int64_t n, int64_t m) {
            n <= (int64_t(1) << 62) / m;
 }
 
+// Cells reachable from (0,0) by the steps (1,1), (1,2), (2,1) are exactly those
+// with j <= 2i and i <= 2j. For column panel p (columns 64p .. 64p+63), the
+// 8-row groups that hold at least one such cell are reach_group_lo(p) ..
+// reach_group_hi(p) (not clamped to the number of groups): group k is reached
+// when 64p <= 2(8k+7) and 8k <= 2(64p+63).
+__host__ __device__ inline int64_t reach_group_lo(int64_t p) {
+    const int64_t jlo = p * kPanel;
+    return jlo <= 14 ? 0 : (jlo - 14 + 15) / 16;
+}
+__host__ __device__ inline int64_t reach_group_hi(int64_t p) { return (p * kPanel + kPanel - 1) / 4; }
+
 inline bool pair_feasible(int64_t n, int64_t m) {
     return (m - 1) <= 2 * (n - 1) && (n - 1) <= 2 * (m - 1);
 }

@@ -18,7 +18,10 @@
 //
 // The tile is written either into the DP's panel layout (rows 0-3 then 4-7 of
 // each 8-row group, 16 contiguous bytes per column: one 16-byte store per lane
-// per 16x16 block) or row-major. With D = 12 the kernel does 24 flop per
+// per 16x16 block) or row-major. For the DP's own use the panel layout can skip
+// every 8-row group of a panel that holds no cell reachable from (0,0) under
+// the step set (the DP never reads those groups): about half of the matrix for
+// a 5:6 pair. With D = 12 the kernel does 24 flop per
 // 4-byte output, far below the MFMA ridge point: it is bound by HBM writes.
 #include "batch.h"
 
@@ -66,10 +69,28 @@ __device__ inline bf16x8 load8_bf16(const float* __restrict__ row, bool ok, int6
 // Epilogue of a 64-row x 64-column tile: acc[b] holds rows 4*(lane/16) + r of
 // column b*16 + lane%16 within the wave's 16 rows; rxl is the inverse norm of
 // row lane%16, ry[b] that of column b*16 + lane%16.
+// Groups of panel p outside [glo, ghi] are not written.
+struct GroupSpan {
+    int64_t lo, hi;
+};
+
+__device__ inline GroupSpan group_span(bool reach, int64_t p) {
+    GroupSpan s;
+    s.lo = reach ? reach_group_lo(p) : 0;
+    s.hi = reach ? reach_group_hi(p) : (int64_t(1) << 62);
+    return s;
+}
+
+// Whether rows [i0, i0 + rows) touch a written group.
+__device__ inline bool rows_written(const GroupSpan& s, int64_t i0, int64_t rows) {
+    return i0 / kBpRows <= s.hi && (i0 + rows - 1) / kBpRows >= s.lo;
+}
+
 template <bool PANEL>
 __device__ __attribute__((always_inline)) inline void store_tile(const f32x4 (&acc)[4], float rxl,
                                                                  const float (&ry)[4], int64_t n, int64_t m,
-                                                                 float* __restrict__ C, int64_t p, int64_t i0) {
+                                                                 float* __restrict__ C, int64_t p, int64_t i0,
+                                                                 const GroupSpan& span) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int tr0 = 4 * (lane >> 4);  // first of the lane's 4 rows within the wave's 16
@@ -79,7 +100,8 @@ __device__ __attribute__((always_inline)) inline void store_tile(const f32x4 (&a
     const int64_t ib = i0 + wave * 16 + tr0;
     if constexpr (PANEL) {
         const int64_t G = bp_groups(n);
-        if (ib / kBpRows < G) {
+        const int64_t grp = ib / kBpRows;
+        if (grp < G && grp >= span.lo && grp <= span.hi) {
             const int64_t half = (p * G + ib / kBpRows) * 2 + (ib % kBpRows) / 4;
             float* dst = C + half * (kPanel * 4);
 #pragma unroll
@@ -112,7 +134,8 @@ template <bool PANEL>
 __device__ __attribute__((always_inline)) inline void sweep_f32_small(const float* __restrict__ X,
                                                                       const float* __restrict__ Y, int64_t n,
                                                                       int64_t m, int64_t d, float* __restrict__ C,
-                                                                      int64_t p, int64_t t0, int tiles) {
+                                                                      int64_t p, int64_t t0, int tiles,
+                                                                      const GroupSpan& span) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 4;
@@ -132,6 +155,7 @@ __device__ __attribute__((always_inline)) inline void sweep_f32_small(const floa
     for (int u = 0; u < tiles; ++u) {
         const int64_t i0 = (t0 + u) * kTileM;
         if (i0 >= n) break;
+        if (!rows_written(span, i0, kTileM)) continue;
         const int64_t arow = i0 + wave * 16 + (lane & 15);
         float av[4], sa = 0.0f;
 #pragma unroll
@@ -148,7 +172,7 @@ __device__ __attribute__((always_inline)) inline void sweep_f32_small(const floa
             for (int t = 0; t < 4; ++t)
                 if (4 * t < d) acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], bv[b][t], acc[b], 0, 0, 0);
         }
-        store_tile<PANEL>(acc, inv_from_sq(sum_groups(sa)), ry, n, m, C, p, i0);
+        store_tile<PANEL>(acc, inv_from_sq(sum_groups(sa)), ry, n, m, C, p, i0, span);
     }
 }
 
@@ -160,7 +184,7 @@ template <bool BF16, bool PANEL, bool VEC>
 __device__ __attribute__((always_inline)) inline void cost_tile(const float* __restrict__ X,
                                                                 const float* __restrict__ Y, int64_t n, int64_t m,
                                                                 int64_t d, float* __restrict__ C, int64_t p,
-                                                                int64_t i0) {
+                                                                int64_t i0, const GroupSpan& span) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 4;
@@ -233,29 +257,35 @@ __device__ __attribute__((always_inline)) inline void cost_tile(const float* __r
     float ry[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) ry[b] = inv_from_sq(sum_groups(sb[b]));
-    store_tile<PANEL>(acc, inv_from_sq(sum_groups(sa)), ry, n, m, C, p, i0);
+    store_tile<PANEL>(acc, inv_from_sq(sum_groups(sa)), ry, n, m, C, p, i0, span);
 }
 
-// A workgroup's sweep: tiles t0 .. t0 + kTilesPerBlock - 1 of panel p.
+// A workgroup's sweep: tiles t0 .. t0 + kTilesPerBlock - 1 of panel p. With
+// `reach` (panel layout only) groups without a reachable cell are skipped.
 template <bool BF16, bool PANEL, bool VEC>
 __device__ __attribute__((always_inline)) inline void sweep(const float* __restrict__ X,
                                                             const float* __restrict__ Y, int64_t n, int64_t m,
-                                                            int64_t d, float* __restrict__ C, int64_t p, int64_t t0) {
+                                                            int64_t d, float* __restrict__ C, int64_t p, int64_t t0,
+                                                            bool reach) {
+    const GroupSpan span = group_span(PANEL && reach, p);
+    if (!rows_written(span, t0 * kTileM, int64_t(kTilesPerBlock) * kTileM)) return;
     if (!BF16 && d <= 16) {
-        sweep_f32_small<PANEL>(X, Y, n, m, d, C, p, t0, kTilesPerBlock);
+        sweep_f32_small<PANEL>(X, Y, n, m, d, C, p, t0, kTilesPerBlock, span);
         return;
     }
     for (int u = 0; u < kTilesPerBlock; ++u) {
         const int64_t i0 = (t0 + u) * kTileM;
         if (i0 >= n) break;
-        cost_tile<BF16, PANEL, VEC>(X, Y, n, m, d, C, p, i0);
+        if (!rows_written(span, i0, kTileM)) continue;
+        cost_tile<BF16, PANEL, VEC>(X, Y, n, m, d, C, p, i0, span);
     }
 }
 
 template <bool BF16, bool PANEL, bool VEC>
 __global__ __launch_bounds__(kThreads) void cost_kernel(const float* __restrict__ X, const float* __restrict__ Y,
-                                                        int64_t n, int64_t m, int64_t d, float* __restrict__ C) {
-    sweep<BF16, PANEL, VEC>(X, Y, n, m, d, C, blockIdx.x, int64_t(blockIdx.y) * kTilesPerBlock);
+                                                        int64_t n, int64_t m, int64_t d, float* __restrict__ C,
+                                                        bool reach) {
+    sweep<BF16, PANEL, VEC>(X, Y, n, m, d, C, blockIdx.x, int64_t(blockIdx.y) * kTilesPerBlock, reach);
 }
 
 // Batched form: block t is block t of the batch's numbering; tile_pair[t]
@@ -272,7 +302,7 @@ __global__ __launch_bounds__(kThreads) void cost_batch_kernel(const BatchPair* _
     const int64_t rows_blk = ceil_div(ceil_div(q.n, kTileM), kTilesPerBlock);
     const int64_t p = local / rows_blk;
     const int64_t t0 = (local % rows_blk) * kTilesPerBlock;
-    sweep<BF16, true, VEC>(X + q.x_off * d, Y + q.y_off * d, q.n, q.m, d, Cbase + q.c_off, p, t0);
+    sweep<BF16, true, VEC>(X + q.x_off * d, Y + q.y_off * d, q.n, q.m, d, Cbase + q.c_off, p, t0, true);
 }
 
 bool vec_ok(const float* X, const float* Y, int64_t d) {
@@ -309,20 +339,21 @@ pardtw_status cost_launch(const float* X, const float* Y, int64_t n, int64_t m, 
     const int64_t rows_blk = ceil_div(ceil_div(n, kTileM), kTilesPerBlock);
     if (rows_blk > 65535 || num_panels(m) > 0x7fffffff) return PARDTW_ERR_UNSUPPORTED;
     dim3 grid(unsigned(num_panels(m)), unsigned(rows_blk));
-    const bool panel = layout == PARDTW_LAYOUT_PANEL;
+    const bool panel = layout != PARDTW_LAYOUT_ROW;
+    const bool reach = layout == PARDTW_LAYOUT_PANEL_REACHABLE;
     const bool vec = vec_ok(X, Y, d);
     if (prec == PARDTW_PREC_F32 && vec && d % 16 == 0) {
-        if (panel) cost_kernel<false, true, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
-        else cost_kernel<false, false, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
+        if (panel) cost_kernel<false, true, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, reach);
+        else cost_kernel<false, false, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, reach);
     } else if (prec == PARDTW_PREC_F32) {
-        if (panel) cost_kernel<false, true, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
-        else cost_kernel<false, false, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
+        if (panel) cost_kernel<false, true, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, reach);
+        else cost_kernel<false, false, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, reach);
     } else if (vec) {
-        if (panel) cost_kernel<true, true, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
-        else cost_kernel<true, false, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
+        if (panel) cost_kernel<true, true, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, reach);
+        else cost_kernel<true, false, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, reach);
     } else {
-        if (panel) cost_kernel<true, true, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
-        else cost_kernel<true, false, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C);
+        if (panel) cost_kernel<true, true, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, reach);
+        else cost_kernel<true, false, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, reach);
     }
     return launch_status();
 }
@@ -332,7 +363,7 @@ pardtw_status cost_launch(const float* X, const float* Y, int64_t n, int64_t m, 
 extern "C" size_t pardtw_cost_elems(int64_t n, int64_t m, pardtw_layout layout) {
     if (!pardtw::valid_sizes(n, m)) return 0;
     if (layout == PARDTW_LAYOUT_ROW) return size_t(n) * size_t(m);
-    if (layout == PARDTW_LAYOUT_PANEL)
+    if (layout == PARDTW_LAYOUT_PANEL || layout == PARDTW_LAYOUT_PANEL_REACHABLE)
         return size_t(pardtw::num_panels(m)) * size_t(pardtw::bp_groups(n)) * pardtw::kPanel * pardtw::kBpRows;
     return 0;
 }
@@ -342,6 +373,7 @@ extern "C" pardtw_status pardtw_cost(const float* X, const float* Y, int64_t n, 
     if (!X || !Y || !C || !pardtw::valid_sizes(n, m) || d <= 0 || d > (int64_t(1) << 20))
         return PARDTW_ERR_INVALID_ARG;
     if (prec != PARDTW_PREC_F32 && prec != PARDTW_PREC_BF16) return PARDTW_ERR_UNSUPPORTED;
-    if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL) return PARDTW_ERR_UNSUPPORTED;
+    if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL && layout != PARDTW_LAYOUT_PANEL_REACHABLE)
+        return PARDTW_ERR_UNSUPPORTED;
     return pardtw::cost_launch(X, Y, n, m, d, prec, layout, C, stream);
 }

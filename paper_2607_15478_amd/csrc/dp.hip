@@ -131,8 +131,8 @@ struct ChunkRanges {
 __device__ inline ChunkRanges chunk_ranges(int p, int64_t G) {
     const int64_t jlo = int64_t(p) * kPanel, jhi = jlo + kPanel - 1;
     ChunkRanges r;
-    const int64_t lo = jlo <= 14 ? 0 : (jlo - 14 + 15) / 16;  // first k with 16k + 14 >= jlo
-    const int64_t hi = jhi / 4;                                // last k with 8k <= 2 jhi
+    const int64_t lo = reach_group_lo(p);  // first k with 16k + 14 >= jlo
+    const int64_t hi = reach_group_hi(p);  // last k with 8k <= 2 jhi
     const int64_t flo = (jhi + 15) / 16;                       // first k with 16k >= jhi
     const int64_t fhi = (2 * jlo - 7) < 0 ? -1 : (2 * jlo - 7) / 8;  // last k with 8k + 7 <= 2 jlo
     auto clampk = [&](int64_t v) { return int(v < -1 ? -1 : (v > G ? G : v)); };
@@ -590,7 +590,8 @@ pardtw_status dp_launch(const float* C, pardtw_layout layout, int64_t n, int64_t
     // about four compute waves per CU (one per SIMD)
     const int per_cu = nw >= 4 ? 1 : 4 / nw;
     const int grid = a.S < cus * per_cu ? a.S : cus * per_cu;
-    const bool panel = layout == PARDTW_LAYOUT_PANEL;
+    // the DP reads only groups with a reachable cell, so both panel layouts are the same to it
+    const bool panel = layout != PARDTW_LAYOUT_ROW;
     dp_prepare<<<1, 1, 0, stream>>>(a.hdr);
     switch (nw) {
         case 1: launch_nw<1>(a, panel, grid, stream); break;
@@ -618,7 +619,8 @@ extern "C" pardtw_status pardtw_dp(const float* C, pardtw_layout layout, int64_t
                                    float* total, int32_t* pair_status, void* workspace,
                                    size_t workspace_bytes, hipStream_t stream) {
     if (!C || !bp || !total || !pair_status || !pardtw::valid_sizes(n, m)) return PARDTW_ERR_INVALID_ARG;
-    if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL) return PARDTW_ERR_UNSUPPORTED;
+    if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL && layout != PARDTW_LAYOUT_PANEL_REACHABLE)
+        return PARDTW_ERR_UNSUPPORTED;
     if (!workspace || workspace_bytes < pardtw::dp_workspace_bytes_impl(n, m)) return PARDTW_ERR_WORKSPACE;
     return pardtw::dp_launch(C, layout, n, m, bp, total, pair_status, workspace, 0, stream);
 }
@@ -627,7 +629,8 @@ extern "C" pardtw_status pardtw_dp_ex(const float* C, pardtw_layout layout, int6
                                       float* total, int32_t* pair_status, void* workspace, size_t workspace_bytes,
                                       int32_t panels_per_workgroup, hipStream_t stream) {
     if (!C || !bp || !total || !pair_status || !pardtw::valid_sizes(n, m)) return PARDTW_ERR_INVALID_ARG;
-    if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL) return PARDTW_ERR_UNSUPPORTED;
+    if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL && layout != PARDTW_LAYOUT_PANEL_REACHABLE)
+        return PARDTW_ERR_UNSUPPORTED;
     if (panels_per_workgroup != 0 && panels_per_workgroup != 1 && panels_per_workgroup != 2 &&
         panels_per_workgroup != 4 && panels_per_workgroup != 8)
         return PARDTW_ERR_INVALID_ARG;

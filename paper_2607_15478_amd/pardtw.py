@@ -23,6 +23,7 @@ PREC_F32 = 0
 PREC_BF16 = 1
 LAYOUT_ROW = 0
 LAYOUT_PANEL = 1
+LAYOUT_PANEL_REACHABLE = 2  # panel layout, only the 8-row groups the DP reads are written
 
 STATUS_NAMES = {0: "OK", 1: "ERR_INVALID_ARG", 2: "ERR_WORKSPACE", 3: "ERR_HIP", 4: "ERR_UNSUPPORTED"}
 
@@ -163,7 +164,7 @@ def pardtw_path_grad(X, Y, path, path_len, g_total, dX, dY, stream=None):
 class Workspace:
     """Device buffers for one (n, m) alignment, reusable across calls."""
 
-    def __init__(self, n: int, m: int, device="cuda", layout: int = LAYOUT_PANEL):
+    def __init__(self, n: int, m: int, device="cuda", layout: int = LAYOUT_PANEL_REACHABLE):
         self.n, self.m, self.layout = n, m, layout
         self.C = torch.empty(pardtw_cost_elems(n, m, layout), dtype=torch.float32, device=device)
         self.bp = torch.empty(pardtw_bp_bytes(n, m), dtype=torch.uint8, device=device)
@@ -183,7 +184,7 @@ def align_into(X: torch.Tensor, Y: torch.Tensor, w: Workspace, prec: int = PREC_
     return w
 
 
-def align(X: torch.Tensor, Y: torch.Tensor, prec: int = PREC_F32, layout: int = LAYOUT_PANEL):
+def align(X: torch.Tensor, Y: torch.Tensor, prec: int = PREC_F32, layout: int = LAYOUT_PANEL_REACHABLE):
     """Exact DTW of two feature sequences on the GPU: (total, path (L,2) int32, status)."""
     w = Workspace(X.shape[0], Y.shape[0], X.device, layout)
     align_into(X, Y, w, prec)

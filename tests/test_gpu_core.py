@@ -130,6 +130,62 @@ def test_cost_bf16_against_oracle_on_rounded_inputs(n, m, d):
     assert np.max(np.abs(got - ref)) < 1e-5 * max(1.0, np.sqrt(d / 12))
 
 
+def _reached_groups(n, m):
+    """(P, G) bool: 8-row group k of panel p holds a cell (i, j), i in
+    [8k, 8k+8), j in [64p, 64p+64), reachable from (0,0) by the three steps,
+    i.e. with j <= 2i and i <= 2j (enumerated cell by cell)."""
+    P, G = -(-m // 64), -(-n // 8)
+    i = np.arange(G * 8)[:, None]
+    j = np.arange(P * 64)[None, :]
+    ok = (j <= 2 * i) & (i <= 2 * j)
+    return ok.reshape(G, 8, P, 64).any(axis=(1, 3)).T
+
+
+@pytest.mark.parametrize("n,m,d,prec", [(1, 1, 12, pd.PREC_F32), (333, 257, 12, pd.PREC_F32),
+                                        (700, 900, 12, pd.PREC_F32), (900, 700, 12, pd.PREC_F32),
+                                        (1000, 130, 64, pd.PREC_F32), (600, 650, 33, pd.PREC_F32),
+                                        (520, 700, 40, pd.PREC_BF16), (2000, 2400, 12, pd.PREC_F32)])
+def test_cost_reachable_layout_writes_exactly_the_reached_groups(n, m, d, prec):
+    rng = np.random.default_rng(n * 7 + m + d)
+    X = rng.normal(size=(n, d)).astype(np.float32)
+    Y = rng.normal(size=(m, d)).astype(np.float32)
+    Xd, Yd = torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV)
+    full = torch.empty(pd.pardtw_cost_elems(n, m, pd.LAYOUT_PANEL), dtype=torch.float32, device=DEV)
+    pd.pardtw_cost(Xd, Yd, full, prec, pd.LAYOUT_PANEL)
+    part = torch.full((pd.pardtw_cost_elems(n, m, pd.LAYOUT_PANEL_REACHABLE),), float("nan"), device=DEV)
+    pd.pardtw_cost(Xd, Yd, part, prec, pd.LAYOUT_PANEL_REACHABLE)
+    P, G = -(-m // 64), -(-n // 8)
+    f = full.cpu().numpy().reshape(P, G, 512)
+    g = part.cpu().numpy().reshape(P, G, 512)
+    reached = _reached_groups(n, m)
+    assert np.array_equal(f[reached], g[reached])          # written groups: the panel layout bit for bit
+    assert np.all(np.isnan(g[~reached]))                    # the others untouched
+
+
+@pytest.mark.parametrize("n,m", [(64, 65), (333, 400), (520, 700), (700, 520), (1500, 1300)])
+def test_dp_on_reachable_layout_matches_full_layout(n, m):
+    rng = np.random.default_rng(n + 3 * m)
+    X = rng.normal(size=(n, 12)).astype(np.float32)
+    Y = rng.normal(size=(m, 12)).astype(np.float32)
+    Xd, Yd = torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV)
+    outs = []
+    for layout in (pd.LAYOUT_PANEL, pd.LAYOUT_PANEL_REACHABLE):
+        w = pd.Workspace(n, m, DEV, layout)
+        w.C.fill_(float("nan"))  # a read of an unwritten group would poison the result
+        pd.align_into(Xd, Yd, w)
+        torch.cuda.synchronize()
+        L = int(w.path_len.item())
+        outs.append((float(w.total.item()), int(w.status.item()), w.bp.cpu().numpy(), w.path[:L].cpu().numpy()))
+    a, b = outs
+    assert a[0] == b[0] and a[1] == b[1]
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
+    assert np.isfinite(a[0]) == pd_feasible(n, m)
+
+
+def pd_feasible(n, m):
+    return (m - 1) <= 2 * (n - 1) and (n - 1) <= 2 * (m - 1)
+
+
 def _align(X, Y, prec=pd.PREC_F32):
     Xd, Yd = torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV)
     total, path, status = pd.align(Xd, Yd, prec)
