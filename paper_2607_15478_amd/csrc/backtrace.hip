@@ -15,12 +15,16 @@
 // * Walker (wave 0). From the current cell (i, j), lane b holds column j - b
 //   and the codes of rows i-31..i in two registers (row i - a in bits
 //   30-2a..31-2a of the first for a < 16, of the second as a - 16 otherwise),
-//   read with five 16-bit LDS loads. The steps that stay in those 32 rows are
-//   resolved with scalar reads of the registers (v_readlane) and scalar
-//   arithmetic; within 32 rows a path moves at most 62 columns, so the row
-//   limit is the only exit test. The cells it passes are written by the lanes
-//   in parallel: lane t finds its offset from the start cell by counting the
-//   double steps among the first t steps (popcount).
+//   read with five 16-bit LDS loads. Every step moves at least one column, so
+//   a column holds at most one cell of the path, and within 32 rows a path
+//   moves at most 62 columns: it leaves the window through the last row. Each
+//   lane turns its codes into row masks (rows whose step goes to the next
+//   column on the next row, to the next column two rows down, or two columns
+//   over on the next row) and the path is traced as a one-cell frontier moved
+//   by shifts of those masks and two lane shifts (DPP) per step, all lanes at
+//   once. The lane holding a path cell writes it; its index along the path is
+//   the number of lower lanes holding one. Near the first row or column a
+//   scalar loop checks every step for the origin instead.
 // * The path is written from the back of the output (the walk runs backward)
 //   and shifted to the front by the whole workgroup at the end.
 #include "batch.h"
@@ -79,18 +83,55 @@ __device__ inline uint32_t compact8(uint32_t lo, uint32_t hi) {
     return x | (y << 8);
 }
 
-// Steps through one 16-row half of the window: packed holds row a0 + a' of
-// the window in bits 30-2a'; off = 30 - 2a' on entry. Returns when the path
-// leaves the half (off < 0). codes receives each step's code at bits 2k.
-__device__ inline void resolve_fast(uint32_t packed, int& off, int& b, uint32_t& codes, int& k) {
-    do {
-        const uint32_t w = __builtin_amdgcn_readlane(packed, b);
-        const uint32_t c = (w >> off) & 3u;
-        codes |= c << (2 * k);
-        ++k;
-        off -= 2 + int(c & 2u);
-        b += 1 + int(c & 1u);
-    } while (off >= 0);
+// lane l receives lane l-1's value (lane 0 receives 0)
+__device__ inline uint32_t from_prev_lane(uint32_t v) {
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x138 /* wave_shr:1 */, 0xf, 0xf, true));
+}
+
+// Bits 0, 2, 4, ... of x to bits 0, 1, 2, ... (16 bits).
+__device__ inline uint32_t even_bits(uint32_t x) {
+    x &= 0x55555555u;
+    x = (x | (x >> 1)) & 0x33333333u;
+    x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+    x = (x | (x >> 4)) & 0x00FF00FFu;
+    return (x | (x >> 8)) & 0x0000FFFFu;
+}
+
+// Row masks of one lane's window, bit 31 - a for row a: the code's bit 0 (the
+// step takes two columns) and bit 1 (two rows).
+struct WindowMasks {
+    uint32_t two_cols, two_rows;
+};
+
+__device__ inline WindowMasks window_masks(uint32_t packed0, uint32_t packed1) {
+    // row a of a half sits at bits 30-2a (low code bit), which even_bits moves to 15 - a
+    WindowMasks w;
+    w.two_cols = (even_bits(packed0) << 16) | even_bits(packed1);
+    w.two_rows = (even_bits(packed0 >> 1) << 16) | even_bits(packed1 >> 1);
+    return w;
+}
+
+// Traces the path through the window from lane 0, row 0 and returns each
+// lane's path cell as a mask (bit 31 - a for row a; at most one bit). A step
+// from row a of lane b goes to lane b + 1 + (code & 1), row a + 1 + (code >> 1);
+// the frontier is empty once the path has left the 32 rows. Code 3 stops it.
+__device__ inline uint32_t trace_window(const WindowMasks& w, int lane) {
+    const uint32_t diag = ~(w.two_cols | w.two_rows) >> 1;      // code 0: next lane, next row
+    const uint32_t down = (w.two_rows & ~w.two_cols) >> 2;      // code 2: next lane, two rows on
+    const uint32_t over = (w.two_cols & ~w.two_rows) >> 1;      // code 1: two lanes on, next row
+    uint32_t f = lane == 0 ? 0x80000000u : 0u;
+    uint32_t on = f;
+    for (int t = 0; t < 32; t += 2) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const uint32_t f1 = f >> 1, f2 = f >> 2;
+            const uint32_t hop = from_prev_lane(f1 & over);
+            f = from_prev_lane((f1 & diag) | (f2 & down) | hop);
+            on |= f;
+        }
+        if (__builtin_amdgcn_ballot_w64(f != 0) == 0) break;
+    }
+    return on;
 }
 
 // Walker: returns the path length (0 if the codes do not lead to the origin).
@@ -160,47 +201,61 @@ __device__ int walk(BtShared& sh, int n, int m, int P, int32_t* path) {
             packed1 = uint32_t(lo >> (s2 - 62));  // rows i-16 .. i-31
         }
 
-        // Resolve the steps inside the window (uniform scalar loops). Bit 1 of
-        // a code says the step takes two rows, bit 0 two columns, so the unused
-        // code 3 reads as an illegal (2, 2) step and is caught after the loops.
-        int off = 30, b = 0, k0 = 0, k1 = 0;
-        uint32_t codes0 = 0, codes1 = 0;  // codes of the steps taken in each half
-        bool origin = false;
-        int a;
         if (i >= 33 && j >= 66) {
             // no cell of the window can be the origin or lie outside the matrix
-            resolve_fast(packed0, off, b, codes0, k0);
-            off += 32;
-            resolve_fast(packed1, off, b, codes1, k1);
-            a = (62 - off) >> 1;
-        } else {
-            // near the first row or column: one 16-row half, every step checked
-            const int ij = i + j;
-            for (;;) {
-                a = (30 - off) >> 1;
-                if (a + b == ij) { origin = true; break; }  // a <= i and b <= j here
-                const uint32_t w = __builtin_amdgcn_readlane(packed0, b);
-                const uint32_t c = (w >> off) & 3u;
-                codes0 |= c << (2 * k0);
-                ++k0;
-                off -= 2 + int(c & 2u);
-                b += 1 + int(c & 1u);
-                if ((30 - off) >> 1 > i || b > j) return 0;  // left the matrix
-                if (off < 0) { a = (30 - off) >> 1; break; }
+            const WindowMasks wm = window_masks(packed0, packed1);
+            const uint32_t on = trace_window(wm, lane);
+            if (__builtin_amdgcn_ballot_w64((on & wm.two_cols & wm.two_rows) != 0)) return 0;  // code 3
+            const uint64_t has = __builtin_amdgcn_ballot_w64(on != 0);
+            const int cnt = __builtin_popcountll(has);
+            const int last = 63 - __builtin_clzll(has);  // lane 0 always holds the start cell
+            const uint32_t lm = __builtin_amdgcn_readlane(on, last);
+            const int la = __builtin_clz(lm);
+            const int a = la + 1 + int((__builtin_amdgcn_readlane(wm.two_rows, last) >> (31 - la)) & 1u);
+            const int b = last + 1 + int((__builtin_amdgcn_readlane(wm.two_cols, last) >> (31 - la)) & 1u);
+            if (a < 32 || len + cnt > cap) return 0;  // the trace did not leave the window
+            if (on != 0) {
+                const uint32_t lo = uint32_t(has), hi = uint32_t(has >> 32);
+                const int idx = int(__builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u)));
+                const int64_t pos = int64_t(cap) - 1 - (len + idx);
+                path[2 * pos] = i - __builtin_clz(on);
+                path[2 * pos + 1] = j - lane;
             }
+            len += cnt;
+            i -= a;
+            j -= b;
+            continue;
         }
-        if (((codes0 & (codes0 >> 1)) | (codes1 & (codes1 >> 1))) & 0x55555555u) return 0;  // code 3
-        const int cnt = k0 + k1 + (origin ? 1 : 0);
+
+        // Near the first row or column: one 16-row half, every step checked
+        // (uniform scalar loop). Bit 1 of a code says the step takes two rows,
+        // bit 0 two columns, so the unused code 3 reads as an illegal (2, 2)
+        // step and is caught after the loop.
+        int off = 30, b = 0, k0 = 0;
+        uint64_t codes0 = 0;
+        bool origin = false;
+        int a;
+        const int ij = i + j;
+        for (;;) {
+            a = (30 - off) >> 1;
+            if (a + b == ij) { origin = true; break; }  // a <= i and b <= j here
+            const uint32_t w = __builtin_amdgcn_readlane(packed0, b);
+            const uint32_t c = (w >> off) & 3u;
+            codes0 |= uint64_t(c) << (2 * k0);
+            ++k0;
+            off -= 2 + int(c & 2u);
+            b += 1 + int(c & 1u);
+            if ((30 - off) >> 1 > i || b > j) return 0;  // left the matrix
+            if (off < 0) { a = (30 - off) >> 1; break; }
+        }
+        if ((codes0 & (codes0 >> 1)) & 0x5555555555555555ull) return 0;  // code 3
+        const int cnt = k0 + (origin ? 1 : 0);
         if (len + cnt > cap) return 0;
         if (lane < cnt) {
             // offsets after the first `lane` steps
-            const int t0 = min(lane, k0), t1 = lane - t0;
-            const uint64_t m0 = (uint64_t(1) << (2 * t0)) - 1, m1 = (uint64_t(1) << (2 * t1)) - 1;
-            const uint64_t c0 = codes0, c1 = codes1;
-            const int da = lane + __builtin_popcountll(c0 & m0 & 0xAAAAAAAAull) +
-                           __builtin_popcountll(c1 & m1 & 0xAAAAAAAAull);
-            const int db = lane + __builtin_popcountll(c0 & m0 & 0x55555555ull) +
-                           __builtin_popcountll(c1 & m1 & 0x55555555ull);
+            const uint64_t m0 = (uint64_t(1) << (2 * lane)) - 1;
+            const int da = lane + __builtin_popcountll(codes0 & m0 & 0xAAAAAAAAAAAAAAAAull);
+            const int db = lane + __builtin_popcountll(codes0 & m0 & 0x5555555555555555ull);
             const int64_t pos = int64_t(cap) - 1 - (len + lane);
             path[2 * pos] = i - da;
             path[2 * pos + 1] = j - db;
