@@ -16,12 +16,17 @@
 // along the anti-diagonal of the (row, panel) grid and every panel is active
 // at once.
 //
-// A workgroup holds NW compute waves (NW consecutive panels) and one helper
-// wave. Boundary columns pass between the compute waves of a workgroup through
-// LDS rings, 8 rows at a time; between workgroups they pass through global
-// records {float D, uint32 epoch} written with agent-scope 64-bit atomic stores
-// and polled, several chunks per round trip, by the helper wave of the next
-// workgroup, so no side issues a cache-flushing fence. Workgroups take groups
+// A workgroup holds NW compute waves (NW consecutive panels) and two helper
+// waves. Boundary columns pass between the compute waves of a workgroup through
+// LDS rings, 8 rows at a time; between workgroups the output helper forwards
+// the last wave's ring to global records {float D, uint32 epoch} written with
+// agent-scope 64-bit atomic stores, which the input helper of the next
+// workgroup polls, several chunks per round trip, into its first ring, so no
+// side issues a cache-flushing fence. The first panel's ring is filled with
+// +inf once. Every compute wave thus runs the same instructions each chunk:
+// only its waits depend on its role, and no register value does, which keeps
+// the compiler from copying the boundary registers and from waiting on their
+// LDS reads early. Workgroups take groups
 // of panels from an atomic ticket in increasing order; a group only waits on
 // lower tickets, held by running workgroups, so the sweep always makes
 // progress whatever the number of resident workgroups.
@@ -96,8 +101,10 @@ __device__ __attribute__((always_inline)) inline void load_chunk(const DpArgs& a
     if constexpr (PANEL) {
         // rows 0-3 of the chunk for all 64 columns, then rows 4-7: each load
         // instruction reads 1 KB of contiguous memory
-        const int64_t off = (int64_t(p) * a.G + (real ? k : 0)) * (kLanes * kChunk);
-        const f32x4* src = reinterpret_cast<const f32x4*>(a.C + off) + lane;
+        // a chunk whose costs are not needed reads panel 0's first chunk,
+        // which holds the origin and so is always written (finite costs)
+        const float* base = real ? a.C + (int64_t(p) * a.G + k) * (kLanes * kChunk) : a.C;
+        const f32x4* src = reinterpret_cast<const f32x4*>(base) + lane;
         const f32x4 v0 = __builtin_nontemporal_load(src);
         const f32x4 v1 = __builtin_nontemporal_load(src + kLanes);
         cb[0] = v0[0]; cb[1] = v0[1]; cb[2] = v0[2]; cb[3] = v0[3];
@@ -115,45 +122,27 @@ __device__ __attribute__((always_inline)) inline void load_chunk(const DpArgs& a
     }
 }
 
-// Cells reachable from (0,0) by the three steps are exactly those with
-// j <= 2i and i <= 2j. For chunk k of panel p (rows 8k..8k+7, columns
-// jlo..jhi = 64p..64p+63) every cell is unreachable when jlo > 2(8k+7) or
-// 8k > 2 jhi: then D = +inf and code 3 everywhere and the chunk's result is
-// known without reading its costs. Every cell is reachable when jhi <= 16k and
-// 8k+7 <= 2 jlo: then no cell can see three infinite candidates and the
-// per-cell unreachable test is not needed. Both sets are ranges of k,
-// computed once per panel.
+// Chunks whose costs the sweep reads: those holding a cell reachable from
+// (0,0). Every other chunk is unreachable as a whole, so all its predecessors
+// are unreachable too and the arithmetic below gives +inf and code 3 there
+// from any finite costs: such chunks run the same instructions on a cost
+// chunk that is always written (the origin's), so the loop has one path.
 struct ChunkRanges {
-    int lo, hi;    // chunks with at least one reachable cell: [lo, hi]
-    int flo, fhi;  // chunks with only reachable cells: [flo, fhi]
+    int lo, hi;  // [lo, hi]
 };
 
 __device__ inline ChunkRanges chunk_ranges(int p, int64_t G) {
-    const int64_t jlo = int64_t(p) * kPanel, jhi = jlo + kPanel - 1;
     ChunkRanges r;
-    const int64_t lo = reach_group_lo(p);  // first k with 16k + 14 >= jlo
-    const int64_t hi = reach_group_hi(p);  // last k with 8k <= 2 jhi
-    const int64_t flo = (jhi + 15) / 16;                       // first k with 16k >= jhi
-    const int64_t fhi = (2 * jlo - 7) < 0 ? -1 : (2 * jlo - 7) / 8;  // last k with 8k + 7 <= 2 jlo
-    auto clampk = [&](int64_t v) { return int(v < -1 ? -1 : (v > G ? G : v)); };
-    r.lo = clampk(lo);
-    r.hi = clampk(hi);
-    r.flo = clampk(flo);
-    r.fhi = clampk(fhi);
+    const int64_t lo = reach_group_lo(p);  // first k with 16k + 14 >= 64p
+    const int64_t hi = reach_group_hi(p);  // last k with 8k <= 2 (64p + 63)
+    r.lo = int(lo < G ? lo : G);
+    r.hi = int(hi < G - 1 ? hi : G - 1);
     return r;
 }
 
-enum { kChunkSkip = 0, kChunkFast = 1, kChunkFull = 2 };
-
-__device__ inline int chunk_class(int k, const ChunkRanges& r) {
-    if (k < r.lo || k > r.hi) return kChunkSkip;
-    if (k >= r.flo && k <= r.fhi) return kChunkFast;
-    return kChunkFull;
-}
-
 // One 8-row chunk of a panel. `lv0/lv1` hold the left boundary columns
-// D[i0+r][64p-2] / D[i0+r][64p-1]; e0/e1 the same for row i0-1.
-template <bool CHECK_INF>
+// D[i0+r][64p-2] / D[i0+r][64p-1]; e0/e1 the same for row i0-1. A cell with
+// three infinite candidates is unreachable and gets code 3.
 __device__ __attribute__((always_inline)) inline void dp_rows(const float (&cb)[kChunk], const float (&lv0)[kChunk],
                                                               const float (&lv1)[kChunk], float e0, float e1,
                                                               float& d1, float& s1p, uint32_t& lo, uint32_t& hi,
@@ -172,7 +161,7 @@ __device__ __attribute__((always_inline)) inline void dp_rows(const float (&cb)[
         const float best = __builtin_fminf(__builtin_fminf(c0, c1), c2);
         uint32_t code = (c1 == best) ? 1u : 2u;
         code = (c0 == best) ? 0u : code;
-        if constexpr (CHECK_INF) code = (best == kInf) ? 3u : code;
+        code = (best == kInf) ? 3u : code;
         if (r < 4) lo |= code << (8 * r); else hi |= code << (8 * (r - 4));
         d1 = best;
         s1p = s1;
@@ -180,30 +169,30 @@ __device__ __attribute__((always_inline)) inline void dp_rows(const float (&cb)[
     }
 }
 
-// A compute wave owns panel p. Its role flags (a left neighbour to read, a
-// right neighbour to feed) are runtime values made opaque to the optimiser, so
-// every role runs the same instructions: the unrolled chunk loop is large and
-// several roles sharing one instruction cache would otherwise evict each
-// other.
+// A compute wave owns panel p. Whether it feeds a right neighbour is a runtime
+// value made opaque to the optimiser and only gates a rare wait, so every role
+// runs the same instructions: the unrolled chunk loop is large and several
+// roles sharing one instruction cache would otherwise evict each other.
 template <bool PANEL>
 __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs& a, DpShared& sh, int wave, int p,
-                                                                   bool have_left, bool have_out) {
+                                                                   bool have_out) {
     const int lane = threadIdx.x & 63;
     const int G = int(a.G);  // chunks per panel (rows padded to a multiple of 8)
     const ChunkRanges cr = chunk_ranges(p, a.G);
     const float kInf = __builtin_inff();
     const int bcol = lane - (kLanes - 2);  // 0 / 1 on the two boundary lanes
-    uint64_t* bp_out = reinterpret_cast<uint64_t*>(a.bp) + int64_t(p) * G * kLanes + lane;
+    uint64_t* bp_pan = reinterpret_cast<uint64_t*>(a.bp) + int64_t(p) * G * kLanes;
+    const int rlo = cr.lo, rhi = cr.hi;
     const float* rin = &sh.ring[wave][0][0][0];
     float* rout = &sh.ring[wave + 1][0][0][0];
-    int flags = __builtin_amdgcn_readfirstlane((have_left ? 1 : 0) | (have_out ? 2 : 0));
+    int flags = __builtin_amdgcn_readfirstlane(have_out ? 2 : 0);
 
     constexpr int kPf = PANEL ? kPfPanel : kPfRow;
     static_assert(kPf % 2 == 0, "boundary buffers alternate between even and odd chunks");
     float cbuf[kPf][kChunk];
 #pragma unroll
     for (int u = 0; u < kPf; ++u)
-        load_chunk<PANEL>(a, p, lane, u, u < G && chunk_class(u, cr) != kChunkSkip, cbuf[u]);
+        load_chunk<PANEL>(a, p, lane, u, u >= rlo && u <= rhi, cbuf[u]);
 
     // D[i-1][j] and D[i-2][j-1]. The origin is produced by the general rule
     // through a virtual D[-2][-1] = -2 C[0][0]: fma(3, C00, -2 C00) = C00
@@ -226,7 +215,8 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
 #pragma unroll
     for (int r = 0; r < kChunk; ++r) { lvA0[r] = kInf; lvA1[r] = kInf; lvB0[r] = kInf; lvB1[r] = kInf; }
     int prog_seen = 0, pv = 0;
-    if (have_left) {
+    {
+        // every wave has an input ring; panel 0's is filled with +inf by the input helper
         while ((prog_seen = lds_get(&sh.prog[wave][0])) <= 0) {}
         compiler_order();
         const f32x4* src = reinterpret_cast<const f32x4*>(rin);
@@ -256,11 +246,14 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
             float(&nxt0)[kChunk] = (u & 1) ? lvA0 : lvB0;
             float(&nxt1)[kChunk] = (u & 1) ? lvA1 : lvB1;
 
-            if ((flags & 1) && k + 1 < G) {
+            {
                 // Compute waves own their SIMD, so a consumer that caught up spins
                 // on the counter without sleeping: each late wake-up would be
                 // lost time it could never win back, adding up along the chain.
-                while (prog_seen <= k + 1) prog_seen = lds_get(&sh.prog[wave][0]);
+                // Only the wait is conditional: the reads below always run, so
+                // their registers need no copies and their latency stays hidden.
+                if (k + 1 < G)
+                    while (prog_seen <= k + 1) prog_seen = lds_get(&sh.prog[wave][0]);
                 compiler_order();
                 const f32x4* src = reinterpret_cast<const f32x4*>(rin + ((k + 1) % kRing) * 2 * kChunk);
                 const f32x4 x0 = src[0], x1 = src[1], y0 = src[2], y1 = src[3];
@@ -276,46 +269,36 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
                 pv = lds_get(&sh.prog[wave][lane & 1]);
             }
 
-            const int cls = inside ? chunk_class(k, cr) : kChunkSkip;
             uint32_t lo, hi;
             float best_r[kChunk];
-            if (cls == kChunkFast) {
-                dp_rows<false>(cbuf[u], cur0, cur1, e0, e1, d1, s1p, lo, hi, best_r);
-            } else if (cls == kChunkFull) {
-                dp_rows<true>(cbuf[u], cur0, cur1, e0, e1, d1, s1p, lo, hi, best_r);
-                if (p == 0 && k == 0) lo = (lane == 0) ? ((lo & ~0xffu) | 3u) : lo;  // the origin's code
-            } else {
-                lo = hi = 0x03030303u;
-                d1 = kInf;
-                s1p = kInf;
-#pragma unroll
-                for (int r = 0; r < kChunk; ++r) best_r[r] = kInf;
-            }
+            dp_rows(cbuf[u], cur0, cur1, e0, e1, d1, s1p, lo, hi, best_r);
+            if (p == 0 && k == 0) lo = (lane == 0) ? ((lo & ~0xffu) | 3u) : lo;  // the origin's code
             e0 = cur0[kChunk - 1];
             e1 = cur1[kChunk - 1];
 
-            __builtin_nontemporal_store(uint64_t(lo) | (uint64_t(hi) << 32),
-                                        inside ? bp_out + int64_t(k) * kLanes : a.hdr->sink + lane);
+            uint64_t* cdst = inside ? bp_pan + int64_t(k) * kLanes : a.hdr->sink;
+            __builtin_nontemporal_store(uint64_t(lo) | (uint64_t(hi) << 32), cdst + lane);
 
             // LDS operations complete in issue order. Drain this chunk's reads
             // (issued a whole chunk ago, so already done) before issuing the
             // ring writes below, so that no later wait queues behind fresh writes.
             __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
-            if (flags & 1) {
+            {
                 const int pv0 = __builtin_amdgcn_readfirstlane(pv);
                 prog_seen = pv0 > prog_seen ? pv0 : prog_seen;
             }
 
-            if ((flags & 2) && inside) {
-                if (cons_seen < k + 1 - kRing) {
+            {
+                // A wave without a right neighbour writes into a ring nobody reads.
+                if ((flags & 2) && inside && cons_seen < k + 1 - kRing) {
                     int v;
                     while ((v = lds_get(&sh.cons[wave + 1])) < k + 1 - kRing) {}
                     cons_seen = v;
                 }
                 compiler_order();
                 {
-                    f32x4* dst = bcol >= 0 ? reinterpret_cast<f32x4*>(rout + (slot * 2 + bcol) * kChunk)
-                                           : &sh.fsink[wave][lane][0];
+                    f32x4* dst = (bcol >= 0 && inside) ? reinterpret_cast<f32x4*>(rout + (slot * 2 + bcol) * kChunk)
+                                                       : &sh.fsink[wave][lane][0];
                     dst[0] = f32x4{best_r[0], best_r[1], best_r[2], best_r[3]};
                     dst[1] = f32x4{best_r[4], best_r[5], best_r[6], best_r[7]};
                 }
@@ -328,7 +311,7 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
             }
 
             const int kn = k + kPf;
-            load_chunk<PANEL>(a, p, lane, kn, kn < G && chunk_class(kn, cr) != kChunkSkip, cbuf[u]);
+            load_chunk<PANEL>(a, p, lane, kn, kn >= rlo && kn <= rhi, cbuf[u]);
         }
     }
     if (int64_t(p) * kPanel + lane == a.m - 1) {
@@ -394,6 +377,16 @@ __device__ __attribute__((always_inline)) inline void in_helper(const DpArgs& a,
     }
 }
 
+// Input of the first panel: no left neighbour, so every boundary value is
+// +inf; the ring is filled once and published as complete.
+__device__ __attribute__((always_inline)) inline void inf_source(DpShared& sh) {
+    const int lane = threadIdx.x & 63;
+    float* ring = &sh.ring[0][0][0][0];
+    for (int e = lane; e < kRing * 2 * kChunk; e += kLanes) ring[e] = __builtin_inff();
+    compiler_order();
+    if (lane < 2) lds_put(&sh.prog[0][lane], 1 << 30);
+}
+
 // Output helper: forwards the boundary columns that the last compute wave of
 // the group (panel pl) leaves in LDS ring NW to the global records, up to four
 // chunks (64 records, one per lane) per store. Keeping these agent-scope
@@ -434,9 +427,10 @@ __device__ __attribute__((always_inline)) inline void run_group(const DpArgs& a,
     const int p0 = q * NW;
     if (wave < NW) {
         const int p = p0 + wave;
-        if (p < a.P) compute_wave<PANEL>(a, sh, wave, p, p > 0, p + 1 < a.P);
+        if (p < a.P) compute_wave<PANEL>(a, sh, wave, p, p + 1 < a.P);
     } else if (wave == NW) {
         if (p0 > 0) in_helper(a, sh, p0 - 1, epoch);
+        else inf_source(sh);
     } else {
         // the group's last panel feeds the next group when one exists
         if (p0 + NW < a.P) out_helper(a, sh, NW, p0 + NW - 1, epoch);
