@@ -12,9 +12,9 @@
 // row and the shifted D of the row before in registers. Row i of lane l needs
 // D[i-1][j-1], D[i-1][j-2] and D[i-2][j-1]: two wave_shr:1 DPP moves per row,
 // whose lane 0 is fed the two boundary columns of the panel to the left.
-// Panel p trails panel p-1 by a few rows, so the sweep front is a staircase
-// along the anti-diagonal of the (row, panel) grid and every panel is active
-// at once.
+// Panel p starts chunk k (8 rows) once panel p-1 has published chunk k, so
+// the sweep front is a staircase along the anti-diagonal of the (row, panel)
+// grid and every panel is active at once.
 //
 // A workgroup holds NW compute waves (NW consecutive panels) and two helper
 // waves. Boundary columns pass between the compute waves of a workgroup through
@@ -188,7 +188,6 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
     int flags = __builtin_amdgcn_readfirstlane(have_out ? 2 : 0);
 
     constexpr int kPf = PANEL ? kPfPanel : kPfRow;
-    static_assert(kPf % 2 == 0, "boundary buffers alternate between even and odd chunks");
     float cbuf[kPf][kChunk];
 #pragma unroll
     for (int u = 0; u < kPf; ++u)
@@ -206,29 +205,13 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
     float dlast = kInf;
     int cons_seen = 0;
 
-    // Boundary columns of chunk k arrive in registers one chunk ahead: while a
-    // wave computes chunk k, the LDS reads of chunk k+1 are in flight, and the
-    // producer's progress counter is read asynchronously one chunk before it
-    // is tested. A consumer therefore trails its producer by two chunks and,
-    // in steady state, never waits on LDS latency.
-    float lvA0[kChunk], lvA1[kChunk], lvB0[kChunk], lvB1[kChunk];
-#pragma unroll
-    for (int r = 0; r < kChunk; ++r) { lvA0[r] = kInf; lvA1[r] = kInf; lvB0[r] = kInf; lvB1[r] = kInf; }
+    // Boundary columns of chunk k: a consumer starts chunk k as soon as its
+    // producer has published chunk k. Row 0 of a chunk needs only the last
+    // boundary row of the chunk before (e0, e1), so the LDS reads of chunk k's
+    // boundary are in flight while row 0 is computed. The producer's progress
+    // counter is read asynchronously one chunk before it is tested.
+    float lv0[kChunk], lv1[kChunk];
     int prog_seen = 0, pv = 0;
-    {
-        // every wave has an input ring; panel 0's is filled with +inf by the input helper
-        while ((prog_seen = lds_get(&sh.prog[wave][0])) <= 0) {}
-        compiler_order();
-        const f32x4* src = reinterpret_cast<const f32x4*>(rin);
-        const f32x4 x0 = src[0], x1 = src[1], y0 = src[2], y1 = src[3];
-        lvA0[0] = x0[0]; lvA0[1] = x0[1]; lvA0[2] = x0[2]; lvA0[3] = x0[3];
-        lvA0[4] = x1[0]; lvA0[5] = x1[1]; lvA0[6] = x1[2]; lvA0[7] = x1[3];
-        lvA1[0] = y0[0]; lvA1[1] = y0[1]; lvA1[2] = y0[2]; lvA1[3] = y0[3];
-        lvA1[4] = y1[0]; lvA1[5] = y1[1]; lvA1[6] = y1[2]; lvA1[7] = y1[3];
-        compiler_order();
-        if (lane == 0) lds_put(&sh.cons[wave], 1);
-        pv = lds_get(&sh.prog[wave][lane & 1]);
-    }
 
     // The unrolled body has no early exit: chunks past the end of the panel
     // (at most kPf - 1) run as known chunks whose code store goes to a sink.
@@ -241,10 +224,6 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
             const bool inside = k < G;
             asm volatile("" : "+s"(flags));
             const int slot = k % kRing;
-            float(&cur0)[kChunk] = (u & 1) ? lvB0 : lvA0;
-            float(&cur1)[kChunk] = (u & 1) ? lvB1 : lvA1;
-            float(&nxt0)[kChunk] = (u & 1) ? lvA0 : lvB0;
-            float(&nxt1)[kChunk] = (u & 1) ? lvA1 : lvB1;
 
             {
                 // Compute waves own their SIMD, so a consumer that caught up spins
@@ -252,17 +231,17 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
                 // lost time it could never win back, adding up along the chain.
                 // Only the wait is conditional: the reads below always run, so
                 // their registers need no copies and their latency stays hidden.
-                if (k + 1 < G)
-                    while (prog_seen <= k + 1) prog_seen = lds_get(&sh.prog[wave][0]);
+                if (k < G)
+                    while (prog_seen <= k) prog_seen = lds_get(&sh.prog[wave][0]);
                 compiler_order();
-                const f32x4* src = reinterpret_cast<const f32x4*>(rin + ((k + 1) % kRing) * 2 * kChunk);
+                const f32x4* src = reinterpret_cast<const f32x4*>(rin + slot * 2 * kChunk);
                 const f32x4 x0 = src[0], x1 = src[1], y0 = src[2], y1 = src[3];
-                nxt0[0] = x0[0]; nxt0[1] = x0[1]; nxt0[2] = x0[2]; nxt0[3] = x0[3];
-                nxt0[4] = x1[0]; nxt0[5] = x1[1]; nxt0[6] = x1[2]; nxt0[7] = x1[3];
-                nxt1[0] = y0[0]; nxt1[1] = y0[1]; nxt1[2] = y0[2]; nxt1[3] = y0[3];
-                nxt1[4] = y1[0]; nxt1[5] = y1[1]; nxt1[6] = y1[2]; nxt1[7] = y1[3];
+                lv0[0] = x0[0]; lv0[1] = x0[1]; lv0[2] = x0[2]; lv0[3] = x0[3];
+                lv0[4] = x1[0]; lv0[5] = x1[1]; lv0[6] = x1[2]; lv0[7] = x1[3];
+                lv1[0] = y0[0]; lv1[1] = y0[1]; lv1[2] = y0[2]; lv1[3] = y0[3];
+                lv1[4] = y1[0]; lv1[5] = y1[1]; lv1[6] = y1[2]; lv1[7] = y1[3];
                 compiler_order();
-                lds_put(lane == 0 ? &sh.cons[wave] : &sh.isink[wave][lane], k + 2);
+                lds_put(lane == 0 ? &sh.cons[wave] : &sh.isink[wave][lane], k + 1);
                 // read per lane from one of two identical copies, so the value
                 // stays in a vector register and is not waited for until the
                 // end of the chunk
@@ -271,10 +250,10 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
 
             uint32_t lo, hi;
             float best_r[kChunk];
-            dp_rows(cbuf[u], cur0, cur1, e0, e1, d1, s1p, lo, hi, best_r);
+            dp_rows(cbuf[u], lv0, lv1, e0, e1, d1, s1p, lo, hi, best_r);
             if (p == 0 && k == 0) lo = (lane == 0) ? ((lo & ~0xffu) | 3u) : lo;  // the origin's code
-            e0 = cur0[kChunk - 1];
-            e1 = cur1[kChunk - 1];
+            e0 = lv0[kChunk - 1];
+            e1 = lv1[kChunk - 1];
 
             uint64_t* cdst = inside ? bp_pan + int64_t(k) * kLanes : a.hdr->sink;
             __builtin_nontemporal_store(uint64_t(lo) | (uint64_t(hi) << 32), cdst + lane);
