@@ -44,9 +44,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kChunk = kBpRows;  // rows per synchronisation chunk (= packed group)
 constexpr int kRing = 32;        // LDS ring depth, in chunks
-constexpr int kPfPanel = 8;      // cost prefetch distance in chunks, panel layout
+constexpr int kPfPanel = 4;      // cost prefetch distance in chunks, panel layout (4 measured best of 2-16)
 constexpr int kPfRow = 4;        // the same for the row-major layout (8 loads per chunk)
-constexpr int kHelperWin = 16;   // chunks polled per helper round trip (4 records per lane)
+constexpr int kHelperWin = 4;   // chunks polled per helper round trip (one record per lane)
 constexpr int kMaxNW = 8;
 
 struct DpShared {
@@ -301,9 +301,11 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
 
 // Input helper: copies the boundary columns of panel pl (the last panel of the
 // previous group, computed by another workgroup) from the global records into
-// LDS ring 0. One poll reads kHelperWin chunks (16 records each, four per
-// lane) and publishes every leading chunk whose epoch tags are all present, so
-// a single memory round trip can hand over 128 rows.
+// LDS ring 0. One poll reads kHelperWin chunks (16 records each, one per
+// lane) and publishes every leading chunk whose epoch tags are all present.
+// Polls are back to back: under full memory load a poll's round trip is the
+// handoff's latency, and it grows with the loads a poll issues (windows of
+// 8, 16 or more chunks measured slower).
 __device__ __attribute__((always_inline)) inline void in_helper(const DpArgs& a, DpShared& sh, int pl,
                                                                 uint32_t epoch) {
     constexpr int kPer = kHelperWin * 16 / kLanes;  // records per lane per poll
@@ -332,10 +334,7 @@ __device__ __attribute__((always_inline)) inline void in_helper(const DpArgs& a,
         while (ready < kHelperWin && k + ready < G &&
                ((good[ready >> 2] >> (16 * (ready & 3))) & 0xffffull) == 0xffffull)
             ++ready;
-        if (ready == 0) {
-            __builtin_amdgcn_s_sleep(2);
-            continue;
-        }
+        if (ready == 0) continue;
         if (cons_seen < k + ready - kRing) {
             int c;
             while ((c = lds_get(&sh.cons[0])) < k + ready - kRing) __builtin_amdgcn_s_sleep(1);
