@@ -2,7 +2,7 @@
 """Benchmark: exact ParDTW on one MI355X, 50000 x 60000 chroma-like pair.
 
 One step = the whole hot path for one pair with inputs resident in HBM:
-  cosine-cost MFMA GEMM (panel layout, reachable groups only) -> staircase-wavefront DP -> backtrace.
+  cosine-cost MFMA GEMM (panel layout, path-band groups only) -> staircase-wavefront DP -> backtrace.
 Prints one JSON line with GCUPS (N*M cells / step time), pairs/s, the DP
 kernel's roofline figures (algorithmic bytes / measured kernel time against
 the 8 TB/s HBM peak), and the CPU baseline leg: the FP64 oracle timed on the
@@ -133,7 +133,7 @@ def main():
 
     Xd = torch.from_numpy(X).to(dev)
     Yd = torch.from_numpy(Y).to(dev)
-    w = pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_REACHABLE)
+    w = pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND)
     stream = torch.cuda.current_stream()
 
     calib = None
@@ -158,9 +158,9 @@ def main():
     for s in range(args.steps):
         e = evs[s]
         e[0].record(stream)
-        pd.pardtw_cost(Xd, Yd, w.C, pd.PREC_F32, pd.LAYOUT_PANEL_REACHABLE)
+        pd.pardtw_cost(Xd, Yd, w.C, pd.PREC_F32, pd.LAYOUT_PANEL_BAND)
         e[1].record(stream)
-        pd.pardtw_dp(w.C, n, m, w.bp, w.total, w.status, w.ws, pd.LAYOUT_PANEL_REACHABLE)
+        pd.pardtw_dp(w.C, n, m, w.bp, w.total, w.status, w.ws, pd.LAYOUT_PANEL_BAND)
         e[2].record(stream)
         pd.pardtw_backtrace(w.bp, n, m, w.status, w.path, w.path_len)
         e[3].record(stream)
@@ -215,7 +215,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "m": m, "d": d, "cells": cells, "layout": "panel64_reachable",
+        "config": {"workload": args.workload, "n": n, "m": m, "d": d, "cells": cells, "layout": "panel64_band",
                    "pairs_per_s": round(1e3 / ms_per_step, 3),
                    "stage_ms": {"cost": round(float(cost_ms), 4), "dp": round(float(dp_ms), 4),
                                 "backtrace": round(float(bt_ms), 4)}},

@@ -11,9 +11,11 @@
  *   DP       steps (1,1), (1,2), (2,1) with weights 2, 3, 3 (Sec. V); the weight
  *            multiplies the cost of the cell a step lands on; D[0,0] = C[0,0];
  *            D[i,j] = min(D[i-1,j-1] + 2C, D[i-1,j-2] + 3C, D[i-2,j-1] + 3C)
- *   codes    0 = (1,1), 1 = (1,2), 2 = (2,1), 3 = origin / unreachable; an exact
- *            tie goes to the lowest code. Four codes = the paper's 2-bit
- *            transition types (Sec. VI-D).
+ *   codes    0 = (1,1), 1 = (1,2), 2 = (2,1), 3 = origin; an exact tie goes to
+ *            the lowest code. Four codes = the paper's 2-bit transition types
+ *            (Sec. VI-D). pardtw_dp defines them on the band of cells that can
+ *            lie on a path from (0,0) to (N-1,M-1); the optimal path and every
+ *            cell the backtrace reads lie in it.
  *   result   D[N-1, M-1] and the path from (0,0) to (N-1,M-1), exactly DTW's
  *            (Sec. II-D: ParDTW changes the order of work, not the result).
  *
@@ -65,14 +67,18 @@ typedef enum {
      * Columns past M and rows past N are padding. A wavefront of the DP reads
      * one 8-row chunk of its panel with two 1 KB contiguous loads. */
     PARDTW_LAYOUT_PANEL = 1,
-    /* The panel layout with only the 8-row groups that pardtw_dp reads: a
-     * group of panel p is written when it holds a cell reachable from (0,0)
-     * with the step set (j <= 2i and i <= 2j, Sec. V), i.e. for
-     *   max(0, ceil((64p - 14)/16)) <= i/8 <= floor((64p + 63)/4).
-     * Other groups are left untouched (about half of a 5:6 pair). Same size
+    /* The panel layout with only the 8-row groups that pardtw_dp reads: the
+     * band of cells that can lie on a path from (0,0) to (N-1,M-1) with the
+     * step set of Sec. V. A group of panel p is written when it holds a real
+     * cell reachable from the origin (j <= 2i and i <= 2j) and a real cell
+     * from which (N-1,M-1) is reachable ((M-1-j) <= 2(N-1-i) and
+     * (N-1-i) <= 2(M-1-j)); for 64p <= 2(N-1), j1 = min(64p+63, M-1):
+     *   max(0, ceil((64p-14)/16), ceil((N-8-2(M-1-64p))/8)) <= i/8
+     *   i/8 <= min(floor(j1/4), floor((2(N-1)-(M-1-j1))/16)).
+     * Other groups are left untouched (about 70% of a 5:6 pair). Same size
      * and element placement as PARDTW_LAYOUT_PANEL; pardtw_dp treats the two
      * alike. */
-    PARDTW_LAYOUT_PANEL_REACHABLE = 2
+    PARDTW_LAYOUT_PANEL_BAND = 2
 } pardtw_layout;
 
 #define PARDTW_PAIR_OK 0
@@ -80,6 +86,12 @@ typedef enum {
 
 /* Number of floats a cost buffer of the given layout occupies (0 on bad args). */
 size_t pardtw_cost_elems(int64_t n, int64_t m, pardtw_layout layout);
+
+/* Host-side helper: the 8-row groups [*lo, *hi] of column panel p (0 <= p <
+ * ceil(M/64)) that PARDTW_LAYOUT_PANEL_BAND writes and pardtw_dp reads,
+ * clamped to [0, ceil(N/8) - 1]; empty when *lo > *hi. Calls no HIP API.
+ * PARDTW_ERR_INVALID_ARG on bad sizes, p out of range or null outputs. */
+pardtw_status pardtw_band_groups(int64_t n, int64_t m, int64_t p, int64_t* lo, int64_t* hi);
 
 /* Bytes of the backtrace buffer written by pardtw_dp (0 on bad args). Codes
  * use 64-column panels and 8-row groups with a column's 8 codes contiguous:
@@ -98,7 +110,7 @@ size_t pardtw_dp_workspace_bytes(int64_t n, int64_t m);
  *   X [device, n*d FP32], Y [device, m*d FP32]: row-major features.
  *   prec: PARDTW_PREC_F32 or PARDTW_PREC_BF16 (BF16 operands, FP32 accumulate;
  *         the norms are taken from the same BF16-rounded values).
- *   layout: PARDTW_LAYOUT_ROW, PARDTW_LAYOUT_PANEL or PARDTW_LAYOUT_PANEL_REACHABLE.
+ *   layout: PARDTW_LAYOUT_ROW, PARDTW_LAYOUT_PANEL or PARDTW_LAYOUT_PANEL_BAND.
  *   C [device, pardtw_cost_elems(n,m,layout) floats]: overwritten. A frame of
  *   zero norm is treated as the zero vector, so its cost is 1. */
 pardtw_status pardtw_cost(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
@@ -109,8 +121,12 @@ pardtw_status pardtw_cost(const float* X, const float* Y, int64_t n, int64_t m, 
  * each panel trails its left neighbour by a few rows, so all cells whose
  * predecessors are final are computed concurrently. Keeps only the last two
  * rows of D per panel on chip and writes one code byte per cell.
- *   C [device]: cost in the given layout (FP32; costs are not clamped).
- *   bp [device, pardtw_bp_bytes(n,m) bytes]: codes, layout as documented above.
+ *   C [device]: cost in the given layout (FP32; costs are not clamped). Only
+ *   the band groups described at PARDTW_LAYOUT_PANEL_BAND are read.
+ *   bp [device, pardtw_bp_bytes(n,m) bytes]: codes, layout as documented
+ *   above: 0 = (1,1), 1 = (1,2), 2 = (2,1) for every cell that can lie on a
+ *   path from (0,0) to (n-1,m-1) (reachable from the origin and able to reach
+ *   the end), 3 at (0,0); the bytes of every other cell are unspecified.
  *   total [device, 1 float]: D[n-1, m-1] in FP32 (+inf if infeasible).
  *   pair_status [device, 1 int32]: PARDTW_PAIR_OK / PARDTW_PAIR_INFEASIBLE.
  *   workspace [device, >= pardtw_dp_workspace_bytes(n,m)], see above.

@@ -28,16 +28,38 @@ inline bool valid_sizes(int64_t n, int64_t m) {
            n <= (int64_t(1) << 62) / m;
 }
 
-// Cells reachable from (0,0) by the steps (1,1), (1,2), (2,1) are exactly those
-// with j <= 2i and i <= 2j. For column panel p (columns 64p .. 64p+63), the
-// 8-row groups that hold at least one such cell are reach_group_lo(p) ..
-// reach_group_hi(p) (not clamped to the number of groups): group k is reached
-// when 64p <= 2(8k+7) and 8k <= 2(64p+63).
-__host__ __device__ inline int64_t reach_group_lo(int64_t p) {
-    const int64_t jlo = p * kPanel;
-    return jlo <= 14 ? 0 : (jlo - 14 + 15) / 16;
+// Cells on some path from (0,0) to (n-1,m-1) with the steps (1,1), (1,2),
+// (2,1) (Sec. V): reachable from the origin, j <= 2i and i <= 2j, and able to
+// reach the end, (m-1-j) <= 2(n-1-i) and (n-1-i) <= 2(m-1-j). Only they can lie
+// on the optimal path. For column panel p (columns 64p .. 64p+63) the 8-row
+// groups k that hold a cell of the first cone and a cell of the second (real
+// cells only, i < n, j < m) are band_group_lo(p) .. band_group_hi(p), empty
+// when lo > hi. Each bound follows from testing the cone against the group's
+// box: a box [a1, a2] x [b1, b2] meets {j <= 2i, i <= 2j} iff b1 <= 2 a2 and
+// a1 <= 2 b2.
+__host__ __device__ inline int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+__host__ __device__ inline int64_t band_group_lo(int64_t p, int64_t n, int64_t m) {
+    const int64_t j0 = p * kPanel;
+    // origin cone: 64p <= 2(8k+7), and the panel must start within 2(n-1)
+    int64_t lo = -floor_div(-(j0 - 14), 16);  // ceil((64p - 14) / 16)
+    if (j0 > 2 * (n - 1)) return int64_t(1) << 40;
+    // end cone: n-1-(8k+7) <= 2(m-1-64p)
+    const int64_t le = -floor_div(-(n - 8 - 2 * (m - 1 - j0)), 8);
+    if (le > lo) lo = le;
+    return lo < 0 ? 0 : lo;
 }
-__host__ __device__ inline int64_t reach_group_hi(int64_t p) { return (p * kPanel + kPanel - 1) / 4; }
+
+__host__ __device__ inline int64_t band_group_hi(int64_t p, int64_t n, int64_t m) {
+    const int64_t j0 = p * kPanel;
+    const int64_t j1 = j0 + kPanel - 1 < m - 1 ? j0 + kPanel - 1 : m - 1;  // last real column
+    // origin cone: 8k <= 2 j1
+    int64_t hi = floor_div(j1, 4);
+    // end cone: m-1-j1 <= 2(n-1-8k)
+    const int64_t he = floor_div(2 * (n - 1) - (m - 1 - j1), 16);
+    if (he < hi) hi = he;
+    return hi;
+}
 
 inline bool pair_feasible(int64_t n, int64_t m) {
     return (m - 1) <= 2 * (n - 1) && (n - 1) <= 2 * (m - 1);

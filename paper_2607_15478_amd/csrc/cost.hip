@@ -19,9 +19,9 @@
 // The tile is written either into the DP's panel layout (rows 0-3 then 4-7 of
 // each 8-row group, 16 contiguous bytes per column: one 16-byte store per lane
 // per 16x16 block) or row-major. For the DP's own use the panel layout can skip
-// every 8-row group of a panel that holds no cell reachable from (0,0) under
-// the step set (the DP never reads those groups): about half of the matrix for
-// a 5:6 pair. With D = 12 the kernel does 24 flop per
+// every 8-row group of a panel outside the band of cells that can lie on a path
+// from (0,0) to (N-1,M-1) (the DP never reads those groups): about 70% of the
+// matrix for a 5:6 pair. With D = 12 the kernel does 24 flop per
 // 4-byte output, far below the MFMA ridge point: it is bound by HBM writes.
 #include "batch.h"
 
@@ -74,10 +74,10 @@ struct GroupSpan {
     int64_t lo, hi;
 };
 
-__device__ inline GroupSpan group_span(bool reach, int64_t p) {
+__device__ inline GroupSpan group_span(bool band, int64_t p, int64_t n, int64_t m) {
     GroupSpan s;
-    s.lo = reach ? reach_group_lo(p) : 0;
-    s.hi = reach ? reach_group_hi(p) : (int64_t(1) << 62);
+    s.lo = band ? band_group_lo(p, n, m) : 0;
+    s.hi = band ? band_group_hi(p, n, m) : (int64_t(1) << 62);
     return s;
 }
 
@@ -261,13 +261,13 @@ __device__ __attribute__((always_inline)) inline void cost_tile(const float* __r
 }
 
 // A workgroup's sweep: tiles t0 .. t0 + kTilesPerBlock - 1 of panel p. With
-// `reach` (panel layout only) groups without a reachable cell are skipped.
+// `band` (panel layout only) groups outside the band of path cells are skipped.
 template <bool BF16, bool PANEL, bool VEC>
 __device__ __attribute__((always_inline)) inline void sweep(const float* __restrict__ X,
                                                             const float* __restrict__ Y, int64_t n, int64_t m,
                                                             int64_t d, float* __restrict__ C, int64_t p, int64_t t0,
-                                                            bool reach) {
-    const GroupSpan span = group_span(PANEL && reach, p);
+                                                            bool band) {
+    const GroupSpan span = group_span(PANEL && band, p, n, m);
     if (!rows_written(span, t0 * kTileM, int64_t(kTilesPerBlock) * kTileM)) return;
     if (!BF16 && d <= 16) {
         sweep_f32_small<PANEL>(X, Y, n, m, d, C, p, t0, kTilesPerBlock, span);
@@ -284,8 +284,8 @@ __device__ __attribute__((always_inline)) inline void sweep(const float* __restr
 template <bool BF16, bool PANEL, bool VEC>
 __global__ __launch_bounds__(kThreads) void cost_kernel(const float* __restrict__ X, const float* __restrict__ Y,
                                                         int64_t n, int64_t m, int64_t d, float* __restrict__ C,
-                                                        bool reach) {
-    sweep<BF16, PANEL, VEC>(X, Y, n, m, d, C, blockIdx.x, int64_t(blockIdx.y) * kTilesPerBlock, reach);
+                                                        bool band) {
+    sweep<BF16, PANEL, VEC>(X, Y, n, m, d, C, blockIdx.x, int64_t(blockIdx.y) * kTilesPerBlock, band);
 }
 
 // Batched form: block t is block t of the batch's numbering; tile_pair[t]
@@ -340,20 +340,20 @@ pardtw_status cost_launch(const float* X, const float* Y, int64_t n, int64_t m, 
     if (rows_blk > 65535 || num_panels(m) > 0x7fffffff) return PARDTW_ERR_UNSUPPORTED;
     dim3 grid(unsigned(num_panels(m)), unsigned(rows_blk));
     const bool panel = layout != PARDTW_LAYOUT_ROW;
-    const bool reach = layout == PARDTW_LAYOUT_PANEL_REACHABLE;
+    const bool band = layout == PARDTW_LAYOUT_PANEL_BAND;
     const bool vec = vec_ok(X, Y, d);
     if (prec == PARDTW_PREC_F32 && vec && d % 16 == 0) {
-        if (panel) cost_kernel<false, true, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, reach);
-        else cost_kernel<false, false, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, reach);
+        if (panel) cost_kernel<false, true, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, band);
+        else cost_kernel<false, false, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, band);
     } else if (prec == PARDTW_PREC_F32) {
-        if (panel) cost_kernel<false, true, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, reach);
-        else cost_kernel<false, false, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, reach);
+        if (panel) cost_kernel<false, true, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, band);
+        else cost_kernel<false, false, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, band);
     } else if (vec) {
-        if (panel) cost_kernel<true, true, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, reach);
-        else cost_kernel<true, false, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, reach);
+        if (panel) cost_kernel<true, true, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, band);
+        else cost_kernel<true, false, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, band);
     } else {
-        if (panel) cost_kernel<true, true, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, reach);
-        else cost_kernel<true, false, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, reach);
+        if (panel) cost_kernel<true, true, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, band);
+        else cost_kernel<true, false, false><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, band);
     }
     return launch_status();
 }
@@ -363,9 +363,18 @@ pardtw_status cost_launch(const float* X, const float* Y, int64_t n, int64_t m, 
 extern "C" size_t pardtw_cost_elems(int64_t n, int64_t m, pardtw_layout layout) {
     if (!pardtw::valid_sizes(n, m)) return 0;
     if (layout == PARDTW_LAYOUT_ROW) return size_t(n) * size_t(m);
-    if (layout == PARDTW_LAYOUT_PANEL || layout == PARDTW_LAYOUT_PANEL_REACHABLE)
+    if (layout == PARDTW_LAYOUT_PANEL || layout == PARDTW_LAYOUT_PANEL_BAND)
         return size_t(pardtw::num_panels(m)) * size_t(pardtw::bp_groups(n)) * pardtw::kPanel * pardtw::kBpRows;
     return 0;
+}
+
+extern "C" pardtw_status pardtw_band_groups(int64_t n, int64_t m, int64_t p, int64_t* lo, int64_t* hi) {
+    if (!lo || !hi || !pardtw::valid_sizes(n, m) || p < 0 || p >= pardtw::num_panels(m)) return PARDTW_ERR_INVALID_ARG;
+    const int64_t G = pardtw::bp_groups(n);
+    const int64_t l = pardtw::band_group_lo(p, n, m), h = pardtw::band_group_hi(p, n, m);
+    *lo = l < G ? l : G;
+    *hi = h < G - 1 ? h : G - 1;
+    return PARDTW_OK;
 }
 
 extern "C" pardtw_status pardtw_cost(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
@@ -373,7 +382,7 @@ extern "C" pardtw_status pardtw_cost(const float* X, const float* Y, int64_t n, 
     if (!X || !Y || !C || !pardtw::valid_sizes(n, m) || d <= 0 || d > (int64_t(1) << 20))
         return PARDTW_ERR_INVALID_ARG;
     if (prec != PARDTW_PREC_F32 && prec != PARDTW_PREC_BF16) return PARDTW_ERR_UNSUPPORTED;
-    if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL && layout != PARDTW_LAYOUT_PANEL_REACHABLE)
+    if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL && layout != PARDTW_LAYOUT_PANEL_BAND)
         return PARDTW_ERR_UNSUPPORTED;
     return pardtw::cost_launch(X, Y, n, m, d, prec, layout, C, stream);
 }

@@ -122,32 +122,35 @@ __device__ __attribute__((always_inline)) inline void load_chunk(const DpArgs& a
     }
 }
 
-// Chunks whose costs the sweep reads: those holding a cell reachable from
-// (0,0). Every other chunk is unreachable as a whole, so all its predecessors
-// are unreachable too and the arithmetic below gives +inf and code 3 there
-// from any finite costs: such chunks run the same instructions on a cost
-// chunk that is always written (the origin's), so the loop has one path.
+// Chunks whose costs the sweep reads: those of the band of cells that can lie
+// on a path from (0,0) to (N-1,M-1). Every other chunk runs the same
+// instructions on a cost chunk that is always written (the origin's), so the
+// loop has one path, and its values do not matter:
+// * a cell unreachable from the origin has only unreachable predecessors, so
+//   its D stays +inf whatever the finite costs;
+// * a cell that cannot reach the end feeds only cells that cannot either, so
+//   whatever finite D it gets never reaches a band cell.
+// Band cells are thus exact and, being reachable, finite: they need no
+// unreachable test, and the codes of cells outside the band are unspecified.
 struct ChunkRanges {
-    int lo, hi;  // [lo, hi]
+    int lo, hi;  // [lo, hi], empty when lo > hi
 };
 
-__device__ inline ChunkRanges chunk_ranges(int p, int64_t G) {
+__device__ inline ChunkRanges chunk_ranges(int p, int64_t n, int64_t m, int64_t G) {
     ChunkRanges r;
-    const int64_t lo = reach_group_lo(p);  // first k with 16k + 14 >= 64p
-    const int64_t hi = reach_group_hi(p);  // last k with 8k <= 2 (64p + 63)
+    const int64_t lo = band_group_lo(p, n, m);
+    const int64_t hi = band_group_hi(p, n, m);
     r.lo = int(lo < G ? lo : G);
     r.hi = int(hi < G - 1 ? hi : G - 1);
     return r;
 }
 
 // One 8-row chunk of a panel. `lv0/lv1` hold the left boundary columns
-// D[i0+r][64p-2] / D[i0+r][64p-1]; e0/e1 the same for row i0-1. A cell with
-// three infinite candidates is unreachable and gets code 3.
+// D[i0+r][64p-2] / D[i0+r][64p-1]; e0/e1 the same for row i0-1.
 __device__ __attribute__((always_inline)) inline void dp_rows(const float (&cb)[kChunk], const float (&lv0)[kChunk],
                                                               const float (&lv1)[kChunk], float e0, float e1,
                                                               float& d1, float& s1p, uint32_t& lo, uint32_t& hi,
                                                               float (&best_r)[kChunk]) {
-    const float kInf = __builtin_inff();
     lo = 0;
     hi = 0;
 #pragma unroll
@@ -161,7 +164,6 @@ __device__ __attribute__((always_inline)) inline void dp_rows(const float (&cb)[
         const float best = __builtin_fminf(__builtin_fminf(c0, c1), c2);
         uint32_t code = (c1 == best) ? 1u : 2u;
         code = (c0 == best) ? 0u : code;
-        code = (best == kInf) ? 3u : code;
         if (r < 4) lo |= code << (8 * r); else hi |= code << (8 * (r - 4));
         d1 = best;
         s1p = s1;
@@ -178,7 +180,7 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
                                                                    bool have_out) {
     const int lane = threadIdx.x & 63;
     const int G = int(a.G);  // chunks per panel (rows padded to a multiple of 8)
-    const ChunkRanges cr = chunk_ranges(p, a.G);
+    const ChunkRanges cr = chunk_ranges(p, a.n, a.m, a.G);
     const float kInf = __builtin_inff();
     const int bcol = lane - (kLanes - 2);  // 0 / 1 on the two boundary lanes
     uint64_t* bp_pan = reinterpret_cast<uint64_t*>(a.bp) + int64_t(p) * G * kLanes;
@@ -486,6 +488,12 @@ __global__ void dp_prepare(DpWsHeader* hdr) {
     hdr->ticket = 0;
 }
 
+// No path reaches (n-1, m-1): the band is empty, nothing is swept.
+__global__ void dp_infeasible(float* total, int32_t* status) {
+    *total = __builtin_inff();
+    *status = PARDTW_PAIR_INFEASIBLE;
+}
+
 int choose_nw(int P) {
     // Four panels per workgroup (one compute wave per SIMD) measured fastest
     // from 188 panels (12000 columns) up; tiny problems keep fewer.
@@ -562,8 +570,12 @@ pardtw_status dp_launch(const float* C, pardtw_layout layout, int64_t n, int64_t
     // about four compute waves per CU (one per SIMD)
     const int per_cu = nw >= 4 ? 1 : 4 / nw;
     const int grid = a.S < cus * per_cu ? a.S : cus * per_cu;
-    // the DP reads only groups with a reachable cell, so both panel layouts are the same to it
+    // the DP reads only band groups, so both panel layouts are the same to it
     const bool panel = layout != PARDTW_LAYOUT_ROW;
+    if (!pair_feasible(n, m)) {
+        dp_infeasible<<<1, 1, 0, stream>>>(total, status);
+        return launch_status();
+    }
     dp_prepare<<<1, 1, 0, stream>>>(a.hdr);
     switch (nw) {
         case 1: launch_nw<1>(a, panel, grid, stream); break;
@@ -591,7 +603,7 @@ extern "C" pardtw_status pardtw_dp(const float* C, pardtw_layout layout, int64_t
                                    float* total, int32_t* pair_status, void* workspace,
                                    size_t workspace_bytes, hipStream_t stream) {
     if (!C || !bp || !total || !pair_status || !pardtw::valid_sizes(n, m)) return PARDTW_ERR_INVALID_ARG;
-    if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL && layout != PARDTW_LAYOUT_PANEL_REACHABLE)
+    if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL && layout != PARDTW_LAYOUT_PANEL_BAND)
         return PARDTW_ERR_UNSUPPORTED;
     if (!workspace || workspace_bytes < pardtw::dp_workspace_bytes_impl(n, m)) return PARDTW_ERR_WORKSPACE;
     return pardtw::dp_launch(C, layout, n, m, bp, total, pair_status, workspace, 0, stream);
@@ -601,7 +613,7 @@ extern "C" pardtw_status pardtw_dp_ex(const float* C, pardtw_layout layout, int6
                                       float* total, int32_t* pair_status, void* workspace, size_t workspace_bytes,
                                       int32_t panels_per_workgroup, hipStream_t stream) {
     if (!C || !bp || !total || !pair_status || !pardtw::valid_sizes(n, m)) return PARDTW_ERR_INVALID_ARG;
-    if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL && layout != PARDTW_LAYOUT_PANEL_REACHABLE)
+    if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL && layout != PARDTW_LAYOUT_PANEL_BAND)
         return PARDTW_ERR_UNSUPPORTED;
     if (panels_per_workgroup != 0 && panels_per_workgroup != 1 && panels_per_workgroup != 2 &&
         panels_per_workgroup != 4 && panels_per_workgroup != 8)

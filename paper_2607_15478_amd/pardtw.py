@@ -23,7 +23,7 @@ PREC_F32 = 0
 PREC_BF16 = 1
 LAYOUT_ROW = 0
 LAYOUT_PANEL = 1
-LAYOUT_PANEL_REACHABLE = 2  # panel layout, only the 8-row groups the DP reads are written
+LAYOUT_PANEL_BAND = 2  # panel layout, only the 8-row groups the DP reads (the path band) are written
 
 STATUS_NAMES = {0: "OK", 1: "ERR_INVALID_ARG", 2: "ERR_WORKSPACE", 3: "ERR_HIP", 4: "ERR_UNSUPPORTED"}
 
@@ -47,6 +47,7 @@ def _sig(name, res, args):
 
 _lib_cost_elems = _sig("pardtw_cost_elems", _SZ, [_I64, _I64, _E])
 _lib_bp_bytes = _sig("pardtw_bp_bytes", _SZ, [_I64, _I64])
+_lib_band = _sig("pardtw_band_groups", _E, [_I64, _I64, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_I64)])
 _lib_dp_ws = _sig("pardtw_dp_workspace_bytes", _SZ, [_I64, _I64])
 _lib_cost = _sig("pardtw_cost", _E, [_P, _P, _I64, _I64, _I64, _E, _E, _P, _P])
 _lib_dp = _sig("pardtw_dp", _E, [_P, _E, _I64, _I64, _P, _P, _P, _P, _SZ, _P])
@@ -96,6 +97,13 @@ def _dev_f32(t: torch.Tensor, name: str) -> torch.Tensor:
 # ---- sizes ------------------------------------------------------------------
 def pardtw_cost_elems(n: int, m: int, layout: int = LAYOUT_PANEL) -> int:
     return int(_lib_cost_elems(n, m, layout))
+
+
+def pardtw_band_groups(n: int, m: int, p: int):
+    """(lo, hi): the 8-row groups of panel p in the path band (empty if lo > hi)."""
+    lo, hi = _I64(), _I64()
+    _check(_lib_band(n, m, p, ctypes.byref(lo), ctypes.byref(hi)), "pardtw_band_groups")
+    return lo.value, hi.value
 
 
 def pardtw_bp_bytes(n: int, m: int) -> int:
@@ -164,7 +172,7 @@ def pardtw_path_grad(X, Y, path, path_len, g_total, dX, dY, stream=None):
 class Workspace:
     """Device buffers for one (n, m) alignment, reusable across calls."""
 
-    def __init__(self, n: int, m: int, device="cuda", layout: int = LAYOUT_PANEL_REACHABLE):
+    def __init__(self, n: int, m: int, device="cuda", layout: int = LAYOUT_PANEL_BAND):
         self.n, self.m, self.layout = n, m, layout
         self.C = torch.empty(pardtw_cost_elems(n, m, layout), dtype=torch.float32, device=device)
         self.bp = torch.empty(pardtw_bp_bytes(n, m), dtype=torch.uint8, device=device)
@@ -184,7 +192,7 @@ def align_into(X: torch.Tensor, Y: torch.Tensor, w: Workspace, prec: int = PREC_
     return w
 
 
-def align(X: torch.Tensor, Y: torch.Tensor, prec: int = PREC_F32, layout: int = LAYOUT_PANEL_REACHABLE):
+def align(X: torch.Tensor, Y: torch.Tensor, prec: int = PREC_F32, layout: int = LAYOUT_PANEL_BAND):
     """Exact DTW of two feature sequences on the GPU: (total, path (L,2) int32, status)."""
     w = Workspace(X.shape[0], Y.shape[0], X.device, layout)
     align_into(X, Y, w, prec)

@@ -81,6 +81,36 @@ def audit_bp_matrix(gpu_bp: np.ndarray, oracle_bp: np.ndarray, D: np.ndarray, C:
     return len(diff)
 
 
+def band_mask(n: int, m: int) -> np.ndarray:
+    """(n, m) bool: cells that can lie on a path from (0,0) to (n-1,m-1) with
+    the steps (1,1), (1,2), (2,1): reachable from the origin (j <= 2i and
+    i <= 2j) and able to reach the end ((m-1-j) <= 2(n-1-i) and
+    (n-1-i) <= 2(m-1-j)). The DP defines codes on these cells only."""
+    i = np.arange(n)[:, None]
+    j = np.arange(m)[None, :]
+    fwd = (j <= 2 * i) & (i <= 2 * j)
+    ri, rj = n - 1 - i, m - 1 - j
+    end = (rj <= 2 * ri) & (ri <= 2 * rj)
+    return fwd & end
+
+
+def band_groups(n: int, m: int) -> np.ndarray:
+    """(P, G) bool: 8-row group k of 64-column panel p holds a real cell
+    reachable from the origin and a real cell from which (n-1,m-1) is
+    reachable (enumerated cell by cell): the groups the band layout writes."""
+    P, G = -(-m // 64), -(-n // 8)
+    i = np.arange(n)[:, None]
+    j = np.arange(m)[None, :]
+    fwd = (j <= 2 * i) & (i <= 2 * j)
+    ri, rj = n - 1 - i, m - 1 - j
+    end = (rj <= 2 * ri) & (ri <= 2 * rj)
+    def per_group(mask):
+        pad = np.zeros((G * 8, P * 64), dtype=bool)
+        pad[:n, :m] = mask
+        return pad.reshape(G, 8, P, 64).any(axis=(1, 3)).T
+    return per_group(fwd) & per_group(end)
+
+
 def check_total(gpu_total: float, oracle_total: float):
     if not np.isfinite(oracle_total):
         assert not np.isfinite(gpu_total)

@@ -52,6 +52,29 @@ def test_size_helpers(lib):
     assert lib.pardtw_cost_elems(3, 5, 7) == 0
 
 
+@pytest.mark.parametrize("n,m", [(1, 1), (8, 8), (9, 5), (5, 9), (100, 199), (100, 200), (333, 400), (520, 700),
+                                 (700, 520), (1000, 130), (130, 1000), (1000, 1999), (1999, 1000), (2000, 2400),
+                                 (777, 1500), (3001, 1501)])
+def test_band_groups_match_cell_enumeration(lib, n, m):
+    """The kernels' band bounds against the band enumerated cell by cell."""
+    from tests import parity
+    import numpy as np
+    I = ctypes.c_int64
+    lib.pardtw_band_groups.restype = ctypes.c_int
+    lib.pardtw_band_groups.argtypes = [I, I, I, ctypes.POINTER(I), ctypes.POINTER(I)]
+    want = parity.band_groups(n, m)
+    P, G = want.shape
+    lo, hi = I(), I()
+    for p in range(P):
+        assert lib.pardtw_band_groups(n, m, p, ctypes.byref(lo), ctypes.byref(hi)) == 0
+        got = np.zeros(G, dtype=bool)
+        if lo.value <= hi.value:
+            got[lo.value:hi.value + 1] = True
+        assert np.array_equal(got, want[p]), (n, m, p, lo.value, hi.value, np.nonzero(want[p])[0][[0, -1]] if want[p].any() else None)
+    assert lib.pardtw_band_groups(n, m, P, ctypes.byref(lo), ctypes.byref(hi)) != 0
+    assert lib.pardtw_band_groups(n, m, 0, None, ctypes.byref(hi)) != 0
+
+
 def test_validation_without_gpu(lib):
     I = ctypes.c_int64
     P = ctypes.c_void_p

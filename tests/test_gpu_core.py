@@ -44,14 +44,19 @@ SHAPES = [(1, 1), (2, 2), (2, 3), (3, 2), (4, 4), (5, 9), (9, 5), (7, 1), (1, 7)
 
 @pytest.mark.parametrize("n,m", SHAPES)
 def test_dp_integer_costs_bit_exact(n, m):
-    """Small-integer costs: every sum is exact in FP32 and FP64, so the full
-    backtrace matrix, the total and the path must match bit for bit,
-    including the tie rule and unreachable cells."""
+    """Small-integer costs: every sum is exact in FP32 and FP64, so the codes
+    of every cell that can lie on a path (the band), the total and the path
+    must match bit for bit, including the tie rule."""
     rng = np.random.default_rng(n * 1000 + m)
     C = rng.integers(0, 3, size=(n, m)).astype(np.float32)
     total, BP, _ = oracle.dtw_matrix(C)
     g_total, g_status, g_BP, g_path = _gpu_dp(C)
-    assert np.array_equal(g_BP, BP)
+    band = parity.band_mask(n, m)
+    assert np.array_equal(g_BP[band], BP[band])
+    # band cells are reachable: the oracle gives them a real step, the origin code 3
+    inner = band.copy()
+    inner[0, 0] = False
+    assert np.all(BP[inner] <= 2) and (not band[0, 0] or BP[0, 0] == 3)
     if oracle.feasible(n, m):
         assert g_status == pd.PAIR_OK and g_total == total
         assert np.array_equal(g_path, oracle.backtrace(BP))
@@ -78,6 +83,8 @@ def test_dp_random_costs_full_bp(n, m):
     C = rng.uniform(0.0, 1.0, size=(n, m)).astype(np.float32)
     total, BP, D = oracle.dtw_matrix(C, want_D=True)
     g_total, g_status, g_BP, g_path = _gpu_dp(C)
+    band = parity.band_mask(n, m)
+    g_BP = np.where(band, g_BP, BP)  # codes outside the band are unspecified
     ties = parity.audit_bp_matrix(g_BP, BP, D, C)
     assert ties <= 1e-4 * n * m + 5
     parity.check_total(g_total, total)
@@ -90,10 +97,11 @@ def test_dp_schedules_and_layouts_bit_identical(nw):
     n, m = 777, 1500  # 24 panels, ragged last panel and last row group
     C = rng.uniform(0.0, 1.0, size=(n, m)).astype(np.float32)
     ref = _gpu_dp(C, pd.LAYOUT_ROW, nw=1)
+    band = parity.band_mask(n, m)
     for layout in (pd.LAYOUT_ROW, pd.LAYOUT_PANEL):
         got = _gpu_dp(C, layout, nw=nw)
         assert got[0] == ref[0] and got[1] == ref[1]
-        assert np.array_equal(got[2], ref[2]) and np.array_equal(got[3], ref[3])
+        assert np.array_equal(got[2][band], ref[2][band]) and np.array_equal(got[3], ref[3])
 
 
 def _gpu_cost(X, Y, prec=pd.PREC_F32, layout=pd.LAYOUT_ROW):
@@ -130,60 +138,55 @@ def test_cost_bf16_against_oracle_on_rounded_inputs(n, m, d):
     assert np.max(np.abs(got - ref)) < 1e-5 * max(1.0, np.sqrt(d / 12))
 
 
-def _reached_groups(n, m):
-    """(P, G) bool: 8-row group k of panel p holds a cell (i, j), i in
-    [8k, 8k+8), j in [64p, 64p+64), reachable from (0,0) by the three steps,
-    i.e. with j <= 2i and i <= 2j (enumerated cell by cell)."""
-    P, G = -(-m // 64), -(-n // 8)
-    i = np.arange(G * 8)[:, None]
-    j = np.arange(P * 64)[None, :]
-    ok = (j <= 2 * i) & (i <= 2 * j)
-    return ok.reshape(G, 8, P, 64).any(axis=(1, 3)).T
-
-
 @pytest.mark.parametrize("n,m,d,prec", [(1, 1, 12, pd.PREC_F32), (333, 257, 12, pd.PREC_F32),
                                         (700, 900, 12, pd.PREC_F32), (900, 700, 12, pd.PREC_F32),
                                         (1000, 130, 64, pd.PREC_F32), (600, 650, 33, pd.PREC_F32),
-                                        (520, 700, 40, pd.PREC_BF16), (2000, 2400, 12, pd.PREC_F32)])
-def test_cost_reachable_layout_writes_exactly_the_reached_groups(n, m, d, prec):
+                                        (520, 700, 40, pd.PREC_BF16), (2000, 2400, 12, pd.PREC_F32),
+                                        (1000, 1999, 12, pd.PREC_F32), (1999, 1000, 12, pd.PREC_F32),
+                                        (3000, 2000, 12, pd.PREC_F32), (130, 1000, 12, pd.PREC_F32)])
+def test_cost_band_layout_writes_exactly_the_band_groups(n, m, d, prec):
     rng = np.random.default_rng(n * 7 + m + d)
     X = rng.normal(size=(n, d)).astype(np.float32)
     Y = rng.normal(size=(m, d)).astype(np.float32)
     Xd, Yd = torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV)
     full = torch.empty(pd.pardtw_cost_elems(n, m, pd.LAYOUT_PANEL), dtype=torch.float32, device=DEV)
     pd.pardtw_cost(Xd, Yd, full, prec, pd.LAYOUT_PANEL)
-    part = torch.full((pd.pardtw_cost_elems(n, m, pd.LAYOUT_PANEL_REACHABLE),), float("nan"), device=DEV)
-    pd.pardtw_cost(Xd, Yd, part, prec, pd.LAYOUT_PANEL_REACHABLE)
+    part = torch.full((pd.pardtw_cost_elems(n, m, pd.LAYOUT_PANEL_BAND),), float("nan"), device=DEV)
+    pd.pardtw_cost(Xd, Yd, part, prec, pd.LAYOUT_PANEL_BAND)
     P, G = -(-m // 64), -(-n // 8)
     f = full.cpu().numpy().reshape(P, G, 512)
     g = part.cpu().numpy().reshape(P, G, 512)
-    reached = _reached_groups(n, m)
-    assert np.array_equal(f[reached], g[reached])          # written groups: the panel layout bit for bit
-    assert np.all(np.isnan(g[~reached]))                    # the others untouched
+    written = parity.band_groups(n, m)
+    assert np.array_equal(f[written], g[written])          # written groups: the panel layout bit for bit
+    assert np.all(np.isnan(g[~written]))                    # the others untouched
 
 
-@pytest.mark.parametrize("n,m", [(64, 65), (333, 400), (520, 700), (700, 520), (1500, 1300)])
-def test_dp_on_reachable_layout_matches_full_layout(n, m):
+@pytest.mark.parametrize("n,m", [(64, 65), (333, 400), (520, 700), (700, 520), (1500, 1300), (1000, 1999),
+                                 (1999, 1000), (500, 1200)])
+def test_dp_on_band_layout_matches_full_layout(n, m):
     rng = np.random.default_rng(n + 3 * m)
     X = rng.normal(size=(n, 12)).astype(np.float32)
     Y = rng.normal(size=(m, 12)).astype(np.float32)
     Xd, Yd = torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV)
     outs = []
-    for layout in (pd.LAYOUT_PANEL, pd.LAYOUT_PANEL_REACHABLE):
+    for layout in (pd.LAYOUT_PANEL, pd.LAYOUT_PANEL_BAND):
         w = pd.Workspace(n, m, DEV, layout)
         w.C.fill_(float("nan"))  # a read of an unwritten group would poison the result
         pd.align_into(Xd, Yd, w)
+        B = pd.pardtw_bp_unpack(w.bp, n, m)
         torch.cuda.synchronize()
         L = int(w.path_len.item())
-        outs.append((float(w.total.item()), int(w.status.item()), w.bp.cpu().numpy(), w.path[:L].cpu().numpy()))
+        outs.append((float(w.total.item()), int(w.status.item()), B.cpu().numpy(), w.path[:L].cpu().numpy()))
     a, b = outs
+    band = parity.band_mask(n, m)
     assert a[0] == b[0] and a[1] == b[1]
-    assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3])
-    assert np.isfinite(a[0]) == pd_feasible(n, m)
-
-
-def pd_feasible(n, m):
-    return (m - 1) <= 2 * (n - 1) and (n - 1) <= 2 * (m - 1)
+    assert np.array_equal(a[2][band], b[2][band]) and np.array_equal(a[3], b[3])
+    assert np.isfinite(a[0]) == oracle.feasible(n, m)
+    if oracle.feasible(n, m):
+        t_o, p_o, _ = oracle.align(X, Y)
+        parity.check_total(a[0], t_o)
+        parity.check_legal(a[3], n, m)
+        assert np.all(band[a[3][:, 0], a[3][:, 1]])  # the path stays in the band
 
 
 def _align(X, Y, prec=pd.PREC_F32):

@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests import brute
+from tests import brute, parity
 
 
 def _rand_C(rng, n, m, kind):
@@ -285,3 +285,27 @@ def test_gradient_finite_differences():
         assert fd == pytest.approx(an, rel=1e-4, abs=1e-7)
         checked += 1
     assert checked >= 40
+
+
+@pytest.mark.parametrize("n,m", [(1, 1), (2, 3), (3, 10), (7, 5), (5, 9), (13, 20), (20, 13), (30, 31), (17, 40)])
+def test_band_mask_is_forward_and_backward_reachability(n, m):
+    """The band helper used by the parity tests equals the set of cells reached
+    from (0,0) by the three steps and reaching (n-1, m-1), found by search."""
+    steps = [(1, 1), (1, 2), (2, 1)]
+    fwd = np.zeros((n, m), dtype=bool)
+    fwd[0, 0] = True
+    for i in range(n):
+        for j in range(m):
+            if fwd[i, j]:
+                for di, dj in steps:
+                    if i + di < n and j + dj < m:
+                        fwd[i + di, j + dj] = True
+    bwd = np.zeros((n, m), dtype=bool)
+    bwd[n - 1, m - 1] = True
+    for i in range(n - 1, -1, -1):
+        for j in range(m - 1, -1, -1):
+            if bwd[i, j]:
+                for di, dj in steps:
+                    if i - di >= 0 and j - dj >= 0:
+                        bwd[i - di, j - dj] = True
+    assert np.array_equal(parity.band_mask(n, m), fwd & bwd)
