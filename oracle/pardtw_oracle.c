@@ -306,3 +306,228 @@ int oracle_path_grad(const float* X, const float* Y, int64_t n, int64_t m, int64
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Subsequence DTW and the segment-level programs of Segmental DTW
+ * (Sec. II-B to II-D: NSDTW and WSDTW).
+ *
+ * Subsequence DTW aligns a short query (a fragment of sequence A, rows i) with
+ * the best-matching stretch of a long reference (sequence B, columns j). The
+ * steps are the same (query, reference) steps (1,1), (1,2), (2,1), now with
+ * multiplicative weights 1, 1, 2 (Sec. II-B), still applied to the cell a step
+ * lands on. A path may begin anywhere on the first query row at no extra
+ * charge: D[0,j] = C[0,j] (start cell weight 1, code 3). For i >= 1
+ *     D[i,j] = min( D[i-1,j-1] + C[i,j],
+ *                   D[i-1,j-2] + C[i,j],
+ *                   D[i-2,j-1] + 2 C[i,j] )
+ * with out-of-range predecessors +inf, exact ties to the lowest step index,
+ * and code 3 where all three are +inf. The weights equal each step's advance
+ * along the query, so every path from row 0 to row n-1 carries total weight n
+ * and the scores S[j] = D[n-1,j] of different end columns are comparable.
+ * ------------------------------------------------------------------------ */
+
+static const double SUB_W[3] = {1.0, 1.0, 2.0};
+
+static void sub_row(int64_t i, int64_t m, const double* crow, const double* prev1, const double* prev2,
+                    double* cur, int8_t* bp_row, double* cand) {
+    for (int64_t j = 0; j < m; ++j) {
+        double c = crow[j];
+        double cd[3];
+        cd[0] = (prev1 && j >= 1) ? prev1[j - 1] + SUB_W[0] * c : INFINITY;
+        cd[1] = (prev1 && j >= 2) ? prev1[j - 2] + SUB_W[1] * c : INFINITY;
+        cd[2] = (prev2 && j >= 1) ? prev2[j - 1] + SUB_W[2] * c : INFINITY;
+        double best = cd[0];
+        int code = CODE_DIAG;
+        if (cd[1] < best) { best = cd[1]; code = CODE_RIGHT; }
+        if (cd[2] < best) { best = cd[2]; code = CODE_DOWN; }
+        if (isinf(best) && best > 0) code = CODE_NONE;
+        if (i == 0) { best = c; code = CODE_NONE; }  /* free start on the first query row */
+        cur[j] = best;
+        if (bp_row) bp_row[j] = (int8_t)code;
+        if (cand) { cand[3 * j] = cd[0]; cand[3 * j + 1] = cd[1]; cand[3 * j + 2] = cd[2]; }
+    }
+}
+
+/* Cost rows come from an FP64 matrix (C64), an FP32 matrix (C32, widened
+ * exactly) or features (X, Y). D_opt (n*m) and BP (n*m) are optional; S (m)
+ * receives the last row. */
+static int sub_sweep(const double* C64, const float* C32, const float* X, const float* Y, int64_t n, int64_t m,
+                     int64_t d, double* D_opt, int8_t* BP, double* S) {
+    if (n <= 0 || m <= 0) return -1;
+    double* xh = NULL;
+    double* yh = NULL;
+    if (!C64 && !C32) {
+        xh = unit_rows(X, n, d);
+        yh = unit_rows(Y, m, d);
+        if (!xh || !yh) { free(xh); free(yh); return -1; }
+    }
+    double* rows = (double*)malloc(sizeof(double) * (size_t)(4 * m));
+    if (!rows) { free(xh); free(yh); return -1; }
+    double* r[3] = {rows, rows + m, rows + 2 * m};
+    double* crow = rows + 3 * m;
+    for (int64_t i = 0; i < n; ++i) {
+        if (C64) memcpy(crow, C64 + i * m, sizeof(double) * (size_t)m);
+        else if (C32) for (int64_t j = 0; j < m; ++j) crow[j] = (double)C32[i * m + j];
+        else cost_row(xh + i * d, yh, m, d, crow);
+        double* cur = r[i % 3];
+        const double* p1 = i >= 1 ? r[(i - 1) % 3] : NULL;
+        const double* p2 = i >= 2 ? r[(i - 2) % 3] : NULL;
+        sub_row(i, m, crow, p1, p2, cur, BP ? BP + i * m : NULL, NULL);
+        if (D_opt) memcpy(D_opt + i * m, cur, sizeof(double) * (size_t)m);
+    }
+    memcpy(S, r[(n - 1) % 3], sizeof(double) * (size_t)m);
+    free(xh); free(yh); free(rows);
+    return 0;
+}
+
+int oracle_subseq_matrix(const double* C, int64_t n, int64_t m, double* D_opt, int8_t* BP, double* S) {
+    return sub_sweep(C, NULL, NULL, NULL, n, m, 0, D_opt, BP, S);
+}
+
+int oracle_subseq_matrix_f32(const float* C, int64_t n, int64_t m, double* D_opt, int8_t* BP, double* S) {
+    return sub_sweep(NULL, C, NULL, NULL, n, m, 0, D_opt, BP, S);
+}
+
+int oracle_subseq_features(const float* X, const float* Y, int64_t n, int64_t m, int64_t d, int8_t* BP, double* S) {
+    if (d <= 0) return -1;
+    return sub_sweep(NULL, NULL, X, Y, n, m, d, NULL, BP, S);
+}
+
+/* Candidate totals and D at requested cells (sorted by row), as oracle_probe
+ * does for DTW, from an FP32 cost matrix or from features. */
+int oracle_subseq_probe(const float* X, const float* Y, const float* C32, int64_t n, int64_t m, int64_t d,
+                        const int64_t* ci, const int64_t* cj, int64_t k, double* cand, double* dval) {
+    if (n <= 0 || m <= 0) return -1;
+    double* xh = NULL;
+    double* yh = NULL;
+    if (!C32) {
+        xh = unit_rows(X, n, d);
+        yh = unit_rows(Y, m, d);
+        if (!xh || !yh) { free(xh); free(yh); return -1; }
+    }
+    double* rows = (double*)malloc(sizeof(double) * (size_t)(4 * m));
+    double* rc = (double*)malloc(sizeof(double) * (size_t)(3 * m));
+    if (!rows || !rc) { free(xh); free(yh); free(rows); free(rc); return -1; }
+    double* r[3] = {rows, rows + m, rows + 2 * m};
+    double* crow = rows + 3 * m;
+    int64_t q = 0;
+    for (int64_t i = 0; i < n && q < k; ++i) {
+        if (C32) for (int64_t j = 0; j < m; ++j) crow[j] = (double)C32[i * m + j];
+        else cost_row(xh + i * d, yh, m, d, crow);
+        double* cur = r[i % 3];
+        const double* p1 = i >= 1 ? r[(i - 1) % 3] : NULL;
+        const double* p2 = i >= 2 ? r[(i - 2) % 3] : NULL;
+        sub_row(i, m, crow, p1, p2, cur, NULL, rc);
+        while (q < k && ci[q] == i) {
+            int64_t j = cj[q];
+            cand[3 * q] = rc[3 * j];
+            cand[3 * q + 1] = rc[3 * j + 1];
+            cand[3 * q + 2] = rc[3 * j + 2];
+            dval[q] = cur[j];
+            ++q;
+        }
+        if (q < k && ci[q] < i) { free(xh); free(yh); free(rows); free(rc); return -2; }
+    }
+    free(xh); free(yh); free(rows); free(rc);
+    return q == k ? 0 : -3;
+}
+
+/* Backtrace of a subsequence path ending at (n-1, end): follow the codes up
+ * to the first query row. Writes the path forward (capacity n pairs) and
+ * returns its length, 0 when (n-1, end) is unreachable, -1 on malformed codes. */
+int64_t oracle_subseq_backtrace(const int8_t* BP, int64_t n, int64_t m, int64_t end, int32_t* path) {
+    if (end < 0 || end >= m) return 0;
+    int64_t i = n - 1, j = end, len = 0;
+    int32_t* rev = (int32_t*)malloc(sizeof(int32_t) * (size_t)(2 * n));
+    if (!rev) return -1;
+    for (;;) {
+        if (len >= n) { free(rev); return -1; }
+        rev[2 * len] = (int32_t)i;
+        rev[2 * len + 1] = (int32_t)j;
+        ++len;
+        if (i == 0) break;
+        int code = BP[i * m + j];
+        if (code == CODE_NONE && len == 1) { free(rev); return 0; }
+        if (code < 0 || code > 2) { free(rev); return -1; }
+        i -= STEP_DI[code];
+        j -= STEP_DJ[code];
+        if (i < 0 || j < 0) { free(rev); return -1; }
+    }
+    for (int64_t l = 0; l < len; ++l) {
+        path[2 * l] = rev[2 * (len - 1 - l)];
+        path[2 * l + 1] = rev[2 * (len - 1 - l) + 1];
+    }
+    free(rev);
+    return len;
+}
+
+/* Segment level (Sec. II-C steps 3-4; Sec. II-B for NSDTW). S is the
+ * (nf x m) matrix whose row f holds fragment f's subsequence scores, one per
+ * end column (the segment-level cost matrix).
+ *
+ * variant 0, NSDTW: each fragment independently ends at its lowest score
+ *   (the first such column); total = sum of those scores.
+ * variant 1, WSDTW: a path through S with (fragment, column) transitions
+ *   (0,1), a free skip, and (1,hop), a match that pays S[f,j]:
+ *       Dseg[f,j] = min( Dseg[f,j-1], Dseg[f-1,j-hop] + S[f,j] ),
+ *   Dseg[f,-1] = +inf, Dseg[-1,j] = 0 for every j (the first fragment may end
+ *   anywhere), Dseg[f-1,j-hop] = +inf for f >= 1 and j < hop. A match replaces
+ *   the skip only when strictly smaller (the skip is the first term). The
+ *   total is Dseg[nf-1,m-1]; backtracking from there, a match at (f,j) ends
+ *   fragment f at column j and moves to (f-1, j-hop), a skip moves to (f, j-1).
+ * ends[f] = -1 and total = +inf when no placement has a finite score.
+ * Returns 0 on success. */
+int oracle_segment_ends(const double* S, int64_t nf, int64_t m, int64_t hop, int variant, int64_t* ends,
+                        double* total) {
+    if (nf <= 0 || m <= 0 || hop < 1) return -1;
+    if (variant == 0) {
+        double sum = 0.0;
+        for (int64_t f = 0; f < nf; ++f) {
+            int64_t arg = -1;
+            double best = INFINITY;
+            for (int64_t j = 0; j < m; ++j)
+                if (S[f * m + j] < best) { best = S[f * m + j]; arg = j; }
+            ends[f] = arg;
+            sum += best;
+        }
+        *total = sum;
+        if (isinf(sum)) for (int64_t f = 0; f < nf; ++f) ends[f] = -1;
+        return 0;
+    }
+    if (variant != 1) return -1;
+    double* D = (double*)malloc(sizeof(double) * (size_t)(nf * m));
+    uint8_t* match = (uint8_t*)malloc((size_t)(nf * m));
+    if (!D || !match) { free(D); free(match); return -1; }
+    for (int64_t f = 0; f < nf; ++f) {
+        for (int64_t j = 0; j < m; ++j) {
+            double skip = j >= 1 ? D[f * m + j - 1] : INFINITY;
+            double prev;
+            if (f == 0) prev = 0.0;
+            else prev = j >= hop ? D[(f - 1) * m + j - hop] : INFINITY;
+            double take = prev + S[f * m + j];
+            double best = skip;
+            uint8_t mt = 0;
+            if (take < best) { best = take; mt = 1; }
+            D[f * m + j] = best;
+            match[f * m + j] = mt;
+        }
+    }
+    *total = D[(nf - 1) * m + m - 1];
+    for (int64_t f = 0; f < nf; ++f) ends[f] = -1;
+    if (!isinf(*total)) {
+        int64_t f = nf - 1, j = m - 1;
+        while (f >= 0) {
+            if (j < 0) { free(D); free(match); return -2; }
+            if (match[f * m + j]) {
+                ends[f] = j;
+                j -= hop;
+                --f;
+            } else {
+                --j;
+            }
+        }
+    }
+    free(D);
+    free(match);
+    return 0;
+}
