@@ -78,7 +78,16 @@ typedef enum {
      * Other groups are left untouched (about 70% of a 5:6 pair). Same size
      * and element placement as PARDTW_LAYOUT_PANEL; pardtw_dp treats the two
      * alike. */
-    PARDTW_LAYOUT_PANEL_BAND = 2
+    PARDTW_LAYOUT_PANEL_BAND = 2,
+    /* The panel layout with only the 8-row groups that pardtw_subseq_dp reads:
+     * the band of cells that can lie on a subsequence path (Sec. II-B), which
+     * starts anywhere on row 0 and ends anywhere on row N-1. A group of panel
+     * p is written when it holds a real cell that row 0 reaches (i <= 2j) and
+     * a real cell that reaches row N-1 ((N-1-i) <= 2(M-1-j)); with
+     * j1 = min(64p+63, M-1):
+     *   max(0, ceil((N-8-2(M-1-64p))/8)) <= i/8 <= floor(j1/4).
+     * Same size and element placement as PARDTW_LAYOUT_PANEL. */
+    PARDTW_LAYOUT_PANEL_SUBSEQ_BAND = 3
 } pardtw_layout;
 
 #define PARDTW_PAIR_OK 0
@@ -237,6 +246,123 @@ pardtw_status pardtw_path_grad_batch(const pardtw_plan* plan, const float* X_pac
                                      const float* Y_packed, const int32_t* paths_packed,
                                      const int32_t* path_len, const float* g_totals, float* dX_packed,
                                      float* dY_packed, hipStream_t stream);
+
+/* ---- Subsequence DTW and Segmental DTW (Sec. II-B, II-C, III-A) ------------
+ * The paper's other GPU algorithm. Sequence A (la x d) is cut into nfrag
+ * fragments of nearly equal length, fragment f being rows
+ * [floor(f la / nfrag), floor((f+1) la / nfrag)). Each fragment (the query,
+ * rows i) is aligned with all of sequence B (the reference, lb x d, columns j)
+ * by subsequence DTW: steps (1,1), (1,2), (2,1) with weights 1, 1, 2 on the
+ * cell a step lands on, a free start anywhere on the first query row,
+ *   D[0,j] = C[0,j],
+ *   D[i,j] = min(D[i-1,j-1] + C, D[i-1,j-2] + C, D[i-2,j-1] + 2C),
+ * codes 0/1/2 as for DTW (exact ties to the lowest), 3 on row 0. The score of
+ * an end column is S[j] = D[n-1, j]; every such path weighs n, so scores of
+ * different ends compare directly. A cell is reachable iff i <= 2j, so S[j] is
+ * +inf for 2j < n-1. The fragments' scores stacked as rows give the
+ * segment-level cost matrix S (nfrag x lb), and the fragment end columns
+ * come from it:
+ *   variant 0, NSDTW: each fragment ends at its lowest score (the first such
+ *     column); total = the sum of those scores.
+ *   variant 1, WSDTW: Dseg[f,j] = min(Dseg[f,j-1], Dseg[f-1,j-hop] + S[f,j])
+ *     with Dseg[-1,.] = 0, Dseg[f,-1] = +inf, and +inf for f >= 1, j < hop; a
+ *     match replaces the skip only when strictly smaller; total =
+ *     Dseg[nfrag-1, lb-1]; ends are strictly increasing, at least hop apart.
+ *     hop = max(1, floor(la / (2 nfrag))): the shortest stretch of B a fragment
+ *     can match under a warping factor of at most 2.
+ * Each fragment is then backtraced from its end to row 0, and the fragment
+ * paths, shifted to A's row numbering and concatenated, are the alignment.
+ * The scores and codes are exactly those of the whole-reference subsequence
+ * DP, which is what the paper's overlapping reference chunks compute (Sec.
+ * III-A); here the staircase sweep already keeps every panel of B busy, so no
+ * chunk is recomputed. */
+#define PARDTW_NSDTW 0
+#define PARDTW_WSDTW 1
+
+/* Host-side helper: the 8-row groups [*lo, *hi] of panel p that
+ * PARDTW_LAYOUT_PANEL_SUBSEQ_BAND writes and pardtw_subseq_dp reads, clamped to
+ * [0, ceil(N/8) - 1]; empty when *lo > *hi. Errors as pardtw_band_groups. */
+pardtw_status pardtw_subseq_band_groups(int64_t n, int64_t m, int64_t p, int64_t* lo, int64_t* hi);
+
+/* Subsequence DP of one fragment (n rows) against the reference (m columns),
+ * swept as pardtw_dp sweeps DTW, with the same per-cell arithmetic:
+ * cand_r = fmaf(w_r, C, D_pred_r), w = (1, 1, 2), strict less-than in order.
+ *   C [device]: cost in layout ROW, PANEL or PANEL_SUBSEQ_BAND (for the last,
+ *   only the groups it writes are read).
+ *   bp [device, pardtw_bp_bytes(n,m)]: codes in the layout of pardtw_dp,
+ *   defined on the subsequence band (3 on row 0); other bytes unspecified.
+ *   scores [device, m floats]: S[j] = D[n-1, j] (+inf where unreachable).
+ *   pair_status [device, 1 int32]: PARDTW_PAIR_OK, or PARDTW_PAIR_INFEASIBLE
+ *   when no end is reachable (n-1 > 2(m-1); every score +inf, nothing swept).
+ *   workspace [device, >= pardtw_dp_workspace_bytes(n,m)], as for pardtw_dp.
+ * PARDTW_ERR_UNSUPPORTED for PARDTW_LAYOUT_PANEL_BAND. */
+pardtw_status pardtw_subseq_dp(const float* C, pardtw_layout layout, int64_t n, int64_t m, uint8_t* bp,
+                               float* scores, int32_t* pair_status, void* workspace, size_t workspace_bytes,
+                               hipStream_t stream);
+
+/* Backtrace of a subsequence path from (n-1, *end_col) to row 0 along the
+ * codes of pardtw_subseq_dp.
+ *   end_col [device, 1 int32]: end column; a column outside [0, m) or one row
+ *   n-1 cannot reach (2 end < n-1) gives path_len 0.
+ *   path [device, 2*n int32, 8-byte aligned]: (i, j) pairs in forward order.
+ *   path_len [device, 1 int32]: pairs written (0 when malformed codes stop
+ *   the walk). */
+pardtw_status pardtw_subseq_backtrace(const uint8_t* bp, int64_t n, int64_t m, const int32_t* end_col,
+                                      int32_t* path, int32_t* path_len, hipStream_t stream);
+
+/* Device workspace of pardtw_segment_ends (0 on bad args). Zero it once
+ * before first use; calls sharing it must not overlap in time. */
+size_t pardtw_segment_workspace_bytes(int64_t nfrag, int64_t m);
+
+/* Segment level (Sec. II-C steps 3-4, or NSDTW's choice): fragment ends from
+ * the stacked scores, as described above. The WSDTW program runs one
+ * workgroup per fragment row, each scanning its row in tiles as soon as the
+ * row before has published the tile it needs.
+ *   scores [device, nfrag*m FP32, row-major]: S, row f = fragment f.
+ *   hop >= 1; variant PARDTW_NSDTW or PARDTW_WSDTW.
+ *   ends [device, nfrag int32]: end column per fragment (-1 when infeasible).
+ *   total [device, 1 float]: the segment-level total in FP32 (+inf when no
+ *   placement has a finite score).
+ *   status [device, 1 int32]: PARDTW_PAIR_OK / PARDTW_PAIR_INFEASIBLE. */
+pardtw_status pardtw_segment_ends(const float* scores, int64_t nfrag, int64_t m, int64_t hop, int32_t variant,
+                                  void* workspace, size_t workspace_bytes, int32_t* ends, float* total,
+                                  int32_t* status, hipStream_t stream);
+
+/* A plan for Segmental DTW of A (la x d) against B (lb x d) with nfrag
+ * fragments (1 <= nfrag <= la). It is a pardtw_plan: free it with
+ * pardtw_plan_destroy, size its workspace (256-byte aligned, zeroed once) with
+ * pardtw_plan_workspace_bytes, and choose its DP schedule with the schedule
+ * calls above. */
+pardtw_status pardtw_segplan_create(int64_t la, int64_t lb, int32_t nfrag, int64_t d, pardtw_prec prec,
+                                    int32_t variant, pardtw_plan** plan);
+
+/* The autotuner of a Segmental DTW plan: computes the fragments' costs once,
+ * times the subsequence DP under every schedule (one warm-up, then `reps`
+ * launches) and selects the fastest; *best_ms (may be NULL) receives its time.
+ * Synchronises the stream. */
+pardtw_status pardtw_segplan_autotune(pardtw_plan* plan, const float* A, const float* B, void* workspace,
+                                      size_t workspace_bytes, int32_t reps, float* best_ms, hipStream_t stream);
+
+/* Byte offset, in the plan's workspace, of the stacked fragment scores S
+ * (nfrag x lb FP32, row-major) left by the last pardtw_segmental_align call
+ * (-1 for a plan of pairs). */
+int64_t pardtw_segplan_scores_offset(const pardtw_plan* plan);
+
+/* Segmental DTW with one call: the cost GEMM of every fragment against B (only
+ * the subsequence band), the subsequence DP of all fragments as one persistent
+ * launch, the segment-level program, the fragments' backtraces (one workgroup
+ * each) and their concatenation. No allocation, copy or synchronisation; it
+ * can be captured in a hipGraph.
+ *   A [device, la*d FP32], B [device, lb*d FP32].
+ *   total [device, 1 float], ends [device, nfrag int32], status [device, 1
+ *   int32]: as pardtw_segment_ends.
+ *   path [device, 2*la int32, 8-byte aligned]: the concatenated alignment,
+ *   (i, j) pairs with i in A's numbering, fragment by fragment (i strictly
+ *   increases; j increases within a fragment).
+ *   path_len [device, 1 int32]: pairs written (0 when infeasible). */
+pardtw_status pardtw_segmental_align(const pardtw_plan* plan, const float* A, const float* B, void* workspace,
+                                     size_t workspace_bytes, float* total, int32_t* ends, int32_t* path,
+                                     int32_t* path_len, int32_t* status, hipStream_t stream);
 
 const char* pardtw_status_string(pardtw_status status);
 

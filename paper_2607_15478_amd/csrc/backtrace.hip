@@ -27,6 +27,9 @@
 //   scalar loop checks every step for the origin instead.
 // * The path is written from the back of the output (the walk runs backward)
 //   and shifted to the front by the whole workgroup at the end.
+//
+// A subsequence path (Sec. II-B) is walked the same way from (n-1, end) and
+// stops on row 0, wherever it lands there.
 #include "batch.h"
 
 namespace pardtw {
@@ -134,11 +137,13 @@ __device__ inline uint32_t trace_window(const WindowMasks& w, int lane) {
     return on;
 }
 
-// Walker: returns the path length (0 if the codes do not lead to the origin).
-__device__ int walk(BtShared& sh, int n, int m, int P, int32_t* path) {
+// Walker: from (n-1, j_end) back to the origin, or with `sub` to row 0.
+// Returns the path length (0 if the codes do not lead there). The output holds
+// `cap` pairs.
+__device__ int walk(BtShared& sh, int n, int j_end, bool sub, int cap, int32_t* path) {
     const int lane = threadIdx.x;
-    const int cap = n < m ? n : m;
-    int i = n - 1, j = m - 1, len = 0;
+    const int P = j_end / kPanel + 1;  // panels the walk can visit
+    int i = n - 1, j = j_end, len = 0;
     int nreq = 0;
     auto request = [&](int p) {
         int glo, ng;
@@ -238,7 +243,7 @@ __device__ int walk(BtShared& sh, int n, int m, int P, int32_t* path) {
         const int ij = i + j;
         for (;;) {
             a = (30 - off) >> 1;
-            if (a + b == ij) { origin = true; break; }  // a <= i and b <= j here
+            if (sub ? a == i : a + b == ij) { origin = true; break; }  // a <= i and b <= j here
             const uint32_t w = __builtin_amdgcn_readlane(packed0, b);
             const uint32_t c = (w >> off) & 3u;
             codes0 |= uint64_t(c) << (2 * k0);
@@ -330,10 +335,12 @@ __device__ void shift_path(int32_t* path, int64_t base, int64_t len) {
     }
 }
 
-__device__ void backtrace_pair(BtShared& sh, const uint8_t* bp, int n, int m, int pair_status, int32_t* path,
-                               int32_t* path_len) {
+// One path: DTW from (n-1, m-1) when `ok` (the pair's status), or with `sub`
+// from (n-1, j_end) to row 0.
+__device__ void backtrace_pair(BtShared& sh, const uint8_t* bp, int n, int j_end, bool sub, bool ok, int cap,
+                               int32_t* path, int32_t* path_len) {
     const int tid = threadIdx.x;
-    if (pair_status != PARDTW_PAIR_OK) {
+    if (!ok) {
         if (tid == 0) *path_len = 0;
         return;
     }
@@ -345,9 +352,8 @@ __device__ void backtrace_pair(BtShared& sh, const uint8_t* bp, int n, int m, in
     }
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int P = int(num_panels(m));
     if (wave == 0) {
-        const int len = walk(sh, n, m, P, path);
+        const int len = walk(sh, n, j_end, sub, cap, path);
         if (tid == 0) {
             sh.len = len;
             lds_store_release(&sh.done, 1);
@@ -357,7 +363,6 @@ __device__ void backtrace_pair(BtShared& sh, const uint8_t* bp, int n, int m, in
     }
     __syncthreads();
     const int len = sh.len;
-    const int cap = n < m ? n : m;
     __threadfence_block();
     shift_path(path, int64_t(cap) - len, len);
     if (tid == 0) *path_len = len;
@@ -367,7 +372,33 @@ __global__ __launch_bounds__(kThreads) void backtrace_kernel(const uint8_t* __re
                                                              const int32_t* __restrict__ status, int32_t* path,
                                                              int32_t* path_len) {
     __shared__ BtShared sh;
-    backtrace_pair(sh, bp, int(n), int(m), *status, path, path_len);
+    backtrace_pair(sh, bp, int(n), int(m - 1), false, *status == PARDTW_PAIR_OK, int(n < m ? n : m), path, path_len);
+}
+
+// A subsequence end is usable when it is a column of the matrix that row 0
+// reaches at row n-1.
+__device__ inline bool sub_end_ok(int64_t n, int64_t m, int32_t e) { return e >= 0 && e < m && 2 * int64_t(e) >= n - 1; }
+
+__global__ __launch_bounds__(kThreads) void subseq_backtrace_kernel(const uint8_t* __restrict__ bp, int64_t n,
+                                                                    int64_t m, const int32_t* __restrict__ end_col,
+                                                                    int32_t* path, int32_t* path_len) {
+    __shared__ BtShared sh;
+    const int32_t e = *end_col;
+    backtrace_pair(sh, bp, int(n), e, true, sub_end_ok(n, m, e), int(n), path, path_len);
+}
+
+// Fragments of a Segmental DTW plan: workgroup b walks fragment b from ends[b]
+// into its own slot of n_b pairs.
+__global__ __launch_bounds__(kThreads) void subseq_backtrace_batch_kernel(const BatchPair* __restrict__ pairs,
+                                                                          const uint8_t* __restrict__ bpbase,
+                                                                          const int32_t* __restrict__ ends,
+                                                                          int32_t* paths, int32_t* path_len) {
+    __shared__ BtShared sh;
+    const int b = blockIdx.x;
+    const BatchPair q = pairs[b];
+    const int32_t e = ends[b];
+    backtrace_pair(sh, bpbase + q.bp_off, int(q.n), e, true, q.feasible && sub_end_ok(q.n, q.m, e), int(q.n),
+                   paths + 2 * q.path_off, path_len + b);
 }
 
 // Batched form: workgroup b walks pair b (infeasible pairs just get length 0).
@@ -378,8 +409,9 @@ __global__ __launch_bounds__(kThreads) void backtrace_batch_kernel(const BatchPa
     __shared__ BtShared sh;
     const int b = blockIdx.x;
     const BatchPair q = pairs[b];
-    const int st = q.feasible ? status[b] : int(PARDTW_PAIR_INFEASIBLE);
-    backtrace_pair(sh, bpbase + q.bp_off, int(q.n), int(q.m), st, paths + 2 * q.path_off, path_len + b);
+    const bool ok = q.feasible && status[b] == PARDTW_PAIR_OK;
+    backtrace_pair(sh, bpbase + q.bp_off, int(q.n), int(q.m - 1), false, ok, int(q.n < q.m ? q.n : q.m),
+                   paths + 2 * q.path_off, path_len + b);
 }
 
 __global__ void bp_unpack_kernel(const uint8_t* __restrict__ bp, int64_t n, int64_t m, int8_t* __restrict__ out) {
@@ -398,6 +430,14 @@ pardtw_status backtrace_batch_launch(const BatchPair* pairs, int32_t batch, cons
     return launch_status();
 }
 
+pardtw_status subseq_backtrace_batch_launch(const BatchPair* pairs, int32_t batch, const uint8_t* bpbase,
+                                            const int32_t* ends, int32_t* paths, int32_t* path_len,
+                                            hipStream_t stream) {
+    if (batch <= 0) return PARDTW_OK;
+    subseq_backtrace_batch_kernel<<<unsigned(batch), kThreads, 0, stream>>>(pairs, bpbase, ends, paths, path_len);
+    return launch_status();
+}
+
 }  // namespace pardtw
 
 extern "C" pardtw_status pardtw_backtrace(const uint8_t* bp, int64_t n, int64_t m, const int32_t* pair_status,
@@ -405,6 +445,14 @@ extern "C" pardtw_status pardtw_backtrace(const uint8_t* bp, int64_t n, int64_t 
     if (!bp || !pair_status || !path || !path_len || !pardtw::valid_sizes(n, m)) return PARDTW_ERR_INVALID_ARG;
     if (reinterpret_cast<uintptr_t>(path) % 8 != 0) return PARDTW_ERR_INVALID_ARG;
     pardtw::backtrace_kernel<<<1, pardtw::kThreads, 0, stream>>>(bp, n, m, pair_status, path, path_len);
+    return pardtw::launch_status();
+}
+
+extern "C" pardtw_status pardtw_subseq_backtrace(const uint8_t* bp, int64_t n, int64_t m, const int32_t* end_col,
+                                                 int32_t* path, int32_t* path_len, hipStream_t stream) {
+    if (!bp || !end_col || !path || !path_len || !pardtw::valid_sizes(n, m)) return PARDTW_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(path) % 8 != 0) return PARDTW_ERR_INVALID_ARG;
+    pardtw::subseq_backtrace_kernel<<<1, pardtw::kThreads, 0, stream>>>(bp, n, m, end_col, path, path_len);
     return pardtw::launch_status();
 }
 

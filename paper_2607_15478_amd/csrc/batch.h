@@ -19,7 +19,9 @@ struct BatchPair {
     int64_t G;             // 8-row groups
     int64_t tile0;         // first cost workgroup of the pair in the batch numbering
     int32_t P;             // column panels
-    int32_t feasible;      // the step set can reach (n-1, m-1)
+    int32_t feasible;      // some path exists (to (n-1, m-1), or to row n-1 for a fragment)
+    int32_t band;          // cost groups written: 1 the DTW path band, 2 the subsequence band
+    int32_t pad;
 };
 
 // Work item of the persistent batched DP: panel group q of pair b.
@@ -36,9 +38,11 @@ pardtw_status cost_batch_launch(const BatchPair* pairs, const int32_t* tile_pair
 
 // Sweeps every item with one persistent launch; hdr/rec as in the single-pair
 // DP (one header for the batch, records at each pair's rec_off).
+// With `sub` every pair is a fragment of Segmental DTW: the subsequence DP,
+// whose scores go to totals + b * m (fragments share m).
 pardtw_status dp_batch_launch(const BatchPair* pairs, const DpItem* items, int32_t nitems, int nw, int grid,
                               const float* Cbase, uint8_t* bpbase, float* totals, int32_t* status, void* dp_ws,
-                              hipStream_t stream);
+                              bool sub, hipStream_t stream);
 
 pardtw_status backtrace_batch_launch(const BatchPair* pairs, int32_t batch, const uint8_t* bpbase,
                                      const int32_t* status, int32_t* paths, int32_t* path_len, hipStream_t stream);
@@ -46,6 +50,21 @@ pardtw_status backtrace_batch_launch(const BatchPair* pairs, int32_t batch, cons
 pardtw_status grad_batch_launch(const BatchPair* pairs, int32_t batch, int64_t max_cap, int64_t d, const float* X,
                                 const float* Y, const int32_t* paths, const int32_t* path_len, const float* g,
                                 float* dX, int64_t dX_count, float* dY, int64_t dY_count, hipStream_t stream);
+
+// Fragment b walked from ends[b] to row 0 into its slot of n_b pairs at path_off.
+pardtw_status subseq_backtrace_batch_launch(const BatchPair* pairs, int32_t batch, const uint8_t* bpbase,
+                                            const int32_t* ends, int32_t* paths, int32_t* path_len,
+                                            hipStream_t stream);
+
+// Segment level of Segmental DTW (segment.hip).
+size_t segment_workspace_bytes_impl(int64_t nf, int64_t m);
+pardtw_status segment_ends_launch(const float* S, int64_t nf, int64_t m, int64_t hop, int variant, void* ws,
+                                  int32_t* ends, float* total, int32_t* status, hipStream_t stream);
+pardtw_status segment_gather_launch(const BatchPair* pairs, int32_t nf, const int32_t* slots,
+                                    const int32_t* frag_len, const int32_t* status, int32_t* path,
+                                    int32_t* path_len, hipStream_t stream);
+pardtw_status segment_init_launch(const BatchPair* pairs, int32_t nf, float* scores, int32_t* frag_status,
+                                  hipStream_t stream);
 
 size_t dp_header_bytes();
 size_t dp_record_bytes(int64_t n, int64_t m);  // boundary records of one pair

@@ -11,6 +11,11 @@
 // group 1, ...; depth: every group of the largest pair, then the next) and the
 // number of resident workgroups; pardtw_plan_autotune times each schedule on
 // the caller's data and keeps the fastest.
+//
+// A Segmental DTW plan (Sec. II-C) reuses all of it: its pairs are the
+// fragments of sequence A, each against the whole of sequence B, swept by the
+// subsequence DP, followed by the segment-level program, the fragments'
+// backtraces and their concatenation.
 #include <algorithm>
 #include <cmath>
 #include <new>
@@ -44,6 +49,10 @@ __global__ void batch_init_kernel(const pardtw::BatchPair* __restrict__ pairs, i
 }  // namespace
 
 struct pardtw_plan {
+    int mode = 0;       // 0 independent pairs, 1 Segmental DTW fragments
+    int variant = 1;    // Segmental DTW: PARDTW_NSDTW or PARDTW_WSDTW
+    int64_t la = 0, lb = 0, hop = 1;
+    size_t off_s = 0, off_fstat = 0, off_slots = 0, off_flen = 0, off_seg = 0;
     int32_t batch = 0;
     int64_t d = 0;
     pardtw_prec prec = PARDTW_PREC_F32;
@@ -97,11 +106,18 @@ std::vector<pardtw::DpItem> make_items(const pardtw_plan& pl, int nw, int order)
     return items;
 }
 
+// A Segmental DTW plan's DP writes the fragments' scores and statuses into
+// its workspace; `totals` / `status` serve plans of pairs.
 pardtw_status run_dp(const pardtw_plan& pl, const Schedule& s, char* ws, float* totals, int32_t* status,
                      hipStream_t stream) {
+    const bool sub = pl.mode == 1;
+    if (sub) {
+        totals = reinterpret_cast<float*>(ws + pl.off_s);
+        status = reinterpret_cast<int32_t*>(ws + pl.off_fstat);
+    }
     return pardtw::dp_batch_launch(pl.pairs_dev, pl.items_dev + s.items_at, s.nitems, s.nw, grid_for(pl, s),
                                    reinterpret_cast<const float*>(ws + pl.off_c),
-                                   reinterpret_cast<uint8_t*>(ws + pl.off_bp), totals, status, ws + pl.off_dp,
+                                   reinterpret_cast<uint8_t*>(ws + pl.off_bp), totals, status, ws + pl.off_dp, sub,
                                    stream);
 }
 
@@ -110,74 +126,41 @@ bool aligned(const void* p, size_t a) { return reinterpret_cast<uintptr_t>(p) % 
 pardtw_status check_call(const pardtw_plan* plan, const float* X, const float* Y, void* ws, size_t ws_bytes,
                          float* totals, int32_t* paths, int32_t* path_len, int32_t* status) {
     if (!plan || !X || !Y || !ws || !totals || !paths || !path_len || !status) return PARDTW_ERR_INVALID_ARG;
+    if (plan->mode != 0) return PARDTW_ERR_INVALID_ARG;
     if (!aligned(ws, kAlign) || !aligned(paths, 8)) return PARDTW_ERR_INVALID_ARG;
     if (ws_bytes < plan->ws_bytes) return PARDTW_ERR_WORKSPACE;
     return PARDTW_OK;
 }
 
-}  // namespace
-
-extern "C" pardtw_status pardtw_plan_create(int32_t batch, const int64_t* n_host, const int64_t* m_host, int64_t d,
-                                            pardtw_prec prec, pardtw_plan** plan_out) {
-    if (!plan_out) return PARDTW_ERR_INVALID_ARG;
-    *plan_out = nullptr;
-    if (batch <= 0 || !n_host || !m_host || d <= 0 || d > (int64_t(1) << 20)) return PARDTW_ERR_INVALID_ARG;
-    if (prec != PARDTW_PREC_F32 && prec != PARDTW_PREC_BF16) return PARDTW_ERR_UNSUPPORTED;
-    for (int b = 0; b < batch; ++b)
-        if (!pardtw::valid_sizes(n_host[b], m_host[b])) return PARDTW_ERR_INVALID_ARG;
-
-    pardtw_plan* pl = new (std::nothrow) pardtw_plan;
-    if (!pl) return PARDTW_ERR_HIP;
-    pl->batch = batch;
-    pl->d = d;
-    pl->prec = prec;
-    if (hipGetDevice(&pl->device) != hipSuccess ||
-        hipDeviceGetAttribute(&pl->cus, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess) {
-        delete pl;
-        return PARDTW_ERR_HIP;
+// Lays out one pair (or fragment) b: descriptor offsets into the cost, code and
+// record regions, counted in the running totals.
+void place_pair(pardtw::BatchPair& q, int64_t n, int64_t m, bool feasible, int band, size_t& c_floats,
+                size_t& bp_bytes, size_t& rec_bytes, int64_t& tiles) {
+    q.n = n;
+    q.m = m;
+    q.G = pardtw::bp_groups(n);
+    q.P = int32_t(pardtw::num_panels(m));
+    q.feasible = feasible ? 1 : 0;
+    q.band = band;
+    q.pad = 0;
+    q.c_off = int64_t(c_floats);
+    q.bp_off = int64_t(bp_bytes);
+    q.rec_off = int64_t(rec_bytes / sizeof(uint64_t));
+    q.tile0 = tiles;
+    if (feasible) {
+        const size_t cells = size_t(q.P) * size_t(q.G) * pardtw::kPanel * pardtw::kBpRows;
+        c_floats += cells;  // multiples of 512: keeps every pair 256-byte aligned
+        bp_bytes += cells;
+        rec_bytes += pardtw::dp_record_bytes(n, m);
+        tiles += pardtw::cost_blocks(n, m);
     }
+}
 
-    // descriptors and the workspace layout: cost panels | codes | DP header + records
-    pl->pairs.resize(batch);
-    size_t c_floats = 0, bp_bytes = 0, rec_bytes = 0;
-    int64_t xr = 0, yr = 0, po = 0, tiles = 0;
-    for (int b = 0; b < batch; ++b) {
-        pardtw::BatchPair& q = pl->pairs[b];
-        const int64_t n = n_host[b], m = m_host[b];
-        q.n = n;
-        q.m = m;
-        q.x_off = xr;
-        q.y_off = yr;
-        q.path_off = po;
-        q.G = pardtw::bp_groups(n);
-        q.P = int32_t(pardtw::num_panels(m));
-        q.feasible = pardtw::pair_feasible(n, m) ? 1 : 0;
-        q.c_off = int64_t(c_floats);
-        q.bp_off = int64_t(bp_bytes);
-        q.rec_off = int64_t(rec_bytes / sizeof(uint64_t));
-        q.tile0 = tiles;
-        if (q.feasible) {
-            const size_t cells = size_t(q.P) * size_t(q.G) * pardtw::kPanel * pardtw::kBpRows;
-            c_floats += cells;  // multiples of 512: keeps every pair 256-byte aligned
-            bp_bytes += cells;
-            rec_bytes += pardtw::dp_record_bytes(n, m);
-            tiles += pardtw::cost_blocks(n, m);
-        }
-        const int64_t cap = std::min(n, m);
-        xr += n;
-        yr += m;
-        po += cap;
-        pl->max_cap = std::max(pl->max_cap, cap);
-    }
-    pl->x_rows = xr;
-    pl->y_rows = yr;
-    pl->path_capacity = po;
-    pl->tiles = tiles;
-    pl->off_c = 0;
-    pl->off_bp = align_up(c_floats * sizeof(float));
-    pl->off_dp = pl->off_bp + align_up(bp_bytes);
-    pl->ws_bytes = pl->off_dp + align_up(pardtw::dp_header_bytes() + rec_bytes);
-
+// The device tables of a laid-out plan: cost block -> pair table, the DP work
+// lists of every candidate schedule, the pair descriptors.
+pardtw_status finish_plan(pardtw_plan* pl, pardtw_plan** plan_out) {
+    const int32_t batch = pl->batch;
+    const int64_t tiles = pl->tiles;
     // cost block -> pair table of the batched cost kernel
     std::vector<int32_t> tile_pair(size_t(std::max<int64_t>(tiles, 1)));
     for (int b = 0; b < batch; ++b) {
@@ -220,6 +203,57 @@ extern "C" pardtw_status pardtw_plan_create(int32_t batch, const int64_t* n_host
     *plan_out = pl;
     return PARDTW_OK;
 }
+
+}  // namespace
+
+extern "C" pardtw_status pardtw_plan_create(int32_t batch, const int64_t* n_host, const int64_t* m_host, int64_t d,
+                                            pardtw_prec prec, pardtw_plan** plan_out) {
+    if (!plan_out) return PARDTW_ERR_INVALID_ARG;
+    *plan_out = nullptr;
+    if (batch <= 0 || !n_host || !m_host || d <= 0 || d > (int64_t(1) << 20)) return PARDTW_ERR_INVALID_ARG;
+    if (prec != PARDTW_PREC_F32 && prec != PARDTW_PREC_BF16) return PARDTW_ERR_UNSUPPORTED;
+    for (int b = 0; b < batch; ++b)
+        if (!pardtw::valid_sizes(n_host[b], m_host[b])) return PARDTW_ERR_INVALID_ARG;
+
+    pardtw_plan* pl = new (std::nothrow) pardtw_plan;
+    if (!pl) return PARDTW_ERR_HIP;
+    pl->batch = batch;
+    pl->d = d;
+    pl->prec = prec;
+    if (hipGetDevice(&pl->device) != hipSuccess ||
+        hipDeviceGetAttribute(&pl->cus, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess) {
+        delete pl;
+        return PARDTW_ERR_HIP;
+    }
+
+    // descriptors and the workspace layout: cost panels | codes | DP header + records
+    pl->pairs.resize(batch);
+    size_t c_floats = 0, bp_bytes = 0, rec_bytes = 0;
+    int64_t xr = 0, yr = 0, po = 0, tiles = 0;
+    for (int b = 0; b < batch; ++b) {
+        pardtw::BatchPair& q = pl->pairs[b];
+        const int64_t n = n_host[b], m = m_host[b];
+        q.x_off = xr;
+        q.y_off = yr;
+        q.path_off = po;
+        place_pair(q, n, m, pardtw::pair_feasible(n, m), 1, c_floats, bp_bytes, rec_bytes, tiles);
+        const int64_t cap = std::min(n, m);
+        xr += n;
+        yr += m;
+        po += cap;
+        pl->max_cap = std::max(pl->max_cap, cap);
+    }
+    pl->x_rows = xr;
+    pl->y_rows = yr;
+    pl->path_capacity = po;
+    pl->tiles = tiles;
+    pl->off_c = 0;
+    pl->off_bp = align_up(c_floats * sizeof(float));
+    pl->off_dp = pl->off_bp + align_up(bp_bytes);
+    pl->ws_bytes = pl->off_dp + align_up(pardtw::dp_header_bytes() + rec_bytes);
+    return finish_plan(pl, plan_out);
+}
+
 
 extern "C" size_t pardtw_plan_workspace_bytes(const pardtw_plan* plan) { return plan ? plan->ws_bytes : 0; }
 
@@ -324,7 +358,155 @@ extern "C" pardtw_status pardtw_path_grad_batch(const pardtw_plan* plan, const f
                                                 float* dY_packed, hipStream_t stream) {
     if (!plan || !X_packed || !Y_packed || !paths_packed || !path_len || !g_totals || !dX_packed || !dY_packed)
         return PARDTW_ERR_INVALID_ARG;
+    if (plan->mode != 0) return PARDTW_ERR_INVALID_ARG;
     return pardtw::grad_batch_launch(plan->pairs_dev, plan->batch, plan->max_cap, plan->d, X_packed, Y_packed,
                                      paths_packed, path_len, g_totals, dX_packed, plan->x_rows * plan->d,
                                      dY_packed, plan->y_rows * plan->d, stream);
+}
+
+// ---- Segmental DTW -----------------------------------------------------------
+
+extern "C" pardtw_status pardtw_segplan_create(int64_t la, int64_t lb, int32_t nfrag, int64_t d, pardtw_prec prec,
+                                               int32_t variant, pardtw_plan** plan_out) {
+    if (!plan_out) return PARDTW_ERR_INVALID_ARG;
+    *plan_out = nullptr;
+    if (nfrag <= 0 || la < nfrag || !pardtw::valid_sizes(la, lb) || d <= 0 || d > (int64_t(1) << 20))
+        return PARDTW_ERR_INVALID_ARG;
+    if (variant != PARDTW_NSDTW && variant != PARDTW_WSDTW) return PARDTW_ERR_INVALID_ARG;
+    if (prec != PARDTW_PREC_F32 && prec != PARDTW_PREC_BF16) return PARDTW_ERR_UNSUPPORTED;
+    if (!pardtw::valid_sizes(nfrag, lb)) return PARDTW_ERR_INVALID_ARG;
+
+    pardtw_plan* pl = new (std::nothrow) pardtw_plan;
+    if (!pl) return PARDTW_ERR_HIP;
+    pl->mode = 1;
+    pl->variant = variant;
+    pl->la = la;
+    pl->lb = lb;
+    pl->hop = std::max<int64_t>(1, la / (2 * int64_t(nfrag)));
+    pl->batch = nfrag;
+    pl->d = d;
+    pl->prec = prec;
+    if (hipGetDevice(&pl->device) != hipSuccess ||
+        hipDeviceGetAttribute(&pl->cus, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess) {
+        delete pl;
+        return PARDTW_ERR_HIP;
+    }
+    // fragment f: rows [floor(f la / N), floor((f+1) la / N)) of A against all of B
+    pl->pairs.resize(nfrag);
+    size_t c_floats = 0, bp_bytes = 0, rec_bytes = 0;
+    int64_t tiles = 0;
+    for (int f = 0; f < nfrag; ++f) {
+        pardtw::BatchPair& q = pl->pairs[f];
+        const int64_t r0 = int64_t(f) * la / nfrag, r1 = int64_t(f + 1) * la / nfrag;
+        q.x_off = r0;
+        q.y_off = 0;
+        q.path_off = r0;  // fragment f's path slot: n_f pairs
+        place_pair(q, r1 - r0, lb, pardtw::subseq_feasible(r1 - r0, lb), 2, c_floats, bp_bytes, rec_bytes, tiles);
+        pl->max_cap = std::max(pl->max_cap, r1 - r0);
+    }
+    pl->x_rows = la;
+    pl->y_rows = lb;
+    pl->path_capacity = la;
+    pl->tiles = tiles;
+    // cost panels | codes | DP header + records | scores | fragment statuses |
+    // fragment path slots | fragment path lengths | segment-level workspace
+    pl->off_c = 0;
+    pl->off_bp = align_up(c_floats * sizeof(float));
+    pl->off_dp = pl->off_bp + align_up(bp_bytes);
+    pl->off_s = pl->off_dp + align_up(pardtw::dp_header_bytes() + rec_bytes);
+    pl->off_fstat = pl->off_s + align_up(size_t(nfrag) * size_t(lb) * sizeof(float));
+    pl->off_slots = pl->off_fstat + align_up(size_t(nfrag) * sizeof(int32_t));
+    pl->off_flen = pl->off_slots + align_up(size_t(la) * 2 * sizeof(int32_t));
+    pl->off_seg = pl->off_flen + align_up(size_t(nfrag) * sizeof(int32_t));
+    pl->ws_bytes = pl->off_seg + align_up(pardtw::segment_workspace_bytes_impl(nfrag, lb));
+    return finish_plan(pl, plan_out);
+}
+
+extern "C" int64_t pardtw_segplan_scores_offset(const pardtw_plan* plan) {
+    return plan && plan->mode == 1 ? int64_t(plan->off_s) : -1;
+}
+
+namespace {
+
+pardtw_status check_seg_call(const pardtw_plan* plan, const float* A, const float* B, void* ws, size_t ws_bytes) {
+    if (!plan || plan->mode != 1 || !A || !B || !ws) return PARDTW_ERR_INVALID_ARG;
+    if (!aligned(ws, kAlign)) return PARDTW_ERR_INVALID_ARG;
+    if (ws_bytes < plan->ws_bytes) return PARDTW_ERR_WORKSPACE;
+    return PARDTW_OK;
+}
+
+pardtw_status seg_front(const pardtw_plan* plan, const float* A, const float* B, char* ws, hipStream_t stream) {
+    pardtw_status st = pardtw::segment_init_launch(plan->pairs_dev, plan->batch,
+                                                   reinterpret_cast<float*>(ws + plan->off_s),
+                                                   reinterpret_cast<int32_t*>(ws + plan->off_fstat), stream);
+    if (st != PARDTW_OK) return st;
+    return pardtw::cost_batch_launch(plan->pairs_dev, plan->tile_pair_dev, plan->tiles, A, B, plan->d, plan->prec,
+                                     reinterpret_cast<float*>(ws + plan->off_c), stream);
+}
+
+}  // namespace
+
+extern "C" pardtw_status pardtw_segmental_align(const pardtw_plan* plan, const float* A, const float* B,
+                                                void* workspace, size_t workspace_bytes, float* total, int32_t* ends,
+                                                int32_t* path, int32_t* path_len, int32_t* status,
+                                                hipStream_t stream) {
+    pardtw_status st = check_seg_call(plan, A, B, workspace, workspace_bytes);
+    if (st != PARDTW_OK) return st;
+    if (!total || !ends || !path || !path_len || !status || !aligned(path, 8)) return PARDTW_ERR_INVALID_ARG;
+    char* ws = static_cast<char*>(workspace);
+    if ((st = seg_front(plan, A, B, ws, stream)) != PARDTW_OK) return st;
+    if ((st = run_dp(*plan, plan->scheds[plan->chosen], ws, nullptr, nullptr, stream)) != PARDTW_OK) return st;
+    st = pardtw::segment_ends_launch(reinterpret_cast<const float*>(ws + plan->off_s), plan->batch, plan->lb,
+                                     plan->hop, plan->variant, ws + plan->off_seg, ends, total, status, stream);
+    if (st != PARDTW_OK) return st;
+    int32_t* slots = reinterpret_cast<int32_t*>(ws + plan->off_slots);
+    int32_t* flen = reinterpret_cast<int32_t*>(ws + plan->off_flen);
+    st = pardtw::subseq_backtrace_batch_launch(plan->pairs_dev, plan->batch,
+                                               reinterpret_cast<const uint8_t*>(ws + plan->off_bp), ends, slots,
+                                               flen, stream);
+    if (st != PARDTW_OK) return st;
+    return pardtw::segment_gather_launch(plan->pairs_dev, plan->batch, slots, flen, status, path, path_len, stream);
+}
+
+extern "C" pardtw_status pardtw_segplan_autotune(pardtw_plan* plan, const float* A, const float* B,
+                                                 void* workspace, size_t workspace_bytes, int32_t reps,
+                                                 float* best_ms, hipStream_t stream) {
+    pardtw_status st = check_seg_call(plan, A, B, workspace, workspace_bytes);
+    if (st != PARDTW_OK) return st;
+    if (reps < 1) reps = 1;
+    char* ws = static_cast<char*>(workspace);
+    if ((st = seg_front(plan, A, B, ws, stream)) != PARDTW_OK) return st;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return PARDTW_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return PARDTW_ERR_HIP;
+    }
+    float best = INFINITY;
+    int best_s = plan->chosen;
+    for (size_t s = 0; s < plan->scheds.size() && st == PARDTW_OK; ++s) {
+        const Schedule& sc = plan->scheds[s];
+        st = run_dp(*plan, sc, ws, nullptr, nullptr, stream);  // warm-up
+        if (st != PARDTW_OK) break;
+        if (hipEventRecord(e0, stream) != hipSuccess) { st = PARDTW_ERR_HIP; break; }
+        for (int r = 0; r < reps && st == PARDTW_OK; ++r) st = run_dp(*plan, sc, ws, nullptr, nullptr, stream);
+        if (st != PARDTW_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = PARDTW_ERR_HIP;
+            break;
+        }
+        ms /= float(reps);
+        if (ms < best) {
+            best = ms;
+            best_s = int(s);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != PARDTW_OK) return st;
+    plan->chosen = best_s;
+    if (best_ms) *best_ms = best;
+    return PARDTW_OK;
 }

@@ -65,6 +65,24 @@ inline bool pair_feasible(int64_t n, int64_t m) {
     return (m - 1) <= 2 * (n - 1) && (n - 1) <= 2 * (m - 1);
 }
 
+// Subsequence DTW (Sec. II-B): a path starts anywhere on row 0 and ends
+// anywhere on row n-1. A cell lies on one iff row 0 reaches it, i <= 2j, and
+// it reaches row n-1 inside the matrix, (n-1-i) <= 2(m-1-j). Per column panel
+// the 8-row groups holding a cell of each are sub_group_lo .. sub_group_hi
+// (the same box tests as above).
+__host__ __device__ inline int64_t sub_group_lo(int64_t p, int64_t n, int64_t m) {
+    const int64_t le = -floor_div(-(n - 8 - 2 * (m - 1 - p * kPanel)), 8);
+    return le < 0 ? 0 : le;
+}
+
+__host__ __device__ inline int64_t sub_group_hi(int64_t p, int64_t n, int64_t m) {
+    const int64_t j1 = p * kPanel + kPanel - 1 < m - 1 ? p * kPanel + kPanel - 1 : m - 1;
+    return floor_div(j1, 4);
+}
+
+// Some end column of row n-1 is reachable from row 0.
+inline bool subseq_feasible(int64_t n, int64_t m) { return n - 1 <= 2 * (m - 1); }
+
 // Device workspace header of the DP (followed by boundary records).
 struct DpWsHeader {
     uint32_t epoch;    // launch counter; boundary records carry it as a tag

@@ -74,10 +74,11 @@ struct GroupSpan {
     int64_t lo, hi;
 };
 
-__device__ inline GroupSpan group_span(bool band, int64_t p, int64_t n, int64_t m) {
+// band: 0 every group, 1 the DTW path band, 2 the subsequence band.
+__device__ inline GroupSpan group_span(int band, int64_t p, int64_t n, int64_t m) {
     GroupSpan s;
-    s.lo = band ? band_group_lo(p, n, m) : 0;
-    s.hi = band ? band_group_hi(p, n, m) : (int64_t(1) << 62);
+    s.lo = band == 1 ? band_group_lo(p, n, m) : band == 2 ? sub_group_lo(p, n, m) : 0;
+    s.hi = band == 1 ? band_group_hi(p, n, m) : band == 2 ? sub_group_hi(p, n, m) : (int64_t(1) << 62);
     return s;
 }
 
@@ -260,14 +261,14 @@ __device__ __attribute__((always_inline)) inline void cost_tile(const float* __r
     store_tile<PANEL>(acc, inv_from_sq(sum_groups(sa)), ry, n, m, C, p, i0, span);
 }
 
-// A workgroup's sweep: tiles t0 .. t0 + kTilesPerBlock - 1 of panel p. With
-// `band` (panel layout only) groups outside the band of path cells are skipped.
+// A workgroup's sweep: tiles t0 .. t0 + kTilesPerBlock - 1 of panel p. With a
+// `band` (panel layout only) the groups outside it are skipped.
 template <bool BF16, bool PANEL, bool VEC>
 __device__ __attribute__((always_inline)) inline void sweep(const float* __restrict__ X,
                                                             const float* __restrict__ Y, int64_t n, int64_t m,
                                                             int64_t d, float* __restrict__ C, int64_t p, int64_t t0,
-                                                            bool band) {
-    const GroupSpan span = group_span(PANEL && band, p, n, m);
+                                                            int band) {
+    const GroupSpan span = group_span(PANEL ? band : 0, p, n, m);
     if (!rows_written(span, t0 * kTileM, int64_t(kTilesPerBlock) * kTileM)) return;
     if (!BF16 && d <= 16) {
         sweep_f32_small<PANEL>(X, Y, n, m, d, C, p, t0, kTilesPerBlock, span);
@@ -284,7 +285,7 @@ __device__ __attribute__((always_inline)) inline void sweep(const float* __restr
 template <bool BF16, bool PANEL, bool VEC>
 __global__ __launch_bounds__(kThreads) void cost_kernel(const float* __restrict__ X, const float* __restrict__ Y,
                                                         int64_t n, int64_t m, int64_t d, float* __restrict__ C,
-                                                        bool band) {
+                                                        int band) {
     sweep<BF16, PANEL, VEC>(X, Y, n, m, d, C, blockIdx.x, int64_t(blockIdx.y) * kTilesPerBlock, band);
 }
 
@@ -302,7 +303,7 @@ __global__ __launch_bounds__(kThreads) void cost_batch_kernel(const BatchPair* _
     const int64_t rows_blk = ceil_div(ceil_div(q.n, kTileM), kTilesPerBlock);
     const int64_t p = local / rows_blk;
     const int64_t t0 = (local % rows_blk) * kTilesPerBlock;
-    sweep<BF16, true, VEC>(X + q.x_off * d, Y + q.y_off * d, q.n, q.m, d, Cbase + q.c_off, p, t0, true);
+    sweep<BF16, true, VEC>(X + q.x_off * d, Y + q.y_off * d, q.n, q.m, d, Cbase + q.c_off, p, t0, q.band);
 }
 
 bool vec_ok(const float* X, const float* Y, int64_t d) {
@@ -340,7 +341,7 @@ pardtw_status cost_launch(const float* X, const float* Y, int64_t n, int64_t m, 
     if (rows_blk > 65535 || num_panels(m) > 0x7fffffff) return PARDTW_ERR_UNSUPPORTED;
     dim3 grid(unsigned(num_panels(m)), unsigned(rows_blk));
     const bool panel = layout != PARDTW_LAYOUT_ROW;
-    const bool band = layout == PARDTW_LAYOUT_PANEL_BAND;
+    const int band = layout == PARDTW_LAYOUT_PANEL_BAND ? 1 : layout == PARDTW_LAYOUT_PANEL_SUBSEQ_BAND ? 2 : 0;
     const bool vec = vec_ok(X, Y, d);
     if (prec == PARDTW_PREC_F32 && vec && d % 16 == 0) {
         if (panel) cost_kernel<false, true, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, band);
@@ -363,7 +364,8 @@ pardtw_status cost_launch(const float* X, const float* Y, int64_t n, int64_t m, 
 extern "C" size_t pardtw_cost_elems(int64_t n, int64_t m, pardtw_layout layout) {
     if (!pardtw::valid_sizes(n, m)) return 0;
     if (layout == PARDTW_LAYOUT_ROW) return size_t(n) * size_t(m);
-    if (layout == PARDTW_LAYOUT_PANEL || layout == PARDTW_LAYOUT_PANEL_BAND)
+    if (layout == PARDTW_LAYOUT_PANEL || layout == PARDTW_LAYOUT_PANEL_BAND ||
+        layout == PARDTW_LAYOUT_PANEL_SUBSEQ_BAND)
         return size_t(pardtw::num_panels(m)) * size_t(pardtw::bp_groups(n)) * pardtw::kPanel * pardtw::kBpRows;
     return 0;
 }
@@ -377,12 +379,22 @@ extern "C" pardtw_status pardtw_band_groups(int64_t n, int64_t m, int64_t p, int
     return PARDTW_OK;
 }
 
+extern "C" pardtw_status pardtw_subseq_band_groups(int64_t n, int64_t m, int64_t p, int64_t* lo, int64_t* hi) {
+    if (!lo || !hi || !pardtw::valid_sizes(n, m) || p < 0 || p >= pardtw::num_panels(m)) return PARDTW_ERR_INVALID_ARG;
+    const int64_t G = pardtw::bp_groups(n);
+    const int64_t l = pardtw::sub_group_lo(p, n, m), h = pardtw::sub_group_hi(p, n, m);
+    *lo = l < G ? l : G;
+    *hi = h < G - 1 ? h : G - 1;
+    return PARDTW_OK;
+}
+
 extern "C" pardtw_status pardtw_cost(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
                                      pardtw_prec prec, pardtw_layout layout, float* C, hipStream_t stream) {
     if (!X || !Y || !C || !pardtw::valid_sizes(n, m) || d <= 0 || d > (int64_t(1) << 20))
         return PARDTW_ERR_INVALID_ARG;
     if (prec != PARDTW_PREC_F32 && prec != PARDTW_PREC_BF16) return PARDTW_ERR_UNSUPPORTED;
-    if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL && layout != PARDTW_LAYOUT_PANEL_BAND)
+    if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL && layout != PARDTW_LAYOUT_PANEL_BAND &&
+        layout != PARDTW_LAYOUT_PANEL_SUBSEQ_BAND)
         return PARDTW_ERR_UNSUPPORTED;
     return pardtw::cost_launch(X, Y, n, m, d, prec, layout, C, stream);
 }

@@ -2,6 +2,9 @@
 //
 // Recurrence (Sec. V step set {(1,1),(1,2),(2,1)}, weights {2,3,3}):
 //   D[i,j] = min(D[i-1,j-1] + 2C, D[i-1,j-2] + 3C, D[i-2,j-1] + 3C),  D[0,0] = C[0,0].
+// The same sweep runs subsequence DTW (Sec. II-B, the frame-level step of
+// Segmental DTW): weights {1,1,2}, every cell of row 0 a start, D[0,j] = C[0,j],
+// and the last row D[n-1, .] as output.
 // A cell needs only the two rows above it (equivalently: anti-diagonal k needs
 // diagonals k-2 and k-3, which is why the paper keeps four diagonal buffers,
 // Sec. II-D). So a whole row of a column panel is one step of independent
@@ -80,7 +83,7 @@ __device__ inline float shift_in(float v, float edge) {
 struct DpArgs {
     const float* C;
     uint8_t* bp;
-    float* total;
+    float* total;   // DTW: D[n-1][m-1]; subsequence DTW: the m scores D[n-1][.]
     int32_t* status;
     DpWsHeader* hdr;
     uint64_t* rec;  // [P][G*8][2] boundary records
@@ -136,10 +139,13 @@ struct ChunkRanges {
     int lo, hi;  // [lo, hi], empty when lo > hi
 };
 
+// Subsequence DTW uses its own band (a path starts anywhere on row 0 and ends
+// anywhere on row n-1); the same two arguments hold for it.
+template <bool SUB>
 __device__ inline ChunkRanges chunk_ranges(int p, int64_t n, int64_t m, int64_t G) {
     ChunkRanges r;
-    const int64_t lo = band_group_lo(p, n, m);
-    const int64_t hi = band_group_hi(p, n, m);
+    const int64_t lo = SUB ? sub_group_lo(p, n, m) : band_group_lo(p, n, m);
+    const int64_t hi = SUB ? sub_group_hi(p, n, m) : band_group_hi(p, n, m);
     r.lo = int(lo < G ? lo : G);
     r.hi = int(hi < G - 1 ? hi : G - 1);
     return r;
@@ -147,6 +153,7 @@ __device__ inline ChunkRanges chunk_ranges(int p, int64_t n, int64_t m, int64_t 
 
 // One 8-row chunk of a panel. `lv0/lv1` hold the left boundary columns
 // D[i0+r][64p-2] / D[i0+r][64p-1]; e0/e1 the same for row i0-1.
+template <bool SUB>
 __device__ __attribute__((always_inline)) inline void dp_rows(const float (&cb)[kChunk], const float (&lv0)[kChunk],
                                                               const float (&lv1)[kChunk], float e0, float e1,
                                                               float& d1, float& s1p, uint32_t& lo, uint32_t& hi,
@@ -158,9 +165,9 @@ __device__ __attribute__((always_inline)) inline void dp_rows(const float (&cb)[
         const float c = cb[r];
         const float s1 = shift_in(d1, r == 0 ? e1 : lv1[r - 1]);  // D[i-1][j-1]
         const float s2 = shift_in(s1, r == 0 ? e0 : lv0[r - 1]);  // D[i-1][j-2]
-        const float c0 = __builtin_fmaf(2.0f, c, s1);
-        const float c1 = __builtin_fmaf(3.0f, c, s2);
-        const float c2 = __builtin_fmaf(3.0f, c, s1p);
+        const float c0 = __builtin_fmaf(SUB ? 1.0f : 2.0f, c, s1);
+        const float c1 = __builtin_fmaf(SUB ? 1.0f : 3.0f, c, s2);
+        const float c2 = __builtin_fmaf(SUB ? 2.0f : 3.0f, c, s1p);
         const float best = __builtin_fminf(__builtin_fminf(c0, c1), c2);
         uint32_t code = (c1 == best) ? 1u : 2u;
         code = (c0 == best) ? 0u : code;
@@ -175,12 +182,12 @@ __device__ __attribute__((always_inline)) inline void dp_rows(const float (&cb)[
 // value made opaque to the optimiser and only gates a rare wait, so every role
 // runs the same instructions: the unrolled chunk loop is large and several
 // roles sharing one instruction cache would otherwise evict each other.
-template <bool PANEL>
+template <bool PANEL, bool SUB>
 __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs& a, DpShared& sh, int wave, int p,
                                                                    bool have_out) {
     const int lane = threadIdx.x & 63;
     const int G = int(a.G);  // chunks per panel (rows padded to a multiple of 8)
-    const ChunkRanges cr = chunk_ranges(p, a.n, a.m, a.G);
+    const ChunkRanges cr = chunk_ranges<SUB>(p, a.n, a.m, a.G);
     const float kInf = __builtin_inff();
     const int bcol = lane - (kLanes - 2);  // 0 / 1 on the two boundary lanes
     uint64_t* bp_pan = reinterpret_cast<uint64_t*>(a.bp) + int64_t(p) * G * kLanes;
@@ -197,9 +204,10 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
 
     // D[i-1][j] and D[i-2][j-1]. The origin is produced by the general rule
     // through a virtual D[-2][-1] = -2 C[0][0]: fma(3, C00, -2 C00) = C00
-    // exactly, and that value is used by no other cell.
+    // exactly, and that value is used by no other cell. Subsequence DTW starts
+    // on every cell of row 0 the same way: fma(2, C0j, -C0j) = C0j.
     float d1 = kInf;
-    float s1p = (p == 0 && lane == 0) ? -2.0f * cbuf[0][0] : kInf;
+    float s1p = SUB ? -cbuf[0][0] : (p == 0 && lane == 0) ? -2.0f * cbuf[0][0] : kInf;
     // left boundary D[i0-1][64p-2], D[i0-1][64p-1] for the first row of a chunk
     float e0 = kInf, e1 = kInf;
     const int last = G - 1;
@@ -252,8 +260,12 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
 
             uint32_t lo, hi;
             float best_r[kChunk];
-            dp_rows(cbuf[u], lv0, lv1, e0, e1, d1, s1p, lo, hi, best_r);
-            if (p == 0 && k == 0) lo = (lane == 0) ? ((lo & ~0xffu) | 3u) : lo;  // the origin's code
+            dp_rows<SUB>(cbuf[u], lv0, lv1, e0, e1, d1, s1p, lo, hi, best_r);
+            if (SUB) {
+                if (k == 0) lo = (lo & ~0xffu) | 3u;  // row 0: every cell is a start
+            } else if (p == 0 && k == 0) {
+                lo = (lane == 0) ? ((lo & ~0xffu) | 3u) : lo;  // the origin's code
+            }
             e0 = lv0[kChunk - 1];
             e1 = lv1[kChunk - 1];
 
@@ -295,8 +307,12 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
             load_chunk<PANEL>(a, p, lane, kn, kn >= rlo && kn <= rhi, cbuf[u]);
         }
     }
-    if (int64_t(p) * kPanel + lane == a.m - 1) {
-        *a.total = dlast;
+    // DTW: total = D[n-1][m-1]. Subsequence DTW: the whole last row, whose
+    // last column is reachable whenever any is.
+    const int64_t col = int64_t(p) * kPanel + lane;
+    if (SUB && col < a.m) a.total[col] = dlast;
+    if (col == a.m - 1) {
+        if (!SUB) *a.total = dlast;
         *a.status = dlast == kInf ? PARDTW_PAIR_INFEASIBLE : PARDTW_PAIR_OK;
     }
 }
@@ -401,13 +417,13 @@ __device__ __attribute__((always_inline)) inline void out_helper(const DpArgs& a
 
 // Panel group q (panels q*NW .. q*NW+NW-1) of one pair: NW compute waves, then
 // the input helper and the output helper.
-template <int NW, bool PANEL>
+template <int NW, bool PANEL, bool SUB>
 __device__ __attribute__((always_inline)) inline void run_group(const DpArgs& a, DpShared& sh, int wave, int q,
                                                                 uint32_t epoch) {
     const int p0 = q * NW;
     if (wave < NW) {
         const int p = p0 + wave;
-        if (p < a.P) compute_wave<PANEL>(a, sh, wave, p, p + 1 < a.P);
+        if (p < a.P) compute_wave<PANEL, SUB>(a, sh, wave, p, p + 1 < a.P);
     } else if (wave == NW) {
         if (p0 > 0) in_helper(a, sh, p0 - 1, epoch);
         else inf_source(sh);
@@ -428,7 +444,7 @@ __device__ inline int next_ticket(DpShared& sh, DpWsHeader* hdr) {
     return __builtin_amdgcn_readfirstlane(sh.super);
 }
 
-template <int NW, bool PANEL>
+template <int NW, bool PANEL, bool SUB>
 __global__ __launch_bounds__(kLanes*(NW + 2)) void dp_kernel(DpArgs a) {
     __shared__ DpShared sh;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);
@@ -436,7 +452,7 @@ __global__ __launch_bounds__(kLanes*(NW + 2)) void dp_kernel(DpArgs a) {
     for (;;) {
         const int q = next_ticket<NW>(sh, a.hdr);
         if (q >= a.S) break;
-        run_group<NW, PANEL>(a, sh, wave, q, epoch);
+        run_group<NW, PANEL, SUB>(a, sh, wave, q, epoch);
         __syncthreads();
     }
 }
@@ -456,7 +472,7 @@ struct DpBatchArgs {
     uint64_t* rec;
 };
 
-template <int NW>
+template <int NW, bool SUB>
 __global__ __launch_bounds__(kLanes*(NW + 2)) void dp_batch_kernel(DpBatchArgs ba) {
     __shared__ DpShared sh;
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);
@@ -469,7 +485,8 @@ __global__ __launch_bounds__(kLanes*(NW + 2)) void dp_batch_kernel(DpBatchArgs b
         DpArgs a;
         a.C = ba.C + q.c_off;
         a.bp = ba.bp + q.bp_off;
-        a.total = ba.totals + it.pair;
+        // fragments of one plan share m: their score rows are stacked
+        a.total = SUB ? ba.totals + int64_t(it.pair) * q.m : ba.totals + it.pair;
         a.status = ba.status + it.pair;
         a.hdr = ba.hdr;
         a.rec = ba.rec + q.rec_off;
@@ -478,7 +495,7 @@ __global__ __launch_bounds__(kLanes*(NW + 2)) void dp_batch_kernel(DpBatchArgs b
         a.G = q.G;
         a.P = q.P;
         a.S = int(ceil_div(q.P, NW));
-        run_group<NW, true>(a, sh, wave, it.group, epoch);
+        run_group<NW, true, SUB>(a, sh, wave, it.group, epoch);
         __syncthreads();
     }
 }
@@ -488,10 +505,12 @@ __global__ void dp_prepare(DpWsHeader* hdr) {
     hdr->ticket = 0;
 }
 
-// No path reaches (n-1, m-1): the band is empty, nothing is swept.
-__global__ void dp_infeasible(float* total, int32_t* status) {
-    *total = __builtin_inff();
-    *status = PARDTW_PAIR_INFEASIBLE;
+// No path reaches (n-1, m-1) (or, for subsequence DTW, row n-1): the band is
+// empty and nothing is swept; the `count` outputs are +inf.
+__global__ void dp_infeasible(float* total, int64_t count, int32_t* status) {
+    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count; e += int64_t(gridDim.x) * blockDim.x)
+        total[e] = __builtin_inff();
+    if (blockIdx.x == 0 && threadIdx.x == 0) *status = PARDTW_PAIR_INFEASIBLE;
 }
 
 int choose_nw(int P) {
@@ -503,14 +522,20 @@ int choose_nw(int P) {
 }
 
 template <int NW>
-void launch_nw(const DpArgs& a, bool panel, int grid, hipStream_t stream) {
-    if (panel) dp_kernel<NW, true><<<grid, kLanes * (NW + 2), 0, stream>>>(a);
-    else dp_kernel<NW, false><<<grid, kLanes * (NW + 2), 0, stream>>>(a);
+void launch_nw(const DpArgs& a, bool panel, bool sub, int grid, hipStream_t stream) {
+    if (sub) {
+        if (panel) dp_kernel<NW, true, true><<<grid, kLanes * (NW + 2), 0, stream>>>(a);
+        else dp_kernel<NW, false, true><<<grid, kLanes * (NW + 2), 0, stream>>>(a);
+    } else {
+        if (panel) dp_kernel<NW, true, false><<<grid, kLanes * (NW + 2), 0, stream>>>(a);
+        else dp_kernel<NW, false, false><<<grid, kLanes * (NW + 2), 0, stream>>>(a);
+    }
 }
 
 template <int NW>
-void launch_batch_nw(const DpBatchArgs& a, int grid, hipStream_t stream) {
-    dp_batch_kernel<NW><<<grid, kLanes * (NW + 2), 0, stream>>>(a);
+void launch_batch_nw(const DpBatchArgs& a, bool sub, int grid, hipStream_t stream) {
+    if (sub) dp_batch_kernel<NW, true><<<grid, kLanes * (NW + 2), 0, stream>>>(a);
+    else dp_batch_kernel<NW, false><<<grid, kLanes * (NW + 2), 0, stream>>>(a);
 }
 
 }  // namespace
@@ -525,7 +550,7 @@ size_t dp_workspace_bytes_impl(int64_t n, int64_t m) { return sizeof(DpWsHeader)
 
 pardtw_status dp_batch_launch(const BatchPair* pairs, const DpItem* items, int32_t nitems, int nw, int grid,
                               const float* Cbase, uint8_t* bpbase, float* totals, int32_t* status, void* dp_ws,
-                              hipStream_t stream) {
+                              bool sub, hipStream_t stream) {
     DpBatchArgs a;
     a.pairs = pairs;
     a.items = items;
@@ -540,17 +565,17 @@ pardtw_status dp_batch_launch(const BatchPair* pairs, const DpItem* items, int32
     if (nitems <= 0) return launch_status();
     if (grid > nitems) grid = nitems;
     switch (nw) {
-        case 1: launch_batch_nw<1>(a, grid, stream); break;
-        case 2: launch_batch_nw<2>(a, grid, stream); break;
-        case 4: launch_batch_nw<4>(a, grid, stream); break;
-        case 8: launch_batch_nw<8>(a, grid, stream); break;
+        case 1: launch_batch_nw<1>(a, sub, grid, stream); break;
+        case 2: launch_batch_nw<2>(a, sub, grid, stream); break;
+        case 4: launch_batch_nw<4>(a, sub, grid, stream); break;
+        case 8: launch_batch_nw<8>(a, sub, grid, stream); break;
         default: return PARDTW_ERR_UNSUPPORTED;
     }
     return launch_status();
 }
 
 pardtw_status dp_launch(const float* C, pardtw_layout layout, int64_t n, int64_t m, uint8_t* bp,
-                        float* total, int32_t* status, void* ws, int nw_override, hipStream_t stream) {
+                        float* total, int32_t* status, void* ws, int nw_override, bool sub, hipStream_t stream) {
     DpArgs a;
     a.C = C;
     a.bp = bp;
@@ -570,18 +595,20 @@ pardtw_status dp_launch(const float* C, pardtw_layout layout, int64_t n, int64_t
     // about four compute waves per CU (one per SIMD)
     const int per_cu = nw >= 4 ? 1 : 4 / nw;
     const int grid = a.S < cus * per_cu ? a.S : cus * per_cu;
-    // the DP reads only band groups, so both panel layouts are the same to it
+    // the DP reads only band groups, so the panel layouts are the same to it
     const bool panel = layout != PARDTW_LAYOUT_ROW;
-    if (!pair_feasible(n, m)) {
-        dp_infeasible<<<1, 1, 0, stream>>>(total, status);
+    if (sub ? !subseq_feasible(n, m) : !pair_feasible(n, m)) {
+        const int64_t count = sub ? m : 1;
+        const unsigned blocks = unsigned(count < 256 * 1024 ? ceil_div(count, 256) : 1024);
+        dp_infeasible<<<blocks, 256, 0, stream>>>(total, count, status);
         return launch_status();
     }
     dp_prepare<<<1, 1, 0, stream>>>(a.hdr);
     switch (nw) {
-        case 1: launch_nw<1>(a, panel, grid, stream); break;
-        case 2: launch_nw<2>(a, panel, grid, stream); break;
-        case 4: launch_nw<4>(a, panel, grid, stream); break;
-        case 8: launch_nw<8>(a, panel, grid, stream); break;
+        case 1: launch_nw<1>(a, panel, sub, grid, stream); break;
+        case 2: launch_nw<2>(a, panel, sub, grid, stream); break;
+        case 4: launch_nw<4>(a, panel, sub, grid, stream); break;
+        case 8: launch_nw<8>(a, panel, sub, grid, stream); break;
         default: return PARDTW_ERR_UNSUPPORTED;
     }
     return launch_status();
@@ -606,7 +633,7 @@ extern "C" pardtw_status pardtw_dp(const float* C, pardtw_layout layout, int64_t
     if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL && layout != PARDTW_LAYOUT_PANEL_BAND)
         return PARDTW_ERR_UNSUPPORTED;
     if (!workspace || workspace_bytes < pardtw::dp_workspace_bytes_impl(n, m)) return PARDTW_ERR_WORKSPACE;
-    return pardtw::dp_launch(C, layout, n, m, bp, total, pair_status, workspace, 0, stream);
+    return pardtw::dp_launch(C, layout, n, m, bp, total, pair_status, workspace, 0, false, stream);
 }
 
 extern "C" pardtw_status pardtw_dp_ex(const float* C, pardtw_layout layout, int64_t n, int64_t m, uint8_t* bp,
@@ -619,5 +646,16 @@ extern "C" pardtw_status pardtw_dp_ex(const float* C, pardtw_layout layout, int6
         panels_per_workgroup != 4 && panels_per_workgroup != 8)
         return PARDTW_ERR_INVALID_ARG;
     if (!workspace || workspace_bytes < pardtw::dp_workspace_bytes_impl(n, m)) return PARDTW_ERR_WORKSPACE;
-    return pardtw::dp_launch(C, layout, n, m, bp, total, pair_status, workspace, panels_per_workgroup, stream);
+    return pardtw::dp_launch(C, layout, n, m, bp, total, pair_status, workspace, panels_per_workgroup, false,
+                             stream);
+}
+
+extern "C" pardtw_status pardtw_subseq_dp(const float* C, pardtw_layout layout, int64_t n, int64_t m, uint8_t* bp,
+                                          float* scores, int32_t* pair_status, void* workspace,
+                                          size_t workspace_bytes, hipStream_t stream) {
+    if (!C || !bp || !scores || !pair_status || !pardtw::valid_sizes(n, m)) return PARDTW_ERR_INVALID_ARG;
+    if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL && layout != PARDTW_LAYOUT_PANEL_SUBSEQ_BAND)
+        return PARDTW_ERR_UNSUPPORTED;
+    if (!workspace || workspace_bytes < pardtw::dp_workspace_bytes_impl(n, m)) return PARDTW_ERR_WORKSPACE;
+    return pardtw::dp_launch(C, layout, n, m, bp, scores, pair_status, workspace, 0, true, stream);
 }

@@ -1,0 +1,284 @@
+// Segment level of Segmental DTW (Sec. II-C steps 3-4; NSDTW's choice, Sec.
+// II-B): fragment end columns from the stacked subsequence scores S (row f =
+// fragment f, column j = end column).
+//
+// WSDTW's program Dseg[f,j] = min(Dseg[f,j-1], Dseg[f-1,j-hop] + S[f,j]) is a
+// running minimum along each row of t_f[j] = Dseg[f-1,j-hop] + S[f,j], with
+// the skip kept on ties, so Dseg[f,j] = min over j' <= j of t_f[j'] and the
+// match behind it is the first column where that minimum is reached. Each row
+// is therefore one prefix scan of (value, first index) pairs, and row f needs
+// only the part of row f-1 that lies hop columns to the left. One workgroup
+// owns a row and scans it in tiles of 2048 columns; a tile starts as soon as
+// the row above has published the columns it needs, so the rows run as a
+// pipeline one tile apart. Values pass between rows as 64-bit records
+// {float, uint32 epoch} written and read with agent-scope atomics (the DP's
+// boundary handoff), so no side issues a cache-flushing fence. NSDTW is the
+// same scan with t_f = S[f, .].
+//
+// The scan's outputs are Dseg (as records) and, per cell, the first column at
+// which the running minimum is reached (int32). The end columns then follow
+// from one serial walk over nfrag entries: e_{N-1} = first[N-1][m-1], then
+// e_f = first[f][e_{f+1} - hop].
+#include "batch.h"
+
+namespace pardtw {
+namespace {
+
+constexpr int kSegThreads = 256;
+constexpr int kSegPer = 8;                              // columns per thread per tile
+constexpr int kSegTile = kSegThreads * kSegPer;         // columns per tile
+
+struct SegHeader {
+    uint32_t epoch;
+    uint32_t ticket;
+    uint32_t pad[62];
+};
+static_assert(sizeof(SegHeader) == 256, "records stay 256-byte aligned");
+
+struct SegArgs {
+    const float* S;
+    int64_t nf, m, hop;
+    int variant;
+    SegHeader* hdr;
+    uint64_t* rec;    // [nf][m] Dseg records
+    int32_t* first;   // [nf][m] first column of the running minimum (-1 while +inf)
+};
+
+// (value, index) running minimum where the earlier element wins ties.
+struct VI {
+    float v;
+    int32_t i;
+};
+__device__ inline VI later_if_less(VI earlier, VI later) { return later.v < earlier.v ? later : earlier; }
+
+__device__ inline VI shfl_up_vi(VI x, int d) {
+    VI y;
+    y.v = __shfl_up(x.v, d, 64);
+    y.i = __shfl_up(x.i, d, 64);
+    return y;
+}
+
+__global__ __launch_bounds__(kSegThreads) void segment_scan_kernel(SegArgs a) {
+    __shared__ VI wave_tot[kSegThreads / 64];
+    __shared__ int ticket;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const uint32_t epoch = __hip_atomic_load(&a.hdr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const float kInf = __builtin_inff();
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) ticket = int(atomicAdd(&a.hdr->ticket, 1u));
+        __syncthreads();
+        const int64_t f = ticket;
+        if (f >= a.nf) break;
+        const bool chained = a.variant == PARDTW_WSDTW && f > 0;
+        const float* srow = a.S + f * a.m;
+        const uint64_t* prow = a.rec + (f - 1) * a.m;  // used only when chained
+        uint64_t* orow = a.rec + f * a.m;
+        int32_t* frow = a.first + f * a.m;
+        VI carry{kInf, -1};  // running minimum over the tiles before
+        for (int64_t t0 = 0; t0 < a.m; t0 += kSegTile) {
+            const int64_t j0 = t0 + int64_t(tid) * kSegPer;
+            float t[kSegPer];
+#pragma unroll
+            for (int e = 0; e < kSegPer; ++e) t[e] = (j0 + e < a.m) ? srow[j0 + e] : kInf;
+            if (chained) {
+                // Dseg[f-1][j - hop]; +inf left of column hop. Poll until every
+                // needed record carries this launch's epoch.
+                float pv[kSegPer];
+                uint32_t need = 0;
+#pragma unroll
+                for (int e = 0; e < kSegPer; ++e) {
+                    pv[e] = kInf;
+                    if (j0 + e < a.m && j0 + e >= a.hop) need |= 1u << e;
+                }
+                while (need) {
+#pragma unroll
+                    for (int e = 0; e < kSegPer; ++e) {
+                        if (need & (1u << e)) {
+                            const uint64_t r = __hip_atomic_load(prow + (j0 + e - a.hop), __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+                            if (uint32_t(r >> 32) == epoch) {
+                                pv[e] = __uint_as_float(uint32_t(r));
+                                need &= ~(1u << e);
+                            }
+                        }
+                    }
+                    if (need) __builtin_amdgcn_s_sleep(1);
+                }
+#pragma unroll
+                for (int e = 0; e < kSegPer; ++e) t[e] = pv[e] + t[e];
+            }
+            // this thread's columns
+            VI loc[kSegPer];
+            VI run{kInf, -1};
+#pragma unroll
+            for (int e = 0; e < kSegPer; ++e) {
+                run = later_if_less(run, VI{t[e], int32_t(j0 + e)});
+                loc[e] = run;
+            }
+            // exclusive scan over the wave's lanes
+            VI inc = run;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const VI up = shfl_up_vi(inc, d);
+                if (lane >= d) inc = later_if_less(up, inc);
+            }
+            VI before = shfl_up_vi(inc, 1);
+            if (lane == 0) before = VI{kInf, -1};
+            if (lane == 63) wave_tot[wave] = inc;
+            __syncthreads();
+            VI pre = carry;
+            for (int w = 0; w < wave; ++w) pre = later_if_less(pre, wave_tot[w]);
+            pre = later_if_less(pre, before);
+#pragma unroll
+            for (int e = 0; e < kSegPer; ++e) {
+                const int64_t j = j0 + e;
+                if (j < a.m) {
+                    const VI r = later_if_less(pre, loc[e]);
+                    frow[j] = r.i;
+                    __hip_atomic_store(orow + j, (uint64_t(epoch) << 32) | uint64_t(__float_as_uint(r.v)),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            for (int w = 0; w < kSegThreads / 64; ++w) carry = later_if_less(carry, wave_tot[w]);
+            __syncthreads();  // wave_tot is rewritten by the next tile
+        }
+    }
+}
+
+__global__ void segment_prepare(SegHeader* hdr) {
+    hdr->epoch = hdr->epoch + 1;
+    hdr->ticket = 0;
+}
+
+// One lane walks the fragment ends back from the last one.
+__global__ void segment_ends_kernel(SegArgs a, int32_t* ends, float* total, int32_t* status) {
+    if (threadIdx.x != 0) return;
+    const float kInf = __builtin_inff();
+    float tot = 0.0f;
+    bool ok = true;
+    if (a.variant == PARDTW_WSDTW) {
+        tot = __uint_as_float(uint32_t(a.rec[(a.nf - 1) * a.m + a.m - 1]));
+        ok = tot < kInf;
+        int64_t j = a.m - 1;
+        for (int64_t f = a.nf - 1; f >= 0 && ok; --f) {
+            const int32_t e = j >= 0 ? a.first[f * a.m + j] : -1;
+            if (e < 0) ok = false;
+            ends[f] = e;
+            j = int64_t(e) - a.hop;
+        }
+    } else {
+        for (int64_t f = 0; f < a.nf; ++f) {
+            const int32_t e = a.first[f * a.m + a.m - 1];
+            ends[f] = e;
+            tot += __uint_as_float(uint32_t(a.rec[f * a.m + a.m - 1]));
+            if (e < 0) ok = false;
+        }
+        ok = ok && tot < kInf;
+    }
+    if (!ok) {
+        for (int64_t f = 0; f < a.nf; ++f) ends[f] = -1;
+        tot = kInf;
+    }
+    *total = tot;
+    *status = ok ? PARDTW_PAIR_OK : PARDTW_PAIR_INFEASIBLE;
+}
+
+// Concatenation of the fragment paths (each in its own slot of n_f pairs at
+// path_off, rows local to the fragment): block f copies fragment f to the sum
+// of the lengths before it, shifting rows by the fragment's first row.
+__global__ __launch_bounds__(256) void segment_gather_kernel(const BatchPair* __restrict__ pairs, int32_t nf,
+                                                             const int32_t* __restrict__ slots,
+                                                             const int32_t* __restrict__ frag_len,
+                                                             const int32_t* __restrict__ status, int32_t* path,
+                                                             int32_t* path_len) {
+    __shared__ int64_t base;
+    const int f = blockIdx.x;
+    const bool ok = *status == PARDTW_PAIR_OK;
+    if (threadIdx.x == 0) {
+        int64_t s = 0;
+        for (int g = 0; g < f; ++g) s += frag_len[g];
+        base = s;
+        if (f == nf - 1) *path_len = ok ? int32_t(s + frag_len[f]) : 0;
+    }
+    __syncthreads();
+    if (!ok) return;
+    const BatchPair q = pairs[f];
+    const int64_t len = frag_len[f];
+    const int2* src = reinterpret_cast<const int2*>(slots) + q.path_off;
+    int2* dst = reinterpret_cast<int2*>(path) + base;
+    for (int64_t c = threadIdx.x; c < len; c += blockDim.x) {
+        int2 v = src[c];
+        v.x += int32_t(q.x_off);
+        dst[c] = v;
+    }
+}
+
+// Rows of fragments that no end column can be reached for: +inf scores.
+__global__ void segment_init_kernel(const BatchPair* __restrict__ pairs, int32_t nf, float* scores,
+                                    int32_t* frag_status) {
+    const int f = blockIdx.x;
+    const BatchPair q = pairs[f];
+    if (q.feasible) return;
+    for (int64_t j = threadIdx.x; j < q.m; j += blockDim.x) scores[int64_t(f) * q.m + j] = __builtin_inff();
+    if (threadIdx.x == 0) frag_status[f] = PARDTW_PAIR_INFEASIBLE;
+}
+
+}  // namespace
+
+size_t segment_workspace_bytes_impl(int64_t nf, int64_t m) {
+    return sizeof(SegHeader) + size_t(nf) * size_t(m) * (sizeof(uint64_t) + sizeof(int32_t));
+}
+
+pardtw_status segment_ends_launch(const float* S, int64_t nf, int64_t m, int64_t hop, int variant, void* ws,
+                                  int32_t* ends, float* total, int32_t* status, hipStream_t stream) {
+    SegArgs a;
+    a.S = S;
+    a.nf = nf;
+    a.m = m;
+    a.hop = hop;
+    a.variant = variant;
+    a.hdr = reinterpret_cast<SegHeader*>(ws);
+    a.rec = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(ws) + sizeof(SegHeader));
+    a.first = reinterpret_cast<int32_t*>(a.rec + nf * m);
+    int dev = 0, cus = 0;
+    PARDTW_HIP_TRY(hipGetDevice(&dev));
+    PARDTW_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    segment_prepare<<<1, 1, 0, stream>>>(a.hdr);
+    const int64_t grid = nf < 2 * int64_t(cus) ? nf : 2 * int64_t(cus);
+    segment_scan_kernel<<<unsigned(grid), kSegThreads, 0, stream>>>(a);
+    segment_ends_kernel<<<1, 64, 0, stream>>>(a, ends, total, status);
+    return launch_status();
+}
+
+pardtw_status segment_gather_launch(const BatchPair* pairs, int32_t nf, const int32_t* slots,
+                                    const int32_t* frag_len, const int32_t* status, int32_t* path,
+                                    int32_t* path_len, hipStream_t stream) {
+    segment_gather_kernel<<<unsigned(nf), 256, 0, stream>>>(pairs, nf, slots, frag_len, status, path, path_len);
+    return launch_status();
+}
+
+pardtw_status segment_init_launch(const BatchPair* pairs, int32_t nf, float* scores, int32_t* frag_status,
+                                  hipStream_t stream) {
+    segment_init_kernel<<<unsigned(nf), 256, 0, stream>>>(pairs, nf, scores, frag_status);
+    return launch_status();
+}
+
+}  // namespace pardtw
+
+extern "C" size_t pardtw_segment_workspace_bytes(int64_t nfrag, int64_t m) {
+    if (nfrag <= 0 || !pardtw::valid_sizes(nfrag, m)) return 0;
+    return pardtw::segment_workspace_bytes_impl(nfrag, m);
+}
+
+extern "C" pardtw_status pardtw_segment_ends(const float* scores, int64_t nfrag, int64_t m, int64_t hop,
+                                             int32_t variant, void* workspace, size_t workspace_bytes,
+                                             int32_t* ends, float* total, int32_t* status, hipStream_t stream) {
+    if (!scores || !ends || !total || !status || !pardtw::valid_sizes(nfrag, m) || hop < 1)
+        return PARDTW_ERR_INVALID_ARG;
+    if (nfrag > 0x7fffffff) return PARDTW_ERR_UNSUPPORTED;
+    if (variant != PARDTW_NSDTW && variant != PARDTW_WSDTW) return PARDTW_ERR_INVALID_ARG;
+    if (!workspace || workspace_bytes < pardtw::segment_workspace_bytes_impl(nfrag, m)) return PARDTW_ERR_WORKSPACE;
+    return pardtw::segment_ends_launch(scores, nfrag, m, hop, variant, workspace, ends, total, status, stream);
+}

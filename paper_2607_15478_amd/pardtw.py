@@ -24,6 +24,9 @@ PREC_BF16 = 1
 LAYOUT_ROW = 0
 LAYOUT_PANEL = 1
 LAYOUT_PANEL_BAND = 2  # panel layout, only the 8-row groups the DP reads (the path band) are written
+LAYOUT_PANEL_SUBSEQ_BAND = 3  # panel layout, only the groups the subsequence DP reads are written
+NSDTW = 0
+WSDTW = 1
 
 STATUS_NAMES = {0: "OK", 1: "ERR_INVALID_ARG", 2: "ERR_WORKSPACE", 3: "ERR_HIP", 4: "ERR_UNSUPPORTED"}
 
@@ -67,6 +70,15 @@ _lib_plan_selected = _sig("pardtw_plan_selected", _I32, [_P])
 _lib_plan_select = _sig("pardtw_plan_select", _E, [_P, _I32])
 _lib_plan_autotune = _sig("pardtw_plan_autotune", _E, [_P, _P, _P, _P, _SZ, _P, _P, _P, _P, _I32, _P, _P])
 _lib_status_string = _sig("pardtw_status_string", ctypes.c_char_p, [_E])
+_lib_sub_band = _sig("pardtw_subseq_band_groups", _E, [_I64, _I64, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_I64)])
+_lib_sub_dp = _sig("pardtw_subseq_dp", _E, [_P, _E, _I64, _I64, _P, _P, _P, _P, _SZ, _P])
+_lib_sub_bt = _sig("pardtw_subseq_backtrace", _E, [_P, _I64, _I64, _P, _P, _P, _P])
+_lib_seg_ws = _sig("pardtw_segment_workspace_bytes", _SZ, [_I64, _I64])
+_lib_seg_ends = _sig("pardtw_segment_ends", _E, [_P, _I64, _I64, _I64, _I32, _P, _SZ, _P, _P, _P, _P])
+_lib_segplan_create = _sig("pardtw_segplan_create", _E, [_I64, _I64, _I32, _I64, _E, _I32, ctypes.POINTER(_P)])
+_lib_segplan_scores = _sig("pardtw_segplan_scores_offset", _I64, [_P])
+_lib_seg_align = _sig("pardtw_segmental_align", _E, [_P, _P, _P, _P, _SZ, _P, _P, _P, _P, _P, _P])
+_lib_segplan_autotune = _sig("pardtw_segplan_autotune", _E, [_P, _P, _P, _P, _SZ, _I32, _P, _P])
 
 
 class PardtwError(RuntimeError):
@@ -294,3 +306,138 @@ def pack(pairs, device="cuda"):
     Xp = torch.from_numpy(np.ascontiguousarray(np.concatenate([p[0] for p in pairs]), dtype=np.float32)).to(device)
     Yp = torch.from_numpy(np.ascontiguousarray(np.concatenate([p[1] for p in pairs]), dtype=np.float32)).to(device)
     return Xp, Yp
+
+
+# ---- subsequence DTW and Segmental DTW --------------------------------------
+def pardtw_subseq_band_groups(n: int, m: int, p: int):
+    """(lo, hi): the 8-row groups of panel p in the subsequence band."""
+    lo, hi = _I64(), _I64()
+    _check(_lib_sub_band(n, m, p, ctypes.byref(lo), ctypes.byref(hi)), "pardtw_subseq_band_groups")
+    return lo.value, hi.value
+
+
+def pardtw_subseq_dp(C: torch.Tensor, n: int, m: int, bp: torch.Tensor, scores: torch.Tensor, status: torch.Tensor,
+                     workspace: torch.Tensor, layout: int = LAYOUT_PANEL, stream=None):
+    _dev_f32(C, "C"), _dev_f32(scores, "scores")
+    if C.numel() < pardtw_cost_elems(n, m, layout):
+        raise ValueError("C is too small for this layout")
+    if bp.dtype != torch.uint8 or bp.numel() < pardtw_bp_bytes(n, m):
+        raise ValueError("bp must be a uint8 tensor of pardtw_bp_bytes(n, m) bytes")
+    if scores.numel() < m or status.dtype != torch.int32:
+        raise ValueError("scores must hold m floats and status be int32")
+    ws_bytes = workspace.numel() * workspace.element_size()
+    _check(_lib_sub_dp(_ptr(C), layout, n, m, _ptr(bp), _ptr(scores), _ptr(status), _ptr(workspace), ws_bytes,
+                       _stream(stream)), "pardtw_subseq_dp")
+
+
+def pardtw_subseq_backtrace(bp: torch.Tensor, n: int, m: int, end_col: torch.Tensor, path: torch.Tensor,
+                            path_len: torch.Tensor, stream=None):
+    if path.dtype != torch.int32 or path.numel() < 2 * n:
+        raise ValueError("path must be int32 with room for 2*n entries")
+    if end_col.dtype != torch.int32:
+        raise ValueError("end_col must be int32")
+    _check(_lib_sub_bt(_ptr(bp), n, m, _ptr(end_col), _ptr(path), _ptr(path_len), _stream(stream)),
+           "pardtw_subseq_backtrace")
+
+
+def pardtw_segment_workspace_bytes(nfrag: int, m: int) -> int:
+    return int(_lib_seg_ws(nfrag, m))
+
+
+def pardtw_segment_ends(scores: torch.Tensor, nfrag: int, m: int, hop: int, variant: int, workspace: torch.Tensor,
+                        ends: torch.Tensor, total: torch.Tensor, status: torch.Tensor, stream=None):
+    _dev_f32(scores, "scores")
+    if scores.numel() < nfrag * m or ends.dtype != torch.int32 or ends.numel() < nfrag:
+        raise ValueError("scores must hold nfrag*m floats and ends nfrag int32")
+    ws_bytes = workspace.numel() * workspace.element_size()
+    _check(_lib_seg_ends(_ptr(scores), nfrag, m, int(hop), int(variant), _ptr(workspace), ws_bytes, _ptr(ends),
+                         _ptr(total), _ptr(status), _stream(stream)), "pardtw_segment_ends")
+
+
+def fragment_starts(la: int, nfrag: int):
+    """First row of each fragment plus la: fragment f is [floor(f la/N), floor((f+1) la/N))."""
+    return [(f * la) // nfrag for f in range(nfrag + 1)]
+
+
+def segment_hop(la: int, nfrag: int) -> int:
+    return max(1, la // (2 * nfrag))
+
+
+class SegPlan:
+    """Segmental DTW of A (la x d) against B (lb x d) with nfrag fragments
+    (pardtw_segplan_create); `buffers()` allocates the outputs and workspace."""
+
+    def __init__(self, la: int, lb: int, nfrag: int, d: int, prec: int = PREC_F32, variant: int = WSDTW):
+        self.la, self.lb, self.nfrag, self.d, self.prec, self.variant = int(la), int(lb), int(nfrag), int(d), prec, variant
+        h = _P()
+        _check(_lib_segplan_create(self.la, self.lb, self.nfrag, self.d, prec, int(variant), ctypes.byref(h)),
+               "pardtw_segplan_create")
+        self._h = h
+        self.workspace_bytes = int(_lib_plan_ws(h))
+        self.scores_offset = int(_lib_segplan_scores(h))
+        self.starts = fragment_starts(self.la, self.nfrag)
+        self.hop = segment_hop(self.la, self.nfrag)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib_plan_destroy(h)
+            self._h = None
+
+    def buffers(self, device="cuda"):
+        return dict(
+            workspace=torch.zeros(self.workspace_bytes, dtype=torch.uint8, device=device),
+            total=torch.empty(1, dtype=torch.float32, device=device),
+            ends=torch.empty(self.nfrag, dtype=torch.int32, device=device),
+            path=torch.empty((self.la, 2), dtype=torch.int32, device=device),
+            path_len=torch.empty(1, dtype=torch.int32, device=device),
+            status=torch.empty(1, dtype=torch.int32, device=device),
+        )
+
+    def _check_inputs(self, A, B):
+        _dev_f32(A, "A"), _dev_f32(B, "B")
+        if A.shape != (self.la, self.d) or B.shape != (self.lb, self.d):
+            raise ValueError("A and B do not match the plan")
+
+    def align(self, A: torch.Tensor, B: torch.Tensor, buf: dict, stream=None):
+        self._check_inputs(A, B)
+        ws = buf["workspace"]
+        _check(_lib_seg_align(self._h, _ptr(A), _ptr(B), _ptr(ws), ws.numel() * ws.element_size(),
+                              _ptr(buf["total"]), _ptr(buf["ends"]), _ptr(buf["path"]), _ptr(buf["path_len"]),
+                              _ptr(buf["status"]), _stream(stream)), "pardtw_segmental_align")
+
+    def autotune(self, A: torch.Tensor, B: torch.Tensor, buf: dict, reps: int = 2, stream=None) -> float:
+        self._check_inputs(A, B)
+        ws = buf["workspace"]
+        best = ctypes.c_float(0.0)
+        _check(_lib_segplan_autotune(self._h, _ptr(A), _ptr(B), _ptr(ws), ws.numel() * ws.element_size(), int(reps),
+                                     ctypes.byref(best), _stream(stream)), "pardtw_segplan_autotune")
+        return float(best.value)
+
+    def scores(self, buf: dict) -> torch.Tensor:
+        """The stacked fragment scores S (nfrag x lb) left in the workspace."""
+        ws = buf["workspace"]
+        n = self.nfrag * self.lb
+        return ws[self.scores_offset: self.scores_offset + 4 * n].view(torch.float32).view(self.nfrag, self.lb)
+
+    def schedule(self, index: int = -1):
+        nw, order, wg = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib_plan_sched(self._h, int(index), ctypes.byref(nw), ctypes.byref(order), ctypes.byref(wg)),
+               "pardtw_plan_schedule")
+        return dict(panels_per_workgroup=nw.value, order=("breadth", "depth")[order.value], workgroups=wg.value)
+
+    def select(self, index: int):
+        _check(_lib_plan_select(self._h, int(index)), "pardtw_plan_select")
+
+    @property
+    def num_schedules(self) -> int:
+        return int(_lib_plan_nsched(self._h))
+
+
+def segmental(A: torch.Tensor, B: torch.Tensor, nfrag: int, variant: int = WSDTW, prec: int = PREC_F32):
+    """Segmental DTW on the GPU: (total, ends (nfrag,), path (L,2), status)."""
+    plan = SegPlan(A.shape[0], B.shape[0], nfrag, A.shape[1], prec, variant)
+    buf = plan.buffers(A.device)
+    plan.align(A, B, buf)
+    L = int(buf["path_len"].item())
+    return float(buf["total"].item()), buf["ends"].clone(), buf["path"][:L].clone(), int(buf["status"].item())

@@ -111,6 +111,29 @@ def band_groups(n: int, m: int) -> np.ndarray:
     return per_group(fwd) & per_group(end)
 
 
+def subseq_band_mask(n: int, m: int) -> np.ndarray:
+    """(n, m) bool: cells that can lie on a subsequence path (Sec. II-B), which
+    starts anywhere on row 0 and ends anywhere on row n-1: row 0 reaches the
+    cell (i <= 2j) and the cell reaches row n-1 inside the matrix
+    ((n-1-i) <= 2(m-1-j)). The subsequence DP defines codes on these cells."""
+    i = np.arange(n)[:, None]
+    j = np.arange(m)[None, :]
+    return (i <= 2 * j) & ((n - 1 - i) <= 2 * (m - 1 - j))
+
+
+def subseq_band_groups(n: int, m: int) -> np.ndarray:
+    """(P, G) bool: group k of panel p holds a real cell that row 0 reaches and
+    a real cell that reaches row n-1 (enumerated cell by cell)."""
+    P, G = -(-m // 64), -(-n // 8)
+    i = np.arange(n)[:, None]
+    j = np.arange(m)[None, :]
+    def per_group(mask):
+        pad = np.zeros((G * 8, P * 64), dtype=bool)
+        pad[:n, :m] = mask
+        return pad.reshape(G, 8, P, 64).any(axis=(1, 3)).T
+    return per_group(i <= 2 * j) & per_group((n - 1 - i) <= 2 * (m - 1 - j))
+
+
 def check_total(gpu_total: float, oracle_total: float):
     if not np.isfinite(oracle_total):
         assert not np.isfinite(gpu_total)

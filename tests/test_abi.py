@@ -75,6 +75,27 @@ def test_band_groups_match_cell_enumeration(lib, n, m):
     assert lib.pardtw_band_groups(n, m, 0, None, ctypes.byref(hi)) != 0
 
 
+@pytest.mark.parametrize("n,m", [(1, 1), (1, 70), (7, 3), (8, 64), (9, 65), (40, 17), (100, 30), (129, 64),
+                                 (500, 1200), (1200, 500), (999, 501), (1562, 60000), (3000, 1500), (64, 4000)])
+def test_subseq_band_groups_match_cell_enumeration(lib, n, m):
+    """The subsequence band bounds against the band enumerated cell by cell."""
+    from tests import parity
+    import numpy as np
+    I = ctypes.c_int64
+    lib.pardtw_subseq_band_groups.restype = ctypes.c_int
+    lib.pardtw_subseq_band_groups.argtypes = [I, I, I, ctypes.POINTER(I), ctypes.POINTER(I)]
+    want = parity.subseq_band_groups(n, m)
+    P, G = want.shape
+    lo, hi = I(), I()
+    for p in range(P):
+        assert lib.pardtw_subseq_band_groups(n, m, p, ctypes.byref(lo), ctypes.byref(hi)) == 0
+        got = np.zeros(G, dtype=bool)
+        if lo.value <= hi.value:
+            got[lo.value:hi.value + 1] = True
+        assert np.array_equal(got, want[p]), (n, m, p, lo.value, hi.value)
+    assert lib.pardtw_subseq_band_groups(n, m, P, ctypes.byref(lo), ctypes.byref(hi)) != 0
+
+
 def test_validation_without_gpu(lib):
     I = ctypes.c_int64
     P = ctypes.c_void_p

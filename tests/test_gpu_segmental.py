@@ -1,0 +1,374 @@
+"""GPU parity of subsequence DTW and Segmental DTW (Sec. II-B, II-C, III-A)
+against the FP64 oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_15478_amd import synth
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - collected on CPU hosts too
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2607_15478_amd import pardtw as pd  # noqa: E402
+
+DEV = "cuda:0"
+SUB_W = (1.0, 1.0, 2.0)
+
+
+def _gpu_subseq(C: np.ndarray, layout=pd.LAYOUT_ROW):
+    n, m = C.shape
+    flat = parity.to_panel(C) if layout == pd.LAYOUT_PANEL else C.reshape(-1).copy()
+    Cd = torch.from_numpy(flat).to(DEV)
+    bp = torch.empty(pd.pardtw_bp_bytes(n, m), dtype=torch.uint8, device=DEV)
+    ws = torch.zeros(pd.pardtw_dp_workspace_bytes(n, m), dtype=torch.uint8, device=DEV)
+    scores = torch.empty(m, dtype=torch.float32, device=DEV)
+    status = torch.empty(1, dtype=torch.int32, device=DEV)
+    pd.pardtw_subseq_dp(Cd, n, m, bp, scores, status, ws, layout)
+    B = pd.pardtw_bp_unpack(bp, n, m)
+    torch.cuda.synchronize()
+    return scores.cpu().numpy(), int(status.item()), B.cpu().numpy(), bp
+
+
+def _gpu_subseq_path(bp, n, m, end):
+    e = torch.tensor([end], dtype=torch.int32, device=DEV)
+    path = torch.empty((n, 2), dtype=torch.int32, device=DEV)
+    plen = torch.empty(1, dtype=torch.int32, device=DEV)
+    pd.pardtw_subseq_backtrace(bp, n, m, e, path, plen)
+    torch.cuda.synchronize()
+    return path[: int(plen.item())].cpu().numpy()
+
+
+def _check_scores(g, o):
+    fin = np.isfinite(o)
+    assert np.array_equal(np.isfinite(g), fin)
+    assert np.all(np.abs(g[fin] - o[fin]) <= parity.TOTAL_REL * np.abs(o[fin]) + 1e-6)
+
+
+SHAPES = [(1, 1), (1, 70), (2, 2), (3, 2), (5, 9), (9, 5), (7, 3), (8, 8), (63, 64), (64, 65), (65, 63),
+          (100, 199), (129, 300), (300, 129), (333, 400), (520, 700), (700, 300), (9, 1), (40, 17)]
+
+
+@pytest.mark.parametrize("n,m", SHAPES)
+def test_subseq_integer_costs_bit_exact(n, m):
+    """Small-integer costs make every sum exact in FP32 and FP64: scores and the
+    codes of the subsequence band (tie rule included) must match bit for bit,
+    and unreachable ends (2j < n-1) must read +inf."""
+    rng = np.random.default_rng(n * 7919 + m)
+    C = rng.integers(0, 3, size=(n, m)).astype(np.float32)
+    S, BP, _ = oracle.subseq_matrix(C)
+    g_S, g_status, g_BP, bp = _gpu_subseq(C)
+    feasible = 2 * (m - 1) >= n - 1
+    assert g_status == (pd.PAIR_OK if feasible else pd.PAIR_INFEASIBLE)
+    assert np.array_equal(np.isinf(g_S), np.isinf(S)) and np.array_equal(g_S[np.isfinite(S)], S[np.isfinite(S)])
+    band = parity.subseq_band_mask(n, m)
+    assert np.array_equal(g_BP[band], BP[band])
+    for e in sorted({0, m // 2, m - 1, (n - 1 + 1) // 2}):
+        if e < m:
+            assert np.array_equal(_gpu_subseq_path(bp, n, m, e), oracle.subseq_backtrace(BP, e)), e
+
+
+@pytest.mark.parametrize("c", [0.5, 1.0])
+@pytest.mark.parametrize("n,m", [(200, 260), (260, 200), (129, 1025), (1000, 1200), (64, 64)])
+def test_subseq_constant_cost(c, n, m):
+    # every subsequence path weighs n: S[j] = c n exactly where reachable
+    C = np.full((n, m), c, dtype=np.float32)
+    S, BP, _ = oracle.subseq_matrix(C)
+    g_S, _, g_BP, _ = _gpu_subseq(C)
+    j = np.arange(m)
+    assert np.all(g_S[2 * j >= n - 1] == c * n) and np.all(np.isinf(g_S[2 * j < n - 1]))
+    band = parity.subseq_band_mask(n, m)
+    assert np.array_equal(g_BP[band], BP[band])
+
+
+def _audit_subseq_bp(g_BP, BP, D, C, band):
+    """Band cells whose codes differ must be declared near-ties of the oracle's
+    FP64 subsequence candidates."""
+    diff = np.argwhere((g_BP != BP) & band)
+    for i, j in diff:
+        cand = np.full(3, np.inf)
+        for r, (di, dj) in enumerate(parity.STEPS):
+            if i - di >= 0 and j - dj >= 0:
+                cand[r] = D[i - di, j - dj] + SUB_W[r] * float(C[i, j])
+        assert 0 <= g_BP[i, j] <= 2 and 0 <= BP[i, j] <= 2, (i, j)
+        assert parity.is_tie(cand, int(BP[i, j]), int(g_BP[i, j])), (i, j, cand)
+    return len(diff)
+
+
+@pytest.mark.parametrize("n,m", [(130, 400), (333, 1000), (600, 520), (1000, 3000)])
+def test_subseq_random_costs_full_bp(n, m):
+    rng = np.random.default_rng(17 + n)
+    C = rng.uniform(0.0, 1.0, size=(n, m)).astype(np.float32)
+    S, BP, D = oracle.subseq_matrix(C, want_D=True)
+    g_S, _, g_BP, bp = _gpu_subseq(C, pd.LAYOUT_PANEL)
+    _check_scores(g_S, S)
+    ties = _audit_subseq_bp(g_BP, BP, D, C, parity.subseq_band_mask(n, m))
+    assert ties <= 1e-4 * n * m + 5
+    # a path from the best end: legal, ends where asked, re-scores to S[e]
+    e = int(np.argmin(g_S))
+    path = _gpu_subseq_path(bp, n, m, e)
+    assert path[0][0] == 0 and tuple(path[-1]) == (n - 1, e)
+    assert np.all(parity.step_codes(path) >= 0)
+    assert oracle.subseq_path_score(C.astype(np.float64), path) <= S.min() * (1 + 1e-6) + 1e-9
+
+
+def test_subseq_layouts_identical_and_band():
+    # ROW, PANEL and the subsequence band layout give bit-identical scores and
+    # band codes (the band layout from the cost kernel itself)
+    rng = np.random.default_rng(5)
+    n, m, d = 333, 2100, 12
+    X = synth.chroma_like(rng, n, d).astype(np.float32)
+    Y = synth.chroma_like(rng, m, d).astype(np.float32)
+    Xd, Yd = torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV)
+    band = parity.subseq_band_mask(n, m)
+    res = []
+    for layout in (pd.LAYOUT_ROW, pd.LAYOUT_PANEL, pd.LAYOUT_PANEL_SUBSEQ_BAND):
+        C = torch.full((pd.pardtw_cost_elems(n, m, layout),), float("nan"), dtype=torch.float32, device=DEV)
+        pd.pardtw_cost(Xd, Yd, C, pd.PREC_F32, layout)
+        bp = torch.empty(pd.pardtw_bp_bytes(n, m), dtype=torch.uint8, device=DEV)
+        ws = torch.zeros(pd.pardtw_dp_workspace_bytes(n, m), dtype=torch.uint8, device=DEV)
+        sc = torch.empty(m, dtype=torch.float32, device=DEV)
+        st = torch.empty(1, dtype=torch.int32, device=DEV)
+        pd.pardtw_subseq_dp(C, n, m, bp, sc, st, ws, layout)
+        res.append((sc.cpu().numpy(), pd.pardtw_bp_unpack(bp, n, m).cpu().numpy()))
+    for s_got, b_got in res[1:]:
+        assert np.array_equal(s_got, res[0][0]) and np.array_equal(b_got[band], res[0][1][band])
+    S, _ = oracle.subseq_features(X, Y)
+    _check_scores(res[0][0], S)
+    with pytest.raises(pd.PardtwError):
+        pd.pardtw_subseq_dp(C, n, m, bp, sc, st, ws, pd.LAYOUT_PANEL_BAND)
+
+
+@pytest.mark.parametrize("n,m", [(50, 3000), (200, 5000)])
+def test_subseq_reference_windows_exact(n, m):
+    """Sec. III-A: the scores of end columns [a, b) need only reference columns
+    [a - 2(n-1), b). A sweep over that window gives bit-identical scores: the
+    result does not depend on how the reference is cut into chunks."""
+    rng = np.random.default_rng(n + m)
+    C = rng.uniform(size=(n, m)).astype(np.float32)
+    full, _, _, _ = _gpu_subseq(C)
+    for k in (2, 5, 9):
+        bounds = [(c * m) // k for c in range(k + 1)]
+        for a, b in zip(bounds[:-1], bounds[1:]):
+            lo = max(0, a - 2 * (n - 1))
+            win, _, _, _ = _gpu_subseq(np.ascontiguousarray(C[:, lo:b]))
+            got, want = win[a - lo:], full[a:b]
+            assert np.array_equal(np.isinf(got), np.isinf(want))
+            assert np.array_equal(got[np.isfinite(got)], want[np.isfinite(want)]), (k, a, b)
+
+
+def test_subseq_backtrace_bad_ends():
+    rng = np.random.default_rng(3)
+    n, m = 100, 300
+    C = rng.uniform(size=(n, m)).astype(np.float32)
+    _, _, _, bp = _gpu_subseq(C)
+    for e in (-1, m, m + 50, 10, 48):  # outside the matrix, or 2e < n-1
+        assert len(_gpu_subseq_path(bp, n, m, e)) == 0, e
+    assert len(_gpu_subseq_path(bp, n, m, 50)) > 0
+
+
+def _gpu_segment(S: np.ndarray, hop: int, variant: int):
+    nf, m = S.shape
+    Sd = torch.from_numpy(np.ascontiguousarray(S, dtype=np.float32)).to(DEV)
+    ws = torch.zeros(pd.pardtw_segment_workspace_bytes(nf, m), dtype=torch.uint8, device=DEV)
+    ends = torch.empty(nf, dtype=torch.int32, device=DEV)
+    total = torch.empty(1, dtype=torch.float32, device=DEV)
+    status = torch.empty(1, dtype=torch.int32, device=DEV)
+    pd.pardtw_segment_ends(Sd, nf, m, hop, variant, ws, ends, total, status)
+    torch.cuda.synchronize()
+    return float(total.item()), ends.cpu().numpy().astype(np.int64), int(status.item())
+
+
+SEG_CASES = [(1, 1, 1), (1, 5000, 3), (2, 7, 2), (3, 2047, 1), (3, 2049, 700), (5, 6000, 40), (32, 20000, 781),
+             (17, 4096, 1), (600, 40, 1), (40, 9000, 100)]
+
+
+@pytest.mark.parametrize("variant", [pd.NSDTW, pd.WSDTW])
+@pytest.mark.parametrize("nf,m,hop", SEG_CASES)
+def test_segment_ends_integer_bit_exact(nf, m, hop, variant):
+    """Small-integer scores are exact in FP32: ends, total and status must equal
+    the oracle's, tie rule included; leading +inf columns model the ends a
+    fragment cannot reach."""
+    rng = np.random.default_rng(nf * 31 + m + hop)
+    S = rng.integers(0, 4, size=(nf, m)).astype(np.float32)
+    S[:, : min(m - 1, int(rng.integers(0, 30)))] = np.inf
+    total, ends = oracle.segment_ends(S, hop, variant)
+    g_total, g_ends, g_status = _gpu_segment(S, hop, variant)
+    if np.isfinite(total):
+        assert g_status == pd.PAIR_OK and g_total == total
+        assert np.array_equal(g_ends, ends)
+    else:
+        assert g_status == pd.PAIR_INFEASIBLE and np.isinf(g_total) and np.all(g_ends == -1)
+
+
+@pytest.mark.parametrize("nf,m,hop", [(8, 3000, 100), (32, 60000, 781), (100, 5000, 20)])
+def test_segment_ends_random_scores(nf, m, hop):
+    rng = np.random.default_rng(nf + m)
+    S = rng.uniform(0.0, 50.0, size=(nf, m)).astype(np.float32)
+    total, ends = oracle.segment_ends(S, hop, pd.WSDTW)
+    g_total, g_ends, g_status = _gpu_segment(S, hop, pd.WSDTW)
+    assert g_status == pd.PAIR_OK
+    parity.check_total(g_total, total)
+    assert np.all(np.diff(g_ends) >= hop) and g_ends[0] >= 0 and g_ends[-1] < m
+    # the GPU's placement is optimal in FP64 up to the tie tolerance
+    got = float(np.sum(S.astype(np.float64)[np.arange(nf), g_ends]))
+    assert got <= total * (1 + parity.TIE_REL) + 1e-9
+
+
+def _pair(seed, la, lb):
+    """A warped chroma pair; slopes within 10% of the length ratio when it is
+    outside the default tempo range."""
+    r = (lb - 1) / (la - 1)
+    lo, hi = (0.8, 1.25) if 0.8 <= r <= 1.25 else (0.9 * r, 1.1 * r)
+    return synth.chroma_pair(seed, la, lb, 12, lo, hi), hi <= 1.25
+
+
+def _scores_of_plan(plan, buf):
+    return plan.scores(buf).cpu().numpy()
+
+
+def _check_segmental(A, B, nf, variant, plan=None, buf=None):
+    la, lb = A.shape[0], B.shape[0]
+    ref = oracle.segmental(A, B, nf, variant)
+    if plan is None:
+        plan = pd.SegPlan(la, lb, nf, A.shape[1], pd.PREC_F32, variant)
+        buf = plan.buffers(DEV)
+    plan.align(torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV), buf)
+    torch.cuda.synchronize()
+    status = int(buf["status"].item())
+    g_total = float(buf["total"].item())
+    g_ends = buf["ends"].cpu().numpy().astype(np.int64)
+    L = int(buf["path_len"].item())
+    g_path = buf["path"][:L].cpu().numpy()
+    g_S = _scores_of_plan(plan, buf)
+    for f in range(nf):
+        _check_scores(g_S[f], ref["S"][f])
+    if not np.isfinite(ref["total"]):
+        assert status == pd.PAIR_INFEASIBLE and np.isinf(g_total) and L == 0 and np.all(g_ends == -1)
+        return ref, None
+    assert status == pd.PAIR_OK
+    parity.check_total(g_total, ref["total"])
+    # the GPU ends are the oracle's, or an equally good placement within the
+    # tie tolerance (scored with the oracle's FP64 scores)
+    got = float(np.sum(ref["S"][np.arange(nf), g_ends]))
+    assert got <= ref["total"] * (1 + parity.TIE_REL) + 1e-9
+    if variant == pd.WSDTW:
+        assert np.all(np.diff(g_ends) >= ref["hop"])
+    # the concatenated path: fragment by fragment, each a legal subsequence
+    # path from the fragment's first row to (last row, end) whose FP64 score
+    # is its fragment's score at that end
+    starts = ref["starts"]
+    rows = g_path[:, 0]
+    assert np.all(np.diff(rows) >= 1)
+    C = oracle.cost(A, B)
+    pos = 0
+    for f in range(nf):
+        k = np.searchsorted(rows, starts[f + 1])
+        seg = g_path[pos:k].astype(np.int64)
+        pos = k
+        assert seg[0][0] == starts[f] and tuple(seg[-1]) == (starts[f + 1] - 1, g_ends[f])
+        loc = seg - np.array([starts[f], 0])
+        sc = oracle.subseq_path_score(C[starts[f]:starts[f + 1]], loc)
+        assert abs(sc - ref["S"][f, g_ends[f]]) <= parity.TOTAL_REL * abs(sc) + 1e-6
+    assert pos == L
+    return ref, (g_total, g_ends, g_path)
+
+
+@pytest.mark.parametrize("variant", [pd.NSDTW, pd.WSDTW])
+@pytest.mark.parametrize("la,lb,nf", [(300, 360, 1), (1000, 1200, 4), (2000, 2400, 16), (1500, 1300, 7),
+                                      (777, 3000, 3), (4000, 4800, 32)])
+def test_segmental_align_against_oracle(la, lb, nf, variant):
+    (A, B), exact = _pair(la * 10 + nf, la, lb)
+    ref, got = _check_segmental(A, B, nf, variant)
+    if exact:
+        # with tempo changes the step set can follow, the placements agree exactly
+        assert np.array_equal(got[1], ref["ends"])
+
+
+@pytest.mark.parametrize("nf", [1, 3, 8])
+def test_segmental_self_alignment(nf):
+    rng = np.random.default_rng(8)
+    A = synth.chroma_like(rng, 900, 12).astype(np.float32)
+    plan = pd.SegPlan(900, 900, nf, 12)
+    buf = plan.buffers(DEV)
+    Ad = torch.from_numpy(A).to(DEV)
+    plan.align(Ad, Ad, buf)
+    starts = np.array(plan.starts)
+    assert np.array_equal(buf["ends"].cpu().numpy(), starts[1:] - 1)
+    L = int(buf["path_len"].item())
+    assert L == 900 and np.array_equal(buf["path"][:L].cpu().numpy(), np.stack([np.arange(900)] * 2, axis=1))
+    assert abs(float(buf["total"].item())) < 1e-3
+
+
+def test_segmental_infeasible_and_reuse():
+    # fragments longer than twice B cannot end anywhere; then the same plan
+    # and workspace serve a feasible call (stale records are not reused)
+    rng = np.random.default_rng(9)
+    A = synth.chroma_like(rng, 500, 12).astype(np.float32)
+    B = synth.chroma_like(rng, 100, 12).astype(np.float32)
+    _check_segmental(A, B, 2, pd.WSDTW)
+    plan = pd.SegPlan(400, 600, 4, 12)
+    buf = plan.buffers(DEV)
+    (A2, B2), _ = _pair(11, 400, 600)
+    for _ in range(2):
+        _check_segmental(A2, B2, 4, pd.WSDTW, plan, buf)
+
+
+def test_segmental_schedules_identical():
+    la, lb, nf = 1200, 2000, 6
+    (A, B), _ = _pair(12, la, lb)
+    plan = pd.SegPlan(la, lb, nf, 12)
+    buf = plan.buffers(DEV)
+    Ad, Bd = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+    outs = []
+    for s in range(plan.num_schedules):
+        plan.select(s)
+        plan.align(Ad, Bd, buf)
+        torch.cuda.synchronize()
+        L = int(buf["path_len"].item())
+        outs.append((float(buf["total"].item()), buf["ends"].cpu().numpy(), buf["path"][:L].cpu().numpy(),
+                     _scores_of_plan(plan, buf)))
+    for o in outs[1:]:
+        assert o[0] == outs[0][0] and np.array_equal(o[1], outs[0][1]) and np.array_equal(o[2], outs[0][2])
+        assert np.array_equal(o[3], outs[0][3])
+    best = plan.autotune(Ad, Bd, buf, reps=1)
+    assert best > 0
+
+
+@pytest.mark.slow
+def test_segmental_full_size_sampled():
+    """50000 x 60000, 32 fragments (the long-pair workload): the fragment
+    scores of three sampled fragments against the oracle, the segment level
+    against the oracle run on the GPU's own scores, and every fragment path
+    re-scored in FP64."""
+    X, Y = synth.make_workload("pair_50000x60000_d12")
+    la, lb, nf = X.shape[0], Y.shape[0], 32
+    plan = pd.SegPlan(la, lb, nf, X.shape[1])
+    buf = plan.buffers(DEV)
+    plan.align(torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV), buf)
+    torch.cuda.synchronize()
+    g_S = _scores_of_plan(plan, buf).astype(np.float64)
+    starts = plan.starts
+    for f in (0, 15, 31):
+        S, _ = oracle.subseq_features(X[starts[f]:starts[f + 1]], Y)
+        _check_scores(g_S[f].astype(np.float32), S)
+    total, ends = oracle.segment_ends(g_S, plan.hop, pd.WSDTW)
+    g_ends = buf["ends"].cpu().numpy().astype(np.int64)
+    g_total = float(buf["total"].item())
+    parity.check_total(g_total, total)
+    got = float(np.sum(g_S[np.arange(nf), g_ends]))
+    assert got <= total * (1 + parity.TIE_REL) + 1e-9
+    L = int(buf["path_len"].item())
+    path = buf["path"][:L].cpu().numpy().astype(np.int64)
+    rows = path[:, 0]
+    assert np.all(np.diff(rows) >= 1) and rows[0] == 0 and rows[-1] == la - 1
+    pos = 0
+    for f in range(nf):
+        k = np.searchsorted(rows, starts[f + 1])
+        seg = path[pos:k]
+        pos = k
+        assert tuple(seg[-1]) == (starts[f + 1] - 1, g_ends[f]) and seg[0][0] == starts[f]
+        assert np.all(parity.step_codes(seg) >= 0)
