@@ -180,6 +180,10 @@ WORKLOADS = {
     "batch256_500to8000_d12_feasible": dict(kind="chroma_batch", seed=4, count=256, lo=500, hi=8000, d=12,
                                             redraw_infeasible=True),
     "batch32_2000to4000_d128": dict(kind="gaussian_batch", seed=5, count=32, lo=2000, hi=4000, d=128),
+    # Segmental DTW of two 100k-frame sequences (Sec. VI-C times WSDTW on the GPU at 100k); the
+    # number of fragments is a run parameter
+    "segmental_100000x100000_d12": dict(kind="pair", seed=6, n=100000, m=100000, d=12, lo=0.8, hi=1.25),
+    "segmental_50000x60000_d12": dict(kind="pair", seed=3, n=50000, m=60000, d=12, lo=0.7, hi=1.4),
 }
 
 
