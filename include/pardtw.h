@@ -154,6 +154,20 @@ pardtw_status pardtw_dp_ex(const float* C, pardtw_layout layout, int64_t n, int6
                            float* total, int32_t* pair_status, void* workspace, size_t workspace_bytes,
                            int32_t panels_per_workgroup, hipStream_t stream);
 
+/* The DP with the cost computed inside it, as ParDTW does (Sec. II-D): no cost
+ * matrix is written or read, so the DP moves one byte per cell (its codes).
+ * Each 64-column panel's costs are produced 16 rows at a time by a producer
+ * wave running the cost GEMM's own MFMA slab into LDS, so every cost, code,
+ * total and status is bit for bit that of pardtw_cost (FP32) followed by
+ * pardtw_dp.
+ *   X [device, n*d FP32], Y [device, m*d FP32]: row-major features, 1 <= d <= 16
+ *   (PARDTW_ERR_UNSUPPORTED otherwise).
+ *   bp, total, pair_status, workspace: as pardtw_dp.
+ *   panels_per_workgroup: 0 (chosen from the size), 1, 2 or 4. */
+pardtw_status pardtw_dp_fused(const float* X, const float* Y, int64_t n, int64_t m, int64_t d, uint8_t* bp,
+                              float* total, int32_t* pair_status, void* workspace, size_t workspace_bytes,
+                              int32_t panels_per_workgroup, hipStream_t stream);
+
 /* a4: backtrace (Sec. II-D, Sec. VI-C) from (n-1, m-1) along the codes.
  *   bp [device]: codes written by pardtw_dp for the same (n, m).
  *   pair_status [device, 1 int32]: as written by pardtw_dp.
@@ -299,6 +313,13 @@ pardtw_status pardtw_subseq_band_groups(int64_t n, int64_t m, int64_t p, int64_t
 pardtw_status pardtw_subseq_dp(const float* C, pardtw_layout layout, int64_t n, int64_t m, uint8_t* bp,
                                float* scores, int32_t* pair_status, void* workspace, size_t workspace_bytes,
                                hipStream_t stream);
+
+/* pardtw_subseq_dp with the cost computed inside the DP, as pardtw_dp_fused:
+ * scores and codes bit for bit those of pardtw_cost (FP32) + pardtw_subseq_dp.
+ * 1 <= d <= 16. */
+pardtw_status pardtw_subseq_dp_fused(const float* X, const float* Y, int64_t n, int64_t m, int64_t d, uint8_t* bp,
+                                     float* scores, int32_t* pair_status, void* workspace, size_t workspace_bytes,
+                                     hipStream_t stream);
 
 /* Backtrace of a subsequence path from (n-1, *end_col) to row 0 along the
  * codes of pardtw_subseq_dp.

@@ -24,24 +24,16 @@
 // matrix for a 5:6 pair. With D = 12 the kernel does 24 flop per
 // 4-byte output, far below the MFMA ridge point: it is bound by HBM writes.
 #include "batch.h"
+#include "cost_slab.h"
 
 namespace pardtw {
 namespace {
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kTileM = 64;
 constexpr int kThreads = 256;
 constexpr int kTilesPerBlock = 8;  // row tiles swept by one workgroup
-
-__device__ inline float sum_groups(float v) {
-    // lanes l, l^16, l^32, l^48 hold the four quarters of one row / column
-    v += __shfl_xor(v, 16, 64);
-    return v + __shfl_xor(v, 32, 64);
-}
-
-__device__ inline float inv_from_sq(float s) { return s > 0.0f ? 1.0f / __builtin_sqrtf(s) : 0.0f; }
 
 // Eight consecutive features k0..k0+7 of one row (zeros past d), rounded to BF16.
 template <bool VEC>
@@ -66,10 +58,7 @@ __device__ inline bf16x8 load8_bf16(const float* __restrict__ row, bool ok, int6
     return out;
 }
 
-// Epilogue of a 64-row x 64-column tile: acc[b] holds rows 4*(lane/16) + r of
-// column b*16 + lane%16 within the wave's 16 rows; rxl is the inverse norm of
-// row lane%16, ry[b] that of column b*16 + lane%16.
-// Groups of panel p outside [glo, ghi] are not written.
+// Groups of panel p outside [lo, hi] are not written.
 struct GroupSpan {
     int64_t lo, hi;
 };
@@ -87,17 +76,15 @@ __device__ inline bool rows_written(const GroupSpan& s, int64_t i0, int64_t rows
     return i0 / kBpRows <= s.hi && (i0 + rows - 1) / kBpRows >= s.lo;
 }
 
+// Store of a wave's 16 rows of a 64-row x 64-column tile: v[b] holds the costs
+// of rows 4*(lane/16) + r of column b*16 + lane%16 (the layout of cost_slab.h).
 template <bool PANEL>
-__device__ __attribute__((always_inline)) inline void store_tile(const f32x4 (&acc)[4], float rxl,
-                                                                 const float (&ry)[4], int64_t n, int64_t m,
+__device__ __attribute__((always_inline)) inline void store_tile(const f32x4 (&v)[4], int64_t n, int64_t m,
                                                                  float* __restrict__ C, int64_t p, int64_t i0,
                                                                  const GroupSpan& span) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int tr0 = 4 * (lane >> 4);  // first of the lane's 4 rows within the wave's 16
-    float rx[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) rx[r] = __shfl(rxl, tr0 + r, 64);
     const int64_t ib = i0 + wave * 16 + tr0;
     if constexpr (PANEL) {
         const int64_t G = bp_groups(n);
@@ -108,10 +95,7 @@ __device__ __attribute__((always_inline)) inline void store_tile(const f32x4 (&a
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int cc = b * 16 + (lane & 15);
-                f32x4 v;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = 1.0f - (acc[b][r] * rx[r]) * ry[b];
-                __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(dst + cc * 4));
+                __builtin_nontemporal_store(v[b], reinterpret_cast<f32x4*>(dst + cc * 4));
             }
         }
     } else {
@@ -122,7 +106,7 @@ __device__ __attribute__((always_inline)) inline void store_tile(const f32x4 (&a
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int64_t j = p * kPanel + b * 16 + (lane & 15);
-                if (j < m) __builtin_nontemporal_store(1.0f - (acc[b][r] * rx[r]) * ry[b], C + i * m + j);
+                if (j < m) __builtin_nontemporal_store(v[b][r], C + i * m + j);
             }
         }
     }
@@ -137,43 +121,16 @@ __device__ __attribute__((always_inline)) inline void sweep_f32_small(const floa
                                                                       int64_t m, int64_t d, float* __restrict__ C,
                                                                       int64_t p, int64_t t0, int tiles,
                                                                       const GroupSpan& span) {
-    const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int g = lane >> 4;
     float bv[4][4], ry[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int64_t col = p * kPanel + b * 16 + (lane & 15);
-        float sq = 0.0f;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int64_t k = 4 * t + g;
-            bv[b][t] = (col < m && k < d) ? Y[col * d + k] : 0.0f;
-            sq = __builtin_fmaf(bv[b][t], bv[b][t], sq);
-        }
-        ry[b] = inv_from_sq(sum_groups(sq));
-    }
+    panel_operands_f32_small(Y, m, d, p, bv, ry);
     for (int u = 0; u < tiles; ++u) {
         const int64_t i0 = (t0 + u) * kTileM;
         if (i0 >= n) break;
         if (!rows_written(span, i0, kTileM)) continue;
-        const int64_t arow = i0 + wave * 16 + (lane & 15);
-        float av[4], sa = 0.0f;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int64_t k = 4 * t + g;
-            av[t] = (arow < n && k < d) ? X[arow * d + k] : 0.0f;
-            sa = __builtin_fmaf(av[t], av[t], sa);
-        }
-        f32x4 acc[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            acc[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-                if (4 * t < d) acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], bv[b][t], acc[b], 0, 0, 0);
-        }
-        store_tile<PANEL>(acc, inv_from_sq(sum_groups(sa)), ry, n, m, C, p, i0, span);
+        f32x4 v[4];
+        slab_costs_f32_small(X, n, d, i0 + wave * 16, bv, ry, v);
+        store_tile<PANEL>(v, n, m, C, p, i0, span);
     }
 }
 
@@ -258,7 +215,9 @@ __device__ __attribute__((always_inline)) inline void cost_tile(const float* __r
     float ry[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) ry[b] = inv_from_sq(sum_groups(sb[b]));
-    store_tile<PANEL>(acc, inv_from_sq(sum_groups(sa)), ry, n, m, C, p, i0, span);
+    f32x4 v[4];
+    costs_from_acc(acc, inv_from_sq(sum_groups(sa)), ry, v);
+    store_tile<PANEL>(v, n, m, C, p, i0, span);
 }
 
 // A workgroup's sweep: tiles t0 .. t0 + kTilesPerBlock - 1 of panel p. With a

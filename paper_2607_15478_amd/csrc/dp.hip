@@ -38,12 +38,17 @@
 // written. In the panel layout a wave reads a chunk's 2 KB of cost with two
 // loads of 1 KB contiguous each (16 bytes per lane) and writes its 512 bytes
 // of codes with one store (8 bytes per lane).
+//
+// Fused cost (the paper computes costs inside the DP, Sec. II-D): each compute
+// wave gets a producer wave that computes its panel's costs from the features,
+// 16 rows at a time with the cost GEMM's own MFMA slab (cost_slab.h), into an
+// LDS ring the compute wave reads instead of HBM. The DP then moves 1 byte per
+// cell (the codes) and its costs are bit for bit those of the GEMM.
 #include "batch.h"
+#include "cost_slab.h"
 
 namespace pardtw {
 namespace {
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kChunk = kBpRows;  // rows per synchronisation chunk (= packed group)
 constexpr int kRing = 32;        // LDS ring depth, in chunks
@@ -51,6 +56,19 @@ constexpr int kPfPanel = 4;      // cost prefetch distance in chunks, panel layo
 constexpr int kPfRow = 4;        // the same for the row-major layout (8 loads per chunk)
 constexpr int kHelperWin = 4;   // chunks polled per helper round trip (one record per lane)
 constexpr int kMaxNW = 8;
+constexpr int kMaxNWFused = 4;   // fused workgroups: NW compute + NW producer + 2 helper waves
+constexpr int kCRing = 8;        // fused cost ring depth, in chunks (2 KB each)
+
+// Where the DP's costs come from.
+enum CostSrc { kSrcRow = 0, kSrcPanel = 1, kSrcFused = 2 };
+
+// Fused cost: per compute wave a ring of cost chunks in the panel layout
+// (rows 0-3 of the 64 columns, then rows 4-7), and its progress counters.
+struct CostRing {
+    float slot[kMaxNWFused][kCRing][kChunk * kLanes];
+    int prog[kMaxNWFused];  // chunks whose costs are in the ring (or need none)
+    int cons[kMaxNWFused];  // chunks the compute wave has taken out
+};
 
 struct DpShared {
     int super;
@@ -82,6 +100,10 @@ __device__ inline float shift_in(float v, float edge) {
 
 struct DpArgs {
     const float* C;
+    const float* X;  // fused cost: features (n x d, m x d FP32, d <= 16)
+    const float* Y;
+    const float* rxs;  // fused cost: inverse norms of the rows of X, zero padded
+    int64_t d;
     uint8_t* bp;
     float* total;   // DTW: D[n-1][m-1]; subsequence DTW: the m scores D[n-1][.]
     int32_t* status;
@@ -98,10 +120,10 @@ struct DpArgs {
 // past the end) the loads read the panel's first chunk instead, which stays
 // cached; each panel uses its own, so these reads spread over the caches. Unconditional loads keep the compiler's count of outstanding
 // memory operations exact, so the prefetch ring really stays kPf chunks deep.
-template <bool PANEL>
+template <int SRC>
 __device__ __attribute__((always_inline)) inline void load_chunk(const DpArgs& a, int p, int lane, int k, bool real,
                                                                  float (&cb)[kChunk]) {
-    if constexpr (PANEL) {
+    if constexpr (SRC != kSrcRow) {
         // rows 0-3 of the chunk for all 64 columns, then rows 4-7: each load
         // instruction reads 1 KB of contiguous memory
         // a chunk whose costs are not needed reads panel 0's first chunk,
@@ -182,9 +204,25 @@ __device__ __attribute__((always_inline)) inline void dp_rows(const float (&cb)[
 // value made opaque to the optimiser and only gates a rare wait, so every role
 // runs the same instructions: the unrolled chunk loop is large and several
 // roles sharing one instruction cache would otherwise evict each other.
-template <bool PANEL, bool SUB>
-__device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs& a, DpShared& sh, int wave, int p,
-                                                                   bool have_out) {
+// Chunk k's costs from the fused ring into cb, once the producer has them
+// (chunks past the end read a slot without waiting; their values are unused).
+__device__ __attribute__((always_inline)) inline void ring_chunk(CostRing& cr, int wave, int lane, int k, int G,
+                                                                 int& cprog_seen, float (&cb)[kChunk]) {
+    if (k < G)
+        while (cprog_seen <= k) cprog_seen = lds_get(&cr.prog[wave]);
+    compiler_order();
+    const f32x4* src = reinterpret_cast<const f32x4*>(&cr.slot[wave][k % kCRing][0]) + lane;
+    const f32x4 v0 = src[0], v1 = src[kLanes];
+    cb[0] = v0[0]; cb[1] = v0[1]; cb[2] = v0[2]; cb[3] = v0[3];
+    cb[4] = v1[0]; cb[5] = v1[1]; cb[6] = v1[2]; cb[7] = v1[3];
+    compiler_order();
+    // the slot is free once read (LDS operations of a wave complete in order)
+    lds_put(&cr.cons[wave], k + 1);
+}
+
+template <int SRC, bool SUB>
+__device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs& a, DpShared& sh, CostRing* cring,
+                                                                   int wave, int p, bool have_out) {
     const int lane = threadIdx.x & 63;
     const int G = int(a.G);  // chunks per panel (rows padded to a multiple of 8)
     const ChunkRanges cr = chunk_ranges<SUB>(p, a.n, a.m, a.G);
@@ -196,11 +234,17 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
     float* rout = &sh.ring[wave + 1][0][0][0];
     int flags = __builtin_amdgcn_readfirstlane(have_out ? 2 : 0);
 
-    constexpr int kPf = PANEL ? kPfPanel : kPfRow;
+    constexpr bool kFused = SRC == kSrcFused;
+    constexpr int kPf = kFused ? 1 : SRC == kSrcPanel ? kPfPanel : kPfRow;
     float cbuf[kPf][kChunk];
+    int cprog_seen = 0;
+    if constexpr (kFused) {
+        ring_chunk(*cring, wave, lane, 0, G, cprog_seen, cbuf[0]);
+    } else {
 #pragma unroll
-    for (int u = 0; u < kPf; ++u)
-        load_chunk<PANEL>(a, p, lane, u, u >= rlo && u <= rhi, cbuf[u]);
+        for (int u = 0; u < kPf; ++u)
+            load_chunk<SRC>(a, p, lane, u, u >= rlo && u <= rhi, cbuf[u]);
+    }
 
     // D[i-1][j] and D[i-2][j-1]. The origin is produced by the general rule
     // through a virtual D[-2][-1] = -2 C[0][0]: fma(3, C00, -2 C00) = C00
@@ -304,7 +348,8 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
             }
 
             const int kn = k + kPf;
-            load_chunk<PANEL>(a, p, lane, kn, kn >= rlo && kn <= rhi, cbuf[u]);
+            if constexpr (kFused) ring_chunk(*cring, wave, lane, kn, G, cprog_seen, cbuf[u]);
+            else load_chunk<SRC>(a, p, lane, kn, kn >= rlo && kn <= rhi, cbuf[u]);
         }
     }
     // DTW: total = D[n-1][m-1]. Subsequence DTW: the whole last row, whose
@@ -314,6 +359,74 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
     if (col == a.m - 1) {
         if (!SUB) *a.total = dlast;
         *a.status = dlast == kInf ? PARDTW_PAIR_INFEASIBLE : PARDTW_PAIR_OK;
+    }
+}
+
+// Producer of compute wave w (panel p) in the fused form: the panel's costs,
+// 16 rows (two chunks) at a time, into the wave's ring. Slabs without a band
+// chunk are not computed: the compute wave then reads whatever finite values
+// the slot holds (zeros at first), which only reach cells outside the band.
+__device__ __attribute__((always_inline)) inline void cost_producer(const DpArgs& a, CostRing& cr, int w, int p,
+                                                                    bool sub) {
+    const int lane = threadIdx.x & 63;
+    const int G = int(a.G);
+    int64_t lo = sub ? sub_group_lo(p, a.n, a.m) : band_group_lo(p, a.n, a.m);
+    const int64_t hi = sub ? sub_group_hi(p, a.n, a.m) : band_group_hi(p, a.n, a.m);
+    float bv[4][4], ry[4];
+    panel_operands_f32_small(a.Y, a.m, a.d, p, bv, ry);
+    f32x4* ring = reinterpret_cast<f32x4*>(&cr.slot[w][0][0]);
+    // the lane's four rows of a slab: row0 + 4*(lane/16) + r
+    const f32x4* rx_base = reinterpret_cast<const f32x4*>(a.rxs) + (lane >> 4);
+    for (int e = lane; e < kCRing * kChunk * kLanes / 4; e += kLanes) ring[e] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    int cons_seen = 0;
+    // rows 4*(lane/16) + r of the slab: chunk 2s + lane/32, half (lane/16) % 2
+    const int kq = lane >> 5, half = (lane >> 4) & 1, col = lane & 15;
+    // Row operands and row norms two slabs ahead, in three rotating buffers:
+    // step s first issues slab s+2's loads, then computes slab s, whose loads
+    // went out two steps earlier with four slabs' worth after them. The loop
+    // is unrolled by three (padded with slabs past the end, which compute and
+    // write nothing), so every path through it issues the same loads and no
+    // register with a load in flight is copied. Rows past n read the zero
+    // padding of the row-norm area.
+    const float* zeros = a.rxs + a.n;
+    float avA[4], avB[4], avC[4];
+    f32x4 rxA, rxB, rxC;
+    // (issued in slab order, as the loop issues them, so that the compiler's
+    // load counts agree on both ways into the loop)
+    slab_rows_f32_small_ahead(a.X, zeros, a.n, a.d, 0, avA);
+    rxA = rx_base[0];
+    compiler_order();
+    slab_rows_f32_small_ahead(a.X, zeros, a.n, a.d, 16, avB);
+    rxB = rx_base[4];
+    compiler_order();
+    auto step = [&](int s, float (&av)[4], f32x4& rx, float (&av_next)[4], f32x4& rx_next) {
+        slab_rows_f32_small_ahead(a.X, zeros, a.n, a.d, int64_t(16) * (s + 2), av_next);
+        rx_next = rx_base[4 * (s + 2)];
+        const int k0 = 2 * s;
+        if (k0 <= hi && k0 + 1 >= lo) {
+            const int need = k0 + 2 - kCRing;  // the consumer has taken chunk k0 + 1 - kCRing out
+            while (cons_seen < need) {
+                cons_seen = lds_get(&cr.cons[w]);
+                if (cons_seen < need) __builtin_amdgcn_s_sleep(1);
+            }
+            f32x4 acc[4], v[4];
+            slab_acc_f32_small(av, bv, acc);
+            costs_from_acc_rx(acc, rx, ry, v);
+            const int kk = k0 + kq;
+            if (kk < G) {
+                float* dst = &cr.slot[w][kk % kCRing][half * (kLanes * 4)];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) *reinterpret_cast<f32x4*>(dst + (b * 16 + col) * 4) = v[b];
+            }
+        }
+        compiler_order();
+        lds_put(&cr.prog[w], k0 + 2 < G ? k0 + 2 : G);
+    };
+    const int slabs = int(ceil_div(G, 2));
+    for (int s = 0; s < slabs; s += 3) {
+        step(s, avA, rxA, avC, rxC);
+        step(s + 1, avB, rxB, avA, rxA);
+        step(s + 2, avC, rxC, avB, rxB);
     }
 }
 
@@ -417,13 +530,16 @@ __device__ __attribute__((always_inline)) inline void out_helper(const DpArgs& a
 
 // Panel group q (panels q*NW .. q*NW+NW-1) of one pair: NW compute waves, then
 // the input helper and the output helper.
-template <int NW, bool PANEL, bool SUB>
-__device__ __attribute__((always_inline)) inline void run_group(const DpArgs& a, DpShared& sh, int wave, int q,
-                                                                uint32_t epoch) {
+template <int NW, int SRC, bool SUB>
+__device__ __attribute__((always_inline)) inline void run_group(const DpArgs& a, DpShared& sh, CostRing* cring,
+                                                                int wave, int q, uint32_t epoch) {
     const int p0 = q * NW;
     if (wave < NW) {
         const int p = p0 + wave;
-        if (p < a.P) compute_wave<PANEL, SUB>(a, sh, wave, p, p + 1 < a.P);
+        if (p < a.P) compute_wave<SRC, SUB>(a, sh, cring, wave, p, p + 1 < a.P);
+    } else if (SRC == kSrcFused && wave >= NW + 2) {
+        const int p = p0 + wave - (NW + 2);
+        if (p < a.P) cost_producer(a, *cring, wave - (NW + 2), p, SUB);
     } else if (wave == NW) {
         if (p0 > 0) in_helper(a, sh, p0 - 1, epoch);
         else inf_source(sh);
@@ -435,25 +551,40 @@ __device__ __attribute__((always_inline)) inline void run_group(const DpArgs& a,
 
 // Takes the next ticket and resets the group's LDS handoff counters.
 template <int NW>
-__device__ inline int next_ticket(DpShared& sh, DpWsHeader* hdr) {
+__device__ inline int next_ticket(DpShared& sh, CostRing* cring, DpWsHeader* hdr) {
     if (threadIdx.x == 0) {
         sh.super = int(atomicAdd(&hdr->ticket, 1u));
         for (int w = 0; w <= NW; ++w) { sh.prog[w][0] = 0; sh.prog[w][1] = 0; sh.cons[w] = 0; }
+        if (cring)
+            for (int w = 0; w < NW && w < kMaxNWFused; ++w) { cring->prog[w] = 0; cring->cons[w] = 0; }
     }
     __syncthreads();
     return __builtin_amdgcn_readfirstlane(sh.super);
 }
 
-template <int NW, bool PANEL, bool SUB>
-__global__ __launch_bounds__(kLanes*(NW + 2)) void dp_kernel(DpArgs a) {
-    __shared__ DpShared sh;
+constexpr int dp_waves(int nw, int src) { return src == kSrcFused ? 2 * nw + 2 : nw + 2; }
+
+template <int NW, int SRC, bool SUB>
+__device__ __attribute__((always_inline)) inline void dp_body(const DpArgs& a, DpShared& sh, CostRing* cring) {
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);
     const uint32_t epoch = __hip_atomic_load(&a.hdr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (;;) {
-        const int q = next_ticket<NW>(sh, a.hdr);
+        const int q = next_ticket<NW>(sh, cring, a.hdr);
         if (q >= a.S) break;
-        run_group<NW, PANEL, SUB>(a, sh, wave, q, epoch);
+        run_group<NW, SRC, SUB>(a, sh, cring, wave, q, epoch);
         __syncthreads();
+    }
+}
+
+template <int NW, int SRC, bool SUB>
+__global__ __launch_bounds__(kLanes * dp_waves(NW, SRC)) void dp_kernel(DpArgs a) {
+    __shared__ DpShared sh;
+    if constexpr (SRC == kSrcFused) {
+        static_assert(NW <= kMaxNWFused, "fused workgroups hold at most kMaxNWFused compute waves");
+        __shared__ CostRing cring;
+        dp_body<NW, SRC, SUB>(a, sh, &cring);
+    } else {
+        dp_body<NW, SRC, SUB>(a, sh, nullptr);
     }
 }
 
@@ -478,7 +609,7 @@ __global__ __launch_bounds__(kLanes*(NW + 2)) void dp_batch_kernel(DpBatchArgs b
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);
     const uint32_t epoch = __hip_atomic_load(&ba.hdr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (;;) {
-        const int t = next_ticket<NW>(sh, ba.hdr);
+        const int t = next_ticket<NW>(sh, nullptr, ba.hdr);
         if (t >= ba.nitems) break;
         const DpItem it = ba.items[t];
         const BatchPair q = ba.pairs[it.pair];
@@ -495,9 +626,15 @@ __global__ __launch_bounds__(kLanes*(NW + 2)) void dp_batch_kernel(DpBatchArgs b
         a.G = q.G;
         a.P = q.P;
         a.S = int(ceil_div(q.P, NW));
-        run_group<NW, true, SUB>(a, sh, wave, it.group, epoch);
+        run_group<NW, kSrcPanel, SUB>(a, sh, nullptr, wave, it.group, epoch);
         __syncthreads();
     }
+}
+
+// Row inverse norms for the fused producers (zeros past n, up to len).
+__global__ void row_norms_kernel(const float* __restrict__ X, int64_t n, int64_t d, float* rxs, int64_t len) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < len; i += int64_t(gridDim.x) * blockDim.x)
+        rxs[i] = row_inv_norm_f32_small(X, n, d, i);
 }
 
 __global__ void dp_prepare(DpWsHeader* hdr) {
@@ -521,15 +658,17 @@ int choose_nw(int P) {
     return 1;
 }
 
+template <int NW, int SRC>
+void launch_src(const DpArgs& a, bool sub, int grid, hipStream_t stream) {
+    if (sub) dp_kernel<NW, SRC, true><<<grid, kLanes * dp_waves(NW, SRC), 0, stream>>>(a);
+    else dp_kernel<NW, SRC, false><<<grid, kLanes * dp_waves(NW, SRC), 0, stream>>>(a);
+}
+
 template <int NW>
-void launch_nw(const DpArgs& a, bool panel, bool sub, int grid, hipStream_t stream) {
-    if (sub) {
-        if (panel) dp_kernel<NW, true, true><<<grid, kLanes * (NW + 2), 0, stream>>>(a);
-        else dp_kernel<NW, false, true><<<grid, kLanes * (NW + 2), 0, stream>>>(a);
-    } else {
-        if (panel) dp_kernel<NW, true, false><<<grid, kLanes * (NW + 2), 0, stream>>>(a);
-        else dp_kernel<NW, false, false><<<grid, kLanes * (NW + 2), 0, stream>>>(a);
-    }
+void launch_nw(const DpArgs& a, int src, bool sub, int grid, hipStream_t stream) {
+    if (src == kSrcPanel) launch_src<NW, kSrcPanel>(a, sub, grid, stream);
+    else if (src == kSrcRow) launch_src<NW, kSrcRow>(a, sub, grid, stream);
+    else if constexpr (NW <= kMaxNWFused) launch_src<NW, kSrcFused>(a, sub, grid, stream);
 }
 
 template <int NW>
@@ -542,11 +681,20 @@ void launch_batch_nw(const DpBatchArgs& a, bool sub, int grid, hipStream_t strea
 
 size_t dp_header_bytes() { return sizeof(DpWsHeader); }
 
+// The DP reads only band groups, so the panel layouts are the same to it.
+int src_of(pardtw_layout layout) { return layout == PARDTW_LAYOUT_ROW ? kSrcRow : kSrcPanel; }
+
 size_t dp_record_bytes(int64_t n, int64_t m) {
     return size_t(num_panels(m)) * size_t(bp_groups(n)) * kChunk * 2 * sizeof(uint64_t);
 }
 
-size_t dp_workspace_bytes_impl(int64_t n, int64_t m) { return sizeof(DpWsHeader) + dp_record_bytes(n, m); }
+// Floats of the fused row-norm area: the producer's loop, padded to a multiple
+// of three slabs, reads up to two slabs past its end.
+int64_t rx_floats(int64_t n) { return (ceil_div(bp_groups(n), 2) + 5) * 16; }
+
+size_t dp_workspace_bytes_impl(int64_t n, int64_t m) {
+    return sizeof(DpWsHeader) + dp_record_bytes(n, m) + size_t(rx_floats(n)) * sizeof(float);
+}
 
 pardtw_status dp_batch_launch(const BatchPair* pairs, const DpItem* items, int32_t nitems, int nw, int grid,
                               const float* Cbase, uint8_t* bpbase, float* totals, int32_t* status, void* dp_ws,
@@ -574,15 +722,22 @@ pardtw_status dp_batch_launch(const BatchPair* pairs, const DpItem* items, int32
     return launch_status();
 }
 
-pardtw_status dp_launch(const float* C, pardtw_layout layout, int64_t n, int64_t m, uint8_t* bp,
-                        float* total, int32_t* status, void* ws, int nw_override, bool sub, hipStream_t stream) {
+// src: the cost source (row-major or panel C, or fused from X, Y).
+pardtw_status dp_launch(const float* C, const float* X, const float* Y, int64_t d, int src, int64_t n, int64_t m,
+                        uint8_t* bp, float* total, int32_t* status, void* ws, int nw_override, bool sub,
+                        hipStream_t stream) {
     DpArgs a;
     a.C = C;
+    a.X = X;
+    a.Y = Y;
+    a.d = d;
     a.bp = bp;
     a.total = total;
     a.status = status;
     a.hdr = reinterpret_cast<DpWsHeader*>(ws);
     a.rec = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(ws) + sizeof(DpWsHeader));
+    // the records are a multiple of 128 bytes, so the row-norm area is 16-byte aligned
+    a.rxs = reinterpret_cast<float*>(reinterpret_cast<char*>(a.rec) + dp_record_bytes(n, m));
     a.n = n;
     a.m = m;
     a.G = bp_groups(n);
@@ -595,8 +750,7 @@ pardtw_status dp_launch(const float* C, pardtw_layout layout, int64_t n, int64_t
     // about four compute waves per CU (one per SIMD)
     const int per_cu = nw >= 4 ? 1 : 4 / nw;
     const int grid = a.S < cus * per_cu ? a.S : cus * per_cu;
-    // the DP reads only band groups, so the panel layouts are the same to it
-    const bool panel = layout != PARDTW_LAYOUT_ROW;
+    if (src == kSrcFused && nw > kMaxNWFused) return PARDTW_ERR_UNSUPPORTED;
     if (sub ? !subseq_feasible(n, m) : !pair_feasible(n, m)) {
         const int64_t count = sub ? m : 1;
         const unsigned blocks = unsigned(count < 256 * 1024 ? ceil_div(count, 256) : 1024);
@@ -604,11 +758,16 @@ pardtw_status dp_launch(const float* C, pardtw_layout layout, int64_t n, int64_t
         return launch_status();
     }
     dp_prepare<<<1, 1, 0, stream>>>(a.hdr);
+    if (src == kSrcFused) {
+        const int64_t len = rx_floats(n);
+        const unsigned blocks = unsigned(len < 256 * 2048 ? ceil_div(len, 256) : 2048);
+        row_norms_kernel<<<blocks, 256, 0, stream>>>(X, n, d, const_cast<float*>(a.rxs), len);
+    }
     switch (nw) {
-        case 1: launch_nw<1>(a, panel, sub, grid, stream); break;
-        case 2: launch_nw<2>(a, panel, sub, grid, stream); break;
-        case 4: launch_nw<4>(a, panel, sub, grid, stream); break;
-        case 8: launch_nw<8>(a, panel, sub, grid, stream); break;
+        case 1: launch_nw<1>(a, src, sub, grid, stream); break;
+        case 2: launch_nw<2>(a, src, sub, grid, stream); break;
+        case 4: launch_nw<4>(a, src, sub, grid, stream); break;
+        case 8: launch_nw<8>(a, src, sub, grid, stream); break;
         default: return PARDTW_ERR_UNSUPPORTED;
     }
     return launch_status();
@@ -633,7 +792,8 @@ extern "C" pardtw_status pardtw_dp(const float* C, pardtw_layout layout, int64_t
     if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL && layout != PARDTW_LAYOUT_PANEL_BAND)
         return PARDTW_ERR_UNSUPPORTED;
     if (!workspace || workspace_bytes < pardtw::dp_workspace_bytes_impl(n, m)) return PARDTW_ERR_WORKSPACE;
-    return pardtw::dp_launch(C, layout, n, m, bp, total, pair_status, workspace, 0, false, stream);
+    return pardtw::dp_launch(C, nullptr, nullptr, 0, pardtw::src_of(layout), n, m, bp, total, pair_status,
+                             workspace, 0, false, stream);
 }
 
 extern "C" pardtw_status pardtw_dp_ex(const float* C, pardtw_layout layout, int64_t n, int64_t m, uint8_t* bp,
@@ -646,8 +806,8 @@ extern "C" pardtw_status pardtw_dp_ex(const float* C, pardtw_layout layout, int6
         panels_per_workgroup != 4 && panels_per_workgroup != 8)
         return PARDTW_ERR_INVALID_ARG;
     if (!workspace || workspace_bytes < pardtw::dp_workspace_bytes_impl(n, m)) return PARDTW_ERR_WORKSPACE;
-    return pardtw::dp_launch(C, layout, n, m, bp, total, pair_status, workspace, panels_per_workgroup, false,
-                             stream);
+    return pardtw::dp_launch(C, nullptr, nullptr, 0, pardtw::src_of(layout), n, m, bp, total, pair_status,
+                             workspace, panels_per_workgroup, false, stream);
 }
 
 extern "C" pardtw_status pardtw_subseq_dp(const float* C, pardtw_layout layout, int64_t n, int64_t m, uint8_t* bp,
@@ -657,5 +817,38 @@ extern "C" pardtw_status pardtw_subseq_dp(const float* C, pardtw_layout layout, 
     if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL && layout != PARDTW_LAYOUT_PANEL_SUBSEQ_BAND)
         return PARDTW_ERR_UNSUPPORTED;
     if (!workspace || workspace_bytes < pardtw::dp_workspace_bytes_impl(n, m)) return PARDTW_ERR_WORKSPACE;
-    return pardtw::dp_launch(C, layout, n, m, bp, scores, pair_status, workspace, 0, true, stream);
+    return pardtw::dp_launch(C, nullptr, nullptr, 0, pardtw::src_of(layout), n, m, bp, scores, pair_status,
+                             workspace, 0, true, stream);
+}
+
+namespace {
+
+pardtw_status check_fused(const float* X, const float* Y, int64_t n, int64_t m, int64_t d, uint8_t* bp, float* out,
+                          int32_t* st, void* ws, size_t ws_bytes, int32_t nw) {
+    if (!X || !Y || !bp || !out || !st || !pardtw::valid_sizes(n, m) || d <= 0) return PARDTW_ERR_INVALID_ARG;
+    if (d > 16) return PARDTW_ERR_UNSUPPORTED;
+    if (nw != 0 && nw != 1 && nw != 2 && nw != 4) return PARDTW_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < pardtw::dp_workspace_bytes_impl(n, m)) return PARDTW_ERR_WORKSPACE;
+    return PARDTW_OK;
+}
+
+}  // namespace
+
+extern "C" pardtw_status pardtw_dp_fused(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
+                                         uint8_t* bp, float* total, int32_t* pair_status, void* workspace,
+                                         size_t workspace_bytes, int32_t panels_per_workgroup, hipStream_t stream) {
+    const pardtw_status st = check_fused(X, Y, n, m, d, bp, total, pair_status, workspace, workspace_bytes,
+                                         panels_per_workgroup);
+    if (st != PARDTW_OK) return st;
+    return pardtw::dp_launch(nullptr, X, Y, d, pardtw::kSrcFused, n, m, bp, total, pair_status, workspace,
+                             panels_per_workgroup, false, stream);
+}
+
+extern "C" pardtw_status pardtw_subseq_dp_fused(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
+                                                uint8_t* bp, float* scores, int32_t* pair_status, void* workspace,
+                                                size_t workspace_bytes, hipStream_t stream) {
+    const pardtw_status st = check_fused(X, Y, n, m, d, bp, scores, pair_status, workspace, workspace_bytes, 0);
+    if (st != PARDTW_OK) return st;
+    return pardtw::dp_launch(nullptr, X, Y, d, pardtw::kSrcFused, n, m, bp, scores, pair_status, workspace, 0, true,
+                             stream);
 }

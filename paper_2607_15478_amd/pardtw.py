@@ -56,6 +56,8 @@ _lib_cost = _sig("pardtw_cost", _E, [_P, _P, _I64, _I64, _I64, _E, _E, _P, _P])
 _lib_dp = _sig("pardtw_dp", _E, [_P, _E, _I64, _I64, _P, _P, _P, _P, _SZ, _P])
 _lib_dp_ex = _sig("pardtw_dp_ex", _E, [_P, _E, _I64, _I64, _P, _P, _P, _P, _SZ, _I32, _P])
 _lib_bt = _sig("pardtw_backtrace", _E, [_P, _I64, _I64, _P, _P, _P, _P])
+_lib_dp_fused = _sig("pardtw_dp_fused", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _SZ, _I32, _P])
+_lib_sub_dp_fused = _sig("pardtw_subseq_dp_fused", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _SZ, _P])
 _lib_unpack = _sig("pardtw_bp_unpack", _E, [_P, _I64, _I64, _P, _P])
 _lib_grad = _sig("pardtw_path_grad", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P])
 _lib_plan_create = _sig("pardtw_plan_create", _E, [_I32, _P, _P, _I64, _E, ctypes.POINTER(_P)])
@@ -158,6 +160,19 @@ def pardtw_dp(C: torch.Tensor, n: int, m: int, bp: torch.Tensor, total: torch.Te
                           int(panels_per_workgroup), _stream(stream)), "pardtw_dp_ex")
 
 
+def pardtw_dp_fused(X: torch.Tensor, Y: torch.Tensor, bp: torch.Tensor, total: torch.Tensor, status: torch.Tensor,
+                    workspace: torch.Tensor, stream=None, panels_per_workgroup: int = 0):
+    """The DP with the cost computed inside it (FP32 features, d <= 16)."""
+    _dev_f32(X, "X"), _dev_f32(Y, "Y")
+    n, d = X.shape
+    m = Y.shape[0]
+    if bp.dtype != torch.uint8 or bp.numel() < pardtw_bp_bytes(n, m):
+        raise ValueError("bp must be a uint8 tensor of pardtw_bp_bytes(n, m) bytes")
+    ws_bytes = workspace.numel() * workspace.element_size()
+    _check(_lib_dp_fused(_ptr(X), _ptr(Y), n, m, d, _ptr(bp), _ptr(total), _ptr(status), _ptr(workspace), ws_bytes,
+                         int(panels_per_workgroup), _stream(stream)), "pardtw_dp_fused")
+
+
 def pardtw_backtrace(bp: torch.Tensor, n: int, m: int, status: torch.Tensor, path: torch.Tensor,
                      path_len: torch.Tensor, stream=None):
     if path.dtype != torch.int32 or path.numel() < 2 * min(n, m):
@@ -184,9 +199,10 @@ def pardtw_path_grad(X, Y, path, path_len, g_total, dX, dY, stream=None):
 class Workspace:
     """Device buffers for one (n, m) alignment, reusable across calls."""
 
-    def __init__(self, n: int, m: int, device="cuda", layout: int = LAYOUT_PANEL_BAND):
+    def __init__(self, n: int, m: int, device="cuda", layout: int = LAYOUT_PANEL_BAND, cost: bool = True):
         self.n, self.m, self.layout = n, m, layout
-        self.C = torch.empty(pardtw_cost_elems(n, m, layout), dtype=torch.float32, device=device)
+        # no cost buffer when the DP computes the costs itself
+        self.C = torch.empty(pardtw_cost_elems(n, m, layout) if cost else 0, dtype=torch.float32, device=device)
         self.bp = torch.empty(pardtw_bp_bytes(n, m), dtype=torch.uint8, device=device)
         self.ws = torch.zeros(pardtw_dp_workspace_bytes(n, m), dtype=torch.uint8, device=device)
         self.total = torch.empty(1, dtype=torch.float32, device=device)
@@ -195,11 +211,18 @@ class Workspace:
         self.path_len = torch.empty(1, dtype=torch.int32, device=device)
 
 
-def align_into(X: torch.Tensor, Y: torch.Tensor, w: Workspace, prec: int = PREC_F32, stream=None):
-    """cost -> dp -> backtrace on the given stream, results left in w."""
+def align_into(X: torch.Tensor, Y: torch.Tensor, w: Workspace, prec: int = PREC_F32, stream=None,
+               fused: bool = False):
+    """cost -> dp -> backtrace on the given stream, results left in w (with
+    `fused`, the DP computes the costs itself and w.C is not used)."""
     n, m = X.shape[0], Y.shape[0]
-    pardtw_cost(X, Y, w.C, prec, w.layout, stream)
-    pardtw_dp(w.C, n, m, w.bp, w.total, w.status, w.ws, w.layout, stream)
+    if fused:
+        if prec != PREC_F32:
+            raise ValueError("the fused DP computes FP32 costs")
+        pardtw_dp_fused(X, Y, w.bp, w.total, w.status, w.ws, stream)
+    else:
+        pardtw_cost(X, Y, w.C, prec, w.layout, stream)
+        pardtw_dp(w.C, n, m, w.bp, w.total, w.status, w.ws, w.layout, stream)
     pardtw_backtrace(w.bp, n, m, w.status, w.path, w.path_len, stream)
     return w
 
@@ -328,6 +351,18 @@ def pardtw_subseq_dp(C: torch.Tensor, n: int, m: int, bp: torch.Tensor, scores: 
     ws_bytes = workspace.numel() * workspace.element_size()
     _check(_lib_sub_dp(_ptr(C), layout, n, m, _ptr(bp), _ptr(scores), _ptr(status), _ptr(workspace), ws_bytes,
                        _stream(stream)), "pardtw_subseq_dp")
+
+
+def pardtw_subseq_dp_fused(X: torch.Tensor, Y: torch.Tensor, bp: torch.Tensor, scores: torch.Tensor,
+                           status: torch.Tensor, workspace: torch.Tensor, stream=None):
+    _dev_f32(X, "X"), _dev_f32(Y, "Y"), _dev_f32(scores, "scores")
+    n, d = X.shape
+    m = Y.shape[0]
+    if bp.dtype != torch.uint8 or bp.numel() < pardtw_bp_bytes(n, m) or scores.numel() < m:
+        raise ValueError("bp must hold pardtw_bp_bytes(n, m) bytes and scores m floats")
+    ws_bytes = workspace.numel() * workspace.element_size()
+    _check(_lib_sub_dp_fused(_ptr(X), _ptr(Y), n, m, d, _ptr(bp), _ptr(scores), _ptr(status), _ptr(workspace),
+                             ws_bytes, _stream(stream)), "pardtw_subseq_dp_fused")
 
 
 def pardtw_subseq_backtrace(bp: torch.Tensor, n: int, m: int, end_col: torch.Tensor, path: torch.Tensor,
