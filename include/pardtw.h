@@ -109,7 +109,8 @@ pardtw_status pardtw_band_groups(int64_t n, int64_t m, int64_t p, int64_t* lo, i
 size_t pardtw_bp_bytes(int64_t n, int64_t m);
 
 /* Bytes of device workspace pardtw_dp needs (0 on bad args). The workspace
- * carries boundary columns between column panels and a launch counter. Zero it
+ * carries boundary columns between column panels, a launch counter and, for
+ * the fused-cost DP, the inverse norms of the rows of X. Zero it
  * once before its first use; afterwards it can be reused by any number of
  * pardtw_dp calls (of any size that fits) issued one after another on one
  * stream. Calls that overlap in time must not share a workspace. */

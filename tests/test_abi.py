@@ -46,7 +46,9 @@ def test_size_helpers(lib):
     G = -(-n // 8)
     assert lib.pardtw_cost_elems(n, m, 1) == P * G * 512
     assert lib.pardtw_bp_bytes(n, m) == P * (-(-n // 8)) * 64 * 8
-    assert lib.pardtw_dp_workspace_bytes(n, m) == 768 + P * G * 8 * 16
+    # header, boundary records, and the fused DP's row norms (two slabs past a
+    # loop padded to three slabs of 16 rows)
+    assert lib.pardtw_dp_workspace_bytes(n, m) == 768 + P * G * 8 * 16 + ((-(-G // 2)) + 5) * 16 * 4
     assert lib.pardtw_cost_elems(0, 5, 0) == 0
     assert lib.pardtw_bp_bytes(-1, 5) == 0
     assert lib.pardtw_cost_elems(3, 5, 7) == 0
