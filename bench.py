@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline leg (and validation)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "dp_traffic.json"))
     ap.add_argument("--nfrag", type=int, default=32, help="segmental workloads: fragments of sequence A")
+    ap.add_argument("--fused", action="store_true",
+                    help="the DP computes the costs itself (no cost matrix; FP32, d <= 16)")
     ap.add_argument("--variant", choices=["wsdtw", "nsdtw"], default="wsdtw", help="segmental workloads")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
@@ -135,7 +137,7 @@ def main():
 
     Xd = torch.from_numpy(X).to(dev)
     Yd = torch.from_numpy(Y).to(dev)
-    w = pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND)
+    w = pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=not args.fused)
     stream = torch.cuda.current_stream()
 
     calib = None
@@ -150,7 +152,7 @@ def main():
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        pd.align_into(Xd, Yd, w)
+        pd.align_into(Xd, Yd, w, fused=args.fused)
     torch.cuda.synchronize()
 
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
@@ -160,9 +162,13 @@ def main():
     for s in range(args.steps):
         e = evs[s]
         e[0].record(stream)
-        pd.pardtw_cost(Xd, Yd, w.C, pd.PREC_F32, pd.LAYOUT_PANEL_BAND)
-        e[1].record(stream)
-        pd.pardtw_dp(w.C, n, m, w.bp, w.total, w.status, w.ws, pd.LAYOUT_PANEL_BAND)
+        if args.fused:
+            e[1].record(stream)
+            pd.pardtw_dp_fused(Xd, Yd, w.bp, w.total, w.status, w.ws)
+        else:
+            pd.pardtw_cost(Xd, Yd, w.C, pd.PREC_F32, pd.LAYOUT_PANEL_BAND)
+            e[1].record(stream)
+            pd.pardtw_dp(w.C, n, m, w.bp, w.total, w.status, w.ws, pd.LAYOUT_PANEL_BAND)
         e[2].record(stream)
         pd.pardtw_backtrace(w.bp, n, m, w.status, w.path, w.path_len)
         e[3].record(stream)
@@ -179,7 +185,9 @@ def main():
     L = int(w.path_len.item())
     path = w.path[:L].cpu().numpy()
 
-    dp_achieved = DP_BYTES_PER_CELL * cells / (dp_ms * 1e-3) / 1e9
+    # the fused DP reads no cost: 1 byte per cell (its codes) is what it must move
+    bpc = 1 if args.fused else DP_BYTES_PER_CELL
+    dp_achieved = bpc * cells / (dp_ms * 1e-3) / 1e9
     # Measured HBM bytes of one DP launch (scaled FETCH_SIZE + WRITE_SIZE counters), valid only while the
     # DP source is the one the counters were taken on.
     traffic = None
@@ -187,14 +195,16 @@ def main():
         try:
             tj = json.load(open(args.traffic_json))
             src = open(os.path.join(ROOT, "paper_2607_15478_amd", "csrc", "dp.hip"), "rb").read()
-            if tj.get("workload") == args.workload and tj.get("dp_source_sha256") == hashlib.sha256(src).hexdigest():
+            if (not args.fused and tj.get("workload") == args.workload
+                    and tj.get("dp_source_sha256") == hashlib.sha256(src).hexdigest()):
                 traffic = tj.get("bytes_per_launch")
         except (OSError, ValueError):
             traffic = None
     roofline = {"bound": "hbm", "achieved": round(dp_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dp_achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "dp_kernel", "algorithmic_bytes_per_launch": DP_BYTES_PER_CELL * cells,
-                "bytes_per_cell": DP_BYTES_PER_CELL, "kernel_ms": round(float(dp_ms), 4)}
+                "kernel": "dp_kernel (fused cost)" if args.fused else "dp_kernel",
+                "algorithmic_bytes_per_launch": bpc * cells,
+                "bytes_per_cell": bpc, "kernel_ms": round(float(dp_ms), 4)}
     if traffic:
         # the kernel reads no cost for chunks the step set cannot reach, so it moves fewer bytes than 5 B/cell
         roofline["moved_GBps"] = round(traffic / (dp_ms * 1e-3) / 1e9, 1)
@@ -217,7 +227,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "m": m, "d": d, "cells": cells, "layout": "panel64_band",
+        "config": {"workload": args.workload, "n": n, "m": m, "d": d, "cells": cells,
+                   "layout": "fused_cost" if args.fused else "panel64_band",
                    "pairs_per_s": round(1e3 / ms_per_step, 3),
                    "stage_ms": {"cost": round(float(cost_ms), 4), "dp": round(float(dp_ms), 4),
                                 "backtrace": round(float(bt_ms), 4)}},
@@ -250,7 +261,7 @@ def run_batch(args):
     Xp, Yp = pd.pack(pairs, dev)
     res = {}
     for prec in ([pd.PREC_F32, pd.PREC_BF16] if d >= 64 else [pd.PREC_F32]):
-        plan = pd.Plan(ns, ms, d, prec)
+        plan = pd.Plan(ns, ms, d, prec, fused=args.fused and d <= 16 and prec == pd.PREC_F32)
         buf = plan.buffers(dev)
         best = plan.autotune(Xp, Yp, buf, reps=2)
         for _ in range(args.warmup):
@@ -384,7 +395,7 @@ def run_segmental(args):
     nf, variant = args.nfrag, (pd.WSDTW if args.variant == "wsdtw" else pd.NSDTW)
     cells = la * lb
     Ad, Bd = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
-    plan = pd.SegPlan(la, lb, nf, d, pd.PREC_F32, variant)
+    plan = pd.SegPlan(la, lb, nf, d, pd.PREC_F32, variant, fused=args.fused)
     buf = plan.buffers(dev)
     print(f"[bench] plan {nf} fragments, workspace {plan.workspace_bytes / 2**30:.1f} GiB; autotune",
           file=sys.stderr, flush=True)
@@ -419,11 +430,13 @@ def run_segmental(args):
     g_ends = buf["ends"].cpu().numpy().astype(np.int64)
     g_total = float(buf["total"].item())
     L = int(buf["path_len"].item())
-    dp_achieved = DP_BYTES_PER_CELL * cells / (dp_ms * 1e-3) / 1e9
+    bpc = 1 if args.fused else DP_BYTES_PER_CELL
+    dp_achieved = bpc * cells / (dp_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(dp_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dp_achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "dp_batch_kernel (subsequence)", "algorithmic_bytes_per_launch": DP_BYTES_PER_CELL * cells,
-                "bytes_per_cell": DP_BYTES_PER_CELL, "kernel_ms": round(float(dp_ms), 4)}
+                "kernel": "dp_batch_kernel (subsequence%s)" % (", fused cost" if args.fused else ""),
+                "algorithmic_bytes_per_launch": bpc * cells, "bytes_per_cell": bpc,
+                "kernel_ms": round(float(dp_ms), 4)}
     cpu, validation = None, None
     if not args.no_cpu:
         # a bounded sample: up to three fragments, at most 3e9 cells (about 15 s on one core)
@@ -450,6 +463,7 @@ def run_segmental(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "algorithm": args.variant, "fragments": nf, "hop": plan.hop,
+                   "fused_cost": bool(args.fused), "workspace_gib": round(plan.workspace_bytes / 2**30, 2),
                    "la": la, "lb": lb, "d": d, "cells": cells, "pairs_per_s": round(1e3 / ms, 3),
                    "wall_ms_per_step": round(wall, 4), "schedule": plan.schedule(), "tuned_dp_ms": round(dp_ms, 4),
                    "status": int(buf["status"].item()), "path_len": L},

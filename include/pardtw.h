@@ -223,6 +223,17 @@ typedef struct pardtw_plan pardtw_plan;
 
 pardtw_status pardtw_plan_create(int32_t batch, const int64_t* n_host, const int64_t* m_host,
                                  int64_t d, pardtw_prec prec, pardtw_plan** plan);
+
+/* Plan flags. PARDTW_PLAN_FUSED_COST: the DP computes the costs itself, as
+ * pardtw_dp_fused does (FP32, d <= 16, else PARDTW_ERR_UNSUPPORTED): the
+ * workspace holds no cost matrix, only the row norms of X, and results are bit
+ * for bit those of the unfused plan. Its schedules use 1, 2 or 4 panels per
+ * workgroup. */
+#define PARDTW_PLAN_FUSED_COST 1
+
+/* pardtw_plan_create with flags. */
+pardtw_status pardtw_plan_create_ex(int32_t batch, const int64_t* n_host, const int64_t* m_host, int64_t d,
+                                    pardtw_prec prec, int32_t flags, pardtw_plan** plan);
 size_t pardtw_plan_workspace_bytes(const pardtw_plan* plan);
 int64_t pardtw_plan_path_capacity(const pardtw_plan* plan); /* sum of min(n_b, m_b) */
 void pardtw_plan_destroy(pardtw_plan* plan);
@@ -351,12 +362,13 @@ pardtw_status pardtw_segment_ends(const float* scores, int64_t nfrag, int64_t m,
                                   int32_t* status, hipStream_t stream);
 
 /* A plan for Segmental DTW of A (la x d) against B (lb x d) with nfrag
- * fragments (1 <= nfrag <= la). It is a pardtw_plan: free it with
+ * fragments (1 <= nfrag <= la); flags as for pardtw_plan_create_ex (0 or
+ * PARDTW_PLAN_FUSED_COST). It is a pardtw_plan: free it with
  * pardtw_plan_destroy, size its workspace (256-byte aligned, zeroed once) with
  * pardtw_plan_workspace_bytes, and choose its DP schedule with the schedule
  * calls above. */
 pardtw_status pardtw_segplan_create(int64_t la, int64_t lb, int32_t nfrag, int64_t d, pardtw_prec prec,
-                                    int32_t variant, pardtw_plan** plan);
+                                    int32_t variant, int32_t flags, pardtw_plan** plan);
 
 /* The autotuner of a Segmental DTW plan: computes the fragments' costs once,
  * times the subsequence DP under every schedule (one warm-up, then `reps`

@@ -18,6 +18,7 @@ struct BatchPair {
     int64_t path_off;      // first (i, j) entry of the pair's path
     int64_t G;             // 8-row groups
     int64_t tile0;         // first cost workgroup of the pair in the batch numbering
+    int64_t rx_off;        // fused cost: first float of the pair's row-norm area
     int32_t P;             // column panels
     int32_t feasible;      // some path exists (to (n-1, m-1), or to row n-1 for a fragment)
     int32_t band;          // cost groups written: 1 the DTW path band, 2 the subsequence band
@@ -39,10 +40,18 @@ pardtw_status cost_batch_launch(const BatchPair* pairs, const int32_t* tile_pair
 // Sweeps every item with one persistent launch; hdr/rec as in the single-pair
 // DP (one header for the batch, records at each pair's rec_off).
 // With `sub` every pair is a fragment of Segmental DTW: the subsequence DP,
-// whose scores go to totals + b * m (fragments share m).
+// whose scores go to totals + b * m (fragments share m). With X (not null) the
+// costs are computed inside the DP from X_packed, Y_packed (d <= 16) and the
+// row norms at rxs (fused form; nw <= 4); otherwise they are read from Cbase.
 pardtw_status dp_batch_launch(const BatchPair* pairs, const DpItem* items, int32_t nitems, int nw, int grid,
-                              const float* Cbase, uint8_t* bpbase, float* totals, int32_t* status, void* dp_ws,
-                              bool sub, hipStream_t stream);
+                              const float* Cbase, const float* X, const float* Y, int64_t d, const float* rxs,
+                              uint8_t* bpbase, float* totals, int32_t* status, void* dp_ws, bool sub,
+                              hipStream_t stream);
+
+// Row norms of every feasible pair for the fused batched DP (rx_floats(n_b)
+// floats at rx_off each).
+pardtw_status row_norms_batch_launch(const BatchPair* pairs, int32_t batch, const float* X, int64_t d, float* rxs,
+                                     hipStream_t stream);
 
 pardtw_status backtrace_batch_launch(const BatchPair* pairs, int32_t batch, const uint8_t* bpbase,
                                      const int32_t* status, int32_t* paths, int32_t* path_len, hipStream_t stream);

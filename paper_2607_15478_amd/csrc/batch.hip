@@ -50,9 +50,10 @@ __global__ void batch_init_kernel(const pardtw::BatchPair* __restrict__ pairs, i
 
 struct pardtw_plan {
     int mode = 0;       // 0 independent pairs, 1 Segmental DTW fragments
+    bool fused = false; // costs computed inside the DP: no cost region, a row-norm region instead
     int variant = 1;    // Segmental DTW: PARDTW_NSDTW or PARDTW_WSDTW
     int64_t la = 0, lb = 0, hop = 1;
-    size_t off_s = 0, off_fstat = 0, off_slots = 0, off_flen = 0, off_seg = 0;
+    size_t off_s = 0, off_fstat = 0, off_slots = 0, off_flen = 0, off_seg = 0, off_rx = 0;
     int32_t batch = 0;
     int64_t d = 0;
     pardtw_prec prec = PARDTW_PREC_F32;
@@ -107,18 +108,29 @@ std::vector<pardtw::DpItem> make_items(const pardtw_plan& pl, int nw, int order)
 }
 
 // A Segmental DTW plan's DP writes the fragments' scores and statuses into
-// its workspace; `totals` / `status` serve plans of pairs.
-pardtw_status run_dp(const pardtw_plan& pl, const Schedule& s, char* ws, float* totals, int32_t* status,
-                     hipStream_t stream) {
+// its workspace; `totals` / `status` serve plans of pairs. X, Y are the packed
+// features, read by the fused form.
+pardtw_status run_dp(const pardtw_plan& pl, const Schedule& s, char* ws, const float* X, const float* Y,
+                     float* totals, int32_t* status, hipStream_t stream) {
     const bool sub = pl.mode == 1;
     if (sub) {
         totals = reinterpret_cast<float*>(ws + pl.off_s);
         status = reinterpret_cast<int32_t*>(ws + pl.off_fstat);
     }
     return pardtw::dp_batch_launch(pl.pairs_dev, pl.items_dev + s.items_at, s.nitems, s.nw, grid_for(pl, s),
-                                   reinterpret_cast<const float*>(ws + pl.off_c),
+                                   reinterpret_cast<const float*>(ws + pl.off_c), pl.fused ? X : nullptr, Y, pl.d,
+                                   reinterpret_cast<const float*>(ws + pl.off_rx),
                                    reinterpret_cast<uint8_t*>(ws + pl.off_bp), totals, status, ws + pl.off_dp, sub,
                                    stream);
+}
+
+// What precedes the DP: the cost GEMM, or for the fused form the row norms.
+pardtw_status run_front(const pardtw_plan& pl, const float* X, const float* Y, char* ws, hipStream_t stream) {
+    if (pl.fused)
+        return pardtw::row_norms_batch_launch(pl.pairs_dev, pl.batch, X, pl.d, reinterpret_cast<float*>(ws + pl.off_rx),
+                                              stream);
+    return pardtw::cost_batch_launch(pl.pairs_dev, pl.tile_pair_dev, pl.tiles, X, Y, pl.d, pl.prec,
+                                     reinterpret_cast<float*>(ws + pl.off_c), stream);
 }
 
 bool aligned(const void* p, size_t a) { return reinterpret_cast<uintptr_t>(p) % a == 0; }
@@ -132,10 +144,10 @@ pardtw_status check_call(const pardtw_plan* plan, const float* X, const float* Y
     return PARDTW_OK;
 }
 
-// Lays out one pair (or fragment) b: descriptor offsets into the cost, code and
-// record regions, counted in the running totals.
-void place_pair(pardtw::BatchPair& q, int64_t n, int64_t m, bool feasible, int band, size_t& c_floats,
-                size_t& bp_bytes, size_t& rec_bytes, int64_t& tiles) {
+// Lays out one pair (or fragment) b: descriptor offsets into the cost (or,
+// fused, row-norm), code and record regions, counted in the running totals.
+void place_pair(pardtw::BatchPair& q, int64_t n, int64_t m, bool feasible, int band, bool fused, size_t& c_floats,
+                size_t& bp_bytes, size_t& rec_bytes, size_t& rx_total, int64_t& tiles) {
     q.n = n;
     q.m = m;
     q.G = pardtw::bp_groups(n);
@@ -147,12 +159,17 @@ void place_pair(pardtw::BatchPair& q, int64_t n, int64_t m, bool feasible, int b
     q.bp_off = int64_t(bp_bytes);
     q.rec_off = int64_t(rec_bytes / sizeof(uint64_t));
     q.tile0 = tiles;
+    q.rx_off = int64_t(rx_total);
     if (feasible) {
         const size_t cells = size_t(q.P) * size_t(q.G) * pardtw::kPanel * pardtw::kBpRows;
-        c_floats += cells;  // multiples of 512: keeps every pair 256-byte aligned
-        bp_bytes += cells;
+        bp_bytes += cells;  // multiples of 512: keeps every pair 256-byte aligned
         rec_bytes += pardtw::dp_record_bytes(n, m);
-        tiles += pardtw::cost_blocks(n, m);
+        if (fused) {
+            rx_total += size_t(pardtw::ceil_div(pardtw::rx_floats(n), 64) * 64);  // 256-byte steps
+        } else {
+            c_floats += cells;
+            tiles += pardtw::cost_blocks(n, m);
+        }
     }
 }
 
@@ -161,19 +178,22 @@ void place_pair(pardtw::BatchPair& q, int64_t n, int64_t m, bool feasible, int b
 pardtw_status finish_plan(pardtw_plan* pl, pardtw_plan** plan_out) {
     const int32_t batch = pl->batch;
     const int64_t tiles = pl->tiles;
-    // cost block -> pair table of the batched cost kernel
+    // cost block -> pair table of the batched cost kernel (none for the fused
+    // form, which runs no cost kernel and counted no blocks)
     std::vector<int32_t> tile_pair(size_t(std::max<int64_t>(tiles, 1)));
-    for (int b = 0; b < batch; ++b) {
+    for (int b = 0; b < batch && !pl->fused; ++b) {
         const pardtw::BatchPair& q = pl->pairs[b];
         if (!q.feasible) continue;
         const int64_t t = pardtw::cost_blocks(q.n, q.m);
         std::fill(tile_pair.begin() + q.tile0, tile_pair.begin() + q.tile0 + t, b);
     }
 
-    // candidate schedules and their work lists
+    // candidate schedules and their work lists (fused workgroups hold at most
+    // four compute waves)
     std::vector<pardtw::DpItem> all_items;
     const int nws[4] = {1, 2, 4, 8};
     for (int nw : nws) {
+        if (pl->fused && nw > 4) continue;
         for (int order = 0; order < 2; ++order) {
             const std::vector<pardtw::DpItem> it = make_items(*pl, nw, order);
             const int64_t at = int64_t(all_items.size());
@@ -206,12 +226,29 @@ pardtw_status finish_plan(pardtw_plan* pl, pardtw_plan** plan_out) {
 
 }  // namespace
 
+namespace {
+
+// The fused form computes FP32 costs from features with at most 16 entries.
+pardtw_status check_flags(int32_t flags, int64_t d, pardtw_prec prec) {
+    if (flags & ~int32_t(PARDTW_PLAN_FUSED_COST)) return PARDTW_ERR_INVALID_ARG;
+    if ((flags & PARDTW_PLAN_FUSED_COST) && (d > 16 || prec != PARDTW_PREC_F32)) return PARDTW_ERR_UNSUPPORTED;
+    return PARDTW_OK;
+}
+
+}  // namespace
+
 extern "C" pardtw_status pardtw_plan_create(int32_t batch, const int64_t* n_host, const int64_t* m_host, int64_t d,
                                             pardtw_prec prec, pardtw_plan** plan_out) {
+    return pardtw_plan_create_ex(batch, n_host, m_host, d, prec, 0, plan_out);
+}
+
+extern "C" pardtw_status pardtw_plan_create_ex(int32_t batch, const int64_t* n_host, const int64_t* m_host,
+                                               int64_t d, pardtw_prec prec, int32_t flags, pardtw_plan** plan_out) {
     if (!plan_out) return PARDTW_ERR_INVALID_ARG;
     *plan_out = nullptr;
     if (batch <= 0 || !n_host || !m_host || d <= 0 || d > (int64_t(1) << 20)) return PARDTW_ERR_INVALID_ARG;
     if (prec != PARDTW_PREC_F32 && prec != PARDTW_PREC_BF16) return PARDTW_ERR_UNSUPPORTED;
+    if (const pardtw_status fs = check_flags(flags, d, prec); fs != PARDTW_OK) return fs;
     for (int b = 0; b < batch; ++b)
         if (!pardtw::valid_sizes(n_host[b], m_host[b])) return PARDTW_ERR_INVALID_ARG;
 
@@ -220,15 +257,17 @@ extern "C" pardtw_status pardtw_plan_create(int32_t batch, const int64_t* n_host
     pl->batch = batch;
     pl->d = d;
     pl->prec = prec;
+    pl->fused = (flags & PARDTW_PLAN_FUSED_COST) != 0;
     if (hipGetDevice(&pl->device) != hipSuccess ||
         hipDeviceGetAttribute(&pl->cus, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess) {
         delete pl;
         return PARDTW_ERR_HIP;
     }
 
-    // descriptors and the workspace layout: cost panels | codes | DP header + records
+    // descriptors and the workspace layout: cost panels (or row norms) | codes |
+    // DP header + records
     pl->pairs.resize(batch);
-    size_t c_floats = 0, bp_bytes = 0, rec_bytes = 0;
+    size_t c_floats = 0, bp_bytes = 0, rec_bytes = 0, rx_total = 0;
     int64_t xr = 0, yr = 0, po = 0, tiles = 0;
     for (int b = 0; b < batch; ++b) {
         pardtw::BatchPair& q = pl->pairs[b];
@@ -236,7 +275,7 @@ extern "C" pardtw_status pardtw_plan_create(int32_t batch, const int64_t* n_host
         q.x_off = xr;
         q.y_off = yr;
         q.path_off = po;
-        place_pair(q, n, m, pardtw::pair_feasible(n, m), 1, c_floats, bp_bytes, rec_bytes, tiles);
+        place_pair(q, n, m, pardtw::pair_feasible(n, m), 1, pl->fused, c_floats, bp_bytes, rec_bytes, rx_total, tiles);
         const int64_t cap = std::min(n, m);
         xr += n;
         yr += m;
@@ -248,7 +287,8 @@ extern "C" pardtw_status pardtw_plan_create(int32_t batch, const int64_t* n_host
     pl->path_capacity = po;
     pl->tiles = tiles;
     pl->off_c = 0;
-    pl->off_bp = align_up(c_floats * sizeof(float));
+    pl->off_rx = 0;  // the fused form's row norms take the cost region's place
+    pl->off_bp = align_up((pl->fused ? rx_total : c_floats) * sizeof(float));
     pl->off_dp = pl->off_bp + align_up(bp_bytes);
     pl->ws_bytes = pl->off_dp + align_up(pardtw::dp_header_bytes() + rec_bytes);
     return finish_plan(pl, plan_out);
@@ -294,10 +334,9 @@ extern "C" pardtw_status pardtw_align_batch(const pardtw_plan* plan, const float
     batch_init_kernel<<<unsigned(pardtw::ceil_div(plan->batch, 256)), 256, 0, stream>>>(
         plan->pairs_dev, plan->batch, totals, pair_status, path_len);
     if ((st = pardtw::launch_status()) != PARDTW_OK) return st;
-    st = pardtw::cost_batch_launch(plan->pairs_dev, plan->tile_pair_dev, plan->tiles, X_packed, Y_packed, plan->d,
-                                   plan->prec, reinterpret_cast<float*>(ws + plan->off_c), stream);
+    st = run_front(*plan, X_packed, Y_packed, ws, stream);
     if (st != PARDTW_OK) return st;
-    st = run_dp(*plan, plan->scheds[plan->chosen], ws, totals, pair_status, stream);
+    st = run_dp(*plan, plan->scheds[plan->chosen], ws, X_packed, Y_packed, totals, pair_status, stream);
     if (st != PARDTW_OK) return st;
     return pardtw::backtrace_batch_launch(plan->pairs_dev, plan->batch,
                                           reinterpret_cast<const uint8_t*>(ws + plan->off_bp), pair_status,
@@ -313,9 +352,8 @@ extern "C" pardtw_status pardtw_plan_autotune(pardtw_plan* plan, const float* X_
     if (st != PARDTW_OK) return st;
     if (reps < 1) reps = 1;
     char* ws = static_cast<char*>(workspace);
-    // the costs do not depend on the schedule: compute them once
-    st = pardtw::cost_batch_launch(plan->pairs_dev, plan->tile_pair_dev, plan->tiles, X_packed, Y_packed, plan->d,
-                                   plan->prec, reinterpret_cast<float*>(ws + plan->off_c), stream);
+    // the costs (or row norms) do not depend on the schedule: compute them once
+    st = run_front(*plan, X_packed, Y_packed, ws, stream);
     if (st != PARDTW_OK) return st;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return PARDTW_ERR_HIP;
@@ -327,10 +365,11 @@ extern "C" pardtw_status pardtw_plan_autotune(pardtw_plan* plan, const float* X_
     int best_s = plan->chosen;
     for (size_t s = 0; s < plan->scheds.size() && st == PARDTW_OK; ++s) {
         const Schedule& sc = plan->scheds[s];
-        st = run_dp(*plan, sc, ws, totals, pair_status, stream);  // warm-up
+        st = run_dp(*plan, sc, ws, X_packed, Y_packed, totals, pair_status, stream);  // warm-up
         if (st != PARDTW_OK) break;
         if (hipEventRecord(e0, stream) != hipSuccess) { st = PARDTW_ERR_HIP; break; }
-        for (int r = 0; r < reps && st == PARDTW_OK; ++r) st = run_dp(*plan, sc, ws, totals, pair_status, stream);
+        for (int r = 0; r < reps && st == PARDTW_OK; ++r)
+            st = run_dp(*plan, sc, ws, X_packed, Y_packed, totals, pair_status, stream);
         if (st != PARDTW_OK) break;
         float ms = 0.0f;
         if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -367,7 +406,7 @@ extern "C" pardtw_status pardtw_path_grad_batch(const pardtw_plan* plan, const f
 // ---- Segmental DTW -----------------------------------------------------------
 
 extern "C" pardtw_status pardtw_segplan_create(int64_t la, int64_t lb, int32_t nfrag, int64_t d, pardtw_prec prec,
-                                               int32_t variant, pardtw_plan** plan_out) {
+                                               int32_t variant, int32_t flags, pardtw_plan** plan_out) {
     if (!plan_out) return PARDTW_ERR_INVALID_ARG;
     *plan_out = nullptr;
     if (nfrag <= 0 || la < nfrag || !pardtw::valid_sizes(la, lb) || d <= 0 || d > (int64_t(1) << 20))
@@ -375,6 +414,7 @@ extern "C" pardtw_status pardtw_segplan_create(int64_t la, int64_t lb, int32_t n
     if (variant != PARDTW_NSDTW && variant != PARDTW_WSDTW) return PARDTW_ERR_INVALID_ARG;
     if (prec != PARDTW_PREC_F32 && prec != PARDTW_PREC_BF16) return PARDTW_ERR_UNSUPPORTED;
     if (!pardtw::valid_sizes(nfrag, lb)) return PARDTW_ERR_INVALID_ARG;
+    if (const pardtw_status fs = check_flags(flags, d, prec); fs != PARDTW_OK) return fs;
 
     pardtw_plan* pl = new (std::nothrow) pardtw_plan;
     if (!pl) return PARDTW_ERR_HIP;
@@ -386,6 +426,7 @@ extern "C" pardtw_status pardtw_segplan_create(int64_t la, int64_t lb, int32_t n
     pl->batch = nfrag;
     pl->d = d;
     pl->prec = prec;
+    pl->fused = (flags & PARDTW_PLAN_FUSED_COST) != 0;
     if (hipGetDevice(&pl->device) != hipSuccess ||
         hipDeviceGetAttribute(&pl->cus, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess) {
         delete pl;
@@ -393,7 +434,7 @@ extern "C" pardtw_status pardtw_segplan_create(int64_t la, int64_t lb, int32_t n
     }
     // fragment f: rows [floor(f la / N), floor((f+1) la / N)) of A against all of B
     pl->pairs.resize(nfrag);
-    size_t c_floats = 0, bp_bytes = 0, rec_bytes = 0;
+    size_t c_floats = 0, bp_bytes = 0, rec_bytes = 0, rx_total = 0;
     int64_t tiles = 0;
     for (int f = 0; f < nfrag; ++f) {
         pardtw::BatchPair& q = pl->pairs[f];
@@ -401,7 +442,8 @@ extern "C" pardtw_status pardtw_segplan_create(int64_t la, int64_t lb, int32_t n
         q.x_off = r0;
         q.y_off = 0;
         q.path_off = r0;  // fragment f's path slot: n_f pairs
-        place_pair(q, r1 - r0, lb, pardtw::subseq_feasible(r1 - r0, lb), 2, c_floats, bp_bytes, rec_bytes, tiles);
+        place_pair(q, r1 - r0, lb, pardtw::subseq_feasible(r1 - r0, lb), 2, pl->fused, c_floats, bp_bytes, rec_bytes,
+                   rx_total, tiles);
         pl->max_cap = std::max(pl->max_cap, r1 - r0);
     }
     pl->x_rows = la;
@@ -411,7 +453,8 @@ extern "C" pardtw_status pardtw_segplan_create(int64_t la, int64_t lb, int32_t n
     // cost panels | codes | DP header + records | scores | fragment statuses |
     // fragment path slots | fragment path lengths | segment-level workspace
     pl->off_c = 0;
-    pl->off_bp = align_up(c_floats * sizeof(float));
+    pl->off_rx = 0;
+    pl->off_bp = align_up((pl->fused ? rx_total : c_floats) * sizeof(float));
     pl->off_dp = pl->off_bp + align_up(bp_bytes);
     pl->off_s = pl->off_dp + align_up(pardtw::dp_header_bytes() + rec_bytes);
     pl->off_fstat = pl->off_s + align_up(size_t(nfrag) * size_t(lb) * sizeof(float));
@@ -440,8 +483,7 @@ pardtw_status seg_front(const pardtw_plan* plan, const float* A, const float* B,
                                                    reinterpret_cast<float*>(ws + plan->off_s),
                                                    reinterpret_cast<int32_t*>(ws + plan->off_fstat), stream);
     if (st != PARDTW_OK) return st;
-    return pardtw::cost_batch_launch(plan->pairs_dev, plan->tile_pair_dev, plan->tiles, A, B, plan->d, plan->prec,
-                                     reinterpret_cast<float*>(ws + plan->off_c), stream);
+    return run_front(*plan, A, B, ws, stream);
 }
 
 }  // namespace
@@ -455,7 +497,7 @@ extern "C" pardtw_status pardtw_segmental_align(const pardtw_plan* plan, const f
     if (!total || !ends || !path || !path_len || !status || !aligned(path, 8)) return PARDTW_ERR_INVALID_ARG;
     char* ws = static_cast<char*>(workspace);
     if ((st = seg_front(plan, A, B, ws, stream)) != PARDTW_OK) return st;
-    if ((st = run_dp(*plan, plan->scheds[plan->chosen], ws, nullptr, nullptr, stream)) != PARDTW_OK) return st;
+    if ((st = run_dp(*plan, plan->scheds[plan->chosen], ws, A, B, nullptr, nullptr, stream)) != PARDTW_OK) return st;
     st = pardtw::segment_ends_launch(reinterpret_cast<const float*>(ws + plan->off_s), plan->batch, plan->lb,
                                      plan->hop, plan->variant, ws + plan->off_seg, ends, total, status, stream);
     if (st != PARDTW_OK) return st;
@@ -486,10 +528,10 @@ extern "C" pardtw_status pardtw_segplan_autotune(pardtw_plan* plan, const float*
     int best_s = plan->chosen;
     for (size_t s = 0; s < plan->scheds.size() && st == PARDTW_OK; ++s) {
         const Schedule& sc = plan->scheds[s];
-        st = run_dp(*plan, sc, ws, nullptr, nullptr, stream);  // warm-up
+        st = run_dp(*plan, sc, ws, A, B, nullptr, nullptr, stream);  // warm-up
         if (st != PARDTW_OK) break;
         if (hipEventRecord(e0, stream) != hipSuccess) { st = PARDTW_ERR_HIP; break; }
-        for (int r = 0; r < reps && st == PARDTW_OK; ++r) st = run_dp(*plan, sc, ws, nullptr, nullptr, stream);
+        for (int r = 0; r < reps && st == PARDTW_OK; ++r) st = run_dp(*plan, sc, ws, A, B, nullptr, nullptr, stream);
         if (st != PARDTW_OK) break;
         float ms = 0.0f;
         if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||

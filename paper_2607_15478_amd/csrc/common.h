@@ -80,6 +80,11 @@ __host__ __device__ inline int64_t sub_group_hi(int64_t p, int64_t n, int64_t m)
     return floor_div(j1, 4);
 }
 
+// Floats of the fused DP's row-norm area for n rows: its producers' loop,
+// padded to a multiple of three 16-row slabs, reads up to two slabs past its
+// end; rows past n hold zeros.
+__host__ __device__ inline int64_t rx_floats(int64_t n) { return (ceil_div(bp_groups(n), 2) + 5) * 16; }
+
 // Some end column of row n-1 is reachable from row 0.
 inline bool subseq_feasible(int64_t n, int64_t m) { return n - 1 <= 2 * (m - 1); }
 

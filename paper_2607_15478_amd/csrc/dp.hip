@@ -596,6 +596,10 @@ struct DpBatchArgs {
     const DpItem* items;
     int32_t nitems;
     const float* C;
+    const float* X;    // fused cost: packed features and row norms
+    const float* Y;
+    const float* rxs;
+    int64_t d;
     uint8_t* bp;
     float* totals;
     int32_t* status;
@@ -603,18 +607,22 @@ struct DpBatchArgs {
     uint64_t* rec;
 };
 
-template <int NW, bool SUB>
-__global__ __launch_bounds__(kLanes*(NW + 2)) void dp_batch_kernel(DpBatchArgs ba) {
-    __shared__ DpShared sh;
+template <int NW, int SRC, bool SUB>
+__device__ __attribute__((always_inline)) inline void dp_batch_body(const DpBatchArgs& ba, DpShared& sh,
+                                                                    CostRing* cring) {
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);
     const uint32_t epoch = __hip_atomic_load(&ba.hdr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (;;) {
-        const int t = next_ticket<NW>(sh, nullptr, ba.hdr);
+        const int t = next_ticket<NW>(sh, cring, ba.hdr);
         if (t >= ba.nitems) break;
         const DpItem it = ba.items[t];
         const BatchPair q = ba.pairs[it.pair];
         DpArgs a;
-        a.C = ba.C + q.c_off;
+        a.C = SRC == kSrcFused ? nullptr : ba.C + q.c_off;
+        a.X = SRC == kSrcFused ? ba.X + q.x_off * ba.d : nullptr;
+        a.Y = SRC == kSrcFused ? ba.Y + q.y_off * ba.d : nullptr;
+        a.rxs = SRC == kSrcFused ? ba.rxs + q.rx_off : nullptr;
+        a.d = ba.d;
         a.bp = ba.bp + q.bp_off;
         // fragments of one plan share m: their score rows are stacked
         a.total = SUB ? ba.totals + int64_t(it.pair) * q.m : ba.totals + it.pair;
@@ -626,9 +634,31 @@ __global__ __launch_bounds__(kLanes*(NW + 2)) void dp_batch_kernel(DpBatchArgs b
         a.G = q.G;
         a.P = q.P;
         a.S = int(ceil_div(q.P, NW));
-        run_group<NW, kSrcPanel, SUB>(a, sh, nullptr, wave, it.group, epoch);
+        run_group<NW, SRC, SUB>(a, sh, cring, wave, it.group, epoch);
         __syncthreads();
     }
+}
+
+template <int NW, int SRC, bool SUB>
+__global__ __launch_bounds__(kLanes * dp_waves(NW, SRC)) void dp_batch_kernel(DpBatchArgs ba) {
+    __shared__ DpShared sh;
+    if constexpr (SRC == kSrcFused) {
+        static_assert(NW <= kMaxNWFused, "fused workgroups hold at most kMaxNWFused compute waves");
+        __shared__ CostRing cring;
+        dp_batch_body<NW, SRC, SUB>(ba, sh, &cring);
+    } else {
+        dp_batch_body<NW, SRC, SUB>(ba, sh, nullptr);
+    }
+}
+
+// Row norms of pair b (block b) for the fused batched DP.
+__global__ void row_norms_batch_kernel(const BatchPair* __restrict__ pairs, const float* __restrict__ X, int64_t d,
+                                       float* rxs) {
+    const BatchPair q = pairs[blockIdx.x];
+    if (!q.feasible) return;
+    const int64_t len = rx_floats(q.n);
+    for (int64_t i = threadIdx.x; i < len; i += blockDim.x)
+        rxs[q.rx_off + i] = row_inv_norm_f32_small(X + q.x_off * d, q.n, d, i);
 }
 
 // Row inverse norms for the fused producers (zeros past n, up to len).
@@ -671,10 +701,16 @@ void launch_nw(const DpArgs& a, int src, bool sub, int grid, hipStream_t stream)
     else if constexpr (NW <= kMaxNWFused) launch_src<NW, kSrcFused>(a, sub, grid, stream);
 }
 
+template <int NW, int SRC>
+void launch_batch_src(const DpBatchArgs& a, bool sub, int grid, hipStream_t stream) {
+    if (sub) dp_batch_kernel<NW, SRC, true><<<grid, kLanes * dp_waves(NW, SRC), 0, stream>>>(a);
+    else dp_batch_kernel<NW, SRC, false><<<grid, kLanes * dp_waves(NW, SRC), 0, stream>>>(a);
+}
+
 template <int NW>
-void launch_batch_nw(const DpBatchArgs& a, bool sub, int grid, hipStream_t stream) {
-    if (sub) dp_batch_kernel<NW, true><<<grid, kLanes * (NW + 2), 0, stream>>>(a);
-    else dp_batch_kernel<NW, false><<<grid, kLanes * (NW + 2), 0, stream>>>(a);
+void launch_batch_nw(const DpBatchArgs& a, bool fused, bool sub, int grid, hipStream_t stream) {
+    if (!fused) launch_batch_src<NW, kSrcPanel>(a, sub, grid, stream);
+    else if constexpr (NW <= kMaxNWFused) launch_batch_src<NW, kSrcFused>(a, sub, grid, stream);
 }
 
 }  // namespace
@@ -688,22 +724,25 @@ size_t dp_record_bytes(int64_t n, int64_t m) {
     return size_t(num_panels(m)) * size_t(bp_groups(n)) * kChunk * 2 * sizeof(uint64_t);
 }
 
-// Floats of the fused row-norm area: the producer's loop, padded to a multiple
-// of three slabs, reads up to two slabs past its end.
-int64_t rx_floats(int64_t n) { return (ceil_div(bp_groups(n), 2) + 5) * 16; }
-
 size_t dp_workspace_bytes_impl(int64_t n, int64_t m) {
     return sizeof(DpWsHeader) + dp_record_bytes(n, m) + size_t(rx_floats(n)) * sizeof(float);
 }
 
 pardtw_status dp_batch_launch(const BatchPair* pairs, const DpItem* items, int32_t nitems, int nw, int grid,
-                              const float* Cbase, uint8_t* bpbase, float* totals, int32_t* status, void* dp_ws,
-                              bool sub, hipStream_t stream) {
+                              const float* Cbase, const float* X, const float* Y, int64_t d, const float* rxs,
+                              uint8_t* bpbase, float* totals, int32_t* status, void* dp_ws, bool sub,
+                              hipStream_t stream) {
+    const bool fused = X != nullptr;
+    if (fused && nw > kMaxNWFused) return PARDTW_ERR_UNSUPPORTED;
     DpBatchArgs a;
     a.pairs = pairs;
     a.items = items;
     a.nitems = nitems;
     a.C = Cbase;
+    a.X = X;
+    a.Y = Y;
+    a.rxs = rxs;
+    a.d = d;
     a.bp = bpbase;
     a.totals = totals;
     a.status = status;
@@ -713,12 +752,19 @@ pardtw_status dp_batch_launch(const BatchPair* pairs, const DpItem* items, int32
     if (nitems <= 0) return launch_status();
     if (grid > nitems) grid = nitems;
     switch (nw) {
-        case 1: launch_batch_nw<1>(a, sub, grid, stream); break;
-        case 2: launch_batch_nw<2>(a, sub, grid, stream); break;
-        case 4: launch_batch_nw<4>(a, sub, grid, stream); break;
-        case 8: launch_batch_nw<8>(a, sub, grid, stream); break;
+        case 1: launch_batch_nw<1>(a, fused, sub, grid, stream); break;
+        case 2: launch_batch_nw<2>(a, fused, sub, grid, stream); break;
+        case 4: launch_batch_nw<4>(a, fused, sub, grid, stream); break;
+        case 8: launch_batch_nw<8>(a, fused, sub, grid, stream); break;
         default: return PARDTW_ERR_UNSUPPORTED;
     }
+    return launch_status();
+}
+
+pardtw_status row_norms_batch_launch(const BatchPair* pairs, int32_t batch, const float* X, int64_t d, float* rxs,
+                                     hipStream_t stream) {
+    if (batch <= 0) return PARDTW_OK;
+    row_norms_batch_kernel<<<unsigned(batch), 256, 0, stream>>>(pairs, X, d, rxs);
     return launch_status();
 }
 

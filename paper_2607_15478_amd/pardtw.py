@@ -27,6 +27,7 @@ LAYOUT_PANEL_BAND = 2  # panel layout, only the 8-row groups the DP reads (the p
 LAYOUT_PANEL_SUBSEQ_BAND = 3  # panel layout, only the groups the subsequence DP reads are written
 NSDTW = 0
 WSDTW = 1
+PLAN_FUSED_COST = 1  # plans whose DP computes the costs itself (FP32, d <= 16)
 
 STATUS_NAMES = {0: "OK", 1: "ERR_INVALID_ARG", 2: "ERR_WORKSPACE", 3: "ERR_HIP", 4: "ERR_UNSUPPORTED"}
 
@@ -60,7 +61,7 @@ _lib_dp_fused = _sig("pardtw_dp_fused", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _
 _lib_sub_dp_fused = _sig("pardtw_subseq_dp_fused", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _SZ, _P])
 _lib_unpack = _sig("pardtw_bp_unpack", _E, [_P, _I64, _I64, _P, _P])
 _lib_grad = _sig("pardtw_path_grad", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P])
-_lib_plan_create = _sig("pardtw_plan_create", _E, [_I32, _P, _P, _I64, _E, ctypes.POINTER(_P)])
+_lib_plan_create = _sig("pardtw_plan_create_ex", _E, [_I32, _P, _P, _I64, _E, _I32, ctypes.POINTER(_P)])
 _lib_plan_ws = _sig("pardtw_plan_workspace_bytes", _SZ, [_P])
 _lib_plan_cap = _sig("pardtw_plan_path_capacity", _I64, [_P])
 _lib_plan_destroy = _sig("pardtw_plan_destroy", None, [_P])
@@ -77,7 +78,8 @@ _lib_sub_dp = _sig("pardtw_subseq_dp", _E, [_P, _E, _I64, _I64, _P, _P, _P, _P, 
 _lib_sub_bt = _sig("pardtw_subseq_backtrace", _E, [_P, _I64, _I64, _P, _P, _P, _P])
 _lib_seg_ws = _sig("pardtw_segment_workspace_bytes", _SZ, [_I64, _I64])
 _lib_seg_ends = _sig("pardtw_segment_ends", _E, [_P, _I64, _I64, _I64, _I32, _P, _SZ, _P, _P, _P, _P])
-_lib_segplan_create = _sig("pardtw_segplan_create", _E, [_I64, _I64, _I32, _I64, _E, _I32, ctypes.POINTER(_P)])
+_lib_segplan_create = _sig("pardtw_segplan_create", _E, [_I64, _I64, _I32, _I64, _E, _I32, _I32,
+                                                         ctypes.POINTER(_P)])
 _lib_segplan_scores = _sig("pardtw_segplan_scores_offset", _I64, [_P])
 _lib_seg_align = _sig("pardtw_segmental_align", _E, [_P, _P, _P, _P, _SZ, _P, _P, _P, _P, _P, _P])
 _lib_segplan_autotune = _sig("pardtw_segplan_autotune", _E, [_P, _P, _P, _P, _SZ, _I32, _P, _P])
@@ -240,7 +242,7 @@ class Plan:
     """A batch of pairs with fixed lengths (pardtw_plan_create). Buffers are
     packed as the C header describes; `buffers()` allocates a matching set."""
 
-    def __init__(self, ns, ms, d: int, prec: int = PREC_F32):
+    def __init__(self, ns, ms, d: int, prec: int = PREC_F32, fused: bool = False):
         ns = [int(v) for v in ns]
         ms = [int(v) for v in ms]
         if len(ns) != len(ms) or not ns:
@@ -250,7 +252,9 @@ class Plan:
         n_arr = (ctypes.c_int64 * self.batch)(*ns)
         m_arr = (ctypes.c_int64 * self.batch)(*ms)
         h = _P()
-        _check(_lib_plan_create(self.batch, n_arr, m_arr, self.d, prec, ctypes.byref(h)), "pardtw_plan_create")
+        self.fused = bool(fused)
+        _check(_lib_plan_create(self.batch, n_arr, m_arr, self.d, prec, PLAN_FUSED_COST if fused else 0,
+                                ctypes.byref(h)), "pardtw_plan_create_ex")
         self._h = h
         self.workspace_bytes = int(_lib_plan_ws(h))
         self.path_capacity = int(_lib_plan_cap(h))
@@ -402,11 +406,13 @@ class SegPlan:
     """Segmental DTW of A (la x d) against B (lb x d) with nfrag fragments
     (pardtw_segplan_create); `buffers()` allocates the outputs and workspace."""
 
-    def __init__(self, la: int, lb: int, nfrag: int, d: int, prec: int = PREC_F32, variant: int = WSDTW):
+    def __init__(self, la: int, lb: int, nfrag: int, d: int, prec: int = PREC_F32, variant: int = WSDTW,
+                 fused: bool = False):
         self.la, self.lb, self.nfrag, self.d, self.prec, self.variant = int(la), int(lb), int(nfrag), int(d), prec, variant
+        self.fused = bool(fused)
         h = _P()
-        _check(_lib_segplan_create(self.la, self.lb, self.nfrag, self.d, prec, int(variant), ctypes.byref(h)),
-               "pardtw_segplan_create")
+        _check(_lib_segplan_create(self.la, self.lb, self.nfrag, self.d, prec, int(variant),
+                                   PLAN_FUSED_COST if fused else 0, ctypes.byref(h)), "pardtw_segplan_create")
         self._h = h
         self.workspace_bytes = int(_lib_plan_ws(h))
         self.scores_offset = int(_lib_segplan_scores(h))
@@ -469,9 +475,10 @@ class SegPlan:
         return int(_lib_plan_nsched(self._h))
 
 
-def segmental(A: torch.Tensor, B: torch.Tensor, nfrag: int, variant: int = WSDTW, prec: int = PREC_F32):
+def segmental(A: torch.Tensor, B: torch.Tensor, nfrag: int, variant: int = WSDTW, prec: int = PREC_F32,
+              fused: bool = False):
     """Segmental DTW on the GPU: (total, ends (nfrag,), path (L,2), status)."""
-    plan = SegPlan(A.shape[0], B.shape[0], nfrag, A.shape[1], prec, variant)
+    plan = SegPlan(A.shape[0], B.shape[0], nfrag, A.shape[1], prec, variant, fused)
     buf = plan.buffers(A.device)
     plan.align(A, B, buf)
     L = int(buf["path_len"].item())

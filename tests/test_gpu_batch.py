@@ -190,3 +190,26 @@ def test_batch_workload_sample_against_oracle():
         parity.check_legal(paths[b], n, m)
         parity.check_total(float(totals[b]), J)
         parity.audit_path(paths[b], BP, lambda c: oracle.probe(c, X=x, Y=y)[0])
+
+
+def test_fused_plan_bit_identical(mixed):
+    """A plan whose DP computes the costs itself gives every pair the unfused
+    plan's total, status and path, under each of its schedules."""
+    pairs, plan, Xp, Yp, buf = mixed
+    ref = _outputs(plan, buf)
+    fplan = pd.Plan([p[0].shape[0] for p in pairs], [p[1].shape[0] for p in pairs], 12, fused=True)
+    fbuf = fplan.buffers(DEV)
+    assert fplan.workspace_bytes < plan.workspace_bytes  # no cost matrix
+    for s in range(fplan.num_schedules):
+        fplan.select(s)
+        assert fplan.schedule()["panels_per_workgroup"] <= 4
+        fplan.align(Xp, Yp, fbuf)
+        got = _outputs(fplan, fbuf)
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2])
+        for b in range(plan.batch):
+            assert np.array_equal(got[3][b], ref[3][b]), (s, b)
+    assert fplan.autotune(Xp, Yp, fbuf, reps=1) > 0
+    with pytest.raises(pd.PardtwError):
+        pd.Plan([10], [10], 17, fused=True)
+    with pytest.raises(pd.PardtwError):
+        pd.Plan([10], [10], 12, pd.PREC_BF16, fused=True)

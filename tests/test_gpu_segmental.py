@@ -372,3 +372,32 @@ def test_segmental_full_size_sampled():
         pos = k
         assert tuple(seg[-1]) == (starts[f + 1] - 1, g_ends[f]) and seg[0][0] == starts[f]
         assert np.all(parity.step_codes(seg) >= 0)
+
+
+@pytest.mark.parametrize("variant", [pd.NSDTW, pd.WSDTW])
+@pytest.mark.parametrize("la,lb,nf", [(1000, 1200, 4), (2000, 2400, 16), (777, 3000, 3), (500, 100, 2)])
+def test_segmental_fused_plan_bit_identical(la, lb, nf, variant):
+    """The Segmental DTW plan with the costs computed inside the DP: scores,
+    ends, total, status and path bit for bit those of the unfused plan."""
+    if 2 * lb >= la:
+        (A, B), _ = _pair(la + lb + nf, la, lb)
+    else:  # fragments longer than twice B: no end is reachable
+        rng = np.random.default_rng(9)
+        A = synth.chroma_like(rng, la, 12).astype(np.float32)
+        B = synth.chroma_like(rng, lb, 12).astype(np.float32)
+    Ad, Bd = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+    outs = []
+    for fused in (False, True):
+        plan = pd.SegPlan(la, lb, nf, 12, pd.PREC_F32, variant, fused)
+        buf = plan.buffers(DEV)
+        plan.align(Ad, Bd, buf)
+        torch.cuda.synchronize()
+        L = int(buf["path_len"].item())
+        outs.append((float(buf["total"].item()), int(buf["status"].item()), buf["ends"].cpu().numpy(),
+                     buf["path"][:L].cpu().numpy(), _scores_of_plan(plan, buf), plan.workspace_bytes))
+    (t0, s0, e0, p0, S0, w0), (t1, s1, e1, p1, S1, w1) = outs
+    assert s0 == s1 and (t0 == t1 or (np.isinf(t0) and np.isinf(t1)))
+    assert np.array_equal(e0, e1) and np.array_equal(p0, p1)
+    assert np.array_equal(np.isinf(S0), np.isinf(S1)) and np.array_equal(S0[np.isfinite(S0)], S1[np.isfinite(S1)])
+    # no cost matrix (when some fragment is swept at all)
+    assert w1 < w0 or s0 == pd.PAIR_INFEASIBLE
