@@ -58,91 +58,132 @@ __device__ inline VI shfl_up_vi(VI x, int d) {
     return y;
 }
 
-__global__ __launch_bounds__(kSegThreads) void segment_scan_kernel(SegArgs a) {
+// One workgroup scans a block of up to kSegRows consecutive rows, tile by tile:
+// at each tile all rows of the block in order. A row of the block after the
+// first reads the row above from LDS, where each row keeps its last two tiles:
+// the columns it needs, j - hop for j in the tile, lie in those two tiles when
+// hop < kSegTile. The first row of a block reads the row above (the last row
+// of the previous block) from its records. So the rows form a chain through
+// HBM only once per block. When hop >= kSegTile a block is one row.
+constexpr int kSegRows = 8;
+
+__global__ __launch_bounds__(kSegThreads) void segment_scan_kernel(SegArgs a, int rows_per_block) {
     __shared__ VI wave_tot[kSegThreads / 64];
+    __shared__ float ring[kSegRows - 1][2][kSegTile];
     __shared__ int ticket;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const uint32_t epoch = __hip_atomic_load(&a.hdr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const float kInf = __builtin_inff();
+    const bool wsdtw = a.variant == PARDTW_WSDTW;
     for (;;) {
         __syncthreads();
         if (tid == 0) ticket = int(atomicAdd(&a.hdr->ticket, 1u));
         __syncthreads();
-        const int64_t f = ticket;
-        if (f >= a.nf) break;
-        const bool chained = a.variant == PARDTW_WSDTW && f > 0;
-        const float* srow = a.S + f * a.m;
-        const uint64_t* prow = a.rec + (f - 1) * a.m;  // used only when chained
-        uint64_t* orow = a.rec + f * a.m;
-        int32_t* frow = a.first + f * a.m;
-        VI carry{kInf, -1};  // running minimum over the tiles before
-        for (int64_t t0 = 0; t0 < a.m; t0 += kSegTile) {
+        const int64_t f0 = int64_t(ticket) * rows_per_block;
+        if (f0 >= a.nf) break;
+        const int rows = int(a.nf - f0 < rows_per_block ? a.nf - f0 : rows_per_block);
+        VI carry[kSegRows];
+#pragma unroll
+        for (int r = 0; r < kSegRows; ++r) carry[r] = VI{kInf, -1};  // running minimum over earlier tiles
+        int tix = 0;
+        for (int64_t t0 = 0; t0 < a.m; t0 += kSegTile, ++tix) {
             const int64_t j0 = t0 + int64_t(tid) * kSegPer;
-            float t[kSegPer];
+            for (int r = 0; r < rows; ++r) {
+                const int64_t f = f0 + r;
+                const float* srow = a.S + f * a.m;
+                float t[kSegPer];
 #pragma unroll
-            for (int e = 0; e < kSegPer; ++e) t[e] = (j0 + e < a.m) ? srow[j0 + e] : kInf;
-            if (chained) {
-                // Dseg[f-1][j - hop]; +inf left of column hop. Poll until every
-                // needed record carries this launch's epoch.
-                float pv[kSegPer];
-                uint32_t need = 0;
+                for (int e = 0; e < kSegPer; ++e) t[e] = (j0 + e < a.m) ? srow[j0 + e] : kInf;
+                if (wsdtw && f > 0) {
+                    // Dseg[f-1][j - hop]; +inf left of column hop
+                    float pv[kSegPer];
+                    if (r == 0) {
+                        // the previous block's last row: poll its records until
+                        // each needed one carries this launch's epoch
+                        const uint64_t* prow = a.rec + (f - 1) * a.m;
+                        uint32_t need = 0;
 #pragma unroll
-                for (int e = 0; e < kSegPer; ++e) {
-                    pv[e] = kInf;
-                    if (j0 + e < a.m && j0 + e >= a.hop) need |= 1u << e;
-                }
-                while (need) {
+                        for (int e = 0; e < kSegPer; ++e) {
+                            pv[e] = kInf;
+                            if (j0 + e < a.m && j0 + e >= a.hop) need |= 1u << e;
+                        }
+                        while (need) {
 #pragma unroll
-                    for (int e = 0; e < kSegPer; ++e) {
-                        if (need & (1u << e)) {
-                            const uint64_t r = __hip_atomic_load(prow + (j0 + e - a.hop), __ATOMIC_RELAXED,
-                                                                 __HIP_MEMORY_SCOPE_AGENT);
-                            if (uint32_t(r >> 32) == epoch) {
-                                pv[e] = __uint_as_float(uint32_t(r));
-                                need &= ~(1u << e);
+                            for (int e = 0; e < kSegPer; ++e) {
+                                if (need & (1u << e)) {
+                                    const uint64_t v = __hip_atomic_load(prow + (j0 + e - a.hop), __ATOMIC_RELAXED,
+                                                                         __HIP_MEMORY_SCOPE_AGENT);
+                                    if (uint32_t(v >> 32) == epoch) {
+                                        pv[e] = __uint_as_float(uint32_t(v));
+                                        need &= ~(1u << e);
+                                    }
+                                }
+                            }
+                            if (need) __builtin_amdgcn_s_sleep(1);
+                        }
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < kSegPer; ++e) {
+                            const int64_t q = j0 + e - a.hop;  // tile tix or tix - 1 (hop < kSegTile)
+                            pv[e] = kInf;
+                            if (q >= 0 && j0 + e < a.m) {
+                                const int qt = int(q / kSegTile);
+                                pv[e] = ring[r - 1][qt & 1][int(q - int64_t(qt) * kSegTile)];
                             }
                         }
                     }
-                    if (need) __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+                    for (int e = 0; e < kSegPer; ++e) t[e] = pv[e] + t[e];
                 }
+                // this thread's columns
+                VI loc[kSegPer];
+                VI run{kInf, -1};
 #pragma unroll
-                for (int e = 0; e < kSegPer; ++e) t[e] = pv[e] + t[e];
-            }
-            // this thread's columns
-            VI loc[kSegPer];
-            VI run{kInf, -1};
-#pragma unroll
-            for (int e = 0; e < kSegPer; ++e) {
-                run = later_if_less(run, VI{t[e], int32_t(j0 + e)});
-                loc[e] = run;
-            }
-            // exclusive scan over the wave's lanes
-            VI inc = run;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const VI up = shfl_up_vi(inc, d);
-                if (lane >= d) inc = later_if_less(up, inc);
-            }
-            VI before = shfl_up_vi(inc, 1);
-            if (lane == 0) before = VI{kInf, -1};
-            if (lane == 63) wave_tot[wave] = inc;
-            __syncthreads();
-            VI pre = carry;
-            for (int w = 0; w < wave; ++w) pre = later_if_less(pre, wave_tot[w]);
-            pre = later_if_less(pre, before);
-#pragma unroll
-            for (int e = 0; e < kSegPer; ++e) {
-                const int64_t j = j0 + e;
-                if (j < a.m) {
-                    const VI r = later_if_less(pre, loc[e]);
-                    frow[j] = r.i;
-                    __hip_atomic_store(orow + j, (uint64_t(epoch) << 32) | uint64_t(__float_as_uint(r.v)),
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int e = 0; e < kSegPer; ++e) {
+                    run = later_if_less(run, VI{t[e], int32_t(j0 + e)});
+                    loc[e] = run;
                 }
+                // exclusive scan over the wave's lanes
+                VI inc = run;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const VI up = shfl_up_vi(inc, d);
+                    if (lane >= d) inc = later_if_less(up, inc);
+                }
+                VI before = shfl_up_vi(inc, 1);
+                if (lane == 0) before = VI{kInf, -1};
+                if (lane == 63) wave_tot[wave] = inc;
+                __syncthreads();
+                VI pre = carry[0];
+#pragma unroll
+                for (int q = 1; q < kSegRows; ++q) pre = (q == r) ? carry[q] : pre;
+                const VI carried = pre;
+                for (int w = 0; w < wave; ++w) pre = later_if_less(pre, wave_tot[w]);
+                pre = later_if_less(pre, before);
+                // the block's last row feeds the next block through records;
+                // every row records its last column (the totals)
+                const bool last_row = r == rows - 1;
+                uint64_t* orow = a.rec + f * a.m;
+                int32_t* frow = a.first + f * a.m;
+#pragma unroll
+                for (int e = 0; e < kSegPer; ++e) {
+                    const int64_t j = j0 + e;
+                    if (j < a.m) {
+                        const VI v = later_if_less(pre, loc[e]);
+                        frow[j] = v.i;
+                        if (last_row || j == a.m - 1)
+                            __hip_atomic_store(orow + j, (uint64_t(epoch) << 32) | uint64_t(__float_as_uint(v.v)),
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (!last_row) ring[r][tix & 1][int(j - t0)] = v.v;
+                    }
+                }
+                VI nc = carried;
+                for (int w = 0; w < kSegThreads / 64; ++w) nc = later_if_less(nc, wave_tot[w]);
+#pragma unroll
+                for (int q = 0; q < kSegRows; ++q) carry[q] = (q == r) ? nc : carry[q];
+                __syncthreads();  // wave_tot and this row's ring tile are read next
             }
-            for (int w = 0; w < kSegThreads / 64; ++w) carry = later_if_less(carry, wave_tot[w]);
-            __syncthreads();  // wave_tot is rewritten by the next tile
         }
     }
 }
@@ -246,8 +287,23 @@ pardtw_status segment_ends_launch(const float* S, int64_t nf, int64_t m, int64_t
     PARDTW_HIP_TRY(hipGetDevice(&dev));
     PARDTW_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     segment_prepare<<<1, 1, 0, stream>>>(a.hdr);
-    const int64_t grid = nf < 2 * int64_t(cus) ? nf : 2 * int64_t(cus);
-    segment_scan_kernel<<<unsigned(grid), kSegThreads, 0, stream>>>(a);
+    // Rows of a block hand over through LDS while the previous row's needed
+    // columns lie in its last two tiles; NSDTW rows are independent. A block
+    // of R rows makes the chain nf/R handoffs long (about 8 us each) but does
+    // tiles x R row-tiles one after another (about 2 us each): R near
+    // sqrt(nf * 8 / (2 * tiles)) balances the two (8 at 1000 rows of 100000
+    // columns, 2 at 32 rows).
+    int rows_per_block = 1;
+    if (variant != PARDTW_WSDTW) {
+        rows_per_block = kSegRows;
+    } else if (hop < kSegTile) {
+        const double tiles = double(ceil_div(m, kSegTile));
+        const int r = int(__builtin_sqrt(double(nf) * 4.0 / tiles) + 0.5);
+        rows_per_block = r < 1 ? 1 : r > kSegRows ? kSegRows : r;
+    }
+    const int64_t blocks = ceil_div(nf, rows_per_block);
+    const int64_t grid2 = blocks < 2 * int64_t(cus) ? blocks : 2 * int64_t(cus);
+    segment_scan_kernel<<<unsigned(grid2), kSegThreads, 0, stream>>>(a, rows_per_block);
     segment_ends_kernel<<<1, 64, 0, stream>>>(a, ends, total, status);
     return launch_status();
 }
