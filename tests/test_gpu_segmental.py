@@ -401,3 +401,42 @@ def test_segmental_fused_plan_bit_identical(la, lb, nf, variant):
     assert np.array_equal(np.isinf(S0), np.isinf(S1)) and np.array_equal(S0[np.isfinite(S0)], S1[np.isfinite(S1)])
     # no cost matrix (when some fragment is swept at all)
     assert w1 < w0 or s0 == pd.PAIR_INFEASIBLE
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_segmental_graph_capture_replays(fused):
+    """pardtw_segmental_align captured in a hipGraph: every replay, with eager
+    work and clobbered outputs in between, gives the eager result."""
+    la, lb, nf = 1500, 1800, 8
+    (A, B), _ = _pair(77, la, lb)
+    Ad, Bd = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+    plan = pd.SegPlan(la, lb, nf, 12, pd.PREC_F32, pd.WSDTW, fused)
+    buf = plan.buffers(DEV)
+    plan.align(Ad, Bd, buf)
+    torch.cuda.synchronize()
+    L = int(buf["path_len"].item())
+    ref = (float(buf["total"].item()), buf["ends"].cpu().numpy(), buf["path"][:L].cpu().numpy())
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.align(Ad, Bd, buf)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.align(Ad, Bd, buf)
+    other = pd.SegPlan(400, 600, 3, 12)
+    obuf = other.buffers(DEV)
+    (A2, B2), _ = _pair(78, 400, 600)
+    for rep in range(3):
+        buf["total"].fill_(-1.0)
+        buf["ends"].fill_(-7)
+        buf["path"].fill_(-3)
+        buf["path_len"].fill_(0)
+        other.align(torch.from_numpy(A2).to(DEV), torch.from_numpy(B2).to(DEV), obuf)
+        g.replay()
+        torch.cuda.synchronize()
+        L2 = int(buf["path_len"].item())
+        assert L2 == L and float(buf["total"].item()) == ref[0], rep
+        assert np.array_equal(buf["ends"].cpu().numpy(), ref[1]), rep
+        assert np.array_equal(buf["path"][:L].cpu().numpy(), ref[2]), rep
