@@ -182,6 +182,46 @@ pardtw_status pardtw_backtrace(const uint8_t* bp, int64_t n, int64_t m, const in
 pardtw_status pardtw_bp_unpack(const uint8_t* bp, int64_t n, int64_t m, int8_t* out,
                                hipStream_t stream);
 
+/* Checkpointed DTW: the exact path without the n x m code matrix, for pairs
+ * whose codes would not fit in memory (Sec. II-D names memory as the limit on
+ * length and cites a divide-and-conquer recomputation as the way past it).
+ * Memory is 8 m / K bytes per row of X (checkpoints) instead of m (codes);
+ * the recomputation adds about n K cells to the sweep's n m.
+ *
+ * pardtw_dp_fused_ckpt: the fused DP (pardtw_dp_fused's arithmetic, so the
+ * same total and status bits) writing no codes; instead the FP32 D of rows
+ * bK-2 and bK-1 for every b >= 1 with bK < n, each row over ceil(m/64)*64
+ * columns (columns past m hold junk), into
+ *   ckpt [device, >= pardtw_ckpt_bytes(n, m, K) bytes, 4-byte aligned],
+ *   checkpoint row 2(b-1) = row bK-2, row 2(b-1)+1 = row bK-1.
+ *   rows_per_block K: a multiple of 16 in [16, 256]
+ *   (PARDTW_ERR_INVALID_ARG otherwise).
+ *   X, Y, d, total, pair_status, workspace: as pardtw_dp_fused.
+ * Only band cells of a checkpoint row (on some path from (0,0) to
+ * (n-1,m-1)) are specified; other cells hold +inf or junk.
+ * PARDTW_ERR_WORKSPACE if ckpt or workspace is missing or short.
+ *
+ * pardtw_ckpt_backtrace: the path, from pardtw_dp_fused_ckpt's checkpoints
+ * with the same X, Y and K. One workgroup recomputes, block by block from the
+ * last, the codes of the cells the path can reach in the block, with the
+ * sweep's own instructions, and follows them: path and path_len are
+ * identical to pardtw_dp_fused (or pardtw_cost + pardtw_dp) followed by
+ * pardtw_backtrace.
+ *   path [device, 2*min(n,m) int32], path_len [device, 1 int32]: as
+ *   pardtw_backtrace (0 if pair_status is not PARDTW_PAIR_OK).
+ * Both run on `stream` without host synchronisation or allocation. */
+size_t pardtw_ckpt_bytes(int64_t n, int64_t m, int32_t rows_per_block);
+
+pardtw_status pardtw_dp_fused_ckpt(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
+                                   int32_t rows_per_block, float* ckpt, size_t ckpt_bytes, float* total,
+                                   int32_t* pair_status, void* workspace, size_t workspace_bytes,
+                                   hipStream_t stream);
+
+pardtw_status pardtw_ckpt_backtrace(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
+                                    int32_t rows_per_block, const float* ckpt, size_t ckpt_bytes,
+                                    const int32_t* pair_status, int32_t* path, int32_t* path_len,
+                                    hipStream_t stream);
+
 /* a6: gradient of g * J with the optimal path held fixed (the paper motivates
  * backpropagating through the optimal alignment path, Sec. I):
  *   J = sum over path cells (i,j) of w_ij * C[i,j], w = 1 at (0,0), else the

@@ -1,0 +1,362 @@
+// Checkpointed backtrace: the exact DTW path without the n x m code matrix,
+// for lengths whose codes would not fit in memory. Sec. II-D cites the
+// divide-and-conquer answer to the same limit (linear memory, cost recomputed);
+// this is its two-level form, sized for one GPU's HBM.
+//
+// Forward: the fused DP (costs computed in the sweep) stores no codes, only D
+// of the two rows before every block of K rows (pardtw_dp_fused_ckpt, in
+// dp.hip): 8 m / K bytes per row instead of m.
+//
+// Backward (here): one workgroup walks the blocks from the last. A path cell
+// (ie, je) in block [r0, r0 + K) reaches row r at a column in
+// [je - 2(ie - r), je], since every step moves one or two columns per row.
+// That trapezoid holds every predecessor of its cells down to row r0, and the
+// two checkpoint rows above r0 hold the rest, so recomputing D over it from
+// those rows gives every cell on the path the D, and so the code, of the full
+// sweep. The recomputation runs the sweep's own instructions: the row step of
+// dp_step.h, one wave per 64-column panel with the same boundary handoff, and
+// the same MFMA slab for the costs (cost_slab.h). Its 2-bit codes stay in LDS,
+// and wave 0 follows them until the path leaves the block; the cell it
+// leaves to starts the next block.
+//
+// Work: the trapezoids cover about K^2 cells per block, n K in all, against
+// n m for the sweep; memory: the checkpoints, 8 n m / K bytes.
+#include "dp_step.h"
+#include "trace.h"
+
+namespace pardtw {
+namespace {
+
+constexpr int kCkGroups = kCkMaxRows / kChunk;         // 8-row groups of a block
+constexpr int kCkPanels = 2 * kCkMaxRows / kPanel + 2;  // panels a window can span
+constexpr int kCkCols = kCkPanels * kPanel;
+constexpr int kCkThreads = kCkPanels * kLanes;          // one wave per window panel
+
+struct CkShared {
+    alignas(16) float xs[kCkMaxRows][16];  // the block's feature rows, zero past n and d
+    alignas(16) float rx[kCkMaxRows];      // their inverse norms, zero past n
+    // per wave: the costs of one 16-row slab, two chunks in the sweep's ring layout
+    alignas(16) float tr[kCkPanels][2][kChunk * kLanes];
+    // ring[w][k][c][r] = D[r0 + 8k + r][64(plo + w) + 62 + c]
+    float ring[kCkPanels][kCkGroups][2][kChunk];
+    // codes[k][cc]: 2 bits per row (row r0 + 8k + r at bits 2r) of column 64 plo + cc
+    uint16_t codes[kCkGroups][kCkCols];
+    int prog[kCkPanels];  // chunks wave w has published
+    int ie, je, len, fail;
+};
+
+struct CkArgs {
+    const float* X;
+    const float* Y;
+    int64_t n, m, d;
+    int K;
+    const float* ckpt;
+    int64_t stride;  // floats per checkpoint row
+    const int32_t* status;
+    int32_t* path;
+    int32_t* path_len;
+};
+
+// Eight 1-byte codes (two words, code r in byte r) to 2 bits each.
+__device__ inline uint32_t compact4(uint32_t x) {
+    x = (x | (x >> 6)) & 0x000F000Fu;
+    return (x | (x >> 12)) & 0xFFu;
+}
+
+// The window of block [r0, ie] ending at column je, on wave `wave` (panel plo + wave).
+__device__ void window_wave(const CkArgs& a, CkShared& sh, int wave, int r0, int ie, int je, int plo, int nch) {
+    const int lane = threadIdx.x & 63;
+    const int p = plo + wave;
+    const float kInf = __builtin_inff();
+    float bv[4][4], ry[4];
+    panel_operands_f32_small(a.Y, a.m, a.d, p, bv, ry);
+    // D[r0-1][j] and D[r0-2][j-1]; the left boundary D[r0-1][64p-2], D[r0-1][64p-1].
+    // The first wave's left boundary is never needed: its columns lie left of
+    // every predecessor of a window cell.
+    float d1 = kInf, s1p = kInf, e0 = kInf, e1 = kInf;
+    const int64_t col = int64_t(p) * kPanel + lane;
+    if (r0 > 0) {
+        const float* c2 = a.ckpt + int64_t(2 * (r0 / a.K - 1)) * a.stride;  // row r0 - 2
+        const float* c1 = c2 + a.stride;                                     // row r0 - 1
+        d1 = c1[col];
+        s1p = col >= 1 ? c2[col - 1] : kInf;
+        if (wave > 0) {
+            e0 = c1[col - lane - 2];
+            e1 = c1[col - lane - 1];
+        }
+    }
+    // the panel holds window cells on rows r0 .. rmax only
+    const int over = je - (p * kPanel + kPanel - 1);
+    const int rmax = over > 0 ? ie - (over + 1) / 2 : ie;
+    const int kend = rmax >= r0 ? (rmax - r0) / kChunk : -1;
+    const bool origin = r0 == 0 && p == 0 && lane == 0;
+    const int kq = lane >> 5, half = (lane >> 4) & 1, tcol = lane & 15;
+    int left_seen = 0;
+    for (int k = 0; k <= kend; ++k) {
+        if ((k & 1) == 0) {
+            // rows r0 + 8k .. r0 + 8k + 15: the sweep's slab (r0 is a multiple of 16)
+            const int rs = kChunk * k;
+            float av[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) av[t] = sh.xs[rs + (lane & 15)][4 * t + (lane >> 4)];
+            const f32x4 rx4 = *reinterpret_cast<const f32x4*>(&sh.rx[rs + 4 * (lane >> 4)]);
+            f32x4 acc[4], v[4];
+            slab_acc_f32_small(av, bv, acc);
+            costs_from_acc_rx(acc, rx4, ry, v);
+            float* dst = &sh.tr[wave][kq][half * (kLanes * 4)];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) *reinterpret_cast<f32x4*>(dst + (b * 16 + tcol) * 4) = v[b];
+            compiler_order();
+        }
+        float cb[kChunk];
+        {
+            const f32x4* src = reinterpret_cast<const f32x4*>(&sh.tr[wave][k & 1][0]) + lane;
+            const f32x4 v0 = src[0], v1 = src[kLanes];
+            cb[0] = v0[0]; cb[1] = v0[1]; cb[2] = v0[2]; cb[3] = v0[3];
+            cb[4] = v1[0]; cb[5] = v1[1]; cb[6] = v1[2]; cb[7] = v1[3];
+        }
+        if (k == 0 && origin) s1p = -2.0f * cb[0];  // D[0][0] = C[0][0], as in the sweep
+        float lv0[kChunk], lv1[kChunk];
+        if (wave > 0) {
+            while (left_seen <= k) {
+                left_seen = lds_get(&sh.prog[wave - 1]);
+                if (left_seen <= k) __builtin_amdgcn_s_sleep(1);
+            }
+            compiler_order();
+#pragma unroll
+            for (int r = 0; r < kChunk; ++r) {
+                lv0[r] = sh.ring[wave - 1][k][0][r];
+                lv1[r] = sh.ring[wave - 1][k][1][r];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < kChunk; ++r) lv0[r] = lv1[r] = kInf;
+        }
+        uint32_t lo, hi;
+        float best_r[kChunk];
+        dp_rows<false>(cb, lv0, lv1, e0, e1, d1, s1p, lo, hi, best_r);
+        if (k == 0 && origin) lo = (lo & ~0xffu) | 3u;
+        e0 = lv0[kChunk - 1];
+        e1 = lv1[kChunk - 1];
+        sh.codes[k][wave * kPanel + lane] = uint16_t(compact4(lo) | (compact4(hi) << 8));
+        if (lane >= kLanes - 2) {
+#pragma unroll
+            for (int r = 0; r < kChunk; ++r) sh.ring[wave][k][lane - (kLanes - 2)][r] = best_r[r];
+        }
+        compiler_order();
+        lds_put(&sh.prog[wave], k + 1);
+    }
+    // rows past kend hold no window cell of this panel: its right neighbour
+    // may read whatever its ring holds there
+    compiler_order();
+    lds_put(&sh.prog[wave], nch);
+}
+
+// Wave 0: follows the codes from (i, j) until the path leaves rows r0 .. ie
+// or reaches the origin. While 32 rows of the block lie at or above i, the
+// window trace resolves rows i-31 .. i of columns j .. j-63 (lane b: column
+// j - b) at once; near the block's first row (and the origin) a scalar loop
+// steps through 16 rows at a time with readlane.
+__device__ void walk_block(const CkArgs& a, CkShared& sh, int r0, int plo, int cap) {
+    const int lane = threadIdx.x & 63;
+    // uniform state: scalar registers, so each step is a readlane and a few
+    // scalar operations
+    int i = __builtin_amdgcn_readfirstlane(sh.ie);
+    int j = __builtin_amdgcn_readfirstlane(sh.je);
+    int len = __builtin_amdgcn_readfirstlane(sh.len);
+    bool done = false, fail = false;
+    const int cbase = plo * kPanel;
+    while (i >= r0 && !done) {
+        const int rr = i - r0;
+        if (rr >= 31 && (r0 > 0 || i >= 33)) {
+            // rows rr-31 .. rr: groups g0 .. g0+4, row x at bit 2(x - 8 g0) of
+            // lo and 2(x - 8 g0) - 16 of hi
+            const int g0 = (rr - 31) >> 3;
+            const int cc = j - lane - cbase;
+            uint32_t w[5];
+#pragma unroll
+            for (int t = 0; t < 5; ++t) {
+                const int g = g0 + t;
+                w[t] = (cc >= 0 && g <= (rr >> 3)) ? uint32_t(sh.codes[g][cc]) : 0u;
+            }
+            const int s2 = 2 * (rr - 8 * g0);  // in [62, 76]
+            const uint64_t lo = uint64_t(w[0]) | (uint64_t(w[1]) << 16) | (uint64_t(w[2]) << 32) |
+                                (uint64_t(w[3]) << 48);
+            const uint64_t hi = uint64_t(w[1]) | (uint64_t(w[2]) << 16) | (uint64_t(w[3]) << 32) |
+                                (uint64_t(w[4]) << 48);
+            const WindowMasks wm = window_masks(uint32_t(hi >> (s2 - 46)), uint32_t(lo >> (s2 - 62)));
+            const uint32_t on = trace_window(wm, lane);
+            if (__builtin_amdgcn_ballot_w64((on & wm.two_cols & wm.two_rows) != 0)) {  // an origin code
+                fail = true;
+                break;
+            }
+            const uint64_t has = __builtin_amdgcn_ballot_w64(on != 0);  // lane 0 holds the start cell
+            const int cnt = __builtin_popcountll(has);
+            const int last = 63 - __builtin_clzll(has);
+            const int la = __builtin_clz(uint32_t(__builtin_amdgcn_readlane(int(on), last)));
+            const int da = la + 1 + int((uint32_t(__builtin_amdgcn_readlane(int(wm.two_rows), last)) >> (31 - la)) & 1u);
+            const int db = last + 1 + int((uint32_t(__builtin_amdgcn_readlane(int(wm.two_cols), last)) >> (31 - la)) & 1u);
+            if (da < 32 || len + cnt > cap) {  // the trace did not leave the 32 rows
+                fail = true;
+                break;
+            }
+            if (on != 0) {
+                const int idx = int(__builtin_amdgcn_mbcnt_hi(uint32_t(has >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo(uint32_t(has), 0u)));
+                const int64_t pos = int64_t(cap) - 1 - (len + idx);
+                a.path[2 * pos] = i - __builtin_clz(on);
+                a.path[2 * pos + 1] = j - lane;
+            }
+            len += cnt;
+            i -= da;
+            j -= db;
+            continue;
+        }
+        const int g0 = (rr - 15) >> 3;  // floor; the groups g0 .. g0 + 2 hold rows rr - 15 .. rr
+        const int cc = j - lane - cbase;
+        uint32_t w[3] = {0u, 0u, 0u};
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int g = g0 + t;
+            if (cc >= 0 && g >= 0 && g <= (rr >> 3)) w[t] = sh.codes[g][cc];
+        }
+        const uint64_t V = uint64_t(w[0]) | (uint64_t(w[1]) << 16) | (uint64_t(w[2]) << 32);
+        // row rr sits at bit 2(rr - 8 g0), in [30, 44]; rows rr .. rr-15 go to bits 30 .. 0
+        const uint32_t packed = uint32_t(V >> (2 * (rr - 8 * g0) - 30));
+        int off = 30, b = 0;
+        while (i >= r0 && off >= 0 && b < kLanes) {
+            if (len >= cap || j < 0) {
+                fail = true;
+                break;
+            }
+            const uint32_t c = (uint32_t(__builtin_amdgcn_readlane(int(packed), b)) >> off) & 3u;
+            if (lane == 0) {
+                const int64_t pos = int64_t(cap) - 1 - len;
+                a.path[2 * pos] = i;
+                a.path[2 * pos + 1] = j;
+            }
+            ++len;
+            if (c == 3u) {
+                fail = i != 0 || j != 0;
+                done = true;
+                break;
+            }
+            const int da = 1 + int(c >> 1), db = 1 + int(c & 1u);
+            i -= da;
+            j -= db;
+            off -= 2 * da;
+            b += db;
+        }
+        if (fail) break;
+    }
+    if (!done && !fail && i < 0) fail = true;
+    if (lane == 0) {
+        sh.ie = (done || fail) ? -1 : i;
+        sh.je = j;
+        sh.len = len;
+        sh.fail = fail ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(kCkThreads) void ckpt_backtrace_kernel(CkArgs a) {
+    __shared__ CkShared sh;
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int cap = int(a.n < a.m ? a.n : a.m);
+    if (*a.status != PARDTW_PAIR_OK) {
+        if (tid == 0) *a.path_len = 0;
+        return;
+    }
+    if (tid == 0) {
+        sh.ie = int(a.n - 1);
+        sh.je = int(a.m - 1);
+        sh.len = 0;
+        sh.fail = 0;
+    }
+    for (int e = tid; e < kCkPanels * kCkGroups * 2 * kChunk; e += kCkThreads)
+        (&sh.ring[0][0][0][0])[e] = __builtin_inff();
+    __syncthreads();
+    for (;;) {
+        const int ie = __builtin_amdgcn_readfirstlane(sh.ie);
+        const int je = __builtin_amdgcn_readfirstlane(sh.je);
+        if (ie < 0) break;
+        const int r0 = ie - ie % a.K;
+        const int A = ie - r0;
+        const int nch = A / kChunk + 1;  // chunks holding rows r0 .. ie
+        const int cl = je - 2 * A - 2;   // leftmost column a window cell reads
+        const int plo = cl > 0 ? cl / kPanel : 0;
+        const int phi = je / kPanel;
+        const int xrows = 16 * ((nch + 1) / 2);  // whole slabs
+        for (int e = tid; e < xrows * 16; e += kCkThreads) {
+            const int rr = e >> 4, k = e & 15;
+            const int64_t row = r0 + rr;
+            sh.xs[rr][k] = (row < a.n && k < a.d) ? a.X[row * a.d + k] : 0.0f;
+        }
+        for (int rr = tid; rr < xrows; rr += kCkThreads)
+            sh.rx[rr] = row_inv_norm_f32_small(a.X, a.n, a.d, r0 + rr);
+        if (tid < kCkPanels) sh.prog[tid] = 0;
+        __syncthreads();
+        if (plo + wave <= phi) window_wave(a, sh, wave, r0, ie, je, plo, nch);
+        __syncthreads();
+        if (wave == 0) walk_block(a, sh, r0, plo, cap);
+        __syncthreads();
+    }
+    // the path was written backwards from entry cap-1: move it to the front
+    const int len = sh.fail ? 0 : sh.len;
+    const int64_t base = int64_t(cap) - len;
+    int2* pp = reinterpret_cast<int2*>(a.path);
+    constexpr int kPer = 8;
+    for (int64_t q0 = 0; q0 < len; q0 += int64_t(kCkThreads) * kPer) {
+        int2 v[kPer];
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+            const int64_t q = q0 + t * kCkThreads + tid;
+            if (q < len) v[t] = pp[base + q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+            const int64_t q = q0 + t * kCkThreads + tid;
+            if (q < len) pp[q] = v[t];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *a.path_len = len;
+}
+
+}  // namespace
+}  // namespace pardtw
+
+extern "C" size_t pardtw_ckpt_bytes(int64_t n, int64_t m, int32_t rows_per_block) {
+    if (!pardtw::valid_sizes(n, m) || rows_per_block < 16 || rows_per_block > pardtw::kCkMaxRows ||
+        rows_per_block % 16)
+        return 0;
+    return size_t(pardtw::ckpt_floats(n, m, rows_per_block)) * sizeof(float);
+}
+
+extern "C" pardtw_status pardtw_ckpt_backtrace(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
+                                               int32_t rows_per_block, const float* ckpt, size_t ckpt_bytes,
+                                               const int32_t* pair_status, int32_t* path, int32_t* path_len,
+                                               hipStream_t stream) {
+    if (!X || !Y || !pair_status || !path || !path_len || !pardtw::valid_sizes(n, m) || d <= 0)
+        return PARDTW_ERR_INVALID_ARG;
+    if (d > 16) return PARDTW_ERR_UNSUPPORTED;
+    if (rows_per_block < 16 || rows_per_block > pardtw::kCkMaxRows || rows_per_block % 16)
+        return PARDTW_ERR_INVALID_ARG;
+    const int64_t floats = pardtw::ckpt_floats(n, m, rows_per_block);
+    if (floats > 0 && (!ckpt || ckpt_bytes < size_t(floats) * sizeof(float))) return PARDTW_ERR_WORKSPACE;
+    pardtw::CkArgs a;
+    a.X = X;
+    a.Y = Y;
+    a.n = n;
+    a.m = m;
+    a.d = d;
+    a.K = rows_per_block;
+    a.ckpt = ckpt;
+    a.stride = pardtw::num_panels(m) * pardtw::kPanel;
+    a.status = pair_status;
+    a.path = path;
+    a.path_len = path_len;
+    pardtw::ckpt_backtrace_kernel<<<1, pardtw::kCkThreads, 0, stream>>>(a);
+    return pardtw::launch_status();
+}

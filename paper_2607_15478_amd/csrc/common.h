@@ -85,6 +85,14 @@ __host__ __device__ inline int64_t sub_group_hi(int64_t p, int64_t n, int64_t m)
 // end; rows past n hold zeros.
 __host__ __device__ inline int64_t rx_floats(int64_t n) { return (ceil_div(bp_groups(n), 2) + 5) * 16; }
 
+// Checkpointed backtrace with blocks of K rows: D of rows bK-2 and bK-1 for
+// every block b > 0, each row over all panel columns.
+__host__ __device__ inline int64_t ckpt_count(int64_t n, int64_t K) { return (n - 1) / K; }
+__host__ __device__ inline int64_t ckpt_floats(int64_t n, int64_t m, int64_t K) {
+    return 2 * ckpt_count(n, K) * num_panels(m) * kPanel;
+}
+constexpr int kCkMaxRows = 256;  // the largest block the backtrace's window holds in LDS
+
 // Some end column of row n-1 is reachable from row 0.
 inline bool subseq_feasible(int64_t n, int64_t m) { return n - 1 <= 2 * (m - 1); }
 

@@ -46,11 +46,11 @@
 // cell (the codes) and its costs are bit for bit those of the GEMM.
 #include "batch.h"
 #include "cost_slab.h"
+#include "dp_step.h"
 
 namespace pardtw {
 namespace {
 
-constexpr int kChunk = kBpRows;  // rows per synchronisation chunk (= packed group)
 constexpr int kRing = 32;        // LDS ring depth, in chunks
 constexpr int kPfPanel = 4;      // cost prefetch distance in chunks, panel layout (4 measured best of 2-16)
 constexpr int kPfRow = 4;        // the same for the row-major layout (8 loads per chunk)
@@ -60,7 +60,10 @@ constexpr int kMaxNWFused = 4;   // fused workgroups: NW compute + NW producer +
 constexpr int kCRing = 8;        // fused cost ring depth, in chunks (2 KB each)
 
 // Where the DP's costs come from.
-enum CostSrc { kSrcRow = 0, kSrcPanel = 1, kSrcFused = 2 };
+// kSrcFusedCk: fused costs, no codes, and D of the last two rows of every
+// block of rows saved for the checkpointed backtrace.
+enum CostSrc { kSrcRow = 0, kSrcPanel = 1, kSrcFused = 2, kSrcFusedCk = 3 };
+constexpr bool is_fused(int src) { return src == kSrcFused || src == kSrcFusedCk; }
 
 // Fused cost: per compute wave a ring of cost chunks in the panel layout
 // (rows 0-3 of the 64 columns, then rows 4-7), and its progress counters.
@@ -82,21 +85,7 @@ struct DpShared {
     int isink[kMaxNW][kLanes];
 };
 
-__device__ inline int lds_get(const int* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ inline void lds_put(int* p, int v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-// LDS operations of one wave are performed in issue order; this only stops the
-// compiler from moving memory accesses across the point.
-__device__ inline void compiler_order() { asm volatile("" ::: "memory"); }
 
-// lane l receives lane l-1's value; lane 0 receives `edge`.
-__device__ inline float shift_in(float v, float edge) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v),
-                                                      0x138 /* wave_shr:1 */, 0xf, 0xf, false));
-}
 
 struct DpArgs {
     const float* C;
@@ -113,6 +102,12 @@ struct DpArgs {
     int64_t G;      // 8-row groups per panel
     int P;          // number of panels
     int S;          // number of panel groups (= ceil(P / NW))
+    // kSrcFusedCk: D of rows (q+1)K-2 and (q+1)K-1 for q < ck_count, stored at
+    // ckpt[(2q + t) * ck_stride + column], K = 8 * ck_chunks
+    float* ckpt;
+    int ck_chunks;
+    int ck_count;
+    int64_t ck_stride;
 };
 
 // Loads chunk k of panel p into cb. Every call issues the same loads: when
@@ -173,32 +168,6 @@ __device__ inline ChunkRanges chunk_ranges(int p, int64_t n, int64_t m, int64_t 
     return r;
 }
 
-// One 8-row chunk of a panel. `lv0/lv1` hold the left boundary columns
-// D[i0+r][64p-2] / D[i0+r][64p-1]; e0/e1 the same for row i0-1.
-template <bool SUB>
-__device__ __attribute__((always_inline)) inline void dp_rows(const float (&cb)[kChunk], const float (&lv0)[kChunk],
-                                                              const float (&lv1)[kChunk], float e0, float e1,
-                                                              float& d1, float& s1p, uint32_t& lo, uint32_t& hi,
-                                                              float (&best_r)[kChunk]) {
-    lo = 0;
-    hi = 0;
-#pragma unroll
-    for (int r = 0; r < kChunk; ++r) {
-        const float c = cb[r];
-        const float s1 = shift_in(d1, r == 0 ? e1 : lv1[r - 1]);  // D[i-1][j-1]
-        const float s2 = shift_in(s1, r == 0 ? e0 : lv0[r - 1]);  // D[i-1][j-2]
-        const float c0 = __builtin_fmaf(SUB ? 1.0f : 2.0f, c, s1);
-        const float c1 = __builtin_fmaf(SUB ? 1.0f : 3.0f, c, s2);
-        const float c2 = __builtin_fmaf(SUB ? 2.0f : 3.0f, c, s1p);
-        const float best = __builtin_fminf(__builtin_fminf(c0, c1), c2);
-        uint32_t code = (c1 == best) ? 1u : 2u;
-        code = (c0 == best) ? 0u : code;
-        if (r < 4) lo |= code << (8 * r); else hi |= code << (8 * (r - 4));
-        d1 = best;
-        s1p = s1;
-        best_r[r] = best;
-    }
-}
 
 // A compute wave owns panel p. Whether it feeds a right neighbour is a runtime
 // value made opaque to the optimiser and only gates a rare wait, so every role
@@ -234,7 +203,10 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
     float* rout = &sh.ring[wave + 1][0][0][0];
     int flags = __builtin_amdgcn_readfirstlane(have_out ? 2 : 0);
 
-    constexpr bool kFused = SRC == kSrcFused;
+    constexpr bool kFused = is_fused(SRC);
+    constexpr bool kCk = SRC == kSrcFusedCk;
+    int ck_next = kCk ? a.ck_chunks - 1 : 0;  // the next chunk that ends a block of rows
+    int ck_q = 0;
     constexpr int kPf = kFused ? 1 : SRC == kSrcPanel ? kPfPanel : kPfRow;
     float cbuf[kPf][kChunk];
     int cprog_seen = 0;
@@ -313,8 +285,20 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
             e0 = lv0[kChunk - 1];
             e1 = lv1[kChunk - 1];
 
-            uint64_t* cdst = inside ? bp_pan + int64_t(k) * kLanes : a.hdr->sink;
-            __builtin_nontemporal_store(uint64_t(lo) | (uint64_t(hi) << 32), cdst + lane);
+            if constexpr (kCk) {
+                // no codes; rows 6 and 7 of a chunk that ends a block are the
+                // two rows the block after it starts from
+                if (k == ck_next && ck_q < a.ck_count) {
+                    float* dst = a.ckpt + int64_t(2 * ck_q) * a.ck_stride + int64_t(p) * kPanel + lane;
+                    dst[0] = best_r[kChunk - 2];
+                    dst[a.ck_stride] = best_r[kChunk - 1];
+                    ++ck_q;
+                    ck_next += a.ck_chunks;
+                }
+            } else {
+                uint64_t* cdst = inside ? bp_pan + int64_t(k) * kLanes : a.hdr->sink;
+                __builtin_nontemporal_store(uint64_t(lo) | (uint64_t(hi) << 32), cdst + lane);
+            }
 
             // LDS operations complete in issue order. Drain this chunk's reads
             // (issued a whole chunk ago, so already done) before issuing the
@@ -537,7 +521,7 @@ __device__ __attribute__((always_inline)) inline void run_group(const DpArgs& a,
     if (wave < NW) {
         const int p = p0 + wave;
         if (p < a.P) compute_wave<SRC, SUB>(a, sh, cring, wave, p, p + 1 < a.P);
-    } else if (SRC == kSrcFused && wave >= NW + 2) {
+    } else if (is_fused(SRC) && wave >= NW + 2) {
         const int p = p0 + wave - (NW + 2);
         if (p < a.P) cost_producer(a, *cring, wave - (NW + 2), p, SUB);
     } else if (wave == NW) {
@@ -562,7 +546,7 @@ __device__ inline int next_ticket(DpShared& sh, CostRing* cring, DpWsHeader* hdr
     return __builtin_amdgcn_readfirstlane(sh.super);
 }
 
-constexpr int dp_waves(int nw, int src) { return src == kSrcFused ? 2 * nw + 2 : nw + 2; }
+constexpr int dp_waves(int nw, int src) { return is_fused(src) ? 2 * nw + 2 : nw + 2; }
 
 template <int NW, int SRC, bool SUB>
 __device__ __attribute__((always_inline)) inline void dp_body(const DpArgs& a, DpShared& sh, CostRing* cring) {
@@ -579,7 +563,7 @@ __device__ __attribute__((always_inline)) inline void dp_body(const DpArgs& a, D
 template <int NW, int SRC, bool SUB>
 __global__ __launch_bounds__(kLanes * dp_waves(NW, SRC)) void dp_kernel(DpArgs a) {
     __shared__ DpShared sh;
-    if constexpr (SRC == kSrcFused) {
+    if constexpr (is_fused(SRC)) {
         static_assert(NW <= kMaxNWFused, "fused workgroups hold at most kMaxNWFused compute waves");
         __shared__ CostRing cring;
         dp_body<NW, SRC, SUB>(a, sh, &cring);
@@ -634,6 +618,10 @@ __device__ __attribute__((always_inline)) inline void dp_batch_body(const DpBatc
         a.G = q.G;
         a.P = q.P;
         a.S = int(ceil_div(q.P, NW));
+        a.ckpt = nullptr;
+        a.ck_chunks = 1;
+        a.ck_count = 0;
+        a.ck_stride = 0;
         run_group<NW, SRC, SUB>(a, sh, cring, wave, it.group, epoch);
         __syncthreads();
     }
@@ -698,7 +686,10 @@ template <int NW>
 void launch_nw(const DpArgs& a, int src, bool sub, int grid, hipStream_t stream) {
     if (src == kSrcPanel) launch_src<NW, kSrcPanel>(a, sub, grid, stream);
     else if (src == kSrcRow) launch_src<NW, kSrcRow>(a, sub, grid, stream);
-    else if constexpr (NW <= kMaxNWFused) launch_src<NW, kSrcFused>(a, sub, grid, stream);
+    else if constexpr (NW <= kMaxNWFused) {
+        if (src == kSrcFused) launch_src<NW, kSrcFused>(a, sub, grid, stream);
+        else dp_kernel<NW, kSrcFusedCk, false><<<grid, kLanes * dp_waves(NW, kSrcFusedCk), 0, stream>>>(a);
+    }
 }
 
 template <int NW, int SRC>
@@ -771,7 +762,7 @@ pardtw_status row_norms_batch_launch(const BatchPair* pairs, int32_t batch, cons
 // src: the cost source (row-major or panel C, or fused from X, Y).
 pardtw_status dp_launch(const float* C, const float* X, const float* Y, int64_t d, int src, int64_t n, int64_t m,
                         uint8_t* bp, float* total, int32_t* status, void* ws, int nw_override, bool sub,
-                        hipStream_t stream) {
+                        hipStream_t stream, float* ckpt = nullptr, int ck_rows = 0) {
     DpArgs a;
     a.C = C;
     a.X = X;
@@ -796,7 +787,14 @@ pardtw_status dp_launch(const float* C, const float* X, const float* Y, int64_t 
     // about four compute waves per CU (one per SIMD)
     const int per_cu = nw >= 4 ? 1 : 4 / nw;
     const int grid = a.S < cus * per_cu ? a.S : cus * per_cu;
-    if (src == kSrcFused && nw > kMaxNWFused) return PARDTW_ERR_UNSUPPORTED;
+    if (is_fused(src) && nw > kMaxNWFused) return PARDTW_ERR_UNSUPPORTED;
+    if (src == kSrcFusedCk && (sub || ck_rows < 16 || ck_rows > kCkMaxRows || ck_rows % 16))
+        return PARDTW_ERR_INVALID_ARG;
+    a.ckpt = ckpt;
+    a.ck_chunks = ck_rows > 0 ? ck_rows / kChunk : 1;
+    a.ck_count = src == kSrcFusedCk ? int(ckpt_count(n, ck_rows)) : 0;
+    if (a.ck_count > 0 && !ckpt) return PARDTW_ERR_INVALID_ARG;
+    a.ck_stride = int64_t(a.P) * kPanel;
     if (sub ? !subseq_feasible(n, m) : !pair_feasible(n, m)) {
         const int64_t count = sub ? m : 1;
         const unsigned blocks = unsigned(count < 256 * 1024 ? ceil_div(count, 256) : 1024);
@@ -804,7 +802,7 @@ pardtw_status dp_launch(const float* C, const float* X, const float* Y, int64_t 
         return launch_status();
     }
     dp_prepare<<<1, 1, 0, stream>>>(a.hdr);
-    if (src == kSrcFused) {
+    if (is_fused(src)) {
         const int64_t len = rx_floats(n);
         const unsigned blocks = unsigned(len < 256 * 2048 ? ceil_div(len, 256) : 2048);
         row_norms_kernel<<<blocks, 256, 0, stream>>>(X, n, d, const_cast<float*>(a.rxs), len);
@@ -888,6 +886,21 @@ extern "C" pardtw_status pardtw_dp_fused(const float* X, const float* Y, int64_t
     if (st != PARDTW_OK) return st;
     return pardtw::dp_launch(nullptr, X, Y, d, pardtw::kSrcFused, n, m, bp, total, pair_status, workspace,
                              panels_per_workgroup, false, stream);
+}
+
+extern "C" pardtw_status pardtw_dp_fused_ckpt(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
+                                              int32_t rows_per_block, float* ckpt, size_t ckpt_bytes, float* total,
+                                              int32_t* pair_status, void* workspace, size_t workspace_bytes,
+                                              hipStream_t stream) {
+    if (!X || !Y || !total || !pair_status || !pardtw::valid_sizes(n, m) || d <= 0) return PARDTW_ERR_INVALID_ARG;
+    if (d > 16) return PARDTW_ERR_UNSUPPORTED;
+    if (rows_per_block < 16 || rows_per_block > pardtw::kCkMaxRows || rows_per_block % 16)
+        return PARDTW_ERR_INVALID_ARG;
+    const int64_t floats = pardtw::ckpt_floats(n, m, rows_per_block);
+    if (floats > 0 && (!ckpt || ckpt_bytes < size_t(floats) * sizeof(float))) return PARDTW_ERR_WORKSPACE;
+    if (!workspace || workspace_bytes < pardtw::dp_workspace_bytes_impl(n, m)) return PARDTW_ERR_WORKSPACE;
+    return pardtw::dp_launch(nullptr, X, Y, d, pardtw::kSrcFusedCk, n, m, nullptr, total, pair_status, workspace, 0,
+                             false, stream, ckpt, rows_per_block);
 }
 
 extern "C" pardtw_status pardtw_subseq_dp_fused(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,

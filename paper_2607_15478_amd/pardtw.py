@@ -60,6 +60,9 @@ _lib_bt = _sig("pardtw_backtrace", _E, [_P, _I64, _I64, _P, _P, _P, _P])
 _lib_dp_fused = _sig("pardtw_dp_fused", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _SZ, _I32, _P])
 _lib_sub_dp_fused = _sig("pardtw_subseq_dp_fused", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _SZ, _P])
 _lib_unpack = _sig("pardtw_bp_unpack", _E, [_P, _I64, _I64, _P, _P])
+_lib_ckpt_bytes = _sig("pardtw_ckpt_bytes", _SZ, [_I64, _I64, _I32])
+_lib_dp_ckpt = _sig("pardtw_dp_fused_ckpt", _E, [_P, _P, _I64, _I64, _I64, _I32, _P, _SZ, _P, _P, _P, _SZ, _P])
+_lib_ckpt_bt = _sig("pardtw_ckpt_backtrace", _E, [_P, _P, _I64, _I64, _I64, _I32, _P, _SZ, _P, _P, _P, _P])
 _lib_grad = _sig("pardtw_path_grad", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P])
 _lib_plan_create = _sig("pardtw_plan_create_ex", _E, [_I32, _P, _P, _I64, _E, _I32, ctypes.POINTER(_P)])
 _lib_plan_ws = _sig("pardtw_plan_workspace_bytes", _SZ, [_P])
@@ -175,6 +178,40 @@ def pardtw_dp_fused(X: torch.Tensor, Y: torch.Tensor, bp: torch.Tensor, total: t
                          int(panels_per_workgroup), _stream(stream)), "pardtw_dp_fused")
 
 
+CKPT_MAX_ROWS = 256  # the largest block of rows the checkpointed backtrace's window holds
+
+
+def pardtw_ckpt_bytes(n: int, m: int, rows_per_block: int) -> int:
+    """Bytes of the checkpoint rows for blocks of `rows_per_block` rows (0 on bad args)."""
+    return int(_lib_ckpt_bytes(n, m, rows_per_block))
+
+
+def pardtw_dp_fused_ckpt(X: torch.Tensor, Y: torch.Tensor, rows_per_block: int, ckpt: torch.Tensor,
+                         total: torch.Tensor, status: torch.Tensor, workspace: torch.Tensor, stream=None):
+    """The fused DP writing no codes, only the D rows every block of rows starts from."""
+    _dev_f32(X, "X"), _dev_f32(Y, "Y")
+    n, d = X.shape
+    m = Y.shape[0]
+    ws_bytes = workspace.numel() * workspace.element_size()
+    ck_bytes = ckpt.numel() * ckpt.element_size()
+    _check(_lib_dp_ckpt(_ptr(X), _ptr(Y), n, m, d, int(rows_per_block), _ptr(ckpt) if ck_bytes else None, ck_bytes,
+                        _ptr(total), _ptr(status), _ptr(workspace), ws_bytes, _stream(stream)),
+           "pardtw_dp_fused_ckpt")
+
+
+def pardtw_ckpt_backtrace(X: torch.Tensor, Y: torch.Tensor, rows_per_block: int, ckpt: torch.Tensor,
+                          status: torch.Tensor, path: torch.Tensor, path_len: torch.Tensor, stream=None):
+    """The path from the checkpoints of pardtw_dp_fused_ckpt (same X, Y and rows_per_block)."""
+    _dev_f32(X, "X"), _dev_f32(Y, "Y")
+    n, d = X.shape
+    m = Y.shape[0]
+    if path.dtype != torch.int32 or path.numel() < 2 * min(n, m):
+        raise ValueError("path must be int32 with room for 2*min(n, m) entries")
+    ck_bytes = ckpt.numel() * ckpt.element_size()
+    _check(_lib_ckpt_bt(_ptr(X), _ptr(Y), n, m, d, int(rows_per_block), _ptr(ckpt) if ck_bytes else None, ck_bytes,
+                        _ptr(status), _ptr(path), _ptr(path_len), _stream(stream)), "pardtw_ckpt_backtrace")
+
+
 def pardtw_backtrace(bp: torch.Tensor, n: int, m: int, status: torch.Tensor, path: torch.Tensor,
                      path_len: torch.Tensor, stream=None):
     if path.dtype != torch.int32 or path.numel() < 2 * min(n, m):
@@ -201,11 +238,20 @@ def pardtw_path_grad(X, Y, path, path_len, g_total, dX, dY, stream=None):
 class Workspace:
     """Device buffers for one (n, m) alignment, reusable across calls."""
 
-    def __init__(self, n: int, m: int, device="cuda", layout: int = LAYOUT_PANEL_BAND, cost: bool = True):
+    def __init__(self, n: int, m: int, device="cuda", layout: int = LAYOUT_PANEL_BAND, cost: bool = True,
+                 ckpt_rows: int = 0):
         self.n, self.m, self.layout = n, m, layout
-        # no cost buffer when the DP computes the costs itself
+        # no cost buffer when the DP computes the costs itself; with ckpt_rows
+        # (checkpointed backtrace, fused cost) no codes either
+        self.ckpt_rows = int(ckpt_rows)
+        if self.ckpt_rows and cost:
+            raise ValueError("the checkpointed DP computes its costs itself (cost=False)")
         self.C = torch.empty(pardtw_cost_elems(n, m, layout) if cost else 0, dtype=torch.float32, device=device)
-        self.bp = torch.empty(pardtw_bp_bytes(n, m), dtype=torch.uint8, device=device)
+        self.bp = torch.empty(0 if self.ckpt_rows else pardtw_bp_bytes(n, m), dtype=torch.uint8, device=device)
+        if self.ckpt_rows and (self.ckpt_rows % 16 or not 16 <= self.ckpt_rows <= CKPT_MAX_ROWS):
+            raise ValueError(f"ckpt_rows must be a multiple of 16 in [16, {CKPT_MAX_ROWS}]")
+        ck_bytes = pardtw_ckpt_bytes(n, m, self.ckpt_rows) if self.ckpt_rows else 0
+        self.ckpt = torch.empty(ck_bytes // 4, dtype=torch.float32, device=device)
         self.ws = torch.zeros(pardtw_dp_workspace_bytes(n, m), dtype=torch.uint8, device=device)
         self.total = torch.empty(1, dtype=torch.float32, device=device)
         self.status = torch.empty(1, dtype=torch.int32, device=device)
@@ -218,6 +264,12 @@ def align_into(X: torch.Tensor, Y: torch.Tensor, w: Workspace, prec: int = PREC_
     """cost -> dp -> backtrace on the given stream, results left in w (with
     `fused`, the DP computes the costs itself and w.C is not used)."""
     n, m = X.shape[0], Y.shape[0]
+    if w.ckpt_rows:
+        if prec != PREC_F32:
+            raise ValueError("the checkpointed DP computes FP32 costs")
+        pardtw_dp_fused_ckpt(X, Y, w.ckpt_rows, w.ckpt, w.total, w.status, w.ws, stream)
+        pardtw_ckpt_backtrace(X, Y, w.ckpt_rows, w.ckpt, w.status, w.path, w.path_len, stream)
+        return w
     if fused:
         if prec != PREC_F32:
             raise ValueError("the fused DP computes FP32 costs")

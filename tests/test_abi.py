@@ -115,3 +115,31 @@ def test_validation_without_gpu(lib):
     lib.pardtw_status_string.restype = ctypes.c_char_p
     lib.pardtw_status_string.argtypes = [ctypes.c_int]
     assert lib.pardtw_status_string(2) == b"workspace missing or too small"
+
+
+def test_ckpt_sizes_and_validation_without_gpu(lib):
+    I, I32, SZ, P = ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t, ctypes.c_void_p
+    lib.pardtw_ckpt_bytes.restype = SZ
+    lib.pardtw_ckpt_bytes.argtypes = [I, I, I32]
+    n, m = 50000, 60000
+    # two FP32 rows of every panel column before each block but the first
+    assert lib.pardtw_ckpt_bytes(n, m, 256) == 2 * ((n - 1) // 256) * (-(-m // 64)) * 64 * 4
+    assert lib.pardtw_ckpt_bytes(256, 300, 256) == 0  # one block: nothing to keep
+    assert lib.pardtw_ckpt_bytes(257, 300, 256) == 2 * 1 * 320 * 4
+    for K in (0, 8, 17, 272, -16):
+        assert lib.pardtw_ckpt_bytes(n, m, K) == 0
+    lib.pardtw_dp_fused_ckpt.restype = ctypes.c_int
+    lib.pardtw_dp_fused_ckpt.argtypes = [P, P, I, I, I, I32, P, SZ, P, P, P, SZ, P]
+    lib.pardtw_ckpt_backtrace.restype = ctypes.c_int
+    lib.pardtw_ckpt_backtrace.argtypes = [P, P, I, I, I, I32, P, SZ, P, P, P, P]
+    f = ctypes.c_void_p(0x1000)
+    ws = lib.pardtw_dp_workspace_bytes(1000, 1000)
+    ck = lib.pardtw_ckpt_bytes(1000, 1000, 64)
+    assert lib.pardtw_dp_fused_ckpt(f, f, 1000, 1000, 12, 17, f, ck, f, f, f, ws, None) == 1  # K not a multiple of 16
+    assert lib.pardtw_dp_fused_ckpt(f, f, 1000, 1000, 17, 64, f, ck, f, f, f, ws, None) == 4  # d > 16
+    assert lib.pardtw_dp_fused_ckpt(f, f, 1000, 1000, 12, 64, f, ck - 4, f, f, f, ws, None) == 2  # short checkpoints
+    assert lib.pardtw_dp_fused_ckpt(f, f, 1000, 1000, 12, 64, f, ck, f, f, f, ws - 1, None) == 2  # short workspace
+    assert lib.pardtw_dp_fused_ckpt(None, f, 1000, 1000, 12, 64, f, ck, f, f, f, ws, None) == 1
+    assert lib.pardtw_ckpt_backtrace(f, f, 1000, 1000, 12, 512, f, ck, f, f, f, None) == 1
+    assert lib.pardtw_ckpt_backtrace(f, f, 1000, 1000, 12, 64, None, ck, f, f, f, None) == 2
+    assert lib.pardtw_ckpt_backtrace(f, f, 1000, 1000, 12, 64, f, ck, f, None, f, None) == 1
