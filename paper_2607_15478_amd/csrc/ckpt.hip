@@ -63,46 +63,84 @@ __device__ inline uint32_t compact4(uint32_t x) {
     return (x | (x >> 12)) & 0xFFu;
 }
 
+// A window wave's inputs, loaded at the start of a block together with the
+// feature rows: the panel's column operands and the D values it starts from,
+// D[r0-1][j] and D[r0-2][j-1], and the left boundary D[r0-1][64p-2],
+// D[r0-1][64p-1].
+struct WaveStart {
+    float bv[4][4], ry[4];
+    float d1, s1p, e0, e1;
+};
+
+__device__ __attribute__((always_inline)) inline void load_start(const CkArgs& a, int wave, int r0, int p,
+                                                                 WaveStart& w) {
+    const int lane = threadIdx.x & 63;
+    const float kInf = __builtin_inff();
+    panel_operands_f32_small(a.Y, a.m, a.d, p, w.bv, w.ry);
+    w.d1 = kInf;
+    w.s1p = kInf;
+    w.e0 = kInf;
+    w.e1 = kInf;
+    // The first wave's left boundary is never needed: its columns lie left of
+    // every predecessor of a window cell.
+    if (r0 > 0) {
+        const int64_t col = int64_t(p) * kPanel + lane;
+        const float* c2 = a.ckpt + int64_t(2 * (r0 / a.K - 1)) * a.stride;  // row r0 - 2
+        const float* c1 = c2 + a.stride;                                     // row r0 - 1
+        w.d1 = c1[col];
+        w.s1p = col >= 1 ? c2[col - 1] : kInf;
+        if (wave > 0) {
+            w.e0 = c1[col - lane - 2];
+            w.e1 = c1[col - lane - 1];
+        }
+    }
+}
+
 // The window of block [r0, ie] ending at column je, on wave `wave` (panel plo + wave).
-__device__ void window_wave(const CkArgs& a, CkShared& sh, int wave, int r0, int ie, int je, int plo, int nch) {
+__device__ void window_wave(CkShared& sh, const WaveStart& st, int wave, int r0, int ie, int je, int plo,
+                            int nch) {
     const int lane = threadIdx.x & 63;
     const int p = plo + wave;
     const float kInf = __builtin_inff();
-    float bv[4][4], ry[4];
-    panel_operands_f32_small(a.Y, a.m, a.d, p, bv, ry);
-    // D[r0-1][j] and D[r0-2][j-1]; the left boundary D[r0-1][64p-2], D[r0-1][64p-1].
-    // The first wave's left boundary is never needed: its columns lie left of
-    // every predecessor of a window cell.
-    float d1 = kInf, s1p = kInf, e0 = kInf, e1 = kInf;
-    const int64_t col = int64_t(p) * kPanel + lane;
-    if (r0 > 0) {
-        const float* c2 = a.ckpt + int64_t(2 * (r0 / a.K - 1)) * a.stride;  // row r0 - 2
-        const float* c1 = c2 + a.stride;                                     // row r0 - 1
-        d1 = c1[col];
-        s1p = col >= 1 ? c2[col - 1] : kInf;
-        if (wave > 0) {
-            e0 = c1[col - lane - 2];
-            e1 = c1[col - lane - 1];
-        }
-    }
-    // the panel holds window cells on rows r0 .. rmax only
+    float d1 = st.d1, s1p = st.s1p, e0 = st.e0, e1 = st.e1;
+    // The panel holds window cells on rows rmin .. rmax only: the cone's left
+    // edge je - 2(ie - r) passes the panel's last column at rmax, its right
+    // edge je - ceil((ie - r) / 2) its first column at rmin.
     const int over = je - (p * kPanel + kPanel - 1);
     const int rmax = over > 0 ? ie - (over + 1) / 2 : ie;
     const int kend = rmax >= r0 ? (rmax - r0) / kChunk : -1;
+    const int rmin = ie - 2 * (je - p * kPanel);
+    const int kbeg = rmin > r0 ? (rmin - r0) / kChunk : 0;
     const bool origin = r0 == 0 && p == 0 && lane == 0;
     const int kq = lane >> 5, half = (lane >> 4) & 1, tcol = lane & 15;
     int left_seen = 0;
-    for (int k = 0; k <= kend; ++k) {
-        if ((k & 1) == 0) {
-            // rows r0 + 8k .. r0 + 8k + 15: the sweep's slab (r0 is a multiple of 16)
-            const int rs = kChunk * k;
+    if (kbeg > 0 && kbeg <= kend) {
+        // Rows above chunk kbeg hold no window cell of this panel, so the window
+        // cells of its first rows take their predecessors from the panel to the
+        // left (wave > 0 here: the first panel starts at row r0): rows R-1 and
+        // R-2 of its last two columns, R = r0 + 8 kbeg.
+        while (left_seen < kbeg) {
+            left_seen = lds_get(&sh.prog[wave - 1]);
+            if (left_seen < kbeg) __builtin_amdgcn_s_sleep(1);
+        }
+        compiler_order();
+        e0 = sh.ring[wave - 1][kbeg - 1][0][kChunk - 1];
+        e1 = sh.ring[wave - 1][kbeg - 1][1][kChunk - 1];
+        const float sl = sh.ring[wave - 1][kbeg - 1][1][kChunk - 2];
+        d1 = kInf;
+        s1p = lane == 0 ? sl : kInf;
+    }
+    for (int k = kbeg; k <= kend; ++k) {
+        if ((k & 1) == 0 || k == kbeg) {
+            // rows r0 + 8(k & ~1) .. + 15: the sweep's slab (r0 is a multiple of 16)
+            const int rs = kChunk * (k & ~1);
             float av[4];
 #pragma unroll
             for (int t = 0; t < 4; ++t) av[t] = sh.xs[rs + (lane & 15)][4 * t + (lane >> 4)];
             const f32x4 rx4 = *reinterpret_cast<const f32x4*>(&sh.rx[rs + 4 * (lane >> 4)]);
             f32x4 acc[4], v[4];
-            slab_acc_f32_small(av, bv, acc);
-            costs_from_acc_rx(acc, rx4, ry, v);
+            slab_acc_f32_small(av, st.bv, acc);
+            costs_from_acc_rx(acc, rx4, st.ry, v);
             float* dst = &sh.tr[wave][kq][half * (kLanes * 4)];
 #pragma unroll
             for (int b = 0; b < 4; ++b) *reinterpret_cast<f32x4*>(dst + (b * 16 + tcol) * 4) = v[b];
@@ -153,101 +191,71 @@ __device__ void window_wave(const CkArgs& a, CkShared& sh, int wave, int r0, int
 }
 
 // Wave 0: follows the codes from (i, j) until the path leaves rows r0 .. ie
-// or reaches the origin. While 32 rows of the block lie at or above i, the
-// window trace resolves rows i-31 .. i of columns j .. j-63 (lane b: column
-// j - b) at once; near the block's first row (and the origin) a scalar loop
-// steps through 16 rows at a time with readlane.
+// or reaches the origin, 32 rows at a time: lane b holds column j - b of rows
+// i-31 .. i, and the window trace resolves them at once. Rows above r0 (the
+// block before) are not traced: the cell the path enters there starts the
+// next block.
 __device__ void walk_block(const CkArgs& a, CkShared& sh, int r0, int plo, int cap) {
     const int lane = threadIdx.x & 63;
-    // uniform state: scalar registers, so each step is a readlane and a few
-    // scalar operations
     int i = __builtin_amdgcn_readfirstlane(sh.ie);
     int j = __builtin_amdgcn_readfirstlane(sh.je);
     int len = __builtin_amdgcn_readfirstlane(sh.len);
     bool done = false, fail = false;
     const int cbase = plo * kPanel;
-    while (i >= r0 && !done) {
+    while (i >= r0 && !done && !fail) {
         const int rr = i - r0;
-        if (rr >= 31 && (r0 > 0 || i >= 33)) {
-            // rows rr-31 .. rr: groups g0 .. g0+4, row x at bit 2(x - 8 g0) of
-            // lo and 2(x - 8 g0) - 16 of hi
-            const int g0 = (rr - 31) >> 3;
-            const int cc = j - lane - cbase;
-            uint32_t w[5];
-#pragma unroll
-            for (int t = 0; t < 5; ++t) {
-                const int g = g0 + t;
-                w[t] = (cc >= 0 && g <= (rr >> 3)) ? uint32_t(sh.codes[g][cc]) : 0u;
-            }
-            const int s2 = 2 * (rr - 8 * g0);  // in [62, 76]
-            const uint64_t lo = uint64_t(w[0]) | (uint64_t(w[1]) << 16) | (uint64_t(w[2]) << 32) |
-                                (uint64_t(w[3]) << 48);
-            const uint64_t hi = uint64_t(w[1]) | (uint64_t(w[2]) << 16) | (uint64_t(w[3]) << 32) |
-                                (uint64_t(w[4]) << 48);
-            const WindowMasks wm = window_masks(uint32_t(hi >> (s2 - 46)), uint32_t(lo >> (s2 - 62)));
-            const uint32_t on = trace_window(wm, lane);
-            if (__builtin_amdgcn_ballot_w64((on & wm.two_cols & wm.two_rows) != 0)) {  // an origin code
-                fail = true;
-                break;
-            }
-            const uint64_t has = __builtin_amdgcn_ballot_w64(on != 0);  // lane 0 holds the start cell
-            const int cnt = __builtin_popcountll(has);
-            const int last = 63 - __builtin_clzll(has);
-            const int la = __builtin_clz(uint32_t(__builtin_amdgcn_readlane(int(on), last)));
-            const int da = la + 1 + int((uint32_t(__builtin_amdgcn_readlane(int(wm.two_rows), last)) >> (31 - la)) & 1u);
-            const int db = last + 1 + int((uint32_t(__builtin_amdgcn_readlane(int(wm.two_cols), last)) >> (31 - la)) & 1u);
-            if (da < 32 || len + cnt > cap) {  // the trace did not leave the 32 rows
-                fail = true;
-                break;
-            }
-            if (on != 0) {
-                const int idx = int(__builtin_amdgcn_mbcnt_hi(uint32_t(has >> 32),
-                                                              __builtin_amdgcn_mbcnt_lo(uint32_t(has), 0u)));
-                const int64_t pos = int64_t(cap) - 1 - (len + idx);
-                a.path[2 * pos] = i - __builtin_clz(on);
-                a.path[2 * pos + 1] = j - lane;
-            }
-            len += cnt;
-            i -= da;
-            j -= db;
-            continue;
-        }
-        const int g0 = (rr - 15) >> 3;  // floor; the groups g0 .. g0 + 2 hold rows rr - 15 .. rr
+        // rows rr-31 .. rr: groups g0 .. g0+4, row x at bit 2(x - 8 g0) of lo
+        // and 2(x - 8 g0) - 16 of hi; groups below 0 are the block before
+        const int g0 = (rr - 31) >> 3;  // floor
         const int cc = j - lane - cbase;
-        uint32_t w[3] = {0u, 0u, 0u};
+        uint32_t w[5];
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
+        for (int t = 0; t < 5; ++t) {
             const int g = g0 + t;
-            if (cc >= 0 && g >= 0 && g <= (rr >> 3)) w[t] = sh.codes[g][cc];
+            w[t] = (cc >= 0 && g >= 0 && g <= (rr >> 3)) ? uint32_t(sh.codes[g][cc]) : 0u;
         }
-        const uint64_t V = uint64_t(w[0]) | (uint64_t(w[1]) << 16) | (uint64_t(w[2]) << 32);
-        // row rr sits at bit 2(rr - 8 g0), in [30, 44]; rows rr .. rr-15 go to bits 30 .. 0
-        const uint32_t packed = uint32_t(V >> (2 * (rr - 8 * g0) - 30));
-        int off = 30, b = 0;
-        while (i >= r0 && off >= 0 && b < kLanes) {
-            if (len >= cap || j < 0) {
-                fail = true;
-                break;
-            }
-            const uint32_t c = (uint32_t(__builtin_amdgcn_readlane(int(packed), b)) >> off) & 3u;
-            if (lane == 0) {
-                const int64_t pos = int64_t(cap) - 1 - len;
-                a.path[2 * pos] = i;
-                a.path[2 * pos + 1] = j;
-            }
-            ++len;
-            if (c == 3u) {
-                fail = i != 0 || j != 0;
-                done = true;
-                break;
-            }
-            const int da = 1 + int(c >> 1), db = 1 + int(c & 1u);
-            i -= da;
-            j -= db;
-            off -= 2 * da;
-            b += db;
+        const int s2 = 2 * (rr - 8 * g0);  // in [62, 76]
+        const uint64_t lo = uint64_t(w[0]) | (uint64_t(w[1]) << 16) | (uint64_t(w[2]) << 32) | (uint64_t(w[3]) << 48);
+        const uint64_t hi = uint64_t(w[1]) | (uint64_t(w[2]) << 16) | (uint64_t(w[3]) << 32) | (uint64_t(w[4]) << 48);
+        const WindowMasks wm = window_masks(uint32_t(hi >> (s2 - 46)), uint32_t(lo >> (s2 - 62)));
+        const uint32_t live = rr >= 31 ? ~0u : ~0u << (31 - rr);  // rows a <= rr
+        const uint32_t on = trace_window_live(wm, live, lane);
+        const uint64_t has = __builtin_amdgcn_ballot_w64(on != 0);  // lane 0 holds the start cell
+        const int last = 63 - __builtin_clzll(has);                   // the last cell marked
+        const int la = __builtin_clz(uint32_t(__builtin_amdgcn_readlane(int(on), last)));
+        const uint32_t lrows = uint32_t(__builtin_amdgcn_readlane(int(wm.two_rows), last));
+        const uint32_t lcols = uint32_t(__builtin_amdgcn_readlane(int(wm.two_cols), last));
+        int cnt = __builtin_popcountll(has);
+        int da, db;
+        if (la > rr) {
+            // entered the block before: that cell is not written here
+            --cnt;
+            da = la;
+            db = last;
+        } else if (((lrows & lcols) >> (31 - la)) & 1u) {
+            // code 3: the origin ends the path
+            done = true;
+            fail = i - la != 0 || j - last != 0;
+            da = la;
+            db = last;
+        } else {
+            // left through the 32nd row
+            da = la + 1 + int((lrows >> (31 - la)) & 1u);
+            db = last + 1 + int((lcols >> (31 - la)) & 1u);
+            if (da < 32) fail = true;
         }
+        if (len + cnt > cap) fail = true;
         if (fail) break;
+        if (on != 0 && (lane != last || cnt == __builtin_popcountll(has))) {
+            const int idx = int(__builtin_amdgcn_mbcnt_hi(uint32_t(has >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo(uint32_t(has), 0u)));
+            const int64_t pos = int64_t(cap) - 1 - (len + idx);
+            a.path[2 * pos] = i - __builtin_clz(on);
+            a.path[2 * pos + 1] = j - lane;
+        }
+        len += cnt;
+        i -= da;
+        j -= db;
     }
     if (!done && !fail && i < 0) fail = true;
     if (lane == 0) {
@@ -276,6 +284,7 @@ __global__ __launch_bounds__(kCkThreads) void ckpt_backtrace_kernel(CkArgs a) {
     for (int e = tid; e < kCkPanels * kCkGroups * 2 * kChunk; e += kCkThreads)
         (&sh.ring[0][0][0][0])[e] = __builtin_inff();
     __syncthreads();
+    constexpr int kXPer = kCkMaxRows * 16 / kCkThreads + 1;  // feature loads per thread
     for (;;) {
         const int ie = __builtin_amdgcn_readfirstlane(sh.ie);
         const int je = __builtin_amdgcn_readfirstlane(sh.je);
@@ -287,16 +296,34 @@ __global__ __launch_bounds__(kCkThreads) void ckpt_backtrace_kernel(CkArgs a) {
         const int plo = cl > 0 ? cl / kPanel : 0;
         const int phi = je / kPanel;
         const int xrows = 16 * ((nch + 1) / 2);  // whole slabs
-        for (int e = tid; e < xrows * 16; e += kCkThreads) {
-            const int rr = e >> 4, k = e & 15;
-            const int64_t row = r0 + rr;
-            sh.xs[rr][k] = (row < a.n && k < a.d) ? a.X[row * a.d + k] : 0.0f;
+        const bool active = plo + wave <= phi;
+        // one round trip: the wave's operands and start values, and the feature rows
+        WaveStart st;
+        if (active) load_start(a, wave, r0, plo + wave, st);
+        float xv[kXPer];
+#pragma unroll
+        for (int t = 0; t < kXPer; ++t) {
+            const int e = tid + t * kCkThreads;
+            const int64_t row = r0 + (e >> 4);
+            const int k = e & 15;
+            xv[t] = (e < xrows * 16 && row < a.n && k < a.d) ? a.X[row * a.d + k] : 0.0f;
         }
-        for (int rr = tid; rr < xrows; rr += kCkThreads)
-            sh.rx[rr] = row_inv_norm_f32_small(a.X, a.n, a.d, r0 + rr);
+#pragma unroll
+        for (int t = 0; t < kXPer; ++t) {
+            const int e = tid + t * kCkThreads;
+            if (e < xrows * 16) sh.xs[e >> 4][e & 15] = xv[t];
+        }
         if (tid < kCkPanels) sh.prog[tid] = 0;
         __syncthreads();
-        if (plo + wave <= phi) window_wave(a, sh, wave, r0, ie, je, plo, nch);
+        // the row norms as the sweep computes them (zero past n, where the rows are zero)
+        for (int rr = tid; rr < xrows; rr += kCkThreads) {
+            float x[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) x[k] = sh.xs[rr][k];
+            sh.rx[rr] = inv_norm16(x);
+        }
+        __syncthreads();
+        if (active) window_wave(sh, st, wave, r0, ie, je, plo, nch);
         __syncthreads();
         if (wave == 0) walk_block(a, sh, r0, plo, cap);
         __syncthreads();

@@ -131,21 +131,25 @@ __device__ __attribute__((always_inline)) inline void slab_costs_f32_small(const
 // sums the squares of features 4t + g over t, and sum_groups adds the four
 // partial sums as (s0 + s1) + (s2 + s3) (the same bits on every lane, since
 // each addition is commutative). 0 past n.
-__device__ inline float row_inv_norm_f32_small(const float* __restrict__ X, int64_t n, int64_t d, int64_t i) {
-    if (i >= n) return 0.0f;
+// The same from the row's 16 features (zeros past d): an all-zero row gives 0.
+__device__ inline float inv_norm16(const float (&x)[16]) {
     float sg[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         float s = 0.0f;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int64_t k = 4 * t + g;
-            const float x = k < d ? X[i * d + k] : 0.0f;
-            s = __builtin_fmaf(x, x, s);
-        }
+        for (int t = 0; t < 4; ++t) s = __builtin_fmaf(x[4 * t + g], x[4 * t + g], s);
         sg[g] = s;
     }
     return inv_from_sq((sg[0] + sg[1]) + (sg[2] + sg[3]));
+}
+
+__device__ inline float row_inv_norm_f32_small(const float* __restrict__ X, int64_t n, int64_t d, int64_t i) {
+    if (i >= n) return 0.0f;
+    float x[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = k < d ? X[i * d + k] : 0.0f;
+    return inv_norm16(x);
 }
 
 // Costs of a slab from its accumulators, with the row inverse norms of the

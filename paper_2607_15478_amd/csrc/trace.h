@@ -41,11 +41,13 @@ __device__ inline WindowMasks window_masks(uint32_t packed0, uint32_t packed1) {
 // Traces the path through the window from lane 0, row 0 and returns each
 // lane's path cell as a mask (bit 31 - a for row a; at most one bit). A step
 // from row a of lane b goes to lane b + 1 + (code & 1), row a + 1 + (code >> 1);
-// the frontier is empty once the path has left the 32 rows. Code 3 stops it.
-__device__ inline uint32_t trace_window(const WindowMasks& w, int lane) {
-    const uint32_t diag = ~(w.two_cols | w.two_rows) >> 1;      // code 0: next lane, next row
-    const uint32_t down = (w.two_rows & ~w.two_cols) >> 2;      // code 2: next lane, two rows on
-    const uint32_t over = (w.two_cols & ~w.two_rows) >> 1;      // code 1: two lanes on, next row
+// the frontier is empty once the path has left the 32 rows. Code 3 stops it,
+// and so does a row outside `live` (bit 31 - a for row a): the cell the path
+// enters there is still marked.
+__device__ inline uint32_t trace_window_live(const WindowMasks& w, uint32_t live, int lane) {
+    const uint32_t diag = (~(w.two_cols | w.two_rows) & live) >> 1;     // code 0: next lane, next row
+    const uint32_t down = ((w.two_rows & ~w.two_cols) & live) >> 2;     // code 2: next lane, two rows on
+    const uint32_t over = ((w.two_cols & ~w.two_rows) & live) >> 1;     // code 1: two lanes on, next row
     uint32_t f = lane == 0 ? 0x80000000u : 0u;
     uint32_t on = f;
     for (int t = 0; t < 32; t += 2) {
@@ -60,6 +62,8 @@ __device__ inline uint32_t trace_window(const WindowMasks& w, int lane) {
     }
     return on;
 }
+
+__device__ inline uint32_t trace_window(const WindowMasks& w, int lane) { return trace_window_live(w, ~0u, lane); }
 
 }  // namespace
 }  // namespace pardtw
