@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--fused", action="store_true",
                     help="the DP computes the costs itself (no cost matrix; FP32, d <= 16)")
     ap.add_argument("--variant", choices=["wsdtw", "nsdtw"], default="wsdtw", help="segmental workloads")
+    ap.add_argument("--ckpt", type=int, default=0, metavar="K",
+                    help="checkpointed DTW: fused DP keeping only D rows every K rows, then the recomputing "
+                         "backtrace (no code matrix; K a multiple of 16 in [16, 256])")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -116,6 +119,41 @@ def cpu_baseline_batch(pairs, paths, totals, status, bf16=None, threads=8):
     return cpu, validation
 
 
+# FP32 vector work per recomputed cell in the checkpointed backtrace: three
+# FMAs and two mins of the recurrence, and 1 - (acc * rx) * ry of the cost
+CKPT_FLOPS_PER_CELL = 3 * 2 + 2 + 3
+# one compute unit's share of the FP32 vector peak (157.3 TFLOP/s over 256 CUs):
+# the backtrace is one workgroup
+CU_FP32_PEAK_TFLOPS = 157.3 / 256
+
+
+def ckpt_window_cells(path, n, m, K):
+    """Cells the checkpointed backtrace recomputes, from the path: per block,
+    the panels and 8-row chunks of the window cone below the block's first
+    path cell (the kernel's own bounds)."""
+    rows = path[:, 0].astype(np.int64)
+    cols = path[:, 1].astype(np.int64)
+    cells = 0
+    for r0 in range(0, n, K):
+        sel = np.nonzero((rows >= r0) & (rows < r0 + K))[0]
+        if len(sel) == 0:
+            continue
+        q = sel[-1]  # the walk enters the block at its last path cell
+        ie, je = int(rows[q]), int(cols[q])
+        A = ie - r0
+        cl = je - 2 * A - 2
+        plo = cl // 64 if cl > 0 else 0
+        for p in range(plo, je // 64 + 1):
+            over = je - (64 * p + 63)
+            rmax = ie - (over + 1) // 2 if over > 0 else ie
+            kend = (rmax - r0) // 8 if rmax >= r0 else -1
+            rmin = ie - 2 * (je - 64 * p)
+            kbeg = (rmin - r0) // 8 if rmin > r0 else 0
+            if kend >= kbeg:
+                cells += (kend - kbeg + 1) * 8 * 64
+    return cells
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -137,7 +175,11 @@ def main():
 
     Xd = torch.from_numpy(X).to(dev)
     Yd = torch.from_numpy(Y).to(dev)
-    w = pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=not args.fused)
+    K = args.ckpt
+    if K:
+        w = pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=False, ckpt_rows=K)
+    else:
+        w = pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=not args.fused)
     stream = torch.cuda.current_stream()
 
     calib = None
@@ -152,7 +194,7 @@ def main():
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        pd.align_into(Xd, Yd, w, fused=args.fused)
+        pd.align_into(Xd, Yd, w, fused=args.fused or bool(K))
     torch.cuda.synchronize()
 
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
@@ -162,6 +204,13 @@ def main():
     for s in range(args.steps):
         e = evs[s]
         e[0].record(stream)
+        if K:
+            e[1].record(stream)
+            pd.pardtw_dp_fused_ckpt(Xd, Yd, K, w.ckpt, w.total, w.status, w.ws)
+            e[2].record(stream)
+            pd.pardtw_ckpt_backtrace(Xd, Yd, K, w.ckpt, w.status, w.path, w.path_len)
+            e[3].record(stream)
+            continue
         if args.fused:
             e[1].record(stream)
             pd.pardtw_dp_fused(Xd, Yd, w.bp, w.total, w.status, w.ws)
@@ -184,6 +233,11 @@ def main():
     total = float(w.total.item())
     L = int(w.path_len.item())
     path = w.path[:L].cpu().numpy()
+
+    if K:
+        out = ckpt_result(args, X, Y, path, total, cells, ms_per_step, cost_ms, dp_ms, bt_ms, w)
+        print(json.dumps(out), flush=True)
+        return
 
     # the fused DP reads no cost: 1 byte per cell (its codes) is what it must move
     bpc = 1 if args.fused else DP_BYTES_PER_CELL
@@ -239,6 +293,49 @@ def main():
     if calib:
         out["calibration_copy"] = calib
     print(json.dumps(out), flush=True)
+
+
+def ckpt_result(args, X, Y, path, total, cells, ms_per_step, cost_ms, dp_ms, bt_ms, w):
+    """The bench line of the checkpointed path. Its dominant kernel is the
+    backtrace, one workgroup that recomputes the window cells block by block:
+    its roofline is one compute unit's FP32 vector peak."""
+    from paper_2607_15478_amd import pardtw as pd
+    n, m, d = X.shape[0], Y.shape[0], X.shape[1]
+    K = args.ckpt
+    wcells = ckpt_window_cells(path, n, m, K)
+    achieved = wcells * CKPT_FLOPS_PER_CELL / (bt_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 5), "peak": round(CU_FP32_PEAK_TFLOPS, 4),
+                "unit": "TFLOP/s", "frac": round(achieved / CU_FP32_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": "ckpt_backtrace_kernel", "peak_scope": "one CU (the kernel is one workgroup)",
+                "window_cells_per_launch": wcells, "flops_per_cell": CKPT_FLOPS_PER_CELL,
+                "kernel_ms": round(float(bt_ms), 4)}
+    cpu, validation = None, None
+    if not args.no_cpu:
+        cpu, validation = cpu_baseline_pair(X, Y, path, total, validate=not args.no_validate)
+    gcups = cells / (ms_per_step * 1e-3) / 1e9
+    return {
+        "metric": "DP cells/sec (GCUPS) + aligned pairs/sec at oracle path match, 1 MI355X",
+        "value": round(gcups, 2),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": m, "d": d, "cells": cells,
+                   "layout": "checkpointed", "rows_per_block": K,
+                   "checkpoint_bytes": pd.pardtw_ckpt_bytes(n, m, K),
+                   "code_matrix_bytes_avoided": pd.pardtw_bp_bytes(n, m),
+                   "pairs_per_s": round(1e3 / ms_per_step, 3),
+                   "stage_ms": {"dp_ckpt": round(float(dp_ms), 4), "backtrace_ckpt": round(float(bt_ms), 4)}},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "validation": validation,
+    }
 
 
 def run_batch(args):
