@@ -31,7 +31,7 @@ WORKLOAD = "pair_50000x60000_d12"
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-validate", action="store_true", help="time the oracle but skip the path check")
@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--fused", action="store_true",
                     help="the DP computes the costs itself (no cost matrix; FP32, d <= 16)")
     ap.add_argument("--variant", choices=["wsdtw", "nsdtw"], default="wsdtw", help="segmental workloads")
+    ap.add_argument("--serial", action="store_true",
+                    help="pair workloads: run each step's backtrace before the next step's cost (no overlap "
+                         "between consecutive pairs)")
     ap.add_argument("--ckpt", type=int, default=0, metavar="K",
                     help="checkpointed DTW: fused DP keeping only D rows every K rows, then the recomputing "
                          "backtrace (no code matrix; K a multiple of 16 in [16, 256])")
@@ -192,10 +195,28 @@ def main():
         calib = {"bytes_each_way": nb}
         del src, dst
 
+    # Pipelined schedule (pairs after pairs, as a serving loop runs them): the
+    # cost and DP of each pair run on the launch stream, and the backtrace of
+    # pair s (one workgroup) on a second stream beside the cost and DP of pair
+    # s + 1. Pairs alternate between two workspaces; a workspace's codes are
+    # written again only once the backtrace that reads them has finished.
+    # (Running the cost GEMM of pair s + 1 beside the DP of pair s as well was
+    # measured slower: the DP, a chain of waits across workgroups, lost more
+    # than the GEMM saved.)
+    pipelined = not args.serial and not K
+    bufs = [w]
+    if pipelined:
+        bufs.append(pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=not args.fused))
+        side = (stream, torch.cuda.Stream(device=dev))  # default priority
+
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        pd.align_into(Xd, Yd, w, fused=args.fused or bool(K))
+        for b in bufs:
+            pd.align_into(Xd, Yd, b, fused=args.fused or bool(K))
     torch.cuda.synchronize()
+
+    if pipelined:
+        return run_pair_pipelined(args, X, Y, Xd, Yd, bufs, stream, side, cells, calib)
 
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
@@ -239,29 +260,7 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
-    # the fused DP reads no cost: 1 byte per cell (its codes) is what it must move
-    bpc = 1 if args.fused else DP_BYTES_PER_CELL
-    dp_achieved = bpc * cells / (dp_ms * 1e-3) / 1e9
-    # Measured HBM bytes of one DP launch (scaled FETCH_SIZE + WRITE_SIZE counters), valid only while the
-    # DP source is the one the counters were taken on.
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        try:
-            tj = json.load(open(args.traffic_json))
-            src = open(os.path.join(ROOT, "paper_2607_15478_amd", "csrc", "dp.hip"), "rb").read()
-            if (not args.fused and tj.get("workload") == args.workload
-                    and tj.get("dp_source_sha256") == hashlib.sha256(src).hexdigest()):
-                traffic = tj.get("bytes_per_launch")
-        except (OSError, ValueError):
-            traffic = None
-    roofline = {"bound": "hbm", "achieved": round(dp_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(dp_achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "dp_kernel (fused cost)" if args.fused else "dp_kernel",
-                "algorithmic_bytes_per_launch": bpc * cells,
-                "bytes_per_cell": bpc, "kernel_ms": round(float(dp_ms), 4)}
-    if traffic:
-        # the kernel reads no cost for chunks the step set cannot reach, so it moves fewer bytes than 5 B/cell
-        roofline["moved_GBps"] = round(traffic / (dp_ms * 1e-3) / 1e9, 1)
+    roofline = pair_roofline(args, cells, dp_ms)
 
     # ---- CPU baseline leg: the oracle on the whole pair, which also validates the GPU path ----
     cpu, validation = None, None
@@ -283,6 +282,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "d": d, "cells": cells,
                    "layout": "fused_cost" if args.fused else "panel64_band",
+                   "schedule": "serial: cost, DP and backtrace of one pair, then the next",
                    "pairs_per_s": round(1e3 / ms_per_step, 3),
                    "stage_ms": {"cost": round(float(cost_ms), 4), "dp": round(float(dp_ms), 4),
                                 "backtrace": round(float(bt_ms), 4)}},
@@ -293,6 +293,117 @@ def main():
     if calib:
         out["calibration_copy"] = calib
     print(json.dumps(out), flush=True)
+
+
+def run_pair_pipelined(args, X, Y, Xd, Yd, bufs, stream, side, cells, calib):
+    """K pairs back to back: cost and DP on the launch stream, each pair's
+    backtrace on a second stream beside the next pair's cost and DP (see
+    main; `side` is the cost stream, here the launch stream, and the
+    backtrace stream). Every step's cost, DP and backtrace run inside the
+    timed region."""
+    import torch
+    from paper_2607_15478_amd import pardtw as pd
+    n, m, d = X.shape[0], Y.shape[0], X.shape[1]
+    s_cost, s_bt = side
+    # per step: cost start/end, DP start/end, backtrace start/end
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    print(f"[bench] timing {args.steps} pipelined steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        e = evs[s]
+        w = bufs[s % 2]
+        if not args.fused:
+            if s >= 2:
+                s_cost.wait_event(evs[s - 2][3])  # the DP that read this cost matrix
+            e[0].record(s_cost)
+            pd.pardtw_cost(Xd, Yd, w.C, pd.PREC_F32, pd.LAYOUT_PANEL_BAND, stream=s_cost)
+            e[1].record(s_cost)
+            stream.wait_event(e[1])
+        if s >= 2:
+            stream.wait_event(evs[s - 2][5])  # the backtrace that read these codes
+        e[2].record(stream)
+        if args.fused:
+            pd.pardtw_dp_fused(Xd, Yd, w.bp, w.total, w.status, w.ws, stream=stream)
+        else:
+            pd.pardtw_dp(w.C, n, m, w.bp, w.total, w.status, w.ws, pd.LAYOUT_PANEL_BAND, stream=stream)
+        e[3].record(stream)
+        s_bt.wait_event(e[3])
+        e[4].record(s_bt)
+        pd.pardtw_backtrace(w.bp, n, m, w.status, w.path, w.path_len, stream=s_bt)
+        e[5].record(s_bt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stage_ms = np.array([[0.0 if args.fused else e[0].elapsed_time(e[1]), e[2].elapsed_time(e[3]),
+                          e[4].elapsed_time(e[5])] for e in evs])
+    cost_ms, dp_ms, bt_ms = stage_ms.mean(0)
+    ms_per_step = wall * 1e3 / args.steps
+    gcups = cells / (ms_per_step * 1e-3) / 1e9
+    print(f"[bench] step {ms_per_step:.3f} ms pipelined (cost {cost_ms:.3f}, dp {dp_ms:.3f}, backtrace {bt_ms:.3f} "
+          f"on its own stream)", file=sys.stderr, flush=True)
+    w = bufs[(args.steps - 1) % 2]
+    total = float(w.total.item())
+    L = int(w.path_len.item())
+    path = w.path[:L].cpu().numpy()
+    roofline = pair_roofline(args, cells, dp_ms)
+    cpu, validation = None, None
+    if not args.no_cpu:
+        cpu, validation = cpu_baseline_pair(X, Y, path, total, validate=not args.no_validate)
+    out = {
+        "metric": "DP cells/sec (GCUPS) + aligned pairs/sec at oracle path match, 1 MI355X",
+        "value": round(gcups, 2),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": m, "d": d, "cells": cells,
+                   "layout": "fused_cost" if args.fused else "panel64_band",
+                   "schedule": "pipelined: each pair's backtrace on a second stream beside the next pair's "
+                               "cost and DP (--serial: one after another)",
+                   "pairs_per_s": round(1e3 / ms_per_step, 3),
+                   "latency_ms": round(float(cost_ms + dp_ms + bt_ms), 4),
+                   "stage_ms": {"cost": round(float(cost_ms), 4), "dp": round(float(dp_ms), 4),
+                                "backtrace": round(float(bt_ms), 4)}},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "validation": validation,
+    }
+    if calib:
+        out["calibration_copy"] = calib
+    print(json.dumps(out), flush=True)
+
+
+def pair_roofline(args, cells, dp_ms):
+    """The DP kernel against the HBM peak: 5 B per cell (4 B cost read + 1 B
+    code written; 1 B with the fused cost), and the measured bytes of one
+    launch when the counters were taken on this DP source."""
+    bpc = 1 if args.fused else DP_BYTES_PER_CELL
+    dp_achieved = bpc * cells / (dp_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            tj = json.load(open(args.traffic_json))
+            src = open(os.path.join(ROOT, "paper_2607_15478_amd", "csrc", "dp.hip"), "rb").read()
+            if (not args.fused and tj.get("workload") == args.workload
+                    and tj.get("dp_source_sha256") == hashlib.sha256(src).hexdigest()):
+                traffic = tj.get("bytes_per_launch")
+        except (OSError, ValueError):
+            traffic = None
+    roofline = {"bound": "hbm", "achieved": round(dp_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dp_achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "dp_kernel (fused cost)" if args.fused else "dp_kernel",
+                "algorithmic_bytes_per_launch": bpc * cells,
+                "bytes_per_cell": bpc, "kernel_ms": round(float(dp_ms), 4)}
+    if traffic:
+        # the kernel reads no cost for chunks the step set cannot reach, so it moves fewer bytes than 5 B/cell
+        roofline["moved_GBps"] = round(traffic / (dp_ms * 1e-3) / 1e9, 1)
+    return roofline
 
 
 def ckpt_result(args, X, Y, path, total, cells, ms_per_step, cost_ms, dp_ms, bt_ms, w):
