@@ -203,10 +203,13 @@ def main():
     # (Running the cost GEMM of pair s + 1 beside the DP of pair s as well was
     # measured slower: the DP, a chain of waits across workgroups, lost more
     # than the GEMM saved.)
-    pipelined = not args.serial and not K
+    pipelined = not args.serial
     bufs = [w]
     if pipelined:
-        bufs.append(pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=not args.fused))
+        if K:
+            bufs.append(pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=False, ckpt_rows=K))
+        else:
+            bufs.append(pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=not args.fused))
         side = (stream, torch.cuda.Stream(device=dev))  # default priority
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
@@ -304,6 +307,7 @@ def run_pair_pipelined(args, X, Y, Xd, Yd, bufs, stream, side, cells, calib):
     import torch
     from paper_2607_15478_amd import pardtw as pd
     n, m, d = X.shape[0], Y.shape[0], X.shape[1]
+    K = args.ckpt
     s_cost, s_bt = side
     # per step: cost start/end, DP start/end, backtrace start/end
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
@@ -313,7 +317,7 @@ def run_pair_pipelined(args, X, Y, Xd, Yd, bufs, stream, side, cells, calib):
     for s in range(args.steps):
         e = evs[s]
         w = bufs[s % 2]
-        if not args.fused:
+        if not args.fused and not K:
             if s >= 2:
                 s_cost.wait_event(evs[s - 2][3])  # the DP that read this cost matrix
             e[0].record(s_cost)
@@ -323,18 +327,23 @@ def run_pair_pipelined(args, X, Y, Xd, Yd, bufs, stream, side, cells, calib):
         if s >= 2:
             stream.wait_event(evs[s - 2][5])  # the backtrace that read these codes
         e[2].record(stream)
-        if args.fused:
+        if K:
+            pd.pardtw_dp_fused_ckpt(Xd, Yd, K, w.ckpt, w.total, w.status, w.ws, stream=stream)
+        elif args.fused:
             pd.pardtw_dp_fused(Xd, Yd, w.bp, w.total, w.status, w.ws, stream=stream)
         else:
             pd.pardtw_dp(w.C, n, m, w.bp, w.total, w.status, w.ws, pd.LAYOUT_PANEL_BAND, stream=stream)
         e[3].record(stream)
         s_bt.wait_event(e[3])
         e[4].record(s_bt)
-        pd.pardtw_backtrace(w.bp, n, m, w.status, w.path, w.path_len, stream=s_bt)
+        if K:
+            pd.pardtw_ckpt_backtrace(Xd, Yd, K, w.ckpt, w.status, w.path, w.path_len, stream=s_bt)
+        else:
+            pd.pardtw_backtrace(w.bp, n, m, w.status, w.path, w.path_len, stream=s_bt)
         e[5].record(s_bt)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    stage_ms = np.array([[0.0 if args.fused else e[0].elapsed_time(e[1]), e[2].elapsed_time(e[3]),
+    stage_ms = np.array([[0.0 if (args.fused or K) else e[0].elapsed_time(e[1]), e[2].elapsed_time(e[3]),
                           e[4].elapsed_time(e[5])] for e in evs])
     cost_ms, dp_ms, bt_ms = stage_ms.mean(0)
     ms_per_step = wall * 1e3 / args.steps
@@ -345,6 +354,13 @@ def run_pair_pipelined(args, X, Y, Xd, Yd, bufs, stream, side, cells, calib):
     total = float(w.total.item())
     L = int(w.path_len.item())
     path = w.path[:L].cpu().numpy()
+    if K:
+        out = ckpt_result(args, X, Y, path, total, cells, ms_per_step, cost_ms, dp_ms, bt_ms, w)
+        out["config"]["schedule"] = ("pipelined: each pair's backtrace on a second stream beside the next pair's "
+                                     "sweep (--serial: one after another)")
+        out["config"]["latency_ms"] = round(float(dp_ms + bt_ms), 4)
+        print(json.dumps(out), flush=True)
+        return
     roofline = pair_roofline(args, cells, dp_ms)
     cpu, validation = None, None
     if not args.no_cpu:
@@ -439,6 +455,7 @@ def ckpt_result(args, X, Y, path, total, cells, ms_per_step, cost_ms, dp_ms, bt_
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "d": d, "cells": cells,
                    "layout": "checkpointed", "rows_per_block": K,
+                   "schedule": "serial: sweep and backtrace of one pair, then the next",
                    "checkpoint_bytes": pd.pardtw_ckpt_bytes(n, m, K),
                    "code_matrix_bytes_avoided": pd.pardtw_bp_bytes(n, m),
                    "pairs_per_s": round(1e3 / ms_per_step, 3),
