@@ -52,13 +52,72 @@ def parse():
     return ap.parse_args()
 
 
+# Pairs above this many cells are too large for the oracle's full sweep (a
+# 600000 x 600000 pair would take about half an hour on one core).
+ORACLE_MAX_CELLS = 5e9
+ORACLE_SAMPLE_FRAMES = 20000
+
+
 def cpu_baseline_pair(X, Y, path, total, validate=True):
     """The oracle (single-threaded FP64 DTW with codes) timed on the whole pair;
     its result is then used to check the GPU path and total. The only use of
-    the oracle in this script."""
+    the oracle in this script. A pair too large for it is timed on its
+    leading 20000 x 20000 frames, and its GPU path is checked for legality
+    and rescored in FP64 against the GPU total."""
     import oracle
     from tests import parity
     n, m = len(X), len(Y)
+    if n * m > ORACLE_MAX_CELLS:
+        s = ORACLE_SAMPLE_FRAMES
+        t0 = time.perf_counter()
+        oracle.dtw_features(X[:s], Y[:s])
+        secs = time.perf_counter() - t0
+        cpu = {"value": round(s * s / secs / 1e9, 5), "unit": "GCUPS", "cores": 1, "kind": "oracle",
+               "sample": f"the leading {s}x{s} frames of the {n}x{m} pair (the whole pair would take "
+                         f"{n * m / (s * s) * secs / 60:.0f} min): FP64 cost rows + DP + int8 code matrix, one "
+                         f"thread, {secs:.1f} s"}
+        if not validate:
+            return cpu, None
+        # (1) The path is legal and its FP64 cost matches the FP32 total within
+        # the FP32 rounding of the sweep: each step rounds a partial sum D_k
+        # by at most 2^-24 D_k, and the partial sums along the path grow to
+        # the total, so L steps stay within L 2^-25 of it on average (a
+        # bound, loose; the measured gap is reported).
+        # (2) Exactness at scale: a stretch of an optimal path is an optimal
+        # path between its end cells (the cost of the rest of the path does
+        # not depend on it), so the oracle is run on the sub-rectangles
+        # between sampled pairs of path cells and must give the GPU's stretch,
+        # up to declared ties. Ties are judged, as everywhere, on the full
+        # problem's candidate totals: the sub-problem's plus D at the stretch's
+        # first cell P less C(P), D(P) taken as the FP64 cost of the path's
+        # prefix (the oracle's cost of the sub-pair from (0,0) to P).
+        tol = max(parity.TOTAL_REL, len(path) * 2.0 ** -25)
+        ok, msg, rescored, rel = True, "ok", None, None
+        segments = []
+        try:
+            parity.check_legal(path, n, m)
+            rescored = oracle.path_cost(X, Y, path)
+            rel = abs(total - rescored) / abs(rescored)
+            assert rel <= tol, f"GPU total {total} vs rescored path {rescored}: {rel:.2e} > {tol:.2e}"
+            seg_len = 1500
+            for q in np.linspace(0, len(path) - 1 - seg_len, 5).astype(np.int64):
+                (pi, pj), (qi, qj) = path[q], path[q + seg_len]
+                Xs, Ys = X[pi:qi + 1], Y[pj:qj + 1]
+                _, BPs = oracle.dtw_features(Xs, Ys)
+                sub = path[q:q + seg_len + 1] - np.array([pi, pj], dtype=path.dtype)
+                parity.check_legal(sub, len(Xs), len(Ys))
+                off = oracle.path_cost(X[:pi + 1], Y[:pj + 1], path[:q + 1]) - float(oracle.cost(Xs[:1], Ys[:1])[0, 0])
+                ties = parity.audit_path(sub, BPs, lambda c, Xs=Xs, Ys=Ys, off=off:
+                                         oracle.probe(c, X=Xs, Y=Ys)[0] + off)
+                segments.append({"from": [int(pi), int(pj)], "to": [int(qi), int(qj)], "declared_ties": ties})
+            msg = ("ok: path legal; FP64 rescoring within the rounding bound; 5 sampled stretches of 1500 steps "
+                   "equal the oracle's optimal paths between their end cells")
+        except AssertionError as exc:
+            ok, msg = False, str(exc)[:300]
+        validation = {"path_legal_rescored_and_segments_exact": ok, "oracle_total": None,
+                      "rescored_path_cost": rescored, "gpu_total": total, "rel_diff": rel, "rel_bound": tol,
+                      "segments": segments, "path_len": int(len(path)), "detail": msg}
+        return cpu, validation
     t0 = time.perf_counter()
     J, BP = oracle.dtw_features(X, Y)
     secs = time.perf_counter() - t0
@@ -138,10 +197,10 @@ def ckpt_window_cells(path, n, m, K):
     cols = path[:, 1].astype(np.int64)
     cells = 0
     for r0 in range(0, n, K):
-        sel = np.nonzero((rows >= r0) & (rows < r0 + K))[0]
-        if len(sel) == 0:
+        q = int(np.searchsorted(rows, r0 + K, side="left")) - 1  # rows ascend along the path
+        if q < 0 or rows[q] < r0:
             continue
-        q = sel[-1]  # the walk enters the block at its last path cell
+        # the walk enters the block at its last path cell
         ie, je = int(rows[q]), int(cols[q])
         A = ie - r0
         cl = je - 2 * A - 2

@@ -175,6 +175,8 @@ WORKLOADS = {
     "pair_1000x1200_d12": dict(kind="pair", seed=1, n=1000, m=1200, d=12, lo=0.8, hi=1.25),
     "pair_10000x12000_d12": dict(kind="pair", seed=2, n=10000, m=12000, d=12, lo=0.8, hi=1.25),
     "pair_50000x60000_d12": dict(kind="pair", seed=3, n=50000, m=60000, d=12, lo=0.7, hi=1.4),
+    # past the code matrix's memory limit (3.6e11 cells: 360 GB of codes), for the checkpointed path
+    "pair_600000x600000_d12": dict(kind="pair", seed=7, n=600000, m=600000, d=12, lo=0.8, hi=1.25),
     "batch256_500to8000_d12": dict(kind="chroma_batch", seed=4, count=256, lo=500, hi=8000, d=12),
     # the same draw with infeasible pairs' m redrawn, so every pair is aligned
     "batch256_500to8000_d12_feasible": dict(kind="chroma_batch", seed=4, count=256, lo=500, hi=8000, d=12,
