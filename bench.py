@@ -189,28 +189,43 @@ CKPT_FLOPS_PER_CELL = 3 * 2 + 2 + 3
 CU_FP32_PEAK_TFLOPS = 157.3 / 256
 
 
-def ckpt_window_cells(path, n, m, K):
-    """Cells the checkpointed backtrace recomputes, from the path: per block,
-    the panels and 8-row chunks of the window cone below the block's first
-    path cell (the kernel's own bounds)."""
+def ckpt_window_ranges(ie, je, r0):
+    """The window the checkpointed backtrace recomputes for the block starting
+    at row r0 entered at path cell (ie, je), with the kernel's own bounds: for
+    each 64-column panel p, the 8-row chunks kbeg .. kend (rows r0 + 8k ..)
+    where the cone je - 2(ie - r) <= c <= je - ceil((ie - r) / 2) meets it."""
+    A = ie - r0
+    cl = je - 2 * A - 2
+    plo = cl // 64 if cl > 0 else 0
+    out = []
+    for p in range(plo, je // 64 + 1):
+        over = je - (64 * p + 63)
+        rmax = ie - (over + 1) // 2 if over > 0 else ie
+        kend = (rmax - r0) // 8 if rmax >= r0 else -1
+        rmin = ie - 2 * (je - 64 * p)
+        kbeg = (rmin - r0) // 8 if rmin > r0 else 0
+        out.append((p, kbeg, kend))
+    return out
+
+
+def ckpt_block_entries(path, n, K):
+    """(r0, ie, je) for every block of K rows the path visits: the walk
+    enters each block at its last path cell."""
     rows = path[:, 0].astype(np.int64)
     cols = path[:, 1].astype(np.int64)
-    cells = 0
+    out = []
     for r0 in range(0, n, K):
         q = int(np.searchsorted(rows, r0 + K, side="left")) - 1  # rows ascend along the path
-        if q < 0 or rows[q] < r0:
-            continue
-        # the walk enters the block at its last path cell
-        ie, je = int(rows[q]), int(cols[q])
-        A = ie - r0
-        cl = je - 2 * A - 2
-        plo = cl // 64 if cl > 0 else 0
-        for p in range(plo, je // 64 + 1):
-            over = je - (64 * p + 63)
-            rmax = ie - (over + 1) // 2 if over > 0 else ie
-            kend = (rmax - r0) // 8 if rmax >= r0 else -1
-            rmin = ie - 2 * (je - 64 * p)
-            kbeg = (rmin - r0) // 8 if rmin > r0 else 0
+        if q >= 0 and rows[q] >= r0:
+            out.append((r0, int(rows[q]), int(cols[q])))
+    return out
+
+
+def ckpt_window_cells(path, n, m, K):
+    """Cells the checkpointed backtrace recomputes, from the path."""
+    cells = 0
+    for r0, ie, je in ckpt_block_entries(path, n, K):
+        for p, kbeg, kend in ckpt_window_ranges(ie, je, r0):
             if kend >= kbeg:
                 cells += (kend - kbeg + 1) * 8 * 64
     return cells
