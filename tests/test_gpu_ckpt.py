@@ -168,3 +168,37 @@ def test_ckpt_full_size_identical():
     ref = _full(Xd, Yd)
     got = _ckpt(Xd, Yd, 256)
     _same(got[:3], ref)
+
+
+def test_ckpt_graph_capture_replays():
+    """The checkpointed sweep and backtrace captured in a hipGraph: every
+    replay, with eager work and clobbered outputs in between, gives the
+    code-matrix path."""
+    X, Y = _features(55, 1500, 1700, 12)
+    Xd, Yd = torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV)
+    ref = _full(Xd, Yd)
+    w = pd.Workspace(1500, 1700, DEV, cost=False, ckpt_rows=128)
+    _same(_ckpt(Xd, Yd, 128, w)[:3], ref)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        pd.align_into(Xd, Yd, w)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pd.align_into(Xd, Yd, w)
+    X2, Y2 = _features(56, 600, 700, 12)
+    X2d, Y2d = torch.from_numpy(X2).to(DEV), torch.from_numpy(Y2).to(DEV)
+    w2 = pd.Workspace(600, 700, DEV, cost=False, ckpt_rows=64)
+    for rep in range(3):
+        w.total.fill_(-1.0)
+        w.status.fill_(-5)
+        w.ckpt.fill_(7.0)
+        w.path.fill_(-3)
+        w.path_len.fill_(0)
+        pd.align_into(X2d, Y2d, w2)
+        g.replay()
+        torch.cuda.synchronize()
+        L = int(w.path_len.item())
+        _same((float(w.total.item()), int(w.status.item()), w.path[:L].cpu().numpy()), ref)
