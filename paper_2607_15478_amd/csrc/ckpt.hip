@@ -7,20 +7,22 @@
 // of the two rows before every block of K rows (pardtw_dp_fused_ckpt, in
 // dp.hip): 8 m / K bytes per row instead of m.
 //
-// Backward (here): one workgroup walks the blocks from the last. A path cell
-// (ie, je) in block [r0, r0 + K) reaches row r at a column in
-// [je - 2(ie - r), je], since every step moves one or two columns per row.
-// That trapezoid holds every predecessor of its cells down to row r0, and the
-// two checkpoint rows above r0 hold the rest, so recomputing D over it from
-// those rows gives every cell on the path the D, and so the code, of the full
+// Backward (here): one workgroup walks the blocks from the last. Above a path
+// cell (ie, je) in block [r0, r0 + K), the path reaches row r at a column in
+// the cone je - 2(ie - r) <= c <= je - ceil((ie - r) / 2): every step moves
+// one or two columns per row, and at least half a column per row. The cone
+// holds every predecessor of its cells down to row r0, and the two
+// checkpoint rows above r0 hold the rest, so recomputing D over it from those
+// rows gives every cell on the path the D, and so the code, of the full
 // sweep. The recomputation runs the sweep's own instructions: the row step of
 // dp_step.h, one wave per 64-column panel with the same boundary handoff, and
-// the same MFMA slab for the costs (cost_slab.h). Its 2-bit codes stay in LDS,
-// and wave 0 follows them until the path leaves the block; the cell it
-// leaves to starts the next block.
+// the same MFMA slab and row norms for the costs (cost_slab.h). Its 2-bit
+// codes stay in LDS, and wave 0 follows them 32 rows at a time with the
+// lane-parallel window trace (trace.h) until the path leaves the block; the
+// cell it leaves to starts the next block.
 //
-// Work: the trapezoids cover about K^2 cells per block, n K in all, against
-// n m for the sweep; memory: the checkpoints, 8 n m / K bytes.
+// Work: the cones cover about 3/4 K^2 cells per block, about n K in all,
+// against n m for the sweep; memory: the checkpoints, 8 n m / K bytes.
 #include "dp_step.h"
 #include "trace.h"
 
@@ -57,7 +59,7 @@ struct CkArgs {
     int32_t* path_len;
 };
 
-// Eight 1-byte codes (two words, code r in byte r) to 2 bits each.
+// Four 1-byte codes (one word, code r in byte r) to 2 bits each, code r at bits 2r.
 __device__ inline uint32_t compact4(uint32_t x) {
     x = (x | (x >> 6)) & 0x000F000Fu;
     return (x | (x >> 12)) & 0xFFu;
