@@ -202,3 +202,18 @@ def test_ckpt_graph_capture_replays():
         torch.cuda.synchronize()
         L = int(w.path_len.item())
         _same((float(w.total.item()), int(w.status.item()), w.path[:L].cpu().numpy()), ref)
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_ckpt_exact_ties(levels):
+    """Features from a few repeated frames: many cells share one cost, and
+    many candidate totals are exactly equal. The recomputed codes break every
+    tie as the sweep does."""
+    rng = np.random.default_rng(40 + levels)
+    base = rng.integers(0, levels, size=(levels + 1, 12)).astype(np.float32) + 1.0
+    X = base[rng.integers(0, levels + 1, size=900)]
+    Y = base[rng.integers(0, levels + 1, size=1000)]
+    Xd, Yd = torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV)
+    ref = _full(Xd, Yd)
+    for K in (16, 128):
+        _same(_ckpt(Xd, Yd, K)[:3], ref)
