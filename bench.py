@@ -372,26 +372,20 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def run_pair_pipelined(args, X, Y, Xd, Yd, bufs, stream, side, cells, calib):
-    """K pairs back to back: cost and DP on the launch stream, each pair's
-    backtrace on a second stream beside the next pair's cost and DP (see
-    main; `side` is the cost stream, here the launch stream, and the
-    backtrace stream). Every step's cost, DP and backtrace run inside the
-    timed region."""
-    import torch
-    from paper_2607_15478_amd import pardtw as pd
-    n, m, d = X.shape[0], Y.shape[0], X.shape[1]
-    K = args.ckpt
+def launch_pipelined(pd, Xd, Yd, bufs, stream, side, steps, fused, K, evs, after_bt=None):
+    """Enqueue `steps` pairs in the pipelined schedule: cost (materialised
+    form) and DP on `stream`, each backtrace on side[1] once its DP is done.
+    Pair s uses workspace bufs[s % 2]; its cost matrix and codes (or
+    checkpoints) are rewritten only after the DP and the backtrace of pair
+    s - 2 that read them. evs[s] holds six events: cost start/end, DP
+    start/end, backtrace start/end. after_bt(s, w, s_bt) may enqueue work on
+    the backtrace stream after pair s's backtrace, before its end event."""
+    n, m = Xd.shape[0], Yd.shape[0]
     s_cost, s_bt = side
-    # per step: cost start/end, DP start/end, backtrace start/end
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
-    print(f"[bench] timing {args.steps} pipelined steps", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
+    for s in range(steps):
         e = evs[s]
         w = bufs[s % 2]
-        if not args.fused and not K:
+        if not fused and not K:
             if s >= 2:
                 s_cost.wait_event(evs[s - 2][3])  # the DP that read this cost matrix
             e[0].record(s_cost)
@@ -403,7 +397,7 @@ def run_pair_pipelined(args, X, Y, Xd, Yd, bufs, stream, side, cells, calib):
         e[2].record(stream)
         if K:
             pd.pardtw_dp_fused_ckpt(Xd, Yd, K, w.ckpt, w.total, w.status, w.ws, stream=stream)
-        elif args.fused:
+        elif fused:
             pd.pardtw_dp_fused(Xd, Yd, w.bp, w.total, w.status, w.ws, stream=stream)
         else:
             pd.pardtw_dp(w.C, n, m, w.bp, w.total, w.status, w.ws, pd.LAYOUT_PANEL_BAND, stream=stream)
@@ -414,7 +408,27 @@ def run_pair_pipelined(args, X, Y, Xd, Yd, bufs, stream, side, cells, calib):
             pd.pardtw_ckpt_backtrace(Xd, Yd, K, w.ckpt, w.status, w.path, w.path_len, stream=s_bt)
         else:
             pd.pardtw_backtrace(w.bp, n, m, w.status, w.path, w.path_len, stream=s_bt)
+        if after_bt is not None:
+            after_bt(s, w, s_bt)
         e[5].record(s_bt)
+
+
+def run_pair_pipelined(args, X, Y, Xd, Yd, bufs, stream, side, cells, calib):
+    """K pairs back to back: cost and DP on the launch stream, each pair's
+    backtrace on a second stream beside the next pair's cost and DP (see
+    main; `side` is the cost stream, here the launch stream, and the
+    backtrace stream). Every step's cost, DP and backtrace run inside the
+    timed region."""
+    import torch
+    from paper_2607_15478_amd import pardtw as pd
+    n, m, d = X.shape[0], Y.shape[0], X.shape[1]
+    K = args.ckpt
+    # per step: cost start/end, DP start/end, backtrace start/end
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    print(f"[bench] timing {args.steps} pipelined steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    launch_pipelined(pd, Xd, Yd, bufs, stream, side, args.steps, args.fused, K, evs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     stage_ms = np.array([[0.0 if (args.fused or K) else e[0].elapsed_time(e[1]), e[2].elapsed_time(e[3]),
