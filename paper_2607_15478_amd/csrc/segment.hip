@@ -24,8 +24,8 @@
 namespace pardtw {
 namespace {
 
-constexpr int kSegThreads = 256;
-constexpr int kSegPer = 8;                              // columns per thread per tile
+constexpr int kSegThreads = 512;
+constexpr int kSegPer = 4;                              // columns per thread per tile
 constexpr int kSegTile = kSegThreads * kSegPer;         // columns per tile
 
 struct SegHeader {
@@ -86,15 +86,33 @@ __global__ __launch_bounds__(kSegThreads) void segment_scan_kernel(SegArgs a, in
         VI carry[kSegRows];
 #pragma unroll
         for (int r = 0; r < kSegRows; ++r) carry[r] = VI{kInf, -1};  // running minimum over earlier tiles
+        // The scores of every row of the block for one tile, loaded a tile
+        // ahead: each row-tile would otherwise wait a memory round trip. The
+        // loads are unconditional (rows past the block or the matrix read a
+        // valid address, and columns past m are replaced by +inf when used),
+        // so the compiler's count of loads in flight stays exact.
+        float cb[kSegRows][kSegPer], nb[kSegRows][kSegPer];
+        auto load_tile = [&](int64_t tt0, float (&buf)[kSegRows][kSegPer]) {
+            const int64_t jj0 = tt0 + int64_t(tid) * kSegPer;
+#pragma unroll
+            for (int r = 0; r < kSegRows; ++r) {
+                const int64_t fr = f0 + r < a.nf ? f0 + r : a.nf - 1;
+                const float* srow = a.S + fr * a.m;
+#pragma unroll
+                for (int e = 0; e < kSegPer; ++e) buf[r][e] = *(jj0 + e < a.m ? srow + jj0 + e : srow);
+            }
+        };
+        load_tile(0, cb);
         int tix = 0;
         for (int64_t t0 = 0; t0 < a.m; t0 += kSegTile, ++tix) {
             const int64_t j0 = t0 + int64_t(tid) * kSegPer;
-            for (int r = 0; r < rows; ++r) {
+#pragma unroll
+            for (int r = 0; r < kSegRows; ++r) {
+                if (r >= rows) break;
                 const int64_t f = f0 + r;
-                const float* srow = a.S + f * a.m;
                 float t[kSegPer];
 #pragma unroll
-                for (int e = 0; e < kSegPer; ++e) t[e] = (j0 + e < a.m) ? srow[j0 + e] : kInf;
+                for (int e = 0; e < kSegPer; ++e) t[e] = (j0 + e < a.m) ? cb[r][e] : kInf;
                 if (wsdtw && f > 0) {
                     // Dseg[f-1][j - hop]; +inf left of column hop
                     float pv[kSegPer];
@@ -136,6 +154,9 @@ __global__ __launch_bounds__(kSegThreads) void segment_scan_kernel(SegArgs a, in
 #pragma unroll
                     for (int e = 0; e < kSegPer; ++e) t[e] = pv[e] + t[e];
                 }
+                // the next tile's scores, issued after row 0 has read its
+                // records so that the waits of that poll do not cover them
+                if (r == 0) load_tile(t0 + kSegTile, nb);
                 // this thread's columns
                 VI loc[kSegPer];
                 VI run{kInf, -1};
@@ -184,6 +205,10 @@ __global__ __launch_bounds__(kSegThreads) void segment_scan_kernel(SegArgs a, in
                 for (int q = 0; q < kSegRows; ++q) carry[q] = (q == r) ? nc : carry[q];
                 __syncthreads();  // wave_tot and this row's ring tile are read next
             }
+#pragma unroll
+            for (int r = 0; r < kSegRows; ++r)
+#pragma unroll
+                for (int e = 0; e < kSegPer; ++e) cb[r][e] = nb[r][e];
         }
     }
 }
