@@ -277,14 +277,19 @@ def main():
     # (Running the cost GEMM of pair s + 1 beside the DP of pair s as well was
     # measured slower: the DP, a chain of waits across workgroups, lost more
     # than the GEMM saved.)
+    # The checkpointed backtrace takes longer than its sweep, so there two
+    # backtraces (of consecutive pairs, one workgroup each) run at once on
+    # two streams, over three workspaces.
     pipelined = not args.serial
     bufs = [w]
     if pipelined:
-        if K:
-            bufs.append(pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=False, ckpt_rows=K))
-        else:
-            bufs.append(pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=not args.fused))
-        side = (stream, torch.cuda.Stream(device=dev))  # default priority
+        for _ in range(2 if K else 1):
+            if K:
+                bufs.append(pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=False, ckpt_rows=K))
+            else:
+                bufs.append(pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=not args.fused))
+        bts = [torch.cuda.Stream(device=dev) for _ in range(2 if K else 1)]  # default priority
+        side = (stream, bts)
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -374,26 +379,29 @@ def main():
 
 def launch_pipelined(pd, Xd, Yd, bufs, stream, side, steps, fused, K, evs, after_bt=None):
     """Enqueue `steps` pairs in the pipelined schedule: cost (materialised
-    form) and DP on `stream`, each backtrace on side[1] once its DP is done.
-    Pair s uses workspace bufs[s % 2]; its cost matrix and codes (or
-    checkpoints) are rewritten only after the DP and the backtrace of pair
-    s - 2 that read them. evs[s] holds six events: cost start/end, DP
-    start/end, backtrace start/end. after_bt(s, w, s_bt) may enqueue work on
-    the backtrace stream after pair s's backtrace, before its end event."""
+    form) and DP on `stream`, each backtrace on one of the backtrace streams
+    side[1] (in turn) once its DP is done. Pair s uses workspace
+    bufs[s % len(bufs)]; its cost matrix and codes (or checkpoints) are
+    rewritten only after the DP and the backtrace of the pair before that
+    read them. evs[s] holds six events: cost start/end, DP start/end,
+    backtrace start/end. after_bt(s, w, s_bt) may enqueue work on the
+    backtrace stream after pair s's backtrace, before its end event."""
     n, m = Xd.shape[0], Yd.shape[0]
-    s_cost, s_bt = side
+    s_cost, bts = side
+    nb = len(bufs)
     for s in range(steps):
         e = evs[s]
-        w = bufs[s % 2]
+        w = bufs[s % nb]
+        s_bt = bts[s % len(bts)]
         if not fused and not K:
-            if s >= 2:
-                s_cost.wait_event(evs[s - 2][3])  # the DP that read this cost matrix
+            if s >= nb:
+                s_cost.wait_event(evs[s - nb][3])  # the DP that read this cost matrix
             e[0].record(s_cost)
             pd.pardtw_cost(Xd, Yd, w.C, pd.PREC_F32, pd.LAYOUT_PANEL_BAND, stream=s_cost)
             e[1].record(s_cost)
             stream.wait_event(e[1])
-        if s >= 2:
-            stream.wait_event(evs[s - 2][5])  # the backtrace that read these codes
+        if s >= nb:
+            stream.wait_event(evs[s - nb][5])  # the backtrace that read these codes
         e[2].record(stream)
         if K:
             pd.pardtw_dp_fused_ckpt(Xd, Yd, K, w.ckpt, w.total, w.status, w.ws, stream=stream)
@@ -438,14 +446,14 @@ def run_pair_pipelined(args, X, Y, Xd, Yd, bufs, stream, side, cells, calib):
     gcups = cells / (ms_per_step * 1e-3) / 1e9
     print(f"[bench] step {ms_per_step:.3f} ms pipelined (cost {cost_ms:.3f}, dp {dp_ms:.3f}, backtrace {bt_ms:.3f} "
           f"on its own stream)", file=sys.stderr, flush=True)
-    w = bufs[(args.steps - 1) % 2]
+    w = bufs[(args.steps - 1) % len(bufs)]
     total = float(w.total.item())
     L = int(w.path_len.item())
     path = w.path[:L].cpu().numpy()
     if K:
         out = ckpt_result(args, X, Y, path, total, cells, ms_per_step, cost_ms, dp_ms, bt_ms, w)
-        out["config"]["schedule"] = ("pipelined: each pair's backtrace on a second stream beside the next pair's "
-                                     "sweep (--serial: one after another)")
+        out["config"]["schedule"] = ("pipelined: each pair's backtrace on one of two backtrace streams beside "
+                                     "the next pairs' sweeps, three workspaces (--serial: one after another)")
         out["config"]["latency_ms"] = round(float(dp_ms + bt_ms), 4)
         print(json.dumps(out), flush=True)
         return

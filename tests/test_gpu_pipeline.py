@@ -1,7 +1,8 @@
-"""The bench's pipelined schedule (each pair's backtrace on a second stream
-beside the next pair's cost and DP, two workspaces alternating): every pair
-of the loop, not only the last, gets the result of the same pair aligned on
-its own."""
+"""The bench's pipelined schedule (each pair's backtrace on a backtrace
+stream beside the next pairs' cost and DP, workspaces taken in turn): every
+pair of the loop, not only the last, gets the result of the same pair
+aligned on its own. Two layouts: two workspaces and one backtrace stream (the
+default), three workspaces and two backtrace streams (checkpointed runs)."""
 import numpy as np
 import pytest
 
@@ -19,8 +20,9 @@ from paper_2607_15478_amd import pardtw as pd  # noqa: E402
 DEV = "cuda:0"
 
 
+@pytest.mark.parametrize("nbuf,nbt", [(2, 1), (3, 2)])
 @pytest.mark.parametrize("mode", ["materialised", "fused", "ckpt"])
-def test_every_pipelined_pair_matches_its_serial_alignment(mode):
+def test_every_pipelined_pair_matches_its_serial_alignment(mode, nbuf, nbt):
     n, m = 2000, 2400
     fused, K = mode == "fused", (64 if mode == "ckpt" else 0)
     X, Y = synth.chroma_pair(5, n, m)
@@ -38,7 +40,7 @@ def test_every_pipelined_pair_matches_its_serial_alignment(mode):
     ref_total, ref_path = float(ref_w.total.item()), ref_w.path[:L].cpu().numpy()
 
     steps = 7
-    bufs = [workspace(), workspace()]
+    bufs = [workspace() for _ in range(nbuf)]
     for b in bufs:  # leave stale results from another pair in both workspaces
         X2, Y2 = synth.chroma_pair(6, n, m)
         pd.align_into(torch.from_numpy(X2).to(DEV), torch.from_numpy(Y2).to(DEV), b, fused=fused or bool(K))
@@ -52,7 +54,7 @@ def test_every_pipelined_pair_matches_its_serial_alignment(mode):
             outs[s][2].copy_(w.path_len)
 
     stream = torch.cuda.current_stream()
-    side = (stream, torch.cuda.Stream(device=DEV))
+    side = (stream, [torch.cuda.Stream(device=DEV) for _ in range(nbt)])
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
     torch.cuda.synchronize()
     bench.launch_pipelined(pd, Xd, Yd, bufs, stream, side, steps, fused, K, evs, after_bt)
