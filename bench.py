@@ -280,15 +280,22 @@ def main():
     # The checkpointed backtrace takes longer than its sweep, so there two
     # backtraces (of consecutive pairs, one workgroup each) run at once on
     # two streams, over three workspaces.
+    # Extra workspaces are taken only as far as free device memory allows
+    # (a 600000 x 600000 checkpointed pair needs 101 GB each); with none the
+    # run is serial.
     pipelined = not args.serial
     bufs = [w]
     if pipelined:
-        for _ in range(2 if K else 1):
+        per = sum(t.numel() * t.element_size() for t in (w.C, w.bp, w.ws, w.ckpt, w.path))
+        free = torch.cuda.mem_get_info(dev)[0]
+        extra = min(2 if K else 1, int(0.9 * free) // max(per, 1))
+        for _ in range(extra):
             if K:
                 bufs.append(pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=False, ckpt_rows=K))
             else:
                 bufs.append(pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=not args.fused))
-        bts = [torch.cuda.Stream(device=dev) for _ in range(2 if K else 1)]  # default priority
+        pipelined = len(bufs) > 1
+        bts = [torch.cuda.Stream(device=dev) for _ in range(len(bufs) - 1)]  # default priority
         side = (stream, bts)
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
@@ -446,14 +453,15 @@ def run_pair_pipelined(args, X, Y, Xd, Yd, bufs, stream, side, cells, calib):
     gcups = cells / (ms_per_step * 1e-3) / 1e9
     print(f"[bench] step {ms_per_step:.3f} ms pipelined (cost {cost_ms:.3f}, dp {dp_ms:.3f}, backtrace {bt_ms:.3f} "
           f"on its own stream)", file=sys.stderr, flush=True)
+    layout = (f"pipelined: each pair's backtrace on one of {len(side[1])} backtrace stream(s) beside the next "
+              f"pairs' {'sweeps' if K else 'cost and DP'}, {len(bufs)} workspaces in turn (--serial: one after another)")
     w = bufs[(args.steps - 1) % len(bufs)]
     total = float(w.total.item())
     L = int(w.path_len.item())
     path = w.path[:L].cpu().numpy()
     if K:
         out = ckpt_result(args, X, Y, path, total, cells, ms_per_step, cost_ms, dp_ms, bt_ms, w)
-        out["config"]["schedule"] = ("pipelined: each pair's backtrace on one of two backtrace streams beside "
-                                     "the next pairs' sweeps, three workspaces (--serial: one after another)")
+        out["config"]["schedule"] = layout
         out["config"]["latency_ms"] = round(float(dp_ms + bt_ms), 4)
         print(json.dumps(out), flush=True)
         return
@@ -476,8 +484,7 @@ def run_pair_pipelined(args, X, Y, Xd, Yd, bufs, stream, side, cells, calib):
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "d": d, "cells": cells,
                    "layout": "fused_cost" if args.fused else "panel64_band",
-                   "schedule": "pipelined: each pair's backtrace on a second stream beside the next pair's "
-                               "cost and DP (--serial: one after another)",
+                   "schedule": layout,
                    "pairs_per_s": round(1e3 / ms_per_step, 3),
                    "latency_ms": round(float(cost_ms + dp_ms + bt_ms), 4),
                    "stage_ms": {"cost": round(float(cost_ms), 4), "dp": round(float(dp_ms), 4),
