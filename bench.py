@@ -234,8 +234,7 @@ def ckpt_window_cells(path, n, m, K):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only; a multi-GPU run is not supported "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py: measures one GPU; runs on more than one GPU are not supported", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -807,7 +806,7 @@ if __name__ == "__main__":
     if _wl.startswith("batch") or _wl.startswith("segmental"):
         _a = parse()
         if _a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-            print("bench.py: this build measures one GPU only", file=sys.stderr)
+            print("bench.py: measures one GPU; runs on more than one GPU are not supported", file=sys.stderr)
             sys.exit(2)
         run_batch(_a) if _wl.startswith("batch") else run_segmental(_a)
     else:
