@@ -217,3 +217,12 @@ def test_ckpt_exact_ties(levels):
     ref = _full(Xd, Yd)
     for K in (16, 128):
         _same(_ckpt(Xd, Yd, K)[:3], ref)
+
+
+@pytest.mark.parametrize("n,m,K", [(5000, 6000, 16), (6000, 5000, 32), (20000, 24000, 256), (24000, 20000, 128)])
+def test_ckpt_many_blocks(n, m, K):
+    """Hundreds of blocks (and the walk across every block boundary) on
+    tempo-warped pairs, against the code-matrix path."""
+    X, Y = synth.chroma_pair(n + 2 * m + K, n, m)
+    Xd, Yd = torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV)
+    _same(_ckpt(Xd, Yd, K)[:3], _full(Xd, Yd))
