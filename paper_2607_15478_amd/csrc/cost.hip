@@ -220,6 +220,61 @@ __device__ __attribute__((always_inline)) inline void cost_tile(const float* __r
     store_tile<PANEL>(v, n, m, C, p, i0, span);
 }
 
+// BF16, d <= 128: the panel's column operands (at most four steps of eight
+// features per lane group) and their inverse norms are loaded once and kept in
+// registers for the whole sweep, instead of once per 64-row tile; the row
+// operands, the MFMA steps and their order are cost_tile's, so the costs are
+// the same bits.
+template <bool PANEL, bool VEC>
+__device__ __attribute__((always_inline)) inline void sweep_bf16_small(const float* __restrict__ X,
+                                                                       const float* __restrict__ Y, int64_t n,
+                                                                       int64_t m, int64_t d, float* __restrict__ C,
+                                                                       int64_t p, int64_t t0, int tiles,
+                                                                       const GroupSpan& span) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int64_t L = (d + 31) / 32 * 8;  // features per lane group, <= 32
+    bf16x8 bv[4][4];
+    float ry[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int64_t col = p * kPanel + b * 16 + (lane & 15);
+        const bool ok = col < m;
+        const float* yrow = Y + (ok ? col : 0) * d;
+        float sb = 0.0f;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            bv[b][s] = bf16x8{};
+            if (8 * s < L) bv[b][s] = load8_bf16<VEC>(yrow, ok, g * L + 8 * s, d, sb);
+        }
+        ry[b] = inv_from_sq(sum_groups(sb));
+    }
+    for (int u = 0; u < tiles; ++u) {
+        const int64_t i0 = (t0 + u) * kTileM;
+        if (i0 >= n) break;
+        if (!rows_written(span, i0, kTileM)) continue;
+        const int64_t arow = i0 + wave * 16 + (lane & 15);
+        const bool arow_ok = arow < n;
+        const float* xrow = X + (arow_ok ? arow : 0) * d;
+        f32x4 acc[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        float sa = 0.0f;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (8 * s < L) {
+                const bf16x8 av = load8_bf16<VEC>(xrow, arow_ok, g * L + 8 * s, d, sa);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[b][s], acc[b], 0, 0, 0);
+            }
+        }
+        f32x4 v[4];
+        costs_from_acc(acc, inv_from_sq(sum_groups(sa)), ry, v);
+        store_tile<PANEL>(v, n, m, C, p, i0, span);
+    }
+}
+
 // A workgroup's sweep: tiles t0 .. t0 + kTilesPerBlock - 1 of panel p. With a
 // `band` (panel layout only) the groups outside it are skipped.
 template <bool BF16, bool PANEL, bool VEC>
@@ -232,6 +287,12 @@ __device__ __attribute__((always_inline)) inline void sweep(const float* __restr
     if (!BF16 && d <= 16) {
         sweep_f32_small<PANEL>(X, Y, n, m, d, C, p, t0, kTilesPerBlock, span);
         return;
+    }
+    if constexpr (BF16) {
+        if (d <= 128) {
+            sweep_bf16_small<PANEL, VEC>(X, Y, n, m, d, C, p, t0, kTilesPerBlock, span);
+            return;
+        }
     }
     for (int u = 0; u < kTilesPerBlock; ++u) {
         const int64_t i0 = (t0 + u) * kTileM;
