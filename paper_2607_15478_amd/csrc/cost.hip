@@ -275,6 +275,74 @@ __device__ __attribute__((always_inline)) inline void sweep_bf16_small(const flo
     }
 }
 
+// FP32 with d % 16 == 0 and 16 < d <= 128: the panel's 64 columns (d floats
+// each, rows padded to d + 4 so that 16 lanes reading 16 columns hit distinct
+// banks) are staged in LDS once for the workgroup's tiles, and their inverse
+// norms computed once, instead of reloading them per 64-row tile. The loads,
+// the MFMA steps and their order are cost_tile's, so the costs are the same
+// bits.
+constexpr int kLdsMaxD = 128;
+template <bool PANEL>
+__device__ __attribute__((always_inline)) inline void sweep_f32_lds(const float* __restrict__ X,
+                                                                    const float* __restrict__ Y, int64_t n,
+                                                                    int64_t m, int64_t d, float* __restrict__ C,
+                                                                    int64_t p, int64_t t0, int tiles,
+                                                                    const GroupSpan& span) {
+    __shared__ __attribute__((aligned(16))) float ys[kPanel][kLdsMaxD + 4];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    for (int64_t e = threadIdx.x; e < int64_t(kPanel) * d; e += kThreads) {
+        const int64_t c = e / d, k = e % d;
+        const int64_t col = p * kPanel + c;
+        ys[c][k] = col < m ? Y[col * d + k] : 0.0f;
+    }
+    __syncthreads();
+    const int64_t L = (d + 15) / 16 * 4;  // features per lane group (d % 16 == 0: L = d / 4)
+    float ry[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const float* yc = &ys[b * 16 + (lane & 15)][0];
+        float sb = 0.0f;
+        for (int64_t t = 0; t < L; t += 4) {
+            const f32x4 bb = *reinterpret_cast<const f32x4*>(yc + g * L + t);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) sb = __builtin_fmaf(bb[e], bb[e], sb);
+        }
+        ry[b] = inv_from_sq(sum_groups(sb));
+    }
+    for (int u = 0; u < tiles; ++u) {
+        const int64_t i0 = (t0 + u) * kTileM;
+        if (i0 >= n) break;
+        if (!rows_written(span, i0, kTileM)) continue;
+        const int64_t arow = i0 + wave * 16 + (lane & 15);
+        const bool arow_ok = arow < n;
+        const float* xrow = X + (arow_ok ? arow : 0) * d;
+        f32x4 acc[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        float sa = 0.0f;
+        for (int64_t t = 0; t < L; t += 4) {
+            const int64_t k0 = g * L + t;
+            f32x4 a = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            if (arow_ok && k0 < d) a = *reinterpret_cast<const f32x4*>(xrow + k0);
+            f32x4 bb[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bb[b] = *reinterpret_cast<const f32x4*>(&ys[b * 16 + (lane & 15)][k0]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                sa = __builtin_fmaf(a[e], a[e], sa);
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], bb[b][e], acc[b], 0, 0, 0);
+            }
+        }
+        f32x4 v[4];
+        costs_from_acc(acc, inv_from_sq(sum_groups(sa)), ry, v);
+        store_tile<PANEL>(v, n, m, C, p, i0, span);
+    }
+}
+
 // A workgroup's sweep: tiles t0 .. t0 + kTilesPerBlock - 1 of panel p. With a
 // `band` (panel layout only) the groups outside it are skipped.
 template <bool BF16, bool PANEL, bool VEC>
@@ -291,6 +359,11 @@ __device__ __attribute__((always_inline)) inline void sweep(const float* __restr
     if constexpr (BF16) {
         if (d <= 128) {
             sweep_bf16_small<PANEL, VEC>(X, Y, n, m, d, C, p, t0, kTilesPerBlock, span);
+            return;
+        }
+    } else if constexpr (VEC) {
+        if (d <= kLdsMaxD) {
+            sweep_f32_lds<PANEL>(X, Y, n, m, d, C, p, t0, kTilesPerBlock, span);
             return;
         }
     }
