@@ -158,18 +158,19 @@ def test_batch_gradient_matches_single_pair(mixed):
             np.testing.assert_allclose(dy1.cpu().numpy(), gy, rtol=1e-4, atol=1e-5)
 
 
-def test_batch_bf16_matches_single_pair_bf16():
+@pytest.mark.parametrize("prec", [pd.PREC_BF16, pd.PREC_F32])
+def test_batch_d128_matches_single_pair(prec):
     rng = np.random.default_rng(5)
     shapes = [(300, 350), (1000, 800), (64, 100)]
     pairs = [synth.gaussian_pair(rng, n, m, 128, 0.8 * (m - 1) / (n - 1), 1.25 * (m - 1) / (n - 1))
              for n, m in shapes]
-    plan = pd.Plan([n for n, _ in shapes], [m for _, m in shapes], 128, pd.PREC_BF16)
+    plan = pd.Plan([n for n, _ in shapes], [m for _, m in shapes], 128, prec)
     Xp, Yp = pd.pack(pairs, DEV)
     buf = plan.buffers(DEV)
     plan.align(Xp, Yp, buf)
     totals, status, _, paths = _outputs(plan, buf)
     for b, (x, y) in enumerate(pairs):
-        t1, s1, p1 = _single(x, y, pd.PREC_BF16)
+        t1, s1, p1 = _single(x, y, prec)
         assert totals[b] == np.float32(t1) and np.array_equal(paths[b], p1)
 
 

@@ -114,7 +114,12 @@ def _gpu_cost(X, Y, prec=pd.PREC_F32, layout=pd.LAYOUT_ROW):
 
 
 @pytest.mark.parametrize("n,m,d", [(1, 1, 12), (70, 130, 12), (333, 257, 12), (100, 90, 128), (65, 200, 5),
-                                   (128, 64, 33)])
+                                   (128, 64, 33),
+                                   # the column operands held in registers (d <= 16), staged in LDS
+                                   # (d a multiple of 16 up to 128) and loaded per tile (beyond):
+                                   # several tiles per workgroup and a ragged last panel
+                                   (600, 700, 16), (600, 700, 32), (257, 1000, 48), (1000, 300, 128),
+                                   (600, 700, 144), (300, 333, 256)])
 def test_cost_fp32_against_oracle(n, m, d):
     rng = np.random.default_rng(n + m + d)
     X = rng.normal(size=(n, d)).astype(np.float32)
@@ -128,7 +133,8 @@ def test_cost_fp32_against_oracle(n, m, d):
     assert np.all(got_row[0] == 1.0)
 
 
-@pytest.mark.parametrize("n,m,d", [(100, 90, 128), (333, 257, 12), (64, 64, 40)])
+@pytest.mark.parametrize("n,m,d", [(100, 90, 128), (333, 257, 12), (64, 64, 40), (600, 700, 128),
+                                   (600, 700, 136), (257, 1000, 16)])
 def test_cost_bf16_against_oracle_on_rounded_inputs(n, m, d):
     rng = np.random.default_rng(n * m + d)
     X = rng.normal(size=(n, d)).astype(np.float32)
@@ -143,7 +149,9 @@ def test_cost_bf16_against_oracle_on_rounded_inputs(n, m, d):
                                         (1000, 130, 64, pd.PREC_F32), (600, 650, 33, pd.PREC_F32),
                                         (520, 700, 40, pd.PREC_BF16), (2000, 2400, 12, pd.PREC_F32),
                                         (1000, 1999, 12, pd.PREC_F32), (1999, 1000, 12, pd.PREC_F32),
-                                        (3000, 2000, 12, pd.PREC_F32), (130, 1000, 12, pd.PREC_F32)])
+                                        (3000, 2000, 12, pd.PREC_F32), (130, 1000, 12, pd.PREC_F32),
+                                        (1000, 1300, 128, pd.PREC_F32), (1300, 1000, 32, pd.PREC_F32),
+                                        (1000, 1300, 128, pd.PREC_BF16)])
 def test_cost_band_layout_writes_exactly_the_band_groups(n, m, d, prec):
     rng = np.random.default_rng(n * 7 + m + d)
     X = rng.normal(size=(n, d)).astype(np.float32)
