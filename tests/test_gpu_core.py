@@ -1,6 +1,5 @@
 """GPU parity of the single-pair hot path (cost, DP, backtrace, gradient)
 against the FP64 oracle, through the C ABI."""
-import os
 
 import numpy as np
 import pytest
@@ -254,7 +253,6 @@ def test_path_grad_against_oracle():
     assert np.all(gx[skipped] == 0)
 
 
-@pytest.mark.skipif(os.environ.get("PARDTW_FULL") != "1", reason="set PARDTW_FULL=1 for the 10k x 12k oracle sweep")
 def test_align_10k_against_oracle():
     X, Y = synth.make_workload("pair_10000x12000_d12")
     J, BP = oracle.dtw_features(X, Y)
