@@ -41,7 +41,8 @@ def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain -O2, no fast-math)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-fno-fast-math", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-fno-fast-math", "-fopenmp", "-o", tmp, _SRC,
+                               "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -61,6 +62,8 @@ def _load():
         lib.oracle_dtw_matrix_f32.restype = ctypes.c_int
         lib.oracle_dtw_features.argtypes = [P, P, I, I, I, P, P]
         lib.oracle_dtw_features.restype = ctypes.c_int
+        lib.oracle_dtw_features_mt.argtypes = [P, P, I, I, I, P, P, ctypes.c_int]
+        lib.oracle_dtw_features_mt.restype = ctypes.c_int
         lib.oracle_probe.argtypes = [P, P, P, I, I, I, P, P, I, P, P]
         lib.oracle_probe.restype = ctypes.c_int
         lib.oracle_backtrace.argtypes = [P, I, I, P]
@@ -130,14 +133,21 @@ def dtw_matrix(C, want_D: bool = False):
     return tot.value, BP, D
 
 
-def dtw_features(X, Y):
-    """DP with the cost computed row by row. Returns (total, BP int8 (n,m))."""
+def dtw_features(X, Y, threads: int = 1):
+    """DP with the cost computed row by row. Returns (total, BP int8 (n,m)).
+    threads > 1 splits the columns of each row over that many OpenMP threads
+    (bit-identical results)."""
     X, Y = _f32(X), _f32(Y)
     n, d = X.shape
     m = Y.shape[0]
     BP = np.empty((n, m), dtype=np.int8)
     tot = ctypes.c_double()
-    if _load().oracle_dtw_features(_p(X), _p(Y), n, m, d, _p(BP), ctypes.byref(tot)) != 0:
+    lib = _load()
+    if threads > 1:
+        rc = lib.oracle_dtw_features_mt(_p(X), _p(Y), n, m, d, _p(BP), ctypes.byref(tot), int(threads))
+    else:
+        rc = lib.oracle_dtw_features(_p(X), _p(Y), n, m, d, _p(BP), ctypes.byref(tot))
+    if rc != 0:
         raise MemoryError("oracle_dtw_features")
     return tot.value, BP
 

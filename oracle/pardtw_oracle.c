@@ -89,9 +89,9 @@ int oracle_cost(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
  * row i-2; NULL when that row does not exist) and the cost row. Writes the
  * accumulated costs into cur and the codes into bp_row. When cand is not NULL
  * it receives the three candidate totals per cell (3*m doubles). */
-static void dp_row(int64_t i, int64_t m, const double* crow, const double* prev1, const double* prev2,
-                   double* cur, int8_t* bp_row, double* cand) {
-    for (int64_t j = 0; j < m; ++j) {
+static void dp_row_range(int64_t i, int64_t j0, int64_t j1, const double* crow, const double* prev1,
+                         const double* prev2, double* cur, int8_t* bp_row, double* cand) {
+    for (int64_t j = j0; j < j1; ++j) {
         double c = crow[j];
         double cd[3];
         cd[0] = (prev1 && j >= 1) ? prev1[j - 1] + STEP_W[0] * c : INFINITY;
@@ -107,6 +107,11 @@ static void dp_row(int64_t i, int64_t m, const double* crow, const double* prev1
         if (bp_row) bp_row[j] = (int8_t)code;
         if (cand) { cand[3 * j] = cd[0]; cand[3 * j + 1] = cd[1]; cand[3 * j + 2] = cd[2]; }
     }
+}
+
+static void dp_row(int64_t i, int64_t m, const double* crow, const double* prev1, const double* prev2,
+                   double* cur, int8_t* bp_row, double* cand) {
+    dp_row_range(i, 0, m, crow, prev1, prev2, cur, bp_row, cand);
 }
 
 /* DP over a given FP64 cost matrix. D_opt (n*m) is optional; BP (n*m int8)
@@ -166,6 +171,39 @@ int oracle_dtw_features(const float* X, const float* Y, int64_t n, int64_t m, in
         const double* p1 = i >= 1 ? r[(i - 1) % 3] : NULL;
         const double* p2 = i >= 2 ? r[(i - 2) % 3] : NULL;
         dp_row(i, m, crow, p1, p2, cur, BP + i * m, NULL);
+    }
+    *total = r[(n - 1) % 3][m - 1];
+    free(xh); free(yh); free(rows);
+    return 0;
+}
+
+/* oracle_dtw_features with the columns of each row split over `threads`
+ * OpenMP threads. A cell needs only the two rows above it, so the cells of a
+ * row are independent; every cell runs the same arithmetic as in the serial
+ * sweep, and BP and total are bit-identical to it. Used to time the oracle on
+ * all host cores. */
+int oracle_dtw_features_mt(const float* X, const float* Y, int64_t n, int64_t m, int64_t d, int8_t* BP,
+                           double* total, int threads) {
+    if (n <= 0 || m <= 0 || d <= 0 || threads <= 0) return -1;
+    double* xh = unit_rows(X, n, d);
+    double* yh = unit_rows(Y, m, d);
+    double* rows = (double*)malloc(sizeof(double) * (size_t)(4 * m));
+    if (!xh || !yh || !rows) { free(xh); free(yh); free(rows); return -1; }
+    double* r[3] = {rows, rows + m, rows + 2 * m};
+    double* crow = rows + 3 * m;
+    const int64_t blocks = 4 * (int64_t)threads < m ? 4 * (int64_t)threads : m;
+#pragma omp parallel num_threads(threads)
+    for (int64_t i = 0; i < n; ++i) {
+        double* cur = r[i % 3];
+        const double* p1 = i >= 1 ? r[(i - 1) % 3] : NULL;
+        const double* p2 = i >= 2 ? r[(i - 2) % 3] : NULL;
+        /* the loop's implicit barrier ends row i before row i+1 starts */
+#pragma omp for schedule(static)
+        for (int64_t b = 0; b < blocks; ++b) {
+            const int64_t j0 = b * m / blocks, j1 = (b + 1) * m / blocks;
+            cost_row(xh + i * d, yh + j0 * d, j1 - j0, d, crow + j0);
+            dp_row_range(i, j0, j1, crow, p1, p2, cur, BP + i * m, NULL);
+        }
     }
     *total = r[(n - 1) % 3][m - 1];
     free(xh); free(yh); free(rows);

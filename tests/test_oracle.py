@@ -309,3 +309,99 @@ def test_band_mask_is_forward_and_backward_reachability(n, m):
                     if i - di >= 0 and j - dj >= 0:
                         bwd[i - di, j - dj] = True
     assert np.array_equal(parity.band_mask(n, m), fwd & bwd)
+
+
+def _probe_expected(C, D, cells):
+    """Candidate totals of the DTW recursion rebuilt from a full D and C."""
+    out = np.full((len(cells), 3), np.inf)
+    for q, (i, j) in enumerate(cells):
+        for r, ((di, dj), w) in enumerate(zip(brute.STEPS, brute.WEIGHTS)):
+            if i - di >= 0 and j - dj >= 0:
+                out[q, r] = D[i - di, j - dj] + w * float(C[i, j])
+    return out
+
+
+def _one_hot_features(rng, n, d=3):
+    """Frames that are unit basis vectors: every cosine distance is exactly 0
+    or 1, so candidate totals tie exactly all over the matrix."""
+    X = np.zeros((n, d), dtype=np.float32)
+    X[np.arange(n), rng.integers(0, d, n)] = 1.0
+    return X
+
+
+@pytest.mark.parametrize("kind", ["chroma", "one_hot"])
+def test_probe_features_branch(kind):
+    """The tie arbiter of every path audit: oracle.probe(cells, X=, Y=) gives
+    the candidate totals and D of the DTW recursion over the cosine cost of
+    the features. Expected values come from scipy's cosine distance and the
+    brute-force-pinned matrix DP, with exact ties in the one-hot case."""
+    from scipy.spatial.distance import cdist
+
+    from paper_2607_15478_amd import synth
+    rng = np.random.default_rng(21)
+    n, m = 37, 45
+    if kind == "chroma":
+        X, Y = synth.chroma_pair(rng, n, m)
+    else:
+        X, Y = _one_hot_features(rng, n), _one_hot_features(rng, m)
+    Cs = cdist(X.astype(np.float64), Y.astype(np.float64), "cosine")
+    _, _, D = oracle.dtw_matrix(Cs, want_D=True)
+    cells = np.array([[i, j] for i in range(n) for j in range(m) if (i * 7 + j * 3) % 5 == 0])
+    cand, dval = oracle.probe(cells, X=X, Y=Y)
+    exp = _probe_expected(Cs, D, cells)
+    fin = np.isfinite(exp)
+    assert np.array_equal(np.isfinite(cand), fin)
+    np.testing.assert_allclose(cand[fin], exp[fin], rtol=1e-12, atol=1e-12)
+    dexp = D[cells[:, 0], cells[:, 1]]
+    assert np.array_equal(np.isfinite(dval), np.isfinite(dexp))
+    np.testing.assert_allclose(dval[np.isfinite(dexp)], dexp[np.isfinite(dexp)], rtol=1e-12, atol=1e-12)
+    if kind == "one_hot":
+        # the winner's candidate equals D exactly, and exact ties really occur
+        ties = sum(1 for c in cand if np.isfinite(c).sum() >= 2 and np.sort(c)[0] == np.sort(c)[1])
+        assert ties > 0
+        assert np.all(np.min(cand[np.isfinite(dval) & (cells[:, 0] + cells[:, 1] > 0)], 1)
+                      == dval[np.isfinite(dval) & (cells[:, 0] + cells[:, 1] > 0)])
+
+
+def test_probe_features_brute_force_prefixes():
+    """On tiny features, the probe's D at (i, j) is the brute-force optimum of
+    the prefix pair X[:i+1], Y[:j+1], and each candidate is the brute-force
+    optimum at the step's source plus the weighted cost (no dynamic program
+    on the expected side)."""
+    from scipy.spatial.distance import cdist
+    rng = np.random.default_rng(22)
+    n, m, d = 6, 7, 4
+    X = rng.uniform(0.0, 1.0, (n, d)).astype(np.float32)
+    Y = rng.uniform(0.0, 1.0, (m, d)).astype(np.float32)
+    Cs = cdist(X.astype(np.float64), Y.astype(np.float64), "cosine")
+
+    def best(i, j):
+        return brute.brute_dtw(Cs[:i + 1, :j + 1])[0]
+
+    cells = np.array([[i, j] for i in range(n) for j in range(m)])
+    cand, dval = oracle.probe(cells, X=X, Y=Y)
+    for q, (i, j) in enumerate(cells):
+        b = best(i, j)
+        assert (np.isinf(dval[q]) and np.isinf(b)) or dval[q] == pytest.approx(b, rel=1e-12, abs=1e-12)
+        for r, ((di, dj), w) in enumerate(zip(brute.STEPS, brute.WEIGHTS)):
+            src = best(i - di, j - dj) if (i - di >= 0 and j - dj >= 0) else np.inf
+            exp = src + w * Cs[i, j]
+            assert (np.isinf(cand[q, r]) and np.isinf(exp)) or cand[q, r] == pytest.approx(exp, rel=1e-12)
+
+
+@pytest.mark.parametrize("threads", [2, 3, 8])
+def test_multithreaded_sweep_bit_identical(threads):
+    """The all-core timing variant splits each row's columns over threads; a
+    cell needs only rows above it, so codes and total equal the serial
+    sweep's bit for bit (on shapes with fewer columns than blocks, too)."""
+    from paper_2607_15478_amd import synth
+    rng = np.random.default_rng(44)
+    for n, m, seed in ((1, 1, 1), (5, 3, 2), (4, 30, 5), (300, 360, 3), (1001, 1203, 4)):
+        if n >= 100:
+            X, Y = synth.chroma_pair(seed, n, m)
+        else:  # tiny and infeasible shapes
+            X, Y = synth.chroma_like(rng, n), synth.chroma_like(rng, m)
+        J1, B1 = oracle.dtw_features(X, Y)
+        Jt, Bt = oracle.dtw_features(X, Y, threads=threads)
+        assert (J1 == Jt) or (np.isinf(J1) and np.isinf(Jt))
+        assert np.array_equal(B1, Bt)

@@ -320,3 +320,62 @@ def test_wsdtw_ends_strictly_increase():
         r = oracle.segmental(X, Y, nf, oracle.WSDTW)
         assert np.isfinite(r["total"])
         assert np.all(np.diff(r["ends"]) >= r["hop"]) and r["hop"] >= 1
+
+
+def test_subseq_matrix_f32_equals_widened_f64():
+    """The FP32 branch of subseq_matrix (used by every subsequence GPU test)
+    widens each cost exactly and runs the same recursion: its scores, codes
+    and D equal, bit for bit, those of the FP64 branch on the widened matrix,
+    which the enumeration pins above cover."""
+    rng = np.random.default_rng(31)
+    for n, m in ((1, 5), (3, 2), (9, 40), (33, 70)):
+        for C32 in (rng.uniform(-0.01, 1.0, (n, m)).astype(np.float32),
+                    rng.integers(0, 3, (n, m)).astype(np.float32)):
+            S1, BP1, D1 = oracle.subseq_matrix(C32, want_D=True)
+            S2, BP2, D2 = oracle.subseq_matrix(C32.astype(np.float64), want_D=True)
+            assert np.array_equal(S1, S2)
+            assert np.array_equal(BP1, BP2)
+            assert np.array_equal(D1, D2)
+
+
+def _sub_candidates(C, D, cells):
+    out = np.full((len(cells), 3), np.inf)
+    for q, (i, j) in enumerate(cells):
+        for r, ((di, dj), w) in enumerate(zip(STEPS, SUB_W)):
+            if i - di >= 0 and j - dj >= 0:
+                out[q, r] = D[i - di, j - dj] + w * float(C[i, j])
+    return out
+
+
+@pytest.mark.parametrize("src", ["C32", "features"])
+def test_subseq_probe(src):
+    """subseq_probe gives the subsequence recursion's candidate totals and D
+    at chosen cells: rebuilt here from the enumeration-pinned matrix sweep
+    (over scipy's cosine distance for the feature branch)."""
+    from scipy.spatial.distance import cdist
+    rng = np.random.default_rng(32)
+    n, m = 23, 61
+    if src == "C32":
+        C = rng.uniform(0.0, 1.0, (n, m)).astype(np.float32)
+        Cref = C.astype(np.float64)
+    else:
+        X = rng.uniform(0.0, 1.0, (n, 5)).astype(np.float32)
+        Y = rng.uniform(0.0, 1.0, (m, 5)).astype(np.float32)
+        Cref = cdist(X.astype(np.float64), Y.astype(np.float64), "cosine")
+    _, _, D = oracle.subseq_matrix(Cref, want_D=True)
+    cells = np.array([[i, j] for i in range(n) for j in range(m) if (3 * i + j) % 4 == 1])
+    if src == "C32":
+        cand, dval = oracle.subseq_probe(cells, C32=C)
+    else:
+        cand, dval = oracle.subseq_probe(cells, X=X, Y=Y)
+    exp = _sub_candidates(Cref, D, cells)
+    assert np.array_equal(np.isfinite(cand), np.isfinite(exp))
+    fin = np.isfinite(exp)
+    np.testing.assert_allclose(cand[fin], exp[fin], rtol=1e-12, atol=1e-12)
+    dexp = D[cells[:, 0], cells[:, 1]]
+    fd = np.isfinite(dexp)
+    assert np.array_equal(np.isfinite(dval), fd)
+    np.testing.assert_allclose(dval[fd], dexp[fd], rtol=1e-12, atol=1e-12)
+    # row 0 is a free start: D = C there and no candidate is finite
+    row0 = cells[:, 0] == 0
+    assert np.all(np.isinf(cand[row0]))
