@@ -168,6 +168,16 @@ __device__ inline ChunkRanges chunk_ranges(int p, int64_t n, int64_t m, int64_t 
     return r;
 }
 
+// The first chunk a panel reads from its left neighbour: the chunk above its
+// first band chunk when the left panel computes it (its rows feed the first
+// band row), else the first band chunk itself. Panel 0 reads its +inf source.
+template <bool SUB>
+__device__ inline int first_input_chunk(int p, int64_t n, int64_t m, int64_t G) {
+    const int k0 = chunk_ranges<SUB>(p, n, m, G).lo;
+    if (p == 0 || k0 == 0) return k0;
+    const int kl = chunk_ranges<SUB>(p - 1, n, m, G).lo;
+    return k0 - 1 >= kl ? k0 - 1 : k0;
+}
 
 // A compute wave owns panel p. Whether it feeds a right neighbour is a runtime
 // value made opaque to the optimiser and only gates a rare wait, so every role
@@ -175,9 +185,9 @@ __device__ inline ChunkRanges chunk_ranges(int p, int64_t n, int64_t m, int64_t 
 // roles sharing one instruction cache would otherwise evict each other.
 // Chunk k's costs from the fused ring into cb, once the producer has them
 // (chunks past the end read a slot without waiting; their values are unused).
-__device__ __attribute__((always_inline)) inline void ring_chunk(CostRing& cr, int wave, int lane, int k, int G,
+__device__ __attribute__((always_inline)) inline void ring_chunk(CostRing& cr, int wave, int lane, int k, int klast,
                                                                  int& cprog_seen, float (&cb)[kChunk]) {
-    if (k < G)
+    if (k <= klast)
         while (cprog_seen <= k) cprog_seen = lds_get(&cr.prog[wave]);
     compiler_order();
     const f32x4* src = reinterpret_cast<const f32x4*>(&cr.slot[wave][k % kCRing][0]) + lane;
@@ -194,38 +204,64 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
                                                                    int wave, int p, bool have_out) {
     const int lane = threadIdx.x & 63;
     const int G = int(a.G);  // chunks per panel (rows padded to a multiple of 8)
+    // The panel sweeps only its band chunks k0 .. k1 (Section "ChunkRanges").
     const ChunkRanges cr = chunk_ranges<SUB>(p, a.n, a.m, a.G);
+    const int k0 = cr.lo, k1 = cr.hi;
+    // The left panel publishes its chunks from its own first band chunk on;
+    // row 8 k0 - 1 and 8 k0 - 2 of it (chunk k0 - 1) feed this panel's first
+    // band row when they are band chunks of the left panel, else +inf does.
+    const int kin = first_input_chunk<SUB>(p, a.n, a.m, a.G);
+    // Chunks k1 + 1 .. khr of the right panel's band get +inf boundary columns.
+    const int khr = have_out ? chunk_ranges<SUB>(p + 1, a.n, a.m, a.G).hi : k1;
     const float kInf = __builtin_inff();
     const int bcol = lane - (kLanes - 2);  // 0 / 1 on the two boundary lanes
     uint64_t* bp_pan = reinterpret_cast<uint64_t*>(a.bp) + int64_t(p) * G * kLanes;
-    const int rlo = cr.lo, rhi = cr.hi;
     const float* rin = &sh.ring[wave][0][0][0];
     float* rout = &sh.ring[wave + 1][0][0][0];
     int flags = __builtin_amdgcn_readfirstlane(have_out ? 2 : 0);
+    // chunks before kin are never read: release their ring slots at once
+    if (lane == 0) lds_put(&sh.cons[wave], kin);
 
     constexpr bool kFused = is_fused(SRC);
     constexpr bool kCk = SRC == kSrcFusedCk;
-    int ck_next = kCk ? a.ck_chunks - 1 : 0;  // the next chunk that ends a block of rows
-    int ck_q = 0;
+    // the first chunk at or after k0 that ends a block of rows, and its checkpoint
+    int ck_q = kCk ? (k0 + 1 + a.ck_chunks - 1) / a.ck_chunks - 1 : 0;
+    int ck_next = kCk ? (ck_q + 1) * a.ck_chunks - 1 : 0;
+    const int ck_q0 = ck_q;
     constexpr int kPf = kFused ? 1 : SRC == kSrcPanel ? kPfPanel : kPfRow;
     float cbuf[kPf][kChunk];
     int cprog_seen = 0;
     if constexpr (kFused) {
-        ring_chunk(*cring, wave, lane, 0, G, cprog_seen, cbuf[0]);
+        if (lane == 0) lds_put(&cring->cons[wave], k0);
+        ring_chunk(*cring, wave, lane, k0, k1, cprog_seen, cbuf[0]);
     } else {
 #pragma unroll
         for (int u = 0; u < kPf; ++u)
-            load_chunk<SRC>(a, p, lane, u, u >= rlo && u <= rhi, cbuf[u]);
+            load_chunk<SRC>(a, p, lane, k0 + u, k0 + u <= k1, cbuf[u]);
     }
 
+    // Rows above the first band chunk: D of this panel's own columns there
+    // is +inf (no band cell has a finite predecessor there), and lane 0
+    // takes the left panel's rows 8 k0 - 1 and 8 k0 - 2 from its chunk k0 - 1.
+    float e0 = kInf, e1 = kInf, s1p0 = kInf;
+    int prog_seen = 0, pv = 0;
+    if (kin < k0) {
+        while (prog_seen <= kin) prog_seen = lds_get(&sh.prog[wave][0]);
+        compiler_order();
+        const float* src = rin + (kin % kRing) * 2 * kChunk;
+        e0 = src[kChunk - 1];
+        e1 = src[2 * kChunk - 1];
+        s1p0 = src[2 * kChunk - 2];
+        compiler_order();
+        if (lane == 0) lds_put(&sh.cons[wave], k0);
+    }
     // D[i-1][j] and D[i-2][j-1]. The origin is produced by the general rule
     // through a virtual D[-2][-1] = -2 C[0][0]: fma(3, C00, -2 C00) = C00
     // exactly, and that value is used by no other cell. Subsequence DTW starts
     // on every cell of row 0 the same way: fma(2, C0j, -C0j) = C0j.
     float d1 = kInf;
-    float s1p = SUB ? -cbuf[0][0] : (p == 0 && lane == 0) ? -2.0f * cbuf[0][0] : kInf;
-    // left boundary D[i0-1][64p-2], D[i0-1][64p-1] for the first row of a chunk
-    float e0 = kInf, e1 = kInf;
+    float s1p = lane == 0 ? s1p0 : kInf;
+    if (k0 == 0) s1p = SUB ? -cbuf[0][0] : (p == 0 && lane == 0) ? -2.0f * cbuf[0][0] : s1p;
     const int last = G - 1;
     const int rlast = int((a.n - 1) % kChunk);
     float dlast = kInf;
@@ -237,17 +273,17 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
     // boundary are in flight while row 0 is computed. The producer's progress
     // counter is read asynchronously one chunk before it is tested.
     float lv0[kChunk], lv1[kChunk];
-    int prog_seen = 0, pv = 0;
 
-    // The unrolled body has no early exit: chunks past the end of the panel
-    // (at most kPf - 1) run as known chunks whose code store goes to a sink.
-    // Every path then issues the same memory operations, which keeps the
-    // compiler's outstanding-load counts exact across the loop back edge.
-    for (int k0 = 0; k0 < G; k0 += kPf) {
+    // The unrolled body has no early exit: chunks past k1 (at most kPf - 1)
+    // run as known chunks whose code store goes to a sink and whose boundary
+    // goes to a ring nobody reads. Every path then issues the same memory
+    // operations, which keeps the compiler's outstanding-load counts exact
+    // across the loop back edge.
+    for (int kb = k0; kb <= k1; kb += kPf) {
 #pragma unroll
         for (int u = 0; u < kPf; ++u) {
-            const int k = k0 + u;
-            const bool inside = k < G;
+            const int k = kb + u;
+            const bool inside = k <= k1;
             asm volatile("" : "+s"(flags));
             const int slot = k % kRing;
 
@@ -257,7 +293,7 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
                 // lost time it could never win back, adding up along the chain.
                 // Only the wait is conditional: the reads below always run, so
                 // their registers need no copies and their latency stays hidden.
-                if (k < G)
+                if (inside)
                     while (prog_seen <= k) prog_seen = lds_get(&sh.prog[wave][0]);
                 compiler_order();
                 const f32x4* src = reinterpret_cast<const f32x4*>(rin + slot * 2 * kChunk);
@@ -288,7 +324,7 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
             if constexpr (kCk) {
                 // no codes; rows 6 and 7 of a chunk that ends a block are the
                 // two rows the block after it starts from
-                if (k == ck_next && ck_q < a.ck_count) {
+                if (k == ck_next && inside && ck_q < a.ck_count) {
                     float* dst = a.ckpt + int64_t(2 * ck_q) * a.ck_stride + int64_t(p) * kPanel + lane;
                     dst[0] = best_r[kChunk - 2];
                     dst[a.ck_stride] = best_r[kChunk - 1];
@@ -324,20 +360,49 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
                     dst[1] = f32x4{best_r[4], best_r[5], best_r[6], best_r[7]};
                 }
                 compiler_order();
-                lds_put(lane < 2 ? &sh.prog[wave + 1][lane] : &sh.isink[wave][lane], k + 1);
+                lds_put(lane < 2 ? &sh.prog[wave + 1][lane] : &sh.isink[wave][lane], inside ? k + 1 : k1 + 1);
             }
-            if (k == last) {
+            if (k == last && inside) {
 #pragma unroll
                 for (int r = 0; r < kChunk; ++r) dlast = (r == rlast) ? best_r[r] : dlast;
             }
 
             const int kn = k + kPf;
-            if constexpr (kFused) ring_chunk(*cring, wave, lane, kn, G, cprog_seen, cbuf[u]);
-            else load_chunk<SRC>(a, p, lane, kn, kn >= rlo && kn <= rhi, cbuf[u]);
+            if constexpr (kFused) ring_chunk(*cring, wave, lane, kn, k1, cprog_seen, cbuf[u]);
+            else load_chunk<SRC>(a, p, lane, kn <= k1 ? kn : k0, kn <= k1, cbuf[u]);
+        }
+    }
+    // Chunks k1 + 1 .. khr of the right panel's band: their left boundary lies
+    // outside this panel's band, so it is handed over as +inf.
+    if (flags & 2) {
+        for (int k = k1 + 1; k <= khr; ++k) {
+            if (cons_seen < k + 1 - kRing) {
+                int v;
+                while ((v = lds_get(&sh.cons[wave + 1])) < k + 1 - kRing) {}
+                cons_seen = v;
+            }
+            compiler_order();
+            if (bcol >= 0) {
+                f32x4* dst = reinterpret_cast<f32x4*>(rout + ((k % kRing) * 2 + bcol) * kChunk);
+                dst[0] = f32x4{kInf, kInf, kInf, kInf};
+                dst[1] = f32x4{kInf, kInf, kInf, kInf};
+            }
+            compiler_order();
+            if (lane < 2) lds_put(&sh.prog[wave + 1][lane], k + 1);
+        }
+    }
+    if constexpr (kCk) {
+        // checkpoints of blocks that end outside the band chunks: +inf
+        for (int q = 0; q < a.ck_count; ++q) {
+            if (q >= ck_q0 && q < ck_q) continue;
+            float* dst = a.ckpt + int64_t(2 * q) * a.ck_stride + int64_t(p) * kPanel + lane;
+            dst[0] = kInf;
+            dst[a.ck_stride] = kInf;
         }
     }
     // DTW: total = D[n-1][m-1]. Subsequence DTW: the whole last row, whose
-    // last column is reachable whenever any is.
+    // last column is reachable whenever any is (+inf in panels whose band
+    // stops above the last row).
     const int64_t col = int64_t(p) * kPanel + lane;
     if (SUB && col < a.m) a.total[col] = dlast;
     if (col == a.m - 1) {
@@ -421,6 +486,7 @@ __device__ __attribute__((always_inline)) inline void cost_producer(const DpArgs
 // Polls are back to back: under full memory load a poll's round trip is the
 // handoff's latency, and it grows with the loads a poll issues (windows of
 // 8, 16 or more chunks measured slower).
+template <bool SUB>
 __device__ __attribute__((always_inline)) inline void in_helper(const DpArgs& a, DpShared& sh, int pl,
                                                                 uint32_t epoch) {
     constexpr int kPer = kHelperWin * 16 / kLanes;  // records per lane per poll
@@ -429,7 +495,9 @@ __device__ __attribute__((always_inline)) inline void in_helper(const DpArgs& a,
     const uint64_t* rec = a.rec + (size_t(pl) * size_t(G) * kChunk) * 2;
     float* ring = &sh.ring[0][0][0][0];
     int cons_seen = 0;
-    for (int64_t k = 0; k < G;) {
+    // the chunks the group's first panel (pl + 1) reads
+    const int64_t khi = chunk_ranges<SUB>(pl + 1, a.n, a.m, G).hi;
+    for (int64_t k = first_input_chunk<SUB>(pl + 1, a.n, a.m, G); k <= khi;) {
         uint64_t v[kPer];
         uint64_t good[kPer];
 #pragma unroll
@@ -438,7 +506,7 @@ __device__ __attribute__((always_inline)) inline void in_helper(const DpArgs& a,
             const int64_t kq = k + (e >> 4);
             bool ok = true;
             v[t] = 0;
-            if (kq < G) {
+            if (kq <= khi) {
                 v[t] = __hip_atomic_load(rec + (kq * kChunk + ((e & 15) >> 1)) * 2 + (e & 1), __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT);
                 ok = uint32_t(v[t] >> 32) == epoch;
@@ -446,7 +514,7 @@ __device__ __attribute__((always_inline)) inline void in_helper(const DpArgs& a,
             good[t] = __builtin_amdgcn_ballot_w64(ok);
         }
         int ready = 0;
-        while (ready < kHelperWin && k + ready < G &&
+        while (ready < kHelperWin && k + ready <= khi &&
                ((good[ready >> 2] >> (16 * (ready & 3))) & 0xffffull) == 0xffffull)
             ++ready;
         if (ready == 0) continue;
@@ -484,6 +552,7 @@ __device__ __attribute__((always_inline)) inline void inf_source(DpShared& sh) {
 // the group (panel pl) leaves in LDS ring NW to the global records, up to four
 // chunks (64 records, one per lane) per store. Keeping these agent-scope
 // stores off the compute waves keeps their memory counter free of slow writes.
+template <bool SUB>
 __device__ __attribute__((always_inline)) inline void out_helper(const DpArgs& a, DpShared& sh, int ring_idx,
                                                                  int pl, uint32_t epoch) {
     const int lane = threadIdx.x & 63;
@@ -492,13 +561,19 @@ __device__ __attribute__((always_inline)) inline void out_helper(const DpArgs& a
     const float* ring = &sh.ring[ring_idx][0][0][0];
     const int q = lane >> 4, row = (lane & 15) >> 1, col = lane & 1;
     int prog_seen = 0;
-    for (int64_t k = 0; k < G;) {
+    // panel pl publishes its band chunks, then +inf up to the last band
+    // chunk of panel pl + 1
+    const int64_t k0 = chunk_ranges<SUB>(pl, a.n, a.m, G).lo;
+    const int64_t khi = chunk_ranges<SUB>(pl + 1, a.n, a.m, G).hi;
+    if (lane == 0) lds_put(&sh.cons[ring_idx], int(k0));
+    for (int64_t k = k0; k <= khi;) {
         if (prog_seen <= k) {
             int v;
             while ((v = lds_get(&sh.prog[ring_idx][0])) <= k) __builtin_amdgcn_s_sleep(1);
             prog_seen = v;
         }
-        const int avail = int(prog_seen - k) < 4 ? int(prog_seen - k) : 4;
+        int avail = int(prog_seen - k) < 4 ? int(prog_seen - k) : 4;
+        avail = khi + 1 - k < avail ? int(khi + 1 - k) : avail;
         compiler_order();
         float val = 0.0f;
         if (q < avail) val = ring[(int((k + q) % kRing) * 2 + col) * kChunk + row];
@@ -525,11 +600,11 @@ __device__ __attribute__((always_inline)) inline void run_group(const DpArgs& a,
         const int p = p0 + wave - (NW + 2);
         if (p < a.P) cost_producer(a, *cring, wave - (NW + 2), p, SUB);
     } else if (wave == NW) {
-        if (p0 > 0) in_helper(a, sh, p0 - 1, epoch);
+        if (p0 > 0) in_helper<SUB>(a, sh, p0 - 1, epoch);
         else inf_source(sh);
     } else {
         // the group's last panel feeds the next group when one exists
-        if (p0 + NW < a.P) out_helper(a, sh, NW, p0 + NW - 1, epoch);
+        if (p0 + NW < a.P) out_helper<SUB>(a, sh, NW, p0 + NW - 1, epoch);
     }
 }
 
