@@ -422,6 +422,16 @@ pardtw_status pardtw_segplan_autotune(pardtw_plan* plan, const float* A, const f
  * (-1 for a plan of pairs). */
 int64_t pardtw_segplan_scores_offset(const pardtw_plan* plan);
 
+/* The segment hop of a Segmental DTW plan, max(1, floor(la / (2 nfrag))): the
+ * column advance of a segment-level match (Sec. II-C), fixed at plan
+ * creation. -1 for a plan of pairs or a null plan. */
+int64_t pardtw_segplan_hop(const pardtw_plan* plan);
+
+/* First row of A of fragment f, floor(f la / nfrag), for 0 <= f < nfrag
+ * (Sec. II-B: fragments of approximately equal length); f = nfrag gives la.
+ * -1 for f out of range, a plan of pairs or a null plan. */
+int64_t pardtw_segplan_fragment_start(const pardtw_plan* plan, int32_t f);
+
 /* Segmental DTW with one call: the cost GEMM of every fragment against B (only
  * the subsequence band), the subsequence DP of all fragments as one persistent
  * launch, the segment-level program, the fragments' backtraces (one workgroup

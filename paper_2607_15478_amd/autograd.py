@@ -45,23 +45,29 @@ def pardtw_cost(X: torch.Tensor, Y: torch.Tensor, prec: int = pd.PREC_F32):
 
 
 class PardtwBatchCost(torch.autograd.Function):
-    """Packed batch -> per-pair totals [B]; paths and statuses in `buf`."""
+    """Packed batch -> per-pair totals [B]; paths and statuses in `buf`.
+
+    The paths are copied at forward time and the copies saved for backward:
+    the plan's kernels write `buf` through raw pointers, which torch's version
+    counters do not see, so a later forward on the same buffers must not
+    change the paths an earlier loss differentiates along."""
 
     @staticmethod
     def forward(ctx, Xp: torch.Tensor, Yp: torch.Tensor, plan: pd.Plan, buf: dict):
         Xp = Xp.detach().contiguous()
         Yp = Yp.detach().contiguous()
         plan.align(Xp, Yp, buf)
-        ctx.plan, ctx.buf = plan, buf
-        ctx.save_for_backward(Xp, Yp)
+        ctx.plan = plan
+        ctx.save_for_backward(Xp, Yp, buf["paths"].clone(), buf["path_len"].clone())
         return buf["totals"].clone()
 
     @staticmethod
     def backward(ctx, g_totals):
-        Xp, Yp = ctx.saved_tensors
+        Xp, Yp, paths, path_len = ctx.saved_tensors
         dX = torch.empty_like(Xp)
         dY = torch.empty_like(Yp)
-        ctx.plan.path_grad(Xp, Yp, ctx.buf, g_totals.to(torch.float32).contiguous(), dX, dY)
+        ctx.plan.path_grad(Xp, Yp, {"paths": paths, "path_len": path_len},
+                           g_totals.to(torch.float32).contiguous(), dX, dY)
         return dX, dY, None, None
 
 

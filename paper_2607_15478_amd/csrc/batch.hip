@@ -469,6 +469,15 @@ extern "C" int64_t pardtw_segplan_scores_offset(const pardtw_plan* plan) {
     return plan && plan->mode == 1 ? int64_t(plan->off_s) : -1;
 }
 
+extern "C" int64_t pardtw_segplan_hop(const pardtw_plan* plan) {
+    return plan && plan->mode == 1 ? plan->hop : -1;
+}
+
+extern "C" int64_t pardtw_segplan_fragment_start(const pardtw_plan* plan, int32_t f) {
+    if (!plan || plan->mode != 1 || f < 0 || f > plan->batch) return -1;
+    return f == plan->batch ? plan->la : plan->pairs[f].x_off;
+}
+
 namespace {
 
 pardtw_status check_seg_call(const pardtw_plan* plan, const float* A, const float* B, void* ws, size_t ws_bytes) {

@@ -84,6 +84,8 @@ _lib_seg_ends = _sig("pardtw_segment_ends", _E, [_P, _I64, _I64, _I64, _I32, _P,
 _lib_segplan_create = _sig("pardtw_segplan_create", _E, [_I64, _I64, _I32, _I64, _E, _I32, _I32,
                                                          ctypes.POINTER(_P)])
 _lib_segplan_scores = _sig("pardtw_segplan_scores_offset", _I64, [_P])
+_lib_segplan_hop = _sig("pardtw_segplan_hop", _I64, [_P])
+_lib_segplan_fstart = _sig("pardtw_segplan_fragment_start", _I64, [_P, ctypes.c_int32])
 _lib_seg_align = _sig("pardtw_segmental_align", _E, [_P, _P, _P, _P, _SZ, _P, _P, _P, _P, _P, _P])
 _lib_segplan_autotune = _sig("pardtw_segplan_autotune", _E, [_P, _P, _P, _P, _SZ, _I32, _P, _P])
 
@@ -445,15 +447,6 @@ def pardtw_segment_ends(scores: torch.Tensor, nfrag: int, m: int, hop: int, vari
                          _ptr(total), _ptr(status), _stream(stream)), "pardtw_segment_ends")
 
 
-def fragment_starts(la: int, nfrag: int):
-    """First row of each fragment plus la: fragment f is [floor(f la/N), floor((f+1) la/N))."""
-    return [(f * la) // nfrag for f in range(nfrag + 1)]
-
-
-def segment_hop(la: int, nfrag: int) -> int:
-    return max(1, la // (2 * nfrag))
-
-
 class SegPlan:
     """Segmental DTW of A (la x d) against B (lb x d) with nfrag fragments
     (pardtw_segplan_create); `buffers()` allocates the outputs and workspace."""
@@ -468,8 +461,9 @@ class SegPlan:
         self._h = h
         self.workspace_bytes = int(_lib_plan_ws(h))
         self.scores_offset = int(_lib_segplan_scores(h))
-        self.starts = fragment_starts(self.la, self.nfrag)
-        self.hop = segment_hop(self.la, self.nfrag)
+        # the plan's own fragment split and segment hop, as the library uses them
+        self.starts = [int(_lib_segplan_fstart(h, f)) for f in range(self.nfrag + 1)]
+        self.hop = int(_lib_segplan_hop(h))
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -138,3 +138,120 @@ def test_bf16_cost_form_against_fp32_and_oracle():
     print("\nBF16 cost form (n, m, mean dev, max dev [frames], |J_bf16 - J*|/J*, rescore gap):")
     for r in report:
         print("  %5d %5d %8.3f %6.1f %10.3e %10.3e" % r)
+
+
+def test_batch_autograd_two_forwards_then_two_backwards():
+    """Two forwards on the same plan and buffers (different features), then
+    both backwards: each loss gets the gradient along its own paths."""
+    shapes = [(180, 210), (140, 120), (95, 150)]
+    sets = [[_pair(300 + 10 * s + k, n, m, 16) for k, (n, m) in enumerate(shapes)] for s in range(2)]
+    plan = pd.Plan([n for n, _ in shapes], [m for _, m in shapes], 16)
+    buf = plan.buffers(DEV)
+    leaves, losses = [], []
+    for pairs in sets:
+        Xp, Yp = pd.pack(pairs, DEV)
+        Xp.requires_grad_(True)
+        Yp.requires_grad_(True)
+        totals = pardtw_batch_cost(Xp, Yp, plan, buf)
+        leaves.append((Xp, Yp))
+        losses.append(totals.sum())
+    for loss in reversed(losses):  # the first loss is differentiated after the second forward
+        loss.backward()
+    for pairs, (Xp, Yp) in zip(sets, leaves):
+        for b, (x, y) in enumerate(pairs):
+            total, path, gx, gy = _grads(x, y)
+            ox, oy = oracle.path_grad(x, y, path, 1.0)
+            xs = slice(plan.x_off[b], plan.x_off[b] + len(x))
+            ys = slice(plan.y_off[b], plan.y_off[b] + len(y))
+            np.testing.assert_array_equal(Xp.grad[xs].cpu().numpy(), gx)
+            np.testing.assert_array_equal(Yp.grad[ys].cpu().numpy(), gy)
+            scale = max(np.abs(ox).max(), np.abs(oy).max())
+            np.testing.assert_allclose(gx, ox, rtol=1e-4, atol=1e-5 * scale)
+
+
+def _d128_batch_grads(pairs, prec=pd.PREC_F32):
+    """Forward (plan, FP32 DP) and backward (pardtw_path_grad_batch) of the
+    packed batch with dL/dJ_b = 1 + b/8; returns per-pair paths, totals and
+    gradients."""
+    ns, ms = [len(p[0]) for p in pairs], [len(p[1]) for p in pairs]
+    plan = pd.Plan(ns, ms, pairs[0][0].shape[1], prec)
+    Xp, Yp = pd.pack(pairs, DEV)
+    buf = plan.buffers(DEV)
+    plan.align(Xp, Yp, buf)
+    g = torch.tensor([1.0 + b / 8 for b in range(len(pairs))], device=DEV)
+    dX, dY = torch.empty_like(Xp), torch.empty_like(Yp)
+    plan.path_grad(Xp, Yp, buf, g, dX, dY)
+    torch.cuda.synchronize()
+    out = []
+    for b, (x, y) in enumerate(pairs):
+        out.append(dict(path=plan.path(buf, b).cpu().numpy(), total=float(buf["totals"][b].item()),
+                        g=float(g[b].item()),
+                        gx=dX[plan.x_off[b]: plan.x_off[b] + len(x)].cpu().numpy(),
+                        gy=dY[plan.y_off[b]: plan.y_off[b] + len(y)].cpu().numpy()))
+    return out
+
+
+@pytest.mark.parametrize("prec", [pd.PREC_F32, pd.PREC_BF16])
+def test_d128_batch_gradient_at_workload_size(prec):
+    """The 32-pair, 2000-4000-frame, D = 128 workload: the batched backward
+    kernel against the FP64 gradient along the same path, element by element,
+    for every pair (the BF16 form differentiates with FP32 features along its
+    BF16-derived path); the first four FP32 paths also pass the oracle audit."""
+    pairs = synth.make_workload("batch32_2000to4000_d128")
+    res = _d128_batch_grads(pairs, prec)
+    for b, ((x, y), r) in enumerate(zip(pairs, res)):
+        parity.check_legal(r["path"], len(x), len(y))
+        ox, oy = oracle.path_grad(x, y, r["path"], r["g"])
+        scale = max(np.abs(ox).max(), np.abs(oy).max())
+        np.testing.assert_allclose(r["gx"], ox, rtol=1e-4, atol=1e-5 * scale, err_msg=f"pair {b} dX")
+        np.testing.assert_allclose(r["gy"], oy, rtol=1e-4, atol=1e-5 * scale, err_msg=f"pair {b} dY")
+        skipped = np.setdiff1d(np.arange(len(x)), r["path"][:, 0])
+        assert np.all(r["gx"][skipped] == 0.0)
+        if prec == pd.PREC_F32 and b < 4:
+            J, BP = oracle.dtw_features(x, y)
+            parity.check_total(r["total"], J)
+            parity.audit_path(r["path"], BP, lambda c, x=x, y=y: oracle.probe(c, X=x, Y=y)[0])
+
+
+def test_d128_gradient_finite_differences_at_workload_size():
+    """Central differences (eps = 1e-3) of the FP64 DTW optimum, re-solved
+    for every perturbation, on 40 sampled coordinates of the smallest of the
+    first four pairs of the D = 128 workload (20 rows of X and 20 of Y on the
+    path). Coordinates whose perturbation moves the optimal path are left out
+    and counted; elsewhere the GPU gradient must match."""
+    pairs = synth.make_workload("batch32_2000to4000_d128")[:4]
+    b = int(np.argmin([len(x) * len(y) for x, y in pairs]))
+    res = _d128_batch_grads(pairs)[b]
+    x, y = pairs[b]
+    C = oracle.cost(x, y)
+    J0, BP0 = oracle.dtw_matrix(C)[:2]
+    path0 = oracle.backtrace(BP0)
+    assert np.array_equal(path0, res["path"]), "GPU path differs from the oracle's on this pair"
+    rng = np.random.default_rng(5)
+    rows = rng.choice(np.unique(path0[:, 0]), 20, replace=False)
+    cols = rng.choice(np.unique(path0[:, 1]), 20, replace=False)
+    coords = [("x", int(r), int(rng.integers(x.shape[1]))) for r in rows] + \
+             [("y", int(c), int(rng.integers(y.shape[1]))) for c in cols]
+    moved, checked = 0, 0
+    for which, r, c in coords:
+        src = x if which == "x" else y
+        vals = []
+        for sgn in (1.0, -1.0):
+            v = src[r].copy()
+            v[c] = np.float32(float(v[c]) + sgn * EPS)
+            Cp = C.copy()
+            if which == "x":
+                Cp[r, :] = oracle.cost(v[None, :], y)[0]
+            else:
+                Cp[:, r] = oracle.cost(x, v[None, :])[:, 0]
+            J, BP = oracle.dtw_matrix(Cp)[:2]
+            vals.append((J, float(v[c]), np.array_equal(oracle.backtrace(BP), path0)))
+        if not (vals[0][2] and vals[1][2]):
+            moved += 1
+            continue
+        fd = (vals[0][0] - vals[1][0]) / (vals[0][1] - vals[1][1])
+        g = (res["gx"] if which == "x" else res["gy"])[r, c] / res["g"]
+        assert abs(fd - g) <= 2e-3 * abs(fd) + 2e-4, (which, r, c, fd, g)
+        checked += 1
+    print(f"\nD=128 pair {b} ({len(x)}x{len(y)}): {checked} coordinates checked, {moved} moved the path")
+    assert checked >= 30

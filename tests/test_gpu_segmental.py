@@ -244,6 +244,8 @@ def _check_segmental(A, B, nf, variant, plan=None, buf=None):
     L = int(buf["path_len"].item())
     g_path = buf["path"][:L].cpu().numpy()
     g_S = _scores_of_plan(plan, buf)
+    # the library's own fragment split and segment hop are the oracle's
+    assert plan.hop == ref["hop"] and np.array_equal(np.array(plan.starts), ref["starts"])
     for f in range(nf):
         _check_scores(g_S[f], ref["S"][f])
     if not np.isfinite(ref["total"]):
@@ -440,3 +442,17 @@ def test_segmental_graph_capture_replays(fused):
         assert L2 == L and float(buf["total"].item()) == ref[0], rep
         assert np.array_equal(buf["ends"].cpu().numpy(), ref[1]), rep
         assert np.array_equal(buf["path"][:L].cpu().numpy(), ref[2]), rep
+
+
+@pytest.mark.parametrize("la,nf", [(1, 1), (2, 1), (3, 2), (7, 7), (100, 3), (101, 50), (1000, 999), (4001, 32),
+                                   (100000, 1000), (100000, 7), (65537, 64)])
+def test_segplan_hop_and_fragments_are_the_oracles(la, nf):
+    """pardtw_segplan_hop and pardtw_segplan_fragment_start (the plan's own
+    values, which its kernels use) against the oracle's fragment split and
+    segment hop; out-of-range fragments and plans of pairs give -1."""
+    plan = pd.SegPlan(la, 50, nf, 4)
+    assert plan.hop == oracle.segment_hop(la, nf)
+    assert np.array_equal(np.array(plan.starts), oracle.fragment_starts(la, nf))
+    assert pd._lib_segplan_fstart(plan._h, nf + 1) == -1 and pd._lib_segplan_fstart(plan._h, -1) == -1
+    pair_plan = pd.Plan([10], [12], 4)
+    assert pd._lib_segplan_hop(pair_plan._h) == -1 and pd._lib_segplan_fstart(pair_plan._h, 0) == -1
