@@ -24,3 +24,21 @@ def test_more_than_one_gpu_is_refused(argv, env):
     assert r.returncode == 2, r.stderr
     assert "more than one GPU" in r.stderr
     assert r.stdout == ""
+
+
+@pytest.mark.parametrize("n,m", [(1, 1), (2, 3), (3, 2), (7, 7), (9, 5), (100, 199), (100, 200), (333, 400),
+                                 (700, 520), (1000, 1999), (1234, 987)])
+def test_band_cell_counts(n, m):
+    """The roofline's algorithmic cells: the closed forms used by the bench
+    against cell-by-cell enumeration of the band masks."""
+    sys.path.insert(0, ROOT)
+    import bench
+    from tests import parity
+    assert bench.band_cells(n, m) == int(parity.band_mask(n, m).sum())
+    assert bench.subseq_band_cells(n, m) == int(parity.subseq_band_mask(n, m).sum())
+
+
+def test_band_cells_of_the_long_pair():
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.band_cells(50000, 60000) == 933333334
