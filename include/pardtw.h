@@ -155,6 +155,26 @@ pardtw_status pardtw_dp_ex(const float* C, pardtw_layout layout, int64_t n, int6
                            float* total, int32_t* pair_status, void* workspace, size_t workspace_bytes,
                            int32_t panels_per_workgroup, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): pardtw_dp
+ * with its workspace taken from a static device array of
+ * PARDTW_NOALLOC_SCRATCH_BYTES bytes that the library holds on each GPU it
+ * runs on until the process ends. Same arguments, results and per-cell
+ * arithmetic as pardtw_dp, minus the workspace. It calls no allocating
+ * routine; on its first call on a device it looks up the array's device
+ * address (hipGetSymbolAddress) with that device current.
+ *   PARDTW_ERR_WORKSPACE when pardtw_dp_workspace_bytes(n, m) exceeds
+ *   PARDTW_NOALLOC_SCRATCH_BYTES (about n*m <= 2.6e8 cells; 10000 x 12000
+ *   fits, 50000 x 60000 does not).
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (boundary records tagged by a launch counter, so stale contents
+ * are never mistaken for new ones): calls that overlap in time on one GPU,
+ * from any stream or thread, race and must not be issued. */
+#define PARDTW_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+pardtw_status pardtw_dp_noalloc(const float* C, pardtw_layout layout, int64_t n, int64_t m, uint8_t* bp,
+                                float* total, int32_t* pair_status, hipStream_t stream);
+
 /* The DP with the cost computed inside it, as ParDTW does (Sec. II-D): no cost
  * matrix is written or read, so the DP moves one byte per cell (its codes).
  * Each 64-column panel's costs are produced 16 rows at a time by a producer

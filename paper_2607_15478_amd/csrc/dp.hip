@@ -44,9 +44,18 @@
 // 16 rows at a time with the cost GEMM's own MFMA slab (cost_slab.h), into an
 // LDS ring the compute wave reads instead of HBM. The DP then moves 1 byte per
 // cell (the codes) and its costs are bit for bit those of the GEMM.
+#include <mutex>
+
 #include "batch.h"
 #include "cost_slab.h"
 #include "dp_step.h"
+
+// Workspace of pardtw_dp_noalloc: one array per GPU for the life of the
+// process, zero at load like every device global without an initialiser.
+// Host code must not pass this name to a kernel (on the host it is only a
+// stand-in for the symbol): its device address comes from
+// hipGetSymbolAddress, once per device.
+static __device__ __align__(256) uint8_t scratch[PARDTW_NOALLOC_SCRATCH_BYTES];
 
 namespace pardtw {
 namespace {
@@ -942,6 +951,26 @@ extern "C" pardtw_status pardtw_subseq_dp(const float* C, pardtw_layout layout, 
 
 namespace {
 
+// Device address of `scratch` per device, taken on the first call on that
+// device with the device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices];
+
+pardtw_status scratch_address(void** out) {
+    int dev = 0;
+    PARDTW_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return PARDTW_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PARDTW_ERR_HIP;
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return PARDTW_OK;
+}
+
 pardtw_status check_fused(const float* X, const float* Y, int64_t n, int64_t m, int64_t d, uint8_t* bp, float* out,
                           int32_t* st, void* ws, size_t ws_bytes, int32_t nw) {
     if (!X || !Y || !bp || !out || !st || !pardtw::valid_sizes(n, m) || d <= 0) return PARDTW_ERR_INVALID_ARG;
@@ -985,4 +1014,16 @@ extern "C" pardtw_status pardtw_subseq_dp_fused(const float* X, const float* Y, 
     if (st != PARDTW_OK) return st;
     return pardtw::dp_launch(nullptr, X, Y, d, pardtw::kSrcFused, n, m, bp, scores, pair_status, workspace, 0, true,
                              stream);
+}
+
+extern "C" pardtw_status pardtw_dp_noalloc(const float* C, pardtw_layout layout, int64_t n, int64_t m, uint8_t* bp,
+                                           float* total, int32_t* pair_status, hipStream_t stream) {
+    if (!C || !bp || !total || !pair_status || !pardtw::valid_sizes(n, m)) return PARDTW_ERR_INVALID_ARG;
+    if (layout != PARDTW_LAYOUT_ROW && layout != PARDTW_LAYOUT_PANEL && layout != PARDTW_LAYOUT_PANEL_BAND)
+        return PARDTW_ERR_UNSUPPORTED;
+    if (pardtw::dp_workspace_bytes_impl(n, m) > size_t(PARDTW_NOALLOC_SCRATCH_BYTES)) return PARDTW_ERR_WORKSPACE;
+    void* ws = nullptr;
+    if (const pardtw_status st = scratch_address(&ws); st != PARDTW_OK) return st;
+    return pardtw::dp_launch(C, nullptr, nullptr, 0, pardtw::src_of(layout), n, m, bp, total, pair_status, ws, 0,
+                             false, stream);
 }

@@ -28,6 +28,7 @@ LAYOUT_PANEL_SUBSEQ_BAND = 3  # panel layout, only the groups the subsequence DP
 NSDTW = 0
 WSDTW = 1
 PLAN_FUSED_COST = 1  # plans whose DP computes the costs itself (FP32, d <= 16)
+NOALLOC_SCRATCH_BYTES = 64 << 20  # static device workspace of pardtw_dp_noalloc
 
 STATUS_NAMES = {0: "OK", 1: "ERR_INVALID_ARG", 2: "ERR_WORKSPACE", 3: "ERR_HIP", 4: "ERR_UNSUPPORTED"}
 
@@ -55,6 +56,7 @@ _lib_band = _sig("pardtw_band_groups", _E, [_I64, _I64, _I64, ctypes.POINTER(_I6
 _lib_dp_ws = _sig("pardtw_dp_workspace_bytes", _SZ, [_I64, _I64])
 _lib_cost = _sig("pardtw_cost", _E, [_P, _P, _I64, _I64, _I64, _E, _E, _P, _P])
 _lib_dp = _sig("pardtw_dp", _E, [_P, _E, _I64, _I64, _P, _P, _P, _P, _SZ, _P])
+_lib_dp_noalloc = _sig("pardtw_dp_noalloc", _E, [_P, _E, _I64, _I64, _P, _P, _P, _P])
 _lib_dp_ex = _sig("pardtw_dp_ex", _E, [_P, _E, _I64, _I64, _P, _P, _P, _P, _SZ, _I32, _P])
 _lib_bt = _sig("pardtw_backtrace", _E, [_P, _I64, _I64, _P, _P, _P, _P])
 _lib_dp_fused = _sig("pardtw_dp_fused", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _SZ, _I32, _P])
@@ -165,6 +167,21 @@ def pardtw_dp(C: torch.Tensor, n: int, m: int, bp: torch.Tensor, total: torch.Te
     else:
         _check(_lib_dp_ex(_ptr(C), layout, n, m, _ptr(bp), _ptr(total), _ptr(status), _ptr(workspace), ws_bytes,
                           int(panels_per_workgroup), _stream(stream)), "pardtw_dp_ex")
+
+
+def pardtw_dp_noalloc(C: torch.Tensor, n: int, m: int, bp: torch.Tensor, total: torch.Tensor, status: torch.Tensor,
+                      layout: int = LAYOUT_PANEL, stream=None):
+    """pardtw_dp without a workspace argument: the library's static device
+    scratch serves as workspace (sizes up to NOALLOC_SCRATCH_BYTES of it)."""
+    _dev_f32(C, "C")
+    if C.numel() < pardtw_cost_elems(n, m, layout):
+        raise ValueError("C is too small for this layout")
+    if bp.dtype != torch.uint8 or bp.numel() < pardtw_bp_bytes(n, m):
+        raise ValueError("bp must be a uint8 tensor of pardtw_bp_bytes(n, m) bytes")
+    if total.dtype != torch.float32 or status.dtype != torch.int32:
+        raise ValueError("total must be float32 and status int32")
+    _check(_lib_dp_noalloc(_ptr(C), layout, n, m, _ptr(bp), _ptr(total), _ptr(status), _stream(stream)),
+           "pardtw_dp_noalloc")
 
 
 def pardtw_dp_fused(X: torch.Tensor, Y: torch.Tensor, bp: torch.Tensor, total: torch.Tensor, status: torch.Tensor,
