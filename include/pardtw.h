@@ -255,6 +255,22 @@ pardtw_status pardtw_path_grad(const float* X, const float* Y, int64_t n, int64_
                                const int32_t* path, const int32_t* path_len, const float* g_total,
                                float* dX, float* dY, hipStream_t stream);
 
+/* Compensated total of a path: its cost (Sec. V: the start cell's cost plus,
+ * per step, the step's weight times the cost of the cell it lands on) summed
+ * in two-float arithmetic, each product and each addition's FP32 rounding
+ * error carried exactly in a second float, and rounded once at the end. The
+ * DP's own total rounds at every step, so on long paths it drifts (about
+ * 1e-4 relative at 600000 x 600000); this one stays at the FP32 rounding of
+ * the costs themselves. Costs are those of the FP32 features, the cosine
+ * distance evaluated as |x/|x| - y/|y||^2 / 2 (equal to 1 - <x,y>/(|x||y|),
+ * without its cancellation for nearly parallel frames; 1 for a zero frame).
+ *   X [device, n*d FP32], Y [device, m*d FP32], path/path_len [device] as
+ *   written by pardtw_backtrace or pardtw_ckpt_backtrace.
+ *   total [device, 1 float]: the path's cost, +inf when path_len is 0.
+ * One workgroup; no allocation or synchronisation. */
+pardtw_status pardtw_path_total(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
+                                const int32_t* path, const int32_t* path_len, float* total, hipStream_t stream);
+
 /* ---- a5: batched form -----------------------------------------------------
  * Many independent pairs of uneven lengths aligned together (the problem of
  * Sec. III for each pair). A plan fixes the pair lengths: pair b has n_b rows

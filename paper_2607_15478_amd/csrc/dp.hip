@@ -64,7 +64,6 @@ constexpr int kRing = 32;        // LDS ring depth, in chunks
 constexpr int kPfPanel = 4;      // cost prefetch distance in chunks, panel layout (4 measured best of 2-16)
 constexpr int kPfRow = 4;        // the same for the row-major layout (8 loads per chunk)
 constexpr int kHelperWin = 4;   // chunks polled per helper round trip (one record per lane)
-constexpr int kMaxNW = 8;
 constexpr int kMaxNWFused = 4;   // fused workgroups: NW compute + NW producer + 2 helper waves
 constexpr int kCRing = 8;        // fused cost ring depth, in chunks (2 KB each)
 
@@ -82,19 +81,18 @@ struct CostRing {
     int cons[kMaxNWFused];  // chunks the compute wave has taken out
 };
 
+template <int NW>
 struct DpShared {
     int super;
-    int prog[kMaxNW + 1][2];  // ring w: chunks published by its producer (two copies, see below)
-    int cons[kMaxNW + 1];  // ring w: chunks released by its consumer
+    int prog[NW + 1][2];  // ring w: chunks published by its producer (two copies, see below)
+    int cons[NW + 1];  // ring w: chunks released by its consumer
     // ring[w][slot][c][r] = D[8k + r][64p - 2 + c] for chunk k, slot = k % kRing
-    float ring[kMaxNW + 1][kRing][2][kChunk];
+    float ring[NW + 1][kRing][2][kChunk];
     // Lanes that have nothing to hand over write here instead, so the handoff
     // stores run on the full wave without masking the execution mask.
-    f32x4 fsink[kMaxNW][kLanes][2];
-    int isink[kMaxNW][kLanes];
+    f32x4 fsink[NW][kLanes][2];
+    int isink[NW][kLanes];
 };
-
-
 
 struct DpArgs {
     const float* C;
@@ -208,8 +206,8 @@ __device__ __attribute__((always_inline)) inline void ring_chunk(CostRing& cr, i
     lds_put(&cr.cons[wave], k + 1);
 }
 
-template <int SRC, bool SUB>
-__device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs& a, DpShared& sh, CostRing* cring,
+template <int SRC, bool SUB, class Sh>
+__device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs& a, Sh& sh, CostRing* cring,
                                                                    int wave, int p, bool have_out) {
     const int lane = threadIdx.x & 63;
     const int G = int(a.G);  // chunks per panel (rows padded to a multiple of 8)
@@ -495,8 +493,8 @@ __device__ __attribute__((always_inline)) inline void cost_producer(const DpArgs
 // Polls are back to back: under full memory load a poll's round trip is the
 // handoff's latency, and it grows with the loads a poll issues (windows of
 // 8, 16 or more chunks measured slower).
-template <bool SUB>
-__device__ __attribute__((always_inline)) inline void in_helper(const DpArgs& a, DpShared& sh, int pl,
+template <bool SUB, class Sh>
+__device__ __attribute__((always_inline)) inline void in_helper(const DpArgs& a, Sh& sh, int pl,
                                                                 uint32_t epoch) {
     constexpr int kPer = kHelperWin * 16 / kLanes;  // records per lane per poll
     const int lane = threadIdx.x & 63;
@@ -549,7 +547,8 @@ __device__ __attribute__((always_inline)) inline void in_helper(const DpArgs& a,
 
 // Input of the first panel: no left neighbour, so every boundary value is
 // +inf; the ring is filled once and published as complete.
-__device__ __attribute__((always_inline)) inline void inf_source(DpShared& sh) {
+template <class Sh>
+__device__ __attribute__((always_inline)) inline void inf_source(Sh& sh) {
     const int lane = threadIdx.x & 63;
     float* ring = &sh.ring[0][0][0][0];
     for (int e = lane; e < kRing * 2 * kChunk; e += kLanes) ring[e] = __builtin_inff();
@@ -561,8 +560,8 @@ __device__ __attribute__((always_inline)) inline void inf_source(DpShared& sh) {
 // the group (panel pl) leaves in LDS ring NW to the global records, up to four
 // chunks (64 records, one per lane) per store. Keeping these agent-scope
 // stores off the compute waves keeps their memory counter free of slow writes.
-template <bool SUB>
-__device__ __attribute__((always_inline)) inline void out_helper(const DpArgs& a, DpShared& sh, int ring_idx,
+template <bool SUB, class Sh>
+__device__ __attribute__((always_inline)) inline void out_helper(const DpArgs& a, Sh& sh, int ring_idx,
                                                                  int pl, uint32_t epoch) {
     const int lane = threadIdx.x & 63;
     const int64_t G = a.G;
@@ -599,7 +598,7 @@ __device__ __attribute__((always_inline)) inline void out_helper(const DpArgs& a
 // Panel group q (panels q*NW .. q*NW+NW-1) of one pair: NW compute waves, then
 // the input helper and the output helper.
 template <int NW, int SRC, bool SUB>
-__device__ __attribute__((always_inline)) inline void run_group(const DpArgs& a, DpShared& sh, CostRing* cring,
+__device__ __attribute__((always_inline)) inline void run_group(const DpArgs& a, DpShared<NW>& sh, CostRing* cring,
                                                                 int wave, int q, uint32_t epoch) {
     const int p0 = q * NW;
     if (wave < NW) {
@@ -619,7 +618,7 @@ __device__ __attribute__((always_inline)) inline void run_group(const DpArgs& a,
 
 // Takes the next ticket and resets the group's LDS handoff counters.
 template <int NW>
-__device__ inline int next_ticket(DpShared& sh, CostRing* cring, DpWsHeader* hdr) {
+__device__ inline int next_ticket(DpShared<NW>& sh, CostRing* cring, DpWsHeader* hdr) {
     if (threadIdx.x == 0) {
         sh.super = int(atomicAdd(&hdr->ticket, 1u));
         for (int w = 0; w <= NW; ++w) { sh.prog[w][0] = 0; sh.prog[w][1] = 0; sh.cons[w] = 0; }
@@ -633,7 +632,7 @@ __device__ inline int next_ticket(DpShared& sh, CostRing* cring, DpWsHeader* hdr
 constexpr int dp_waves(int nw, int src) { return is_fused(src) ? 2 * nw + 2 : nw + 2; }
 
 template <int NW, int SRC, bool SUB>
-__device__ __attribute__((always_inline)) inline void dp_body(const DpArgs& a, DpShared& sh, CostRing* cring) {
+__device__ __attribute__((always_inline)) inline void dp_body(const DpArgs& a, DpShared<NW>& sh, CostRing* cring) {
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);
     const uint32_t epoch = __hip_atomic_load(&a.hdr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (;;) {
@@ -646,7 +645,7 @@ __device__ __attribute__((always_inline)) inline void dp_body(const DpArgs& a, D
 
 template <int NW, int SRC, bool SUB>
 __global__ __launch_bounds__(kLanes * dp_waves(NW, SRC)) void dp_kernel(DpArgs a) {
-    __shared__ DpShared sh;
+    __shared__ DpShared<NW> sh;
     if constexpr (is_fused(SRC)) {
         static_assert(NW <= kMaxNWFused, "fused workgroups hold at most kMaxNWFused compute waves");
         __shared__ CostRing cring;
@@ -676,7 +675,7 @@ struct DpBatchArgs {
 };
 
 template <int NW, int SRC, bool SUB>
-__device__ __attribute__((always_inline)) inline void dp_batch_body(const DpBatchArgs& ba, DpShared& sh,
+__device__ __attribute__((always_inline)) inline void dp_batch_body(const DpBatchArgs& ba, DpShared<NW>& sh,
                                                                     CostRing* cring) {
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);
     const uint32_t epoch = __hip_atomic_load(&ba.hdr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -713,7 +712,7 @@ __device__ __attribute__((always_inline)) inline void dp_batch_body(const DpBatc
 
 template <int NW, int SRC, bool SUB>
 __global__ __launch_bounds__(kLanes * dp_waves(NW, SRC)) void dp_batch_kernel(DpBatchArgs ba) {
-    __shared__ DpShared sh;
+    __shared__ DpShared<NW> sh;
     if constexpr (SRC == kSrcFused) {
         static_assert(NW <= kMaxNWFused, "fused workgroups hold at most kMaxNWFused compute waves");
         __shared__ CostRing cring;

@@ -65,6 +65,7 @@ _lib_unpack = _sig("pardtw_bp_unpack", _E, [_P, _I64, _I64, _P, _P])
 _lib_ckpt_bytes = _sig("pardtw_ckpt_bytes", _SZ, [_I64, _I64, _I32])
 _lib_dp_ckpt = _sig("pardtw_dp_fused_ckpt", _E, [_P, _P, _I64, _I64, _I64, _I32, _P, _SZ, _P, _P, _P, _SZ, _P])
 _lib_ckpt_bt = _sig("pardtw_ckpt_backtrace", _E, [_P, _P, _I64, _I64, _I64, _I32, _P, _SZ, _P, _P, _P, _P])
+_lib_total = _sig("pardtw_path_total", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P])
 _lib_grad = _sig("pardtw_path_grad", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P])
 _lib_plan_create = _sig("pardtw_plan_create_ex", _E, [_I32, _P, _P, _I64, _E, _I32, ctypes.POINTER(_P)])
 _lib_plan_ws = _sig("pardtw_plan_workspace_bytes", _SZ, [_P])
@@ -184,6 +185,18 @@ def pardtw_dp_noalloc(C: torch.Tensor, n: int, m: int, bp: torch.Tensor, total: 
            "pardtw_dp_noalloc")
 
 
+def pardtw_path_total(X: torch.Tensor, Y: torch.Tensor, path: torch.Tensor, path_len: torch.Tensor,
+                      total: torch.Tensor, stream=None):
+    """The path's cost summed in two-float arithmetic (compensated total)."""
+    _dev_f32(X, "X"), _dev_f32(Y, "Y"), _dev_f32(total, "total")
+    if path.dtype != torch.int32 or path_len.dtype != torch.int32:
+        raise ValueError("path and path_len must be int32")
+    n, d = X.shape
+    m = Y.shape[0]
+    _check(_lib_total(_ptr(X), _ptr(Y), n, m, d, _ptr(path), _ptr(path_len), _ptr(total), _stream(stream)),
+           "pardtw_path_total")
+
+
 def pardtw_dp_fused(X: torch.Tensor, Y: torch.Tensor, bp: torch.Tensor, total: torch.Tensor, status: torch.Tensor,
                     workspace: torch.Tensor, stream=None, panels_per_workgroup: int = 0):
     """The DP with the cost computed inside it (FP32 features, d <= 16)."""
@@ -273,6 +286,7 @@ class Workspace:
         self.ckpt = torch.empty(ck_bytes // 4, dtype=torch.float32, device=device)
         self.ws = torch.zeros(pardtw_dp_workspace_bytes(n, m), dtype=torch.uint8, device=device)
         self.total = torch.empty(1, dtype=torch.float32, device=device)
+        self.total_comp = torch.empty(1, dtype=torch.float32, device=device)  # pardtw_path_total's output
         self.status = torch.empty(1, dtype=torch.int32, device=device)
         self.path = torch.empty((min(n, m), 2), dtype=torch.int32, device=device)
         self.path_len = torch.empty(1, dtype=torch.int32, device=device)

@@ -104,3 +104,18 @@ def test_large_pair_check_rejects_a_changed_step(monkeypatch):
     val = _large_check(monkeypatch, X, Y, path, total)
     assert not val["path_legal_rescored_and_segments_exact"]
     assert "mismatch" in val["detail"]
+
+
+def test_large_pair_check_reports_the_totals_against_1e5(monkeypatch):
+    """Both totals are judged against the FP64 re-score of the path at 1e-5,
+    with no allowance growing with the path length: a total 2e-5 off fails,
+    a compensated total equal to the re-score passes."""
+    X, Y = synth.chroma_pair(21, 3000, 3600)
+    total, path = oracle.align(X, Y)[:2]
+    path = np.asarray(path, dtype=np.int32)
+    monkeypatch.setattr(bench, "ORACLE_MAX_CELLS", 1e6)
+    monkeypatch.setattr(bench, "ORACLE_SAMPLE_FRAMES", 500)
+    _, val = bench.cpu_baseline_pair(X, Y, path, total * (1 + 2e-5), comp=total)
+    assert val["path_legal_rescored_and_segments_exact"]
+    assert val["total_within_1e-5"] is False and val["rel_bound"] == 1e-5
+    assert val["compensated_total_within_1e-5"] is True

@@ -1,0 +1,84 @@
+"""The compensated path total (pardtw_path_total) against the FP64 oracle.
+
+The DP's own total rounds once per step, in FP32; the compensated total sums
+the chosen path's costs with every rounding error carried exactly, so it
+must agree with the FP64 cost of the same path far inside the 1e-5 bound,
+also on paths long enough for the plain FP32 running sum to drift."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2607_15478_amd import synth
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - collected on CPU hosts too
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2607_15478_amd import pardtw as pd  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _total(X, Y, path):
+    Xd, Yd = torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV)
+    p = torch.from_numpy(np.ascontiguousarray(path, dtype=np.int32)).to(DEV)
+    plen = torch.tensor([len(path)], dtype=torch.int32, device=DEV)
+    out = torch.empty(1, dtype=torch.float32, device=DEV)
+    pd.pardtw_path_total(Xd, Yd, p if len(path) else torch.empty((1, 2), dtype=torch.int32, device=DEV), plen, out)
+    torch.cuda.synchronize()
+    return float(out.item())
+
+
+@pytest.mark.parametrize("n,m,seed", [(1, 1, 1), (2, 3, 2), (300, 360, 3), (1000, 1200, 4), (4000, 3000, 5)])
+def test_total_of_the_gpu_path(n, m, seed):
+    """The aligned path's compensated total against its FP64 cost and the
+    oracle's optimum (within the tie tolerance of the path audit)."""
+    rng = np.random.default_rng(seed)
+    r = (m - 1) / max(n - 1, 1)
+    X, Y = (synth.chroma_pair(seed, n, m, 12, 0.8 * r, 1.25 * r) if n >= 100
+            else (synth.chroma_like(rng, n), synth.chroma_like(rng, m)))
+    total, path, status = pd.align(torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV))
+    path = path.cpu().numpy()
+    J = oracle.path_cost(X, Y, path)
+    comp = _total(X, Y, path)
+    # FP32 costs: error relative to each distance, about 1e-6 of the total here
+    assert abs(comp - J) <= 2e-6 * J + 1e-6
+    J_opt, _, _ = oracle.align(X, Y)
+    assert comp >= J_opt * (1 - 2e-6) and comp <= J_opt * (1 + parity.TIE_REL * 10) + 1e-6
+
+
+def test_total_of_a_long_path():
+    """A 400000-cell path (diagonal runs with (1,2) and (2,1) steps mixed in)
+    over chroma-like frames: the compensated total matches the FP64 cost to
+    5e-7 relative, where a plain FP32 running sum of the same terms drifts."""
+    rng = np.random.default_rng(11)
+    steps = rng.choice(3, size=399999, p=[0.8, 0.1, 0.1])
+    d = np.array([(1, 1), (1, 2), (2, 1)])[steps]
+    path = np.concatenate([[[0, 0]], np.cumsum(d, 0)]).astype(np.int32)
+    n, m = int(path[-1, 0]) + 1, int(path[-1, 1]) + 1
+    X = synth.chroma_like(rng, n)
+    Y = synth.chroma_like(rng, m)
+    J = oracle.path_cost(X, Y, path)
+    comp = _total(X, Y, path)
+    assert abs(comp - J) <= 5e-7 * J
+    # the same terms summed in FP32 one after another, as the DP's running sum does
+    C = 1.0 - np.sum((X[path[:, 0]] / np.linalg.norm(X[path[:, 0]], axis=1, keepdims=True)) *
+                     (Y[path[:, 1]] / np.linalg.norm(Y[path[:, 1]], axis=1, keepdims=True)), axis=1)
+    w = np.concatenate([[1.0], np.array([2.0, 3.0, 3.0])[steps]])
+    run = np.float32(0.0)
+    for t in (w * C).astype(np.float32):
+        run = np.float32(run + t)
+    assert abs(float(run) - J) > 10 * abs(comp - J)
+
+
+def test_total_zero_frames_and_empty_path():
+    X = np.ones((3, 4), np.float32)
+    Y = np.ones((4, 4), np.float32)
+    X[1] = 0.0
+    path = np.array([[0, 0], [1, 2], [2, 3]], np.int32)
+    # costs 0, 1 (zero frame), 0; weights 1, 3, 2
+    assert _total(X, Y, path) == pytest.approx(3.0, abs=1e-6)
+    assert np.isinf(_total(X, Y, np.empty((0, 2), np.int32)))
