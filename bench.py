@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--serial", action="store_true",
                     help="pair workloads: run each step's backtrace before the next step's cost (no overlap "
                          "between consecutive pairs)")
+    ap.add_argument("--packed", action="store_true",
+                    help="pair workloads: codes packed 2 bits per cell (pardtw_dp_packed / pardtw_dp_fused_packed "
+                         "and pardtw_backtrace_packed), a memory mode")
     ap.add_argument("--ckpt", type=int, default=0, metavar="K",
                     help="checkpointed DTW: fused DP keeping only D rows every K rows, then the recomputing "
                          "backtrace (no code matrix; K a multiple of 16 in [16, 256])")
@@ -313,7 +316,7 @@ def main():
     if K:
         w = pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=False, ckpt_rows=K)
     else:
-        w = pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=not args.fused)
+        w = pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=not args.fused, packed=args.packed)
     stream = torch.cuda.current_stream()
 
     calib = None
@@ -350,7 +353,7 @@ def main():
             if K:
                 bufs.append(pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=False, ckpt_rows=K))
             else:
-                bufs.append(pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=not args.fused))
+                bufs.append(pd.Workspace(n, m, dev, pd.LAYOUT_PANEL_BAND, cost=not args.fused, packed=args.packed))
         pipelined = len(bufs) > 1
         bts = [torch.cuda.Stream(device=dev) for _ in range(len(bufs) - 1)]  # default priority
         side = (stream, bts)
@@ -383,13 +386,22 @@ def main():
             continue
         if args.fused:
             e[1].record(stream)
-            pd.pardtw_dp_fused(Xd, Yd, w.bp, w.total, w.status, w.ws)
+            if args.packed:
+                pd.pardtw_dp_fused_packed(Xd, Yd, w.bp, w.total, w.status, w.ws)
+            else:
+                pd.pardtw_dp_fused(Xd, Yd, w.bp, w.total, w.status, w.ws)
         else:
             pd.pardtw_cost(Xd, Yd, w.C, pd.PREC_F32, pd.LAYOUT_PANEL_BAND)
             e[1].record(stream)
-            pd.pardtw_dp(w.C, n, m, w.bp, w.total, w.status, w.ws, pd.LAYOUT_PANEL_BAND)
+            if args.packed:
+                pd.pardtw_dp_packed(w.C, n, m, w.bp, w.total, w.status, w.ws, pd.LAYOUT_PANEL_BAND)
+            else:
+                pd.pardtw_dp(w.C, n, m, w.bp, w.total, w.status, w.ws, pd.LAYOUT_PANEL_BAND)
         e[2].record(stream)
-        pd.pardtw_backtrace(w.bp, n, m, w.status, w.path, w.path_len)
+        if args.packed:
+            pd.pardtw_backtrace_packed(w.bp, n, m, w.status, w.path, w.path_len)
+        else:
+            pd.pardtw_backtrace(w.bp, n, m, w.status, w.path, w.path_len)
         if comp:
             pd.pardtw_path_total(Xd, Yd, w.path, w.path_len, w.total_comp)
         e[3].record(stream)
@@ -434,7 +446,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "d": d, "cells": cells,
-                   "layout": "fused_cost" if args.fused else "panel64_band",
+                   "layout": ("fused_cost" if args.fused else "panel64_band") + ("+packed_codes" if args.packed else ""),
                    "schedule": "serial: cost, DP and backtrace of one pair, then the next",
                    "pairs_per_s": round(1e3 / ms_per_step, 3),
                    "stage_ms": {"cost": round(float(cost_ms), 4), "dp": round(float(dp_ms), 4),
@@ -476,8 +488,12 @@ def launch_pipelined(pd, Xd, Yd, bufs, stream, side, steps, fused, K, evs, after
         e[2].record(stream)
         if K:
             pd.pardtw_dp_fused_ckpt(Xd, Yd, K, w.ckpt, w.total, w.status, w.ws, stream=stream)
+        elif fused and w.packed:
+            pd.pardtw_dp_fused_packed(Xd, Yd, w.bp, w.total, w.status, w.ws, stream=stream)
         elif fused:
             pd.pardtw_dp_fused(Xd, Yd, w.bp, w.total, w.status, w.ws, stream=stream)
+        elif w.packed:
+            pd.pardtw_dp_packed(w.C, n, m, w.bp, w.total, w.status, w.ws, pd.LAYOUT_PANEL_BAND, stream=stream)
         else:
             pd.pardtw_dp(w.C, n, m, w.bp, w.total, w.status, w.ws, pd.LAYOUT_PANEL_BAND, stream=stream)
         e[3].record(stream)
@@ -485,6 +501,8 @@ def launch_pipelined(pd, Xd, Yd, bufs, stream, side, steps, fused, K, evs, after
         e[4].record(s_bt)
         if K:
             pd.pardtw_ckpt_backtrace(Xd, Yd, K, w.ckpt, w.status, w.path, w.path_len, stream=s_bt)
+        elif w.packed:
+            pd.pardtw_backtrace_packed(w.bp, n, m, w.status, w.path, w.path_len, stream=s_bt)
         else:
             pd.pardtw_backtrace(w.bp, n, m, w.status, w.path, w.path_len, stream=s_bt)
         if after_bt is not None:
@@ -553,7 +571,7 @@ def run_pair_pipelined(args, X, Y, Xd, Yd, bufs, stream, side, cells, calib):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "d": d, "cells": cells,
-                   "layout": "fused_cost" if args.fused else "panel64_band",
+                   "layout": ("fused_cost" if args.fused else "panel64_band") + ("+packed_codes" if args.packed else ""),
                    "schedule": layout,
                    "pairs_per_s": round(1e3 / ms_per_step, 3),
                    "latency_ms": round(float(cost_ms + dp_ms + bt_ms), 4),

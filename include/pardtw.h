@@ -202,6 +202,37 @@ pardtw_status pardtw_backtrace(const uint8_t* bp, int64_t n, int64_t m, const in
 pardtw_status pardtw_bp_unpack(const uint8_t* bp, int64_t n, int64_t m, int8_t* out,
                                hipStream_t stream);
 
+/* ---- Packed codes: 2 bits per cell (Sec. VI-D stores the transition types as
+ * 2-bit values) -------------------------------------------------------------
+ * A memory mode, not the throughput default: the codes take a quarter of the
+ * bytes, so longer pairs fit (the code matrix plus the DP's 0.25 B per cell of
+ * boundary records: 0.5 B per cell with the fused cost, against 1.25 B), at a
+ * few percent of sweep time. Layout: one 16-bit word per column and 8-row
+ * group, row r of the group in bits 2r, 2r+1:
+ *   word((i,j)) = (p*G + i/8)*64 + (j%64),  p = j/64, G = ceil(N/8),
+ * the same codes as the byte layout (0, 1, 2 by step, 3 at the origin), on the
+ * same band. pardtw_bp2_bytes gives the buffer size (0 on bad args). */
+size_t pardtw_bp2_bytes(int64_t n, int64_t m);
+
+/* pardtw_dp with packed codes: same arguments and results, bp2 [device,
+ * pardtw_bp2_bytes(n,m) bytes, 16-byte aligned]. Layouts PANEL or PANEL_BAND
+ * (PARDTW_ERR_UNSUPPORTED for ROW). */
+pardtw_status pardtw_dp_packed(const float* C, pardtw_layout layout, int64_t n, int64_t m, uint16_t* bp2,
+                               float* total, int32_t* pair_status, void* workspace, size_t workspace_bytes,
+                               hipStream_t stream);
+
+/* pardtw_dp_fused with packed codes (FP32 features, 1 <= d <= 16). */
+pardtw_status pardtw_dp_fused_packed(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
+                                     uint16_t* bp2, float* total, int32_t* pair_status, void* workspace,
+                                     size_t workspace_bytes, hipStream_t stream);
+
+/* pardtw_backtrace over packed codes: the same path. bp2 16-byte aligned. */
+pardtw_status pardtw_backtrace_packed(const uint16_t* bp2, int64_t n, int64_t m, const int32_t* pair_status,
+                                      int32_t* path, int32_t* path_len, hipStream_t stream);
+
+/* Inspection helper: packed codes as a row-major n x m int8 matrix. */
+pardtw_status pardtw_bp2_unpack(const uint16_t* bp2, int64_t n, int64_t m, int8_t* out, hipStream_t stream);
+
 /* Checkpointed DTW: the exact path without the n x m code matrix, for pairs
  * whose codes would not fit in memory (Sec. II-D names memory as the limit on
  * length and cites a divide-and-conquer recomputation as the way past it).

@@ -224,7 +224,10 @@ __device__ int walk(BtShared& sh, int n, int j_end, bool sub, int cap, int32_t* 
 }
 
 // Loader wave w: serves requests w, w + kLoaders, ... (each alone), compacting
-// the codes of each (group, column) to 16 bits.
+// the codes of each (group, column) to 16 bits. With PACK the codes already are
+// 16 bits per (group, column) in HBM, in the slot's own order, so the
+// requested groups are copied as they are.
+template <bool PACK>
 __device__ void load_panels(BtShared& sh, const uint8_t* bp, int64_t G, int w) {
     const int lane = threadIdx.x & (kLanes - 1);
     for (int r = w;; r += kLoaders) {
@@ -235,6 +238,27 @@ __device__ void load_panels(BtShared& sh, const uint8_t* bp, int64_t G, int w) {
         const int e = r % kSlots;
         const int p = sh.req_panel[e];
         const int glo = sh.req_glo[e];
+        if constexpr (PACK) {
+            const int bytes = sh.req_ng[e] * kPanel * 2;  // a multiple of 128
+            const uint8_t* src = bp + (int64_t(p) * G + glo) * (kPanel * 2);
+            uint8_t* dst = sh.slot[p % kSlots];
+            for (int u0 = 0; u0 < bytes; u0 += kUnitBytes * kBatch) {
+                uint4 buf[kBatch];
+#pragma unroll
+                for (int t = 0; t < kBatch; ++t) {
+                    const int off = u0 + t * kUnitBytes + lane * 16;
+                    buf[t] = *reinterpret_cast<const uint4*>(src + (off < bytes ? off : bytes - 16));
+                }
+#pragma unroll
+                for (int t = 0; t < kBatch; ++t) {
+                    const int off = u0 + t * kUnitBytes + lane * 16;
+                    if (off < bytes) *reinterpret_cast<uint4*>(dst + off) = buf[t];
+                }
+            }
+            if (lane == 0)
+                __hip_atomic_fetch_add(&sh.loaded[p % kSlots], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            continue;
+        }
         const int bytes = sh.req_ng[e] * kGroupBytes;
         const int units = (bytes + kUnitBytes - 1) / kUnitBytes;
         const uint8_t* src = bp + (int64_t(p) * G + glo) * kGroupBytes;
@@ -287,7 +311,8 @@ __device__ void shift_path(int32_t* path, int64_t base, int64_t len) {
 }
 
 // One path: DTW from (n-1, m-1) when `ok` (the pair's status), or with `sub`
-// from (n-1, j_end) to row 0.
+// from (n-1, j_end) to row 0. PACK: codes packed 2 bits per cell.
+template <bool PACK = false>
 __device__ void backtrace_pair(BtShared& sh, const uint8_t* bp, int n, int j_end, bool sub, bool ok, int cap,
                                int32_t* path, int32_t* path_len) {
     const int tid = threadIdx.x;
@@ -310,7 +335,7 @@ __device__ void backtrace_pair(BtShared& sh, const uint8_t* bp, int n, int j_end
             lds_store_release(&sh.done, 1);
         }
     } else {
-        load_panels(sh, bp, bp_groups(n), wave - 1);
+        load_panels<PACK>(sh, bp, bp_groups(n), wave - 1);
     }
     __syncthreads();
     const int len = sh.len;
@@ -324,6 +349,14 @@ __global__ __launch_bounds__(kThreads) void backtrace_kernel(const uint8_t* __re
                                                              int32_t* path_len) {
     __shared__ BtShared sh;
     backtrace_pair(sh, bp, int(n), int(m - 1), false, *status == PARDTW_PAIR_OK, int(n < m ? n : m), path, path_len);
+}
+
+__global__ __launch_bounds__(kThreads) void backtrace_packed_kernel(const uint8_t* __restrict__ bp2, int64_t n,
+                                                                    int64_t m, const int32_t* __restrict__ status,
+                                                                    int32_t* path, int32_t* path_len) {
+    __shared__ BtShared sh;
+    backtrace_pair<true>(sh, bp2, int(n), int(m - 1), false, *status == PARDTW_PAIR_OK, int(n < m ? n : m), path,
+                         path_len);
 }
 
 // A subsequence end is usable when it is a column of the matrix that row 0
@@ -372,6 +405,14 @@ __global__ void bp_unpack_kernel(const uint8_t* __restrict__ bp, int64_t n, int6
     out[idx] = int8_t(bp[bp_offset(n, i, j)]);
 }
 
+__global__ void bp2_unpack_kernel(const uint16_t* __restrict__ bp2, int64_t n, int64_t m, int8_t* __restrict__ out) {
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n * m) return;
+    const int64_t i = idx / m, j = idx % m;
+    const int64_t word = (j / kPanel * bp_groups(n) + i / kBpRows) * kPanel + j % kPanel;
+    out[idx] = int8_t((bp2[word] >> (2 * (i % kBpRows))) & 3u);
+}
+
 }  // namespace
 
 pardtw_status backtrace_batch_launch(const BatchPair* pairs, int32_t batch, const uint8_t* bpbase,
@@ -413,5 +454,25 @@ extern "C" pardtw_status pardtw_bp_unpack(const uint8_t* bp, int64_t n, int64_t 
     const int64_t blocks = pardtw::ceil_div(cells, 256);
     if (blocks > 0x7fffffff) return PARDTW_ERR_UNSUPPORTED;
     pardtw::bp_unpack_kernel<<<unsigned(blocks), 256, 0, stream>>>(bp, n, m, out);
+    return pardtw::launch_status();
+}
+
+extern "C" pardtw_status pardtw_backtrace_packed(const uint16_t* bp2, int64_t n, int64_t m,
+                                                 const int32_t* pair_status, int32_t* path, int32_t* path_len,
+                                                 hipStream_t stream) {
+    if (!bp2 || !pair_status || !path || !path_len || !pardtw::valid_sizes(n, m)) return PARDTW_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(path) % 8 != 0 || reinterpret_cast<uintptr_t>(bp2) % 16 != 0)
+        return PARDTW_ERR_INVALID_ARG;
+    pardtw::backtrace_packed_kernel<<<1, pardtw::kThreads, 0, stream>>>(reinterpret_cast<const uint8_t*>(bp2), n, m,
+                                                                       pair_status, path, path_len);
+    return pardtw::launch_status();
+}
+
+extern "C" pardtw_status pardtw_bp2_unpack(const uint16_t* bp2, int64_t n, int64_t m, int8_t* out,
+                                           hipStream_t stream) {
+    if (!bp2 || !out || !pardtw::valid_sizes(n, m)) return PARDTW_ERR_INVALID_ARG;
+    const int64_t blocks = pardtw::ceil_div(n * m, 256);
+    if (blocks > 0x7fffffff) return PARDTW_ERR_UNSUPPORTED;
+    pardtw::bp2_unpack_kernel<<<unsigned(blocks), 256, 0, stream>>>(bp2, n, m, out);
     return pardtw::launch_status();
 }

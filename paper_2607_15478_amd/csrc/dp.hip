@@ -70,8 +70,11 @@ constexpr int kCRing = 8;        // fused cost ring depth, in chunks (2 KB each)
 // Where the DP's costs come from.
 // kSrcFusedCk: fused costs, no codes, and D of the last two rows of every
 // block of rows saved for the checkpointed backtrace.
-enum CostSrc { kSrcRow = 0, kSrcPanel = 1, kSrcFused = 2, kSrcFusedCk = 3 };
-constexpr bool is_fused(int src) { return src == kSrcFused || src == kSrcFusedCk; }
+// kSrcPanelPk / kSrcFusedPk: panel or fused costs, codes packed 2 bits per
+// cell (one 16-bit word per column and 8-row group).
+enum CostSrc { kSrcRow = 0, kSrcPanel = 1, kSrcFused = 2, kSrcFusedCk = 3, kSrcPanelPk = 4, kSrcFusedPk = 5 };
+constexpr bool is_fused(int src) { return src == kSrcFused || src == kSrcFusedCk || src == kSrcFusedPk; }
+constexpr bool is_packed(int src) { return src == kSrcPanelPk || src == kSrcFusedPk; }
 
 // Fused cost: per compute wave a ring of cost chunks in the panel layout
 // (rows 0-3 of the 64 columns, then rows 4-7), and its progress counters.
@@ -235,7 +238,8 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
     int ck_q = kCk ? (k0 + 1 + a.ck_chunks - 1) / a.ck_chunks - 1 : 0;
     int ck_next = kCk ? (ck_q + 1) * a.ck_chunks - 1 : 0;
     const int ck_q0 = ck_q;
-    constexpr int kPf = kFused ? 1 : SRC == kSrcPanel ? kPfPanel : kPfRow;
+    constexpr bool kPack = is_packed(SRC);
+    constexpr int kPf = kFused ? 1 : SRC == kSrcRow ? kPfRow : kPfPanel;
     float cbuf[kPf][kChunk];
     int cprog_seen = 0;
     if constexpr (kFused) {
@@ -319,11 +323,12 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
 
             uint32_t lo, hi;
             float best_r[kChunk];
-            dp_rows<SUB>(cbuf[u], lv0, lv1, e0, e1, d1, s1p, lo, hi, best_r);
+            dp_rows<SUB, kPack>(cbuf[u], lv0, lv1, e0, e1, d1, s1p, lo, hi, best_r);
             if (SUB) {
                 if (k == 0) lo = (lo & ~0xffu) | 3u;  // row 0: every cell is a start
             } else if (p == 0 && k == 0) {
-                lo = (lane == 0) ? ((lo & ~0xffu) | 3u) : lo;  // the origin's code
+                const uint32_t row0 = kPack ? 0x3u : 0xffu;
+                lo = (lane == 0) ? ((lo & ~row0) | 3u) : lo;  // the origin's code
             }
             e0 = lv0[kChunk - 1];
             e1 = lv1[kChunk - 1];
@@ -338,6 +343,11 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
                     ++ck_q;
                     ck_next += a.ck_chunks;
                 }
+            } else if constexpr (kPack) {
+                // one 16-bit word per lane: 128 bytes per chunk
+                uint16_t* cdst = inside ? reinterpret_cast<uint16_t*>(a.bp) + (int64_t(p) * G + k) * kLanes
+                                        : reinterpret_cast<uint16_t*>(a.hdr->sink);
+                __builtin_nontemporal_store(uint16_t(lo), cdst + lane);
             } else {
                 uint64_t* cdst = inside ? bp_pan + int64_t(k) * kLanes : a.hdr->sink;
                 __builtin_nontemporal_store(uint64_t(lo) | (uint64_t(hi) << 32), cdst + lane);
@@ -769,8 +779,11 @@ template <int NW>
 void launch_nw(const DpArgs& a, int src, bool sub, int grid, hipStream_t stream) {
     if (src == kSrcPanel) launch_src<NW, kSrcPanel>(a, sub, grid, stream);
     else if (src == kSrcRow) launch_src<NW, kSrcRow>(a, sub, grid, stream);
+    else if (src == kSrcPanelPk) dp_kernel<NW, kSrcPanelPk, false><<<grid, kLanes * dp_waves(NW, src), 0, stream>>>(a);
     else if constexpr (NW <= kMaxNWFused) {
         if (src == kSrcFused) launch_src<NW, kSrcFused>(a, sub, grid, stream);
+        else if (src == kSrcFusedPk)
+            dp_kernel<NW, kSrcFusedPk, false><<<grid, kLanes * dp_waves(NW, kSrcFusedPk), 0, stream>>>(a);
         else dp_kernel<NW, kSrcFusedCk, false><<<grid, kLanes * dp_waves(NW, kSrcFusedCk), 0, stream>>>(a);
     }
 }
@@ -1025,4 +1038,29 @@ extern "C" pardtw_status pardtw_dp_noalloc(const float* C, pardtw_layout layout,
     if (const pardtw_status st = scratch_address(&ws); st != PARDTW_OK) return st;
     return pardtw::dp_launch(C, nullptr, nullptr, 0, pardtw::src_of(layout), n, m, bp, total, pair_status, ws, 0,
                              false, stream);
+}
+
+extern "C" size_t pardtw_bp2_bytes(int64_t n, int64_t m) {
+    if (!pardtw::valid_sizes(n, m)) return 0;
+    return size_t(pardtw::num_panels(m)) * size_t(pardtw::bp_groups(n)) * pardtw::kLanes * sizeof(uint16_t);
+}
+
+extern "C" pardtw_status pardtw_dp_packed(const float* C, pardtw_layout layout, int64_t n, int64_t m, uint16_t* bp2,
+                                          float* total, int32_t* pair_status, void* workspace,
+                                          size_t workspace_bytes, hipStream_t stream) {
+    if (!C || !bp2 || !total || !pair_status || !pardtw::valid_sizes(n, m)) return PARDTW_ERR_INVALID_ARG;
+    if (layout != PARDTW_LAYOUT_PANEL && layout != PARDTW_LAYOUT_PANEL_BAND) return PARDTW_ERR_UNSUPPORTED;
+    if (!workspace || workspace_bytes < pardtw::dp_workspace_bytes_impl(n, m)) return PARDTW_ERR_WORKSPACE;
+    return pardtw::dp_launch(C, nullptr, nullptr, 0, pardtw::kSrcPanelPk, n, m, reinterpret_cast<uint8_t*>(bp2),
+                             total, pair_status, workspace, 0, false, stream);
+}
+
+extern "C" pardtw_status pardtw_dp_fused_packed(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
+                                                uint16_t* bp2, float* total, int32_t* pair_status, void* workspace,
+                                                size_t workspace_bytes, hipStream_t stream) {
+    const pardtw_status st = check_fused(X, Y, n, m, d, reinterpret_cast<uint8_t*>(bp2), total, pair_status,
+                                         workspace, workspace_bytes, 0);
+    if (st != PARDTW_OK) return st;
+    return pardtw::dp_launch(nullptr, X, Y, d, pardtw::kSrcFusedPk, n, m, reinterpret_cast<uint8_t*>(bp2), total,
+                             pair_status, workspace, 0, false, stream);
 }

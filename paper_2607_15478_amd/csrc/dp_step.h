@@ -29,8 +29,10 @@ __device__ inline float shift_in(float v, float edge) {
 }
 
 // One 8-row chunk of a panel. `lv0/lv1` hold the left boundary columns
-// D[i0+r][64p-2] / D[i0+r][64p-1]; e0/e1 the same for row i0-1.
-template <bool SUB>
+// D[i0+r][64p-2] / D[i0+r][64p-1]; e0/e1 the same for row i0-1. The codes of
+// the 8 rows come back one byte per row (row r in byte r of lo, hi), or with
+// PACK as 2 bits per row in lo (row r in bits 2r, 2r+1; hi = 0).
+template <bool SUB, bool PACK = false>
 __device__ __attribute__((always_inline)) inline void dp_rows(const float (&cb)[kChunk], const float (&lv0)[kChunk],
                                                               const float (&lv1)[kChunk], float e0, float e1,
                                                               float& d1, float& s1p, uint32_t& lo, uint32_t& hi,
@@ -48,7 +50,9 @@ __device__ __attribute__((always_inline)) inline void dp_rows(const float (&cb)[
         const float best = __builtin_fminf(__builtin_fminf(c0, c1), c2);
         uint32_t code = (c1 == best) ? 1u : 2u;
         code = (c0 == best) ? 0u : code;
-        if (r < 4) lo |= code << (8 * r); else hi |= code << (8 * (r - 4));
+        if (PACK) lo |= code << (2 * r);
+        else if (r < 4) lo |= code << (8 * r);
+        else hi |= code << (8 * (r - 4));
         d1 = best;
         s1p = s1;
         best_r[r] = best;

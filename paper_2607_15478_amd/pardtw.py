@@ -62,6 +62,11 @@ _lib_bt = _sig("pardtw_backtrace", _E, [_P, _I64, _I64, _P, _P, _P, _P])
 _lib_dp_fused = _sig("pardtw_dp_fused", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _SZ, _I32, _P])
 _lib_sub_dp_fused = _sig("pardtw_subseq_dp_fused", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _SZ, _P])
 _lib_unpack = _sig("pardtw_bp_unpack", _E, [_P, _I64, _I64, _P, _P])
+_lib_bp2_bytes = _sig("pardtw_bp2_bytes", _SZ, [_I64, _I64])
+_lib_dp_packed = _sig("pardtw_dp_packed", _E, [_P, _E, _I64, _I64, _P, _P, _P, _P, _SZ, _P])
+_lib_dp_fused_packed = _sig("pardtw_dp_fused_packed", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _SZ, _P])
+_lib_bt_packed = _sig("pardtw_backtrace_packed", _E, [_P, _I64, _I64, _P, _P, _P, _P])
+_lib_unpack2 = _sig("pardtw_bp2_unpack", _E, [_P, _I64, _I64, _P, _P])
 _lib_ckpt_bytes = _sig("pardtw_ckpt_bytes", _SZ, [_I64, _I64, _I32])
 _lib_dp_ckpt = _sig("pardtw_dp_fused_ckpt", _E, [_P, _P, _I64, _I64, _I64, _I32, _P, _SZ, _P, _P, _P, _SZ, _P])
 _lib_ckpt_bt = _sig("pardtw_ckpt_backtrace", _E, [_P, _P, _I64, _I64, _I64, _I32, _P, _SZ, _P, _P, _P, _P])
@@ -252,6 +257,55 @@ def pardtw_backtrace(bp: torch.Tensor, n: int, m: int, status: torch.Tensor, pat
            "pardtw_backtrace")
 
 
+def pardtw_bp2_bytes(n: int, m: int) -> int:
+    return int(_lib_bp2_bytes(n, m))
+
+
+def _check_bp2(bp2: torch.Tensor, n: int, m: int):
+    if bp2.dtype != torch.uint8 or bp2.numel() < pardtw_bp2_bytes(n, m) or bp2.data_ptr() % 16:
+        raise ValueError("bp2 must be a 16-byte aligned uint8 tensor of pardtw_bp2_bytes(n, m) bytes")
+
+
+def pardtw_dp_packed(C: torch.Tensor, n: int, m: int, bp2: torch.Tensor, total: torch.Tensor,
+                     status: torch.Tensor, workspace: torch.Tensor, layout: int = LAYOUT_PANEL_BAND, stream=None):
+    """pardtw_dp with 2-bit packed codes."""
+    _dev_f32(C, "C")
+    if C.numel() < pardtw_cost_elems(n, m, layout):
+        raise ValueError("C is too small for this layout")
+    _check_bp2(bp2, n, m)
+    ws_bytes = workspace.numel() * workspace.element_size()
+    _check(_lib_dp_packed(_ptr(C), layout, n, m, _ptr(bp2), _ptr(total), _ptr(status), _ptr(workspace), ws_bytes,
+                          _stream(stream)), "pardtw_dp_packed")
+
+
+def pardtw_dp_fused_packed(X: torch.Tensor, Y: torch.Tensor, bp2: torch.Tensor, total: torch.Tensor,
+                           status: torch.Tensor, workspace: torch.Tensor, stream=None):
+    """pardtw_dp_fused with 2-bit packed codes."""
+    _dev_f32(X, "X"), _dev_f32(Y, "Y")
+    n, d = X.shape
+    m = Y.shape[0]
+    _check_bp2(bp2, n, m)
+    ws_bytes = workspace.numel() * workspace.element_size()
+    _check(_lib_dp_fused_packed(_ptr(X), _ptr(Y), n, m, d, _ptr(bp2), _ptr(total), _ptr(status), _ptr(workspace),
+                                ws_bytes, _stream(stream)), "pardtw_dp_fused_packed")
+
+
+def pardtw_backtrace_packed(bp2: torch.Tensor, n: int, m: int, status: torch.Tensor, path: torch.Tensor,
+                            path_len: torch.Tensor, stream=None):
+    _check_bp2(bp2, n, m)
+    if path.dtype != torch.int32 or path.numel() < 2 * min(n, m):
+        raise ValueError("path must be int32 with room for 2*min(n, m) entries")
+    _check(_lib_bt_packed(_ptr(bp2), n, m, _ptr(status), _ptr(path), _ptr(path_len), _stream(stream)),
+           "pardtw_backtrace_packed")
+
+
+def pardtw_bp2_unpack(bp2: torch.Tensor, n: int, m: int, out: Optional[torch.Tensor] = None, stream=None):
+    if out is None:
+        out = torch.empty((n, m), dtype=torch.int8, device=bp2.device)
+    _check(_lib_unpack2(_ptr(bp2), n, m, _ptr(out), _stream(stream)), "pardtw_bp2_unpack")
+    return out
+
+
 def pardtw_bp_unpack(bp: torch.Tensor, n: int, m: int, out: Optional[torch.Tensor] = None, stream=None):
     if out is None:
         out = torch.empty((n, m), dtype=torch.int8, device=bp.device)
@@ -271,7 +325,7 @@ class Workspace:
     """Device buffers for one (n, m) alignment, reusable across calls."""
 
     def __init__(self, n: int, m: int, device="cuda", layout: int = LAYOUT_PANEL_BAND, cost: bool = True,
-                 ckpt_rows: int = 0):
+                 ckpt_rows: int = 0, packed: bool = False):
         self.n, self.m, self.layout = n, m, layout
         # no cost buffer when the DP computes the costs itself; with ckpt_rows
         # (checkpointed backtrace, fused cost) no codes either
@@ -279,7 +333,10 @@ class Workspace:
         if self.ckpt_rows and cost:
             raise ValueError("the checkpointed DP computes its costs itself (cost=False)")
         self.C = torch.empty(pardtw_cost_elems(n, m, layout) if cost else 0, dtype=torch.float32, device=device)
-        self.bp = torch.empty(0 if self.ckpt_rows else pardtw_bp_bytes(n, m), dtype=torch.uint8, device=device)
+        # packed: codes 2 bits per cell (pardtw_dp_packed / pardtw_dp_fused_packed)
+        self.packed = bool(packed)
+        code_bytes = pardtw_bp2_bytes(n, m) if self.packed else pardtw_bp_bytes(n, m)
+        self.bp = torch.empty(0 if self.ckpt_rows else code_bytes, dtype=torch.uint8, device=device)
         if self.ckpt_rows and (self.ckpt_rows % 16 or not 16 <= self.ckpt_rows <= CKPT_MAX_ROWS):
             raise ValueError(f"ckpt_rows must be a multiple of 16 in [16, {CKPT_MAX_ROWS}]")
         ck_bytes = pardtw_ckpt_bytes(n, m, self.ckpt_rows) if self.ckpt_rows else 0
@@ -306,11 +363,20 @@ def align_into(X: torch.Tensor, Y: torch.Tensor, w: Workspace, prec: int = PREC_
     if fused:
         if prec != PREC_F32:
             raise ValueError("the fused DP computes FP32 costs")
-        pardtw_dp_fused(X, Y, w.bp, w.total, w.status, w.ws, stream)
+        if w.packed:
+            pardtw_dp_fused_packed(X, Y, w.bp, w.total, w.status, w.ws, stream)
+        else:
+            pardtw_dp_fused(X, Y, w.bp, w.total, w.status, w.ws, stream)
     else:
         pardtw_cost(X, Y, w.C, prec, w.layout, stream)
-        pardtw_dp(w.C, n, m, w.bp, w.total, w.status, w.ws, w.layout, stream)
-    pardtw_backtrace(w.bp, n, m, w.status, w.path, w.path_len, stream)
+        if w.packed:
+            pardtw_dp_packed(w.C, n, m, w.bp, w.total, w.status, w.ws, w.layout, stream)
+        else:
+            pardtw_dp(w.C, n, m, w.bp, w.total, w.status, w.ws, w.layout, stream)
+    if w.packed:
+        pardtw_backtrace_packed(w.bp, n, m, w.status, w.path, w.path_len, stream)
+    else:
+        pardtw_backtrace(w.bp, n, m, w.status, w.path, w.path_len, stream)
     return w
 
 

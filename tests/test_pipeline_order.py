@@ -48,6 +48,15 @@ class Lib:
     def pardtw_dp_fused(self, X, Y, bp, total, status, ws, stream):
         self._call("dp", bp.owner, stream)
 
+    def pardtw_dp_packed(self, C, n, m, bp, total, status, ws, layout, stream):
+        self._call("dp_packed", bp.owner, stream)
+
+    def pardtw_dp_fused_packed(self, X, Y, bp, total, status, ws, stream):
+        self._call("dp_packed", bp.owner, stream)
+
+    def pardtw_backtrace_packed(self, bp, n, m, status, path, path_len, stream):
+        self._call("bt_packed", bp.owner, stream)
+
     def pardtw_dp_fused_ckpt(self, X, Y, K, ckpt, total, status, ws, stream):
         self._call("dp", ckpt.owner, stream)
 
@@ -64,8 +73,9 @@ class Buf:
 
 
 class Workspace:
-    def __init__(self, name):
+    def __init__(self, name, packed=False):
         self.name = name
+        self.packed = packed
         for f in ("C", "bp", "ckpt", "total", "status", "ws", "path", "path_len"):
             setattr(self, f, Buf(self))
 
@@ -74,14 +84,16 @@ class Shape:
     shape = (100, 12)
 
 
-@pytest.mark.parametrize("fused,K", [(False, 0), (True, 0), (False, 64)])
+@pytest.mark.parametrize("fused,K,packed", [(False, 0, False), (True, 0, False), (False, 64, False),
+                                            (False, 0, True), (True, 0, True)])
 @pytest.mark.parametrize("nbuf,nbt", [(2, 1), (3, 2), (2, 2)])
-def test_pipelined_order(fused, K, nbuf, nbt):
+def test_pipelined_order(fused, K, packed, nbuf, nbt):
     log = []
     steps = 9
     stream = Stream(log, "main")
     bts = [Stream(log, f"bt{i}") for i in range(nbt)]
-    bufs = [Workspace(f"w{i}") for i in range(nbuf)]
+    bufs = [Workspace(f"w{i}", packed) for i in range(nbuf)]
+    dp_kind, bt_kind = ("dp_packed", "bt_packed") if packed else ("dp", "bt")
     evs = [[Event(log, (s, k)) for k in range(6)] for s in range(steps)]
     bench.launch_pipelined(Lib(log), Shape(), Shape(), bufs, stream, (stream, bts), steps, fused, K, evs)
 
@@ -91,8 +103,8 @@ def test_pipelined_order(fused, K, nbuf, nbt):
     for s in range(steps):
         w = f"w{s % nbuf}"
         s_bt = f"bt{s % nbt}"
-        dp = pos(("call", "main", "dp", w, s))
-        bt = pos(("call", s_bt, "bt", w, s))
+        dp = pos(("call", "main", dp_kind, w, s))
+        bt = pos(("call", s_bt, bt_kind, w, s))
         # the backtrace waits on this pair's DP end event, recorded after the DP call
         dp_end = pos(("record", "main", (s, 3)))
         assert dp < dp_end < pos(("wait", s_bt, (s, 3))) < bt
@@ -104,7 +116,7 @@ def test_pipelined_order(fused, K, nbuf, nbt):
             # the backtrace of pair s - nbuf, which read them, has ended
             prev_bt_end = pos(("record", f"bt{(s - nbuf) % nbt}", (s - nbuf, 5)))
             assert prev_bt_end < pos(("wait", "main", (s - nbuf, 5))) < dp
-            assert pos(("call", f"bt{(s - nbuf) % nbt}", "bt", w, s - nbuf)) < prev_bt_end
+            assert pos(("call", f"bt{(s - nbuf) % nbt}", bt_kind, w, s - nbuf)) < prev_bt_end
             if not fused and not K:
                 # and the cost matrix only after the DP of pair s - nbuf, which read it
                 assert pos(("wait", "main", (s - nbuf, 3))) < pos(("call", "main", "cost", w, s))
