@@ -94,6 +94,13 @@ ORACLE_MAX_CELLS = 5e9
 ORACLE_SAMPLE_FRAMES = 20000
 
 
+def workspace_device_bytes(w) -> int:
+    """Device bytes one pair's workspace holds: cost matrix, codes or
+    checkpoints, DP workspace (header, boundary records, row norms), path."""
+    return int(sum(t.numel() * t.element_size()
+                   for t in (w.C, w.bp, w.ws, w.ckpt, w.path, w.path_len, w.total, w.status) if t is not None))
+
+
 def cpu_baseline_pair(X, Y, path, total, validate=True, comp=None):
     """The oracle (single-threaded FP64 DTW with codes) timed on the whole pair;
     its result is then used to check the GPU path and total. The only use of
@@ -447,6 +454,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "d": d, "cells": cells,
                    "layout": ("fused_cost" if args.fused else "panel64_band") + ("+packed_codes" if args.packed else ""),
+                   "device_bytes_per_pair": workspace_device_bytes(w),
+                   "device_bytes_per_cell": round(workspace_device_bytes(w) / cells, 4),
                    "schedule": "serial: cost, DP and backtrace of one pair, then the next",
                    "pairs_per_s": round(1e3 / ms_per_step, 3),
                    "stage_ms": {"cost": round(float(cost_ms), 4), "dp": round(float(dp_ms), 4),
@@ -572,6 +581,8 @@ def run_pair_pipelined(args, X, Y, Xd, Yd, bufs, stream, side, cells, calib):
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "d": d, "cells": cells,
                    "layout": ("fused_cost" if args.fused else "panel64_band") + ("+packed_codes" if args.packed else ""),
+                   "device_bytes_per_pair": workspace_device_bytes(bufs[0]),
+                   "device_bytes_per_cell": round(workspace_device_bytes(bufs[0]) / cells, 4),
                    "schedule": layout,
                    "pairs_per_s": round(1e3 / ms_per_step, 3),
                    "latency_ms": round(float(cost_ms + dp_ms + bt_ms), 4),
@@ -658,6 +669,8 @@ def ckpt_result(args, X, Y, path, total, cells, ms_per_step, cost_ms, dp_ms, bt_
                    "layout": "checkpointed", "rows_per_block": K,
                    "schedule": "serial: sweep and backtrace of one pair, then the next",
                    "checkpoint_bytes": pd.pardtw_ckpt_bytes(n, m, K),
+                   "device_bytes_per_pair": workspace_device_bytes(w),
+                   "device_bytes_per_cell": round(workspace_device_bytes(w) / cells, 4),
                    "code_matrix_bytes_avoided": pd.pardtw_bp_bytes(n, m),
                    "pairs_per_s": round(1e3 / ms_per_step, 3),
                    "stage_ms": {"dp_ckpt": round(float(dp_ms), 4), "backtrace_ckpt": round(float(bt_ms), 4)}},

@@ -109,8 +109,10 @@ pardtw_status pardtw_band_groups(int64_t n, int64_t m, int64_t p, int64_t* lo, i
 size_t pardtw_bp_bytes(int64_t n, int64_t m);
 
 /* Bytes of device workspace pardtw_dp needs (0 on bad args). The workspace
- * carries boundary columns between column panels, a launch counter and, for
- * the fused-cost DP, the inverse norms of the rows of X. Zero it
+ * carries boundary columns between column panels (16 B per row for at most
+ * 257 boundaries in flight: 16 * N * min(ceil(M/64), 257) bytes, reused
+ * round robin), a launch counter and, for the fused-cost DP, the inverse
+ * norms of the rows of X. Zero it
  * once before its first use; afterwards it can be reused by any number of
  * pardtw_dp calls (of any size that fits) issued one after another on one
  * stream. Calls that overlap in time must not share a workspace. */
@@ -205,9 +207,9 @@ pardtw_status pardtw_bp_unpack(const uint8_t* bp, int64_t n, int64_t m, int8_t* 
 /* ---- Packed codes: 2 bits per cell (Sec. VI-D stores the transition types as
  * 2-bit values) -------------------------------------------------------------
  * A memory mode, not the throughput default: the codes take a quarter of the
- * bytes, so longer pairs fit (the code matrix plus the DP's 0.25 B per cell of
- * boundary records: 0.5 B per cell with the fused cost, against 1.25 B), at a
- * few percent of sweep time. Layout: one 16-bit word per column and 8-row
+ * bytes, so longer pairs fit (with the fused cost the DP then needs 0.25 B per
+ * cell plus O(N) of workspace, against 1 B per cell for byte codes), at about
+ * a tenth more sweep time. Layout: one 16-bit word per column and 8-row
  * group, row r of the group in bits 2r, 2r+1:
  *   word((i,j)) = (p*G + i/8)*64 + (j%64),  p = j/64, G = ceil(N/8),
  * the same codes as the byte layout (0, 1, 2 by step, 3 at the origin), on the

@@ -25,7 +25,12 @@
 // the last wave's ring to global records {float D, uint32 epoch} written with
 // agent-scope 64-bit atomic stores, which the input helper of the next
 // workgroup polls, several chunks per round trip, into its first ring, so no
-// side issues a cache-flushing fence. The first panel's ring is filled with
+// side issues a cache-flushing fence. A pair's boundaries take record columns
+// round robin from kRecSlots of them, one column of n rows each: at most
+// `grid` groups run at once and a group's input helper ends before the next
+// group's, so while group q runs every boundary below q - grid has been read
+// (the tags carry the column's lap parity besides the launch epoch). Records
+// then take 16 B per row and resident workgroup, not per row and panel. The first panel's ring is filled with
 // +inf once. Every compute wave thus runs the same instructions each chunk:
 // only its waits depend on its role, and no register value does, which keeps
 // the compiler from copying the boundary registers and from waiting on their
@@ -66,6 +71,7 @@ constexpr int kPfRow = 4;        // the same for the row-major layout (8 loads p
 constexpr int kHelperWin = 4;   // chunks polled per helper round trip (one record per lane)
 constexpr int kMaxNWFused = 4;   // fused workgroups: NW compute + NW producer + 2 helper waves
 constexpr int kCRing = 8;        // fused cost ring depth, in chunks (2 KB each)
+constexpr int kRecSlots = 257;   // record columns of one pair; the grid stays below it
 
 // Where the DP's costs come from.
 // kSrcFusedCk: fused costs, no codes, and D of the last two rows of every
@@ -107,7 +113,11 @@ struct DpArgs {
     float* total;   // DTW: D[n-1][m-1]; subsequence DTW: the m scores D[n-1][.]
     int32_t* status;
     DpWsHeader* hdr;
-    uint64_t* rec;  // [P][G*8][2] boundary records
+    // Boundary records, [column][G*8][2] {float D, uint32 tag}. rec_slots > 0:
+    // boundary q (group q to q + 1) in column q % rec_slots; rec_slots == 0:
+    // one column per panel, boundary q in column q*NW + NW - 1.
+    uint64_t* rec;
+    int rec_slots;
     int64_t n, m;
     int64_t G;      // 8-row groups per panel
     int P;          // number of panels
@@ -505,11 +515,10 @@ __device__ __attribute__((always_inline)) inline void cost_producer(const DpArgs
 // 8, 16 or more chunks measured slower).
 template <bool SUB, class Sh>
 __device__ __attribute__((always_inline)) inline void in_helper(const DpArgs& a, Sh& sh, int pl,
-                                                                uint32_t epoch) {
+                                                                const uint64_t* rec, uint32_t tag) {
     constexpr int kPer = kHelperWin * 16 / kLanes;  // records per lane per poll
     const int lane = threadIdx.x & 63;
     const int64_t G = a.G;
-    const uint64_t* rec = a.rec + (size_t(pl) * size_t(G) * kChunk) * 2;
     float* ring = &sh.ring[0][0][0][0];
     int cons_seen = 0;
     // the chunks the group's first panel (pl + 1) reads
@@ -526,7 +535,7 @@ __device__ __attribute__((always_inline)) inline void in_helper(const DpArgs& a,
             if (kq <= khi) {
                 v[t] = __hip_atomic_load(rec + (kq * kChunk + ((e & 15) >> 1)) * 2 + (e & 1), __ATOMIC_RELAXED,
                                          __HIP_MEMORY_SCOPE_AGENT);
-                ok = uint32_t(v[t] >> 32) == epoch;
+                ok = uint32_t(v[t] >> 32) == tag;
             }
             good[t] = __builtin_amdgcn_ballot_w64(ok);
         }
@@ -572,10 +581,9 @@ __device__ __attribute__((always_inline)) inline void inf_source(Sh& sh) {
 // stores off the compute waves keeps their memory counter free of slow writes.
 template <bool SUB, class Sh>
 __device__ __attribute__((always_inline)) inline void out_helper(const DpArgs& a, Sh& sh, int ring_idx,
-                                                                 int pl, uint32_t epoch) {
+                                                                 int pl, uint64_t* rec, uint32_t tag) {
     const int lane = threadIdx.x & 63;
     const int64_t G = a.G;
-    uint64_t* rec = a.rec + (size_t(pl) * size_t(G) * kChunk) * 2;
     const float* ring = &sh.ring[ring_idx][0][0][0];
     const int q = lane >> 4, row = (lane & 15) >> 1, col = lane & 1;
     int prog_seen = 0;
@@ -598,11 +606,26 @@ __device__ __attribute__((always_inline)) inline void out_helper(const DpArgs& a
         compiler_order();
         if (lane == 0) lds_put(&sh.cons[ring_idx], int(k + avail));
         if (q < avail) {
-            const uint64_t v = (uint64_t(epoch) << 32) | uint64_t(__float_as_uint(val));
+            const uint64_t v = (uint64_t(tag) << 32) | uint64_t(__float_as_uint(val));
             __hip_atomic_store(rec + ((k + q) * kChunk + row) * 2 + col, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         k += avail;
     }
+}
+
+// The record column of boundary b (group b to b + 1) and the tag its records
+// carry: the launch epoch and, when columns are reused, the lap's parity. A
+// column is written again only after its previous boundary has been read in
+// full, and band ranges only move down with the panel, so a slot holds this
+// boundary's record, the previous lap's, or one of an earlier launch.
+__device__ inline uint64_t* rec_column(const DpArgs& a, int b, int NW) {
+    const int col = a.rec_slots > 0 ? b % a.rec_slots : b * NW + NW - 1;
+    return a.rec + size_t(col) * size_t(a.G) * kChunk * 2;
+}
+
+__device__ inline uint32_t rec_tag(const DpArgs& a, int b, uint32_t epoch) {
+    const uint32_t lap = a.rec_slots > 0 ? uint32_t(b / a.rec_slots) & 1u : 0u;
+    return (epoch << 1) | lap;
 }
 
 // Panel group q (panels q*NW .. q*NW+NW-1) of one pair: NW compute waves, then
@@ -618,11 +641,11 @@ __device__ __attribute__((always_inline)) inline void run_group(const DpArgs& a,
         const int p = p0 + wave - (NW + 2);
         if (p < a.P) cost_producer(a, *cring, wave - (NW + 2), p, SUB);
     } else if (wave == NW) {
-        if (p0 > 0) in_helper<SUB>(a, sh, p0 - 1, epoch);
+        if (p0 > 0) in_helper<SUB>(a, sh, p0 - 1, rec_column(a, q - 1, NW), rec_tag(a, q - 1, epoch));
         else inf_source(sh);
     } else {
         // the group's last panel feeds the next group when one exists
-        if (p0 + NW < a.P) out_helper<SUB>(a, sh, NW, p0 + NW - 1, epoch);
+        if (p0 + NW < a.P) out_helper<SUB>(a, sh, NW, p0 + NW - 1, rec_column(a, q, NW), rec_tag(a, q, epoch));
     }
 }
 
@@ -706,6 +729,7 @@ __device__ __attribute__((always_inline)) inline void dp_batch_body(const DpBatc
         a.status = ba.status + it.pair;
         a.hdr = ba.hdr;
         a.rec = ba.rec + q.rec_off;
+        a.rec_slots = 0;
         a.n = q.n;
         a.m = q.m;
         a.G = q.G;
@@ -807,12 +831,19 @@ size_t dp_header_bytes() { return sizeof(DpWsHeader); }
 // The DP reads only band groups, so the panel layouts are the same to it.
 int src_of(pardtw_layout layout) { return layout == PARDTW_LAYOUT_ROW ? kSrcRow : kSrcPanel; }
 
+// Batched pairs: one record column per panel.
 size_t dp_record_bytes(int64_t n, int64_t m) {
     return size_t(num_panels(m)) * size_t(bp_groups(n)) * kChunk * 2 * sizeof(uint64_t);
 }
 
+// One pair: kRecSlots columns at most, whatever the panels per workgroup.
+size_t dp_pair_record_bytes(int64_t n, int64_t m) {
+    const int64_t cols = num_panels(m) < kRecSlots ? num_panels(m) : kRecSlots;
+    return size_t(cols) * size_t(bp_groups(n)) * kChunk * 2 * sizeof(uint64_t);
+}
+
 size_t dp_workspace_bytes_impl(int64_t n, int64_t m) {
-    return sizeof(DpWsHeader) + dp_record_bytes(n, m) + size_t(rx_floats(n)) * sizeof(float);
+    return sizeof(DpWsHeader) + dp_pair_record_bytes(n, m) + size_t(rx_floats(n)) * sizeof(float);
 }
 
 pardtw_status dp_batch_launch(const BatchPair* pairs, const DpItem* items, int32_t nitems, int nw, int grid,
@@ -870,7 +901,7 @@ pardtw_status dp_launch(const float* C, const float* X, const float* Y, int64_t 
     a.hdr = reinterpret_cast<DpWsHeader*>(ws);
     a.rec = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(ws) + sizeof(DpWsHeader));
     // the records are a multiple of 128 bytes, so the row-norm area is 16-byte aligned
-    a.rxs = reinterpret_cast<float*>(reinterpret_cast<char*>(a.rec) + dp_record_bytes(n, m));
+    a.rxs = reinterpret_cast<float*>(reinterpret_cast<char*>(a.rec) + dp_pair_record_bytes(n, m));
     a.n = n;
     a.m = m;
     a.G = bp_groups(n);
@@ -882,7 +913,10 @@ pardtw_status dp_launch(const float* C, const float* X, const float* Y, int64_t 
     PARDTW_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     // about four compute waves per CU (one per SIMD)
     const int per_cu = nw >= 4 ? 1 : 4 / nw;
-    const int grid = a.S < cus * per_cu ? a.S : cus * per_cu;
+    int grid = a.S < cus * per_cu ? a.S : cus * per_cu;
+    // the record columns must outnumber the groups in flight
+    grid = grid < kRecSlots - 1 ? grid : kRecSlots - 1;
+    a.rec_slots = a.S < kRecSlots ? a.S : kRecSlots;
     if (is_fused(src) && nw > kMaxNWFused) return PARDTW_ERR_UNSUPPORTED;
     if (src == kSrcFusedCk && (sub || ck_rows < 16 || ck_rows > kCkMaxRows || ck_rows % 16))
         return PARDTW_ERR_INVALID_ARG;

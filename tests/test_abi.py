@@ -46,9 +46,14 @@ def test_size_helpers(lib):
     G = -(-n // 8)
     assert lib.pardtw_cost_elems(n, m, 1) == P * G * 512
     assert lib.pardtw_bp_bytes(n, m) == P * (-(-n // 8)) * 64 * 8
-    # header, boundary records, and the fused DP's row norms (two slabs past a
-    # loop padded to three slabs of 16 rows)
-    assert lib.pardtw_dp_workspace_bytes(n, m) == 768 + P * G * 8 * 16 + ((-(-G // 2)) + 5) * 16 * 4
+    # header, boundary records (16 B per row for at most 257 record columns),
+    # and the fused DP's row norms (two slabs past a loop padded to three slabs
+    # of 16 rows)
+    assert lib.pardtw_dp_workspace_bytes(n, m) == 768 + min(P, 257) * G * 8 * 16 + ((-(-G // 2)) + 5) * 16 * 4
+    assert lib.pardtw_dp_workspace_bytes(800, 64 * 100) == 768 + 100 * 100 * 8 * 16 + (50 + 5) * 16 * 4
+    # the records no longer grow with the columns past 257 panels: O(N) at L = 1M
+    L = 1_000_000
+    assert lib.pardtw_dp_workspace_bytes(L, L) < 16 * L * 258 + 10 ** 7
     assert lib.pardtw_cost_elems(0, 5, 0) == 0
     assert lib.pardtw_bp_bytes(-1, 5) == 0
     assert lib.pardtw_cost_elems(3, 5, 7) == 0
