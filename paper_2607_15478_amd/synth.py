@@ -179,6 +179,7 @@ WORKLOADS = {
     "pair_600000x600000_d12": dict(kind="pair", seed=7, n=600000, m=600000, d=12, lo=0.8, hi=1.25),
     "pair_650000x650000_d12": dict(kind="pair", seed=8, n=650000, m=650000, d=12, lo=0.8, hi=1.25),
     "pair_1000000x1000000_d12": dict(kind="pair", seed=9, n=1000000, m=1000000, d=12, lo=0.8, hi=1.25),
+    "pair_2800000x2800000_d12": dict(kind="pair", seed=10, n=2800000, m=2800000, d=12, lo=0.8, hi=1.25),
     "batch256_500to8000_d12": dict(kind="chroma_batch", seed=4, count=256, lo=500, hi=8000, d=12),
     # the same draw with infeasible pairs' m redrawn, so every pair is aligned
     "batch256_500to8000_d12_feasible": dict(kind="chroma_batch", seed=4, count=256, lo=500, hi=8000, d=12,
