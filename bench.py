@@ -64,12 +64,20 @@ def parse():
     ap.add_argument("--fused", action="store_true",
                     help="the DP computes the costs itself (no cost matrix; FP32, d <= 16)")
     ap.add_argument("--variant", choices=["wsdtw", "nsdtw"], default="wsdtw", help="segmental workloads")
+    ap.add_argument("--pipelined", action="store_true",
+                    help="pair workloads: run each pair's backtrace on a second stream beside the next pair's "
+                         "cost and DP (default with --ckpt; otherwise each step's backtrace runs before the next "
+                         "step's cost)")
     ap.add_argument("--serial", action="store_true",
-                    help="pair workloads: run each step's backtrace before the next step's cost (no overlap "
-                         "between consecutive pairs)")
+                    help="pair workloads: the serial schedule (the default; overrides --pipelined)")
     ap.add_argument("--packed", action="store_true",
                     help="pair workloads: codes packed 2 bits per cell (pardtw_dp_packed / pardtw_dp_fused_packed "
                          "and pardtw_backtrace_packed), a memory mode")
+    ap.add_argument("--walk", choices=["auto", "split", "serial"], default="auto",
+                    help="pair workloads: the backtrace, split walk (pardtw_backtrace_parallel, many workgroups) "
+                         "or one-workgroup walk (pardtw_backtrace); the same path. auto: split in the serial "
+                         "schedule (it shortens the step), one workgroup in the pipelined one (it hides beside "
+                         "the next DP on one CU, where the split walk would take CUs from that DP)")
     ap.add_argument("--ckpt", type=int, default=0, metavar="K",
                     help="checkpointed DTW: fused DP keeping only D rows every K rows, then the recomputing "
                          "backtrace (no code matrix; K a multiple of 16 in [16, 256])")
@@ -336,7 +344,12 @@ def main():
         calib = {"bytes_each_way": nb}
         del src, dst
 
-    # Pipelined schedule (pairs after pairs, as a serving loop runs them): the
+    # Serial schedule (the default for code matrices): cost, DP, split-walk
+    # backtrace and compensated total of one pair, then the next. The split
+    # walk takes about 0.1 ms at 50000 x 60000, so hiding it buys less than
+    # the CUs it would take from the next pair's DP.
+    # Pipelined schedule (--pipelined, and the default for checkpoints, whose
+    # backtrace is as long as a sweep): the
     # cost and DP of each pair run on the launch stream, and the backtrace of
     # pair s (one workgroup) on a second stream beside the cost and DP of pair
     # s + 1. Pairs alternate between two workspaces; a workspace's codes are
@@ -350,7 +363,7 @@ def main():
     # Extra workspaces are taken only as far as free device memory allows
     # (a 600000 x 600000 checkpointed pair needs 101 GB each); with none the
     # run is serial.
-    pipelined = not args.serial
+    pipelined = (args.pipelined or bool(K)) and not args.serial
     bufs = [w]
     if pipelined:
         per = sum(t.numel() * t.element_size() for t in (w.C, w.bp, w.ws, w.ckpt, w.path))
@@ -388,7 +401,7 @@ def main():
             e[2].record(stream)
             pd.pardtw_ckpt_backtrace(Xd, Yd, K, w.ckpt, w.status, w.path, w.path_len)
             if comp:
-                pd.pardtw_path_total(Xd, Yd, w.path, w.path_len, w.total_comp)
+                pd.pardtw_path_total(Xd, Yd, w.path, w.path_len, w.total_comp, w.total_ws)
             e[3].record(stream)
             continue
         if args.fused:
@@ -405,12 +418,14 @@ def main():
             else:
                 pd.pardtw_dp(w.C, n, m, w.bp, w.total, w.status, w.ws, pd.LAYOUT_PANEL_BAND)
         e[2].record(stream)
-        if args.packed:
+        if args.walk != "serial":
+            pd.pardtw_backtrace_parallel(w.bp, n, m, w.status, w.path, w.path_len, w.bt_ws, packed=args.packed)
+        elif args.packed:
             pd.pardtw_backtrace_packed(w.bp, n, m, w.status, w.path, w.path_len)
         else:
             pd.pardtw_backtrace(w.bp, n, m, w.status, w.path, w.path_len)
         if comp:
-            pd.pardtw_path_total(Xd, Yd, w.path, w.path_len, w.total_comp)
+            pd.pardtw_path_total(Xd, Yd, w.path, w.path_len, w.total_comp, w.total_ws)
         e[3].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -457,6 +472,7 @@ def main():
                    "device_bytes_per_pair": workspace_device_bytes(w),
                    "device_bytes_per_cell": round(workspace_device_bytes(w) / cells, 4),
                    "schedule": "serial: cost, DP and backtrace of one pair, then the next",
+                   "walk": "one workgroup" if args.walk == "serial" else "split",
                    "pairs_per_s": round(1e3 / ms_per_step, 3),
                    "stage_ms": {"cost": round(float(cost_ms), 4), "dp": round(float(dp_ms), 4),
                                 "backtrace": round(float(bt_ms), 4)}},
@@ -469,7 +485,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def launch_pipelined(pd, Xd, Yd, bufs, stream, side, steps, fused, K, evs, after_bt=None):
+def launch_pipelined(pd, Xd, Yd, bufs, stream, side, steps, fused, K, evs, after_bt=None, serial_walk=False):
     """Enqueue `steps` pairs in the pipelined schedule: cost (materialised
     form) and DP on `stream`, each backtrace on one of the backtrace streams
     side[1] (in turn) once its DP is done. Pair s uses workspace
@@ -510,6 +526,9 @@ def launch_pipelined(pd, Xd, Yd, bufs, stream, side, steps, fused, K, evs, after
         e[4].record(s_bt)
         if K:
             pd.pardtw_ckpt_backtrace(Xd, Yd, K, w.ckpt, w.status, w.path, w.path_len, stream=s_bt)
+        elif not serial_walk:
+            pd.pardtw_backtrace_parallel(w.bp, n, m, w.status, w.path, w.path_len, w.bt_ws, stream=s_bt,
+                                         packed=w.packed)
         elif w.packed:
             pd.pardtw_backtrace_packed(w.bp, n, m, w.status, w.path, w.path_len, stream=s_bt)
         else:
@@ -537,8 +556,9 @@ def run_pair_pipelined(args, X, Y, Xd, Yd, bufs, stream, side, cells, calib):
     after = None
     if not args.no_comp_total:
         def after(s, w, s_bt):
-            pd.pardtw_path_total(Xd, Yd, w.path, w.path_len, w.total_comp, stream=s_bt)
-    launch_pipelined(pd, Xd, Yd, bufs, stream, side, args.steps, args.fused, K, evs, after_bt=after)
+            pd.pardtw_path_total(Xd, Yd, w.path, w.path_len, w.total_comp, w.total_ws, stream=s_bt)
+    launch_pipelined(pd, Xd, Yd, bufs, stream, side, args.steps, args.fused, K, evs, after_bt=after,
+                     serial_walk=args.walk != "split")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     stage_ms = np.array([[0.0 if (args.fused or K) else e[0].elapsed_time(e[1]), e[2].elapsed_time(e[3]),
@@ -584,6 +604,7 @@ def run_pair_pipelined(args, X, Y, Xd, Yd, bufs, stream, side, cells, calib):
                    "device_bytes_per_pair": workspace_device_bytes(bufs[0]),
                    "device_bytes_per_cell": round(workspace_device_bytes(bufs[0]) / cells, 4),
                    "schedule": layout,
+                   "walk": "split" if args.walk == "split" else "one workgroup",
                    "pairs_per_s": round(1e3 / ms_per_step, 3),
                    "latency_ms": round(float(cost_ms + dp_ms + bt_ms), 4),
                    "stage_ms": {"cost": round(float(cost_ms), 4), "dp": round(float(dp_ms), 4),

@@ -199,6 +199,28 @@ pardtw_status pardtw_dp_fused(const float* X, const float* Y, int64_t n, int64_t
 pardtw_status pardtw_backtrace(const uint8_t* bp, int64_t n, int64_t m, const int32_t* pair_status,
                                int32_t* path, int32_t* path_len, hipStream_t stream);
 
+/* a4, split walk: the path pardtw_backtrace returns, walked by many
+ * workgroups. The rows are cut into S segments of R rows (R = max(512,
+ * ceil(N/256))); each segment is walked from a guessed start (the diagonal,
+ * clamped to the band), then again from where the segment above ended; one
+ * workgroup then checks, from the last segment down, that every segment
+ * started where the one above ended, and walks again serially any that did
+ * not, so the result never depends on the guesses (Sec. VI-C puts the
+ * backtrace on one thread; paths from nearby cells merge within a few dozen
+ * steps, which is what makes the guesses pay).
+ *   bp, n, m, pair_status, path, path_len: as for pardtw_backtrace.
+ *   workspace [device, >= pardtw_backtrace_parallel_bytes(n, m) bytes,
+ *     16-byte aligned]: segment starts, ends and cells (8 B per row); no
+ *     initialisation needed. Calls that overlap in time must not share it.
+ * Errors: PARDTW_ERR_INVALID_ARG (null or misaligned pointers, bad sizes),
+ * PARDTW_ERR_WORKSPACE (workspace too small). Corrupt codes give path_len 0,
+ * as in the serial walk. Five kernels on `stream`; pairs of at most 1024 rows
+ * (two segments or fewer) take the one-workgroup walk instead. */
+size_t pardtw_backtrace_parallel_bytes(int64_t n, int64_t m);
+pardtw_status pardtw_backtrace_parallel(const uint8_t* bp, int64_t n, int64_t m, const int32_t* pair_status,
+                                        int32_t* path, int32_t* path_len, void* workspace,
+                                        size_t workspace_bytes, hipStream_t stream);
+
 /* Inspection helper: the DP's backtrace buffer as a row-major n x m int8
  * matrix out [device, n*m bytes]. */
 pardtw_status pardtw_bp_unpack(const uint8_t* bp, int64_t n, int64_t m, int8_t* out,
@@ -231,6 +253,12 @@ pardtw_status pardtw_dp_fused_packed(const float* X, const float* Y, int64_t n, 
 /* pardtw_backtrace over packed codes: the same path. bp2 16-byte aligned. */
 pardtw_status pardtw_backtrace_packed(const uint16_t* bp2, int64_t n, int64_t m, const int32_t* pair_status,
                                       int32_t* path, int32_t* path_len, hipStream_t stream);
+
+/* pardtw_backtrace_parallel over packed codes (bp2 16-byte aligned); the same
+ * path as pardtw_backtrace_packed. */
+pardtw_status pardtw_backtrace_packed_parallel(const uint16_t* bp2, int64_t n, int64_t m,
+                                               const int32_t* pair_status, int32_t* path, int32_t* path_len,
+                                               void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* Inspection helper: packed codes as a row-major n x m int8 matrix. */
 pardtw_status pardtw_bp2_unpack(const uint16_t* bp2, int64_t n, int64_t m, int8_t* out, hipStream_t stream);
@@ -300,9 +328,17 @@ pardtw_status pardtw_path_grad(const float* X, const float* Y, int64_t n, int64_
  *   X [device, n*d FP32], Y [device, m*d FP32], path/path_len [device] as
  *   written by pardtw_backtrace or pardtw_ckpt_backtrace.
  *   total [device, 1 float]: the path's cost, +inf when path_len is 0.
- * One workgroup; no allocation or synchronisation. */
+ *   workspace [device, >= pardtw_path_total_bytes() bytes, 8-byte aligned]:
+ *     the pieces' partial sums; no initialisation needed. Calls that overlap
+ *     in time must not share it.
+ * The path is cut into 256 contiguous pieces by its length alone, summed one
+ * per workgroup and then added in a fixed tree, so the result does not depend
+ * on the schedule. Two kernels on `stream`; no allocation or synchronisation.
+ * PARDTW_ERR_WORKSPACE if the workspace is too small. */
+size_t pardtw_path_total_bytes(void);
 pardtw_status pardtw_path_total(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
-                                const int32_t* path, const int32_t* path_len, float* total, hipStream_t stream);
+                                const int32_t* path, const int32_t* path_len, float* total, void* workspace,
+                                size_t workspace_bytes, hipStream_t stream);
 
 /* ---- a5: batched form -----------------------------------------------------
  * Many independent pairs of uneven lengths aligned together (the problem of

@@ -88,13 +88,20 @@ __device__ inline uint32_t compact8(uint32_t lo, uint32_t hi) {
 }
 
 
-// Walker: from (n-1, j_end) back to the origin, or with `sub` to row 0.
-// Returns the path length (0 if the codes do not lead there). The output holds
-// `cap` pairs.
-__device__ int walk(BtShared& sh, int n, int j_end, bool sub, int cap, int32_t* path) {
+// Walker: from (i0, j0) back to the origin, or with `sub` to row 0. Returns
+// the number of cells written (0 if the codes do not lead there). The output
+// holds `cap` pairs; without SEG the k-th cell is written at cap - 1 - k (so
+// the path ends up in forward order at the back).
+// SEG (one segment of a split walk): the k-th cell is written at k, and with
+// stop_row >= 0 the walk ends at the first cell on a row <= stop_row, which is
+// not written but returned in *exit; such a walk must stay at row >= 33 and
+// column >= 66 (the path's cells there do), else it fails.
+template <bool SEG = false>
+__device__ int walk(BtShared& sh, int i0, int j0, bool sub, int cap, int32_t* path, int stop_row = -1,
+                    int2* exit = nullptr) {
     const int lane = threadIdx.x;
-    const int P = j_end / kPanel + 1;  // panels the walk can visit
-    int i = n - 1, j = j_end, len = 0;
+    const int P = j0 / kPanel + 1;  // panels the walk can visit
+    int i = i0, j = j0, len = 0;
     int nreq = 0;
     auto request = [&](int p) {
         int glo, ng;
@@ -123,6 +130,10 @@ __device__ int walk(BtShared& sh, int n, int j_end, bool sub, int cap, int32_t* 
 
     const uint8_t* lds = &sh.slot[0][0];
     for (;;) {
+        if (SEG && i <= stop_row) {
+            *exit = make_int2(i, j);
+            return len;
+        }
         const int q0 = j / kPanel;
         if (q0 != cur_q) {  // entered panel q0 (panels are entered in decreasing order)
             cur_q = q0;
@@ -160,8 +171,29 @@ __device__ int walk(BtShared& sh, int n, int j_end, bool sub, int cap, int32_t* 
         if (i >= 33 && j >= 66) {
             // no cell of the window can be the origin or lie outside the matrix
             const WindowMasks wm = window_masks(packed0, packed1);
-            const uint32_t on = trace_window(wm, lane);
-            if (__builtin_amdgcn_ballot_w64((on & wm.two_cols & wm.two_rows) != 0)) return 0;  // code 3
+            // rows above the stop row (bit 31 - a for row a), where the trace may step
+            const int above = i - stop_row;
+            const uint32_t live = SEG && stop_row >= 0 && above < 32 ? ~(0xFFFFFFFFu >> above) : ~0u;
+            const uint32_t on = SEG ? trace_window_live(wm, live, lane) : trace_window(wm, lane);
+            if (__builtin_amdgcn_ballot_w64((on & live & wm.two_cols & wm.two_rows) != 0)) return 0;  // code 3
+            if constexpr (SEG) {
+                // the trace ends on the first cell past the stop row: the last one it marks
+                const uint64_t past = __builtin_amdgcn_ballot_w64((on & ~live) != 0);
+                if (past) {
+                    const int xl = 63 - __builtin_clzll(past);
+                    const uint64_t in = past ^ __builtin_amdgcn_ballot_w64(on != 0);
+                    const int cnt = __builtin_popcountll(in);
+                    if (len + cnt > cap) return 0;
+                    if ((on & live) != 0) {
+                        const uint32_t lo = uint32_t(in), hi = uint32_t(in >> 32);
+                        const int idx = int(__builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u)));
+                        path[2 * (len + idx)] = i - __builtin_clz(on);
+                        path[2 * (len + idx) + 1] = j - lane;
+                    }
+                    *exit = make_int2(i - __builtin_clz(__builtin_amdgcn_readlane(on, xl)), j - xl);
+                    return len + cnt;
+                }
+            }
             const uint64_t has = __builtin_amdgcn_ballot_w64(on != 0);
             const int cnt = __builtin_popcountll(has);
             const int last = 63 - __builtin_clzll(has);  // lane 0 always holds the start cell
@@ -173,7 +205,7 @@ __device__ int walk(BtShared& sh, int n, int j_end, bool sub, int cap, int32_t* 
             if (on != 0) {
                 const uint32_t lo = uint32_t(has), hi = uint32_t(has >> 32);
                 const int idx = int(__builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u)));
-                const int64_t pos = int64_t(cap) - 1 - (len + idx);
+                const int64_t pos = SEG ? int64_t(len + idx) : int64_t(cap) - 1 - (len + idx);
                 path[2 * pos] = i - __builtin_clz(on);
                 path[2 * pos + 1] = j - lane;
             }
@@ -187,6 +219,7 @@ __device__ int walk(BtShared& sh, int n, int j_end, bool sub, int cap, int32_t* 
         // (uniform scalar loop). Bit 1 of a code says the step takes two rows,
         // bit 0 two columns, so the unused code 3 reads as an illegal (2, 2)
         // step and is caught after the loop.
+        if (SEG && stop_row >= 0) return 0;
         int off = 30, b = 0, k0 = 0;
         uint64_t codes0 = 0;
         bool origin = false;
@@ -212,7 +245,7 @@ __device__ int walk(BtShared& sh, int n, int j_end, bool sub, int cap, int32_t* 
             const uint64_t m0 = (uint64_t(1) << (2 * lane)) - 1;
             const int da = lane + __builtin_popcountll(codes0 & m0 & 0xAAAAAAAAAAAAAAAAull);
             const int db = lane + __builtin_popcountll(codes0 & m0 & 0x5555555555555555ull);
-            const int64_t pos = int64_t(cap) - 1 - (len + lane);
+            const int64_t pos = SEG ? int64_t(len + lane) : int64_t(cap) - 1 - (len + lane);
             path[2 * pos] = i - da;
             path[2 * pos + 1] = j - db;
         }
@@ -329,7 +362,7 @@ __device__ void backtrace_pair(BtShared& sh, const uint8_t* bp, int n, int j_end
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     if (wave == 0) {
-        const int len = walk(sh, n, j_end, sub, cap, path);
+        const int len = walk(sh, n - 1, j_end, sub, cap, path);
         if (tid == 0) {
             sh.len = len;
             lds_store_release(&sh.done, 1);
@@ -342,6 +375,176 @@ __device__ void backtrace_pair(BtShared& sh, const uint8_t* bp, int n, int j_end
     __threadfence_block();
     shift_path(path, int64_t(cap) - len, len);
     if (tid == 0) *path_len = len;
+}
+
+// ---- Split walk ------------------------------------------------------------
+// The rows are cut into S segments of R rows; segment s holds the path's cells
+// on rows (s R - 1, (s + 1) R - 1] (segment 0 down to the origin). A segment
+// starts at the first path cell on or below its top row, which is where the
+// segment above ends, so the segments could be walked at once if their starts
+// were known. Paths walked back from nearby cells merge within a few dozen
+// steps (all of them do at the origin), so:
+//   round 0: every segment walks from a guess on its top row (the diagonal
+//            through the corners, clamped to the band; the last segment from
+//            (n-1, m-1), exactly);
+//   round r: every segment walks again from where the segment above ended in
+//            round r - 1, unless it already started there;
+//   finish:  one workgroup checks, from the last segment down, that each
+//            segment started where the one above ended, and walks again any
+//            that did not (its start is then exact); then it takes the
+//            offsets, and a copy kernel lays the segments out in order.
+// Whatever the guesses, every segment is at last walked from its exact start,
+// so the path is the serial walk's; good guesses only save the serial rewalks.
+struct SegInfo {
+    int32_t si, sj;  // start cell
+    int32_t ei, ej;  // first cell past the segment (segment 0: unused)
+    int32_t len;     // cells written (0: the walk failed)
+    int32_t off;     // position of the segment's last cell in the path
+    int32_t pad[2];
+};
+
+constexpr int kSegMaxCount = 256;  // segments of one walk at most
+
+struct SegArgs {
+    const uint8_t* bp;
+    int n, m;
+    int R, S;
+    SegInfo* info;   // [2][S]: rounds alternate between the halves
+    int32_t* cells;  // [S][R][2]: segment s's cells from its start backward
+};
+
+__host__ __device__ inline int seg_stop_row(int s, int R) { return s == 0 ? -1 : s * R - 1; }
+
+// A cell on row i of the band (reachable from the origin, reaching (n-1, m-1))
+// near the diagonal through the corners.
+__device__ inline int seg_guess_col(int i, int n, int m) {
+    const int64_t jd = (int64_t(i) * (m - 1) + (n - 1) / 2) / (n > 1 ? n - 1 : 1);
+    const int64_t lo1 = (i + 1) / 2, lo2 = int64_t(m - 1) - 2 * int64_t(n - 1 - i);
+    const int64_t hi1 = 2 * int64_t(i), hi2 = int64_t(m - 1) - (int64_t(n - 1 - i) + 1) / 2;
+    const int64_t lo = lo1 > lo2 ? lo1 : lo2, hi = hi1 < hi2 ? hi1 : hi2;
+    const int64_t c = jd < lo ? lo : jd > hi ? hi : jd;
+    return int(c < 0 ? 0 : c > m - 1 ? m - 1 : c);
+}
+
+// One segment walk by the whole workgroup (walker wave 0, loader waves
+// 1..kLoaders); the result goes to info_out and, for every thread, to `res`.
+template <bool PACK>
+__device__ SegInfo walk_segment(BtShared& sh, SegInfo& res, const SegArgs& a, int s, int si, int sj,
+                                SegInfo* info_out) {
+    const int tid = threadIdx.x;
+    if (tid < kSlots) sh.loaded[tid] = 0;
+    if (tid == 0) {
+        sh.req_count = 0;
+        sh.done = 0;
+        sh.len = 0;
+    }
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (wave == 0) {
+        int2 ex = make_int2(-1, -1);
+        const int len = walk<true>(sh, si, sj, false, a.R, a.cells + int64_t(s) * a.R * 2, seg_stop_row(s, a.R), &ex);
+        if (tid == 0) {
+            SegInfo r;
+            r.si = si;
+            r.sj = sj;
+            r.ei = ex.x;
+            r.ej = ex.y;
+            r.len = len;
+            r.off = 0;
+            r.pad[0] = r.pad[1] = 0;
+            *info_out = r;
+            res = r;
+            lds_store_release(&sh.done, 1);
+        }
+    } else {
+        load_panels<PACK>(sh, a.bp, bp_groups(a.n), wave - 1);
+    }
+    __syncthreads();
+    return res;
+}
+
+// One round: workgroup s walks segment s.
+template <bool PACK>
+__global__ __launch_bounds__(kThreads) void seg_round_kernel(SegArgs a, const int32_t* __restrict__ status,
+                                                             int round) {
+    __shared__ BtShared sh;
+    __shared__ SegInfo res;
+    if (*status != PARDTW_PAIR_OK) return;
+    const int s = blockIdx.x;
+    const SegInfo* prev = a.info + (round & 1 ? 0 : a.S);
+    SegInfo* cur = a.info + (round & 1 ? a.S : 0);
+    int si, sj;
+    if (s == a.S - 1) {
+        si = a.n - 1;
+        sj = a.m - 1;
+    } else if (round == 0) {
+        si = (s + 1) * a.R - 1;
+        sj = seg_guess_col(si, a.n, a.m);
+    } else {
+        const SegInfo up = prev[s + 1];
+        si = up.ei;
+        sj = up.ej;
+    }
+    if (round > 0) {
+        const SegInfo me = prev[s];
+        // unchanged start (or none known: the segment above failed)
+        if ((me.si == si && me.sj == sj && me.len > 0) || si < 0) {
+            if (threadIdx.x == 0) cur[s] = me;
+            return;
+        }
+    }
+    walk_segment<PACK>(sh, res, a, s, si, sj, cur + s);
+}
+
+// Check from the last segment down, walk again what started elsewhere, take
+// the offsets and the length. `fin` is the half the last round wrote.
+template <bool PACK>
+__global__ __launch_bounds__(kThreads) void seg_finish_kernel(SegArgs a, const int32_t* __restrict__ status, int fin,
+                                                              int cap, int32_t* path_len) {
+    __shared__ BtShared sh;
+    __shared__ SegInfo res;
+    __shared__ SegInfo sinfo[kSegMaxCount];
+    const int tid = threadIdx.x;
+    if (*status != PARDTW_PAIR_OK) {
+        if (tid == 0) *path_len = 0;
+        return;
+    }
+    SegInfo* info = a.info + fin * a.S;
+    for (int k = tid; k < a.S; k += kThreads) sinfo[k] = info[k];
+    __syncthreads();
+    int si = a.n - 1, sj = a.m - 1;
+    for (int s = a.S - 1; s >= 0; --s) {
+        SegInfo me = sinfo[s];
+        if (me.si != si || me.sj != sj || me.len <= 0) {
+            me = walk_segment<PACK>(sh, res, a, s, si, sj, info + s);
+            if (me.len <= 0) {
+                if (tid == 0) *path_len = 0;
+                return;
+            }
+            if (tid == 0) sinfo[s] = me;
+        }
+        si = me.ei;
+        sj = me.ej;
+    }
+    // offsets: segment s's cells go after those of segments 0 .. s-1
+    if (tid == 0) {
+        int64_t off = 0;
+        for (int s = 0; s < a.S; ++s) {
+            info[s].off = int32_t(off);
+            off += sinfo[s].len;
+        }
+        *path_len = off > cap ? 0 : int32_t(off);
+    }
+}
+
+// Block s copies segment s, reversed, to its place in the path.
+__global__ __launch_bounds__(256) void seg_copy_kernel(SegArgs a, int fin, const int32_t* __restrict__ path_len,
+                                                       int32_t* __restrict__ path) {
+    if (*path_len <= 0) return;
+    const SegInfo me = a.info[fin * a.S + blockIdx.x];
+    const int2* src = reinterpret_cast<const int2*>(a.cells + int64_t(blockIdx.x) * a.R * 2);
+    int2* dst = reinterpret_cast<int2*>(path) + me.off;
+    for (int k = threadIdx.x; k < me.len; k += blockDim.x) dst[me.len - 1 - k] = src[k];
 }
 
 __global__ __launch_bounds__(kThreads) void backtrace_kernel(const uint8_t* __restrict__ bp, int64_t n, int64_t m,
@@ -438,6 +641,76 @@ extern "C" pardtw_status pardtw_backtrace(const uint8_t* bp, int64_t n, int64_t 
     if (reinterpret_cast<uintptr_t>(path) % 8 != 0) return PARDTW_ERR_INVALID_ARG;
     pardtw::backtrace_kernel<<<1, pardtw::kThreads, 0, stream>>>(bp, n, m, pair_status, path, path_len);
     return pardtw::launch_status();
+}
+
+namespace pardtw {
+namespace {
+
+constexpr int kSegMinRows = 512;  // rows per segment at least
+constexpr int kSegMax = kSegMaxCount;
+constexpr int kSegRounds = 3;     // parallel rounds before the check
+
+void seg_shape(int64_t n, int& R, int& S) {
+    const int64_t r = ceil_div(n, int64_t(kSegMax));
+    R = int(r > kSegMinRows ? r : kSegMinRows);
+    S = int(ceil_div(n, int64_t(R)));
+}
+
+size_t seg_bytes(int64_t n) {
+    int R, S;
+    seg_shape(n, R, S);
+    return size_t(2) * S * sizeof(SegInfo) + size_t(S) * R * 2 * sizeof(int32_t);
+}
+
+template <bool PACK>
+pardtw_status seg_backtrace(const uint8_t* bp, int64_t n, int64_t m, const int32_t* status, int32_t* path,
+                            int32_t* path_len, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!bp || !status || !path || !path_len || !ws || !valid_sizes(n, m)) return PARDTW_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(path) % 8 != 0 || reinterpret_cast<uintptr_t>(ws) % 16 != 0)
+        return PARDTW_ERR_INVALID_ARG;
+    if (PACK && reinterpret_cast<uintptr_t>(bp) % 16 != 0) return PARDTW_ERR_INVALID_ARG;
+    if (ws_bytes < seg_bytes(n)) return PARDTW_ERR_WORKSPACE;
+    SegArgs a;
+    a.bp = bp;
+    a.n = int(n);
+    a.m = int(m);
+    seg_shape(n, a.R, a.S);
+    if (a.S <= 2) {
+        // a pair of at most 1024 rows: one workgroup walks it faster than
+        // five launches split it
+        if (PACK) backtrace_packed_kernel<<<1, kThreads, 0, stream>>>(bp, n, m, status, path, path_len);
+        else backtrace_kernel<<<1, kThreads, 0, stream>>>(bp, n, m, status, path, path_len);
+        return launch_status();
+    }
+    a.info = reinterpret_cast<SegInfo*>(ws);
+    a.cells = reinterpret_cast<int32_t*>(a.info + 2 * a.S);
+    for (int r = 0; r < kSegRounds; ++r) seg_round_kernel<PACK><<<a.S, kThreads, 0, stream>>>(a, status, r);
+    const int fin = (kSegRounds - 1) & 1;
+    seg_finish_kernel<PACK><<<1, kThreads, 0, stream>>>(a, status, fin, int(n < m ? n : m), path_len);
+    seg_copy_kernel<<<a.S, 256, 0, stream>>>(a, fin, path_len, path);
+    return launch_status();
+}
+
+}  // namespace
+}  // namespace pardtw
+
+extern "C" size_t pardtw_backtrace_parallel_bytes(int64_t n, int64_t m) {
+    if (!pardtw::valid_sizes(n, m)) return 0;
+    return pardtw::seg_bytes(n);
+}
+
+extern "C" pardtw_status pardtw_backtrace_parallel(const uint8_t* bp, int64_t n, int64_t m,
+                                                   const int32_t* pair_status, int32_t* path, int32_t* path_len,
+                                                   void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    return pardtw::seg_backtrace<false>(bp, n, m, pair_status, path, path_len, workspace, workspace_bytes, stream);
+}
+
+extern "C" pardtw_status pardtw_backtrace_packed_parallel(const uint16_t* bp2, int64_t n, int64_t m,
+                                                          const int32_t* pair_status, int32_t* path,
+                                                          int32_t* path_len, void* workspace,
+                                                          size_t workspace_bytes, hipStream_t stream) {
+    return pardtw::seg_backtrace<true>(reinterpret_cast<const uint8_t*>(bp2), n, m, pair_status, path, path_len,
+                                       workspace, workspace_bytes, stream);
 }
 
 extern "C" pardtw_status pardtw_subseq_backtrace(const uint8_t* bp, int64_t n, int64_t m, const int32_t* end_col,

@@ -66,6 +66,7 @@ __device__ inline float cell_cost(const VX& x, const VY& y, int64_t d) {
 }
 
 constexpr int kTotalThreads = 256;  // four waves, one per SIMD, with room for kCells rows in registers
+constexpr int kTotalBlocks = 256;   // one per CU: the path is cut into this many contiguous pieces
 constexpr int kCells = 8;   // path cells per thread and round, their loads issued together
 constexpr int kRegD = 16;   // features held in registers (d <= 16, d % 4 == 0); other rows are read in place
 
@@ -76,25 +77,42 @@ __device__ inline float step_weight(const int2* __restrict__ pp, int64_t l, int2
     return (cur.x - prev.x == 1 && cur.y - prev.y == 1) ? 2.0f : 3.0f;
 }
 
-// One workgroup: each thread sums a strided share of the path cells, kCells
-// at a time, then the (hi, lo) pairs are added in a tree through LDS.
+// Adds the (hi, lo) pairs of a block's threads in a tree through LDS; thread 0
+// gets the sum.
+__device__ inline F2 block_sum(F2* part, F2 acc) {
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kTotalThreads / 2; s > 0; s >>= 1) {
+        if (int(threadIdx.x) < s) part[threadIdx.x] = f2_add(part[threadIdx.x], part[threadIdx.x + s]);
+        __syncthreads();
+    }
+    return part[0];
+}
+
+// Block b sums piece b of the path (cells [b q, (b + 1) q), q = ceil(len /
+// kTotalBlocks)): each thread a strided share, kCells at a time, then the
+// block's pairs in a tree. The pieces depend only on the length, so the
+// result does not depend on the schedule.
 __global__ __launch_bounds__(kTotalThreads) void path_total_kernel(const float* __restrict__ X,
                                                                    const float* __restrict__ Y, int64_t d,
                                                                    const int32_t* __restrict__ path,
                                                                    const int32_t* __restrict__ path_len,
-                                                                   float* total) {
+                                                                   F2* partial) {
     __shared__ F2 part[kTotalThreads];
     const int64_t len = *path_len;
+    const int64_t q = (len + kTotalBlocks - 1) / kTotalBlocks;
+    const int64_t beg = int64_t(blockIdx.x) * q;
+    const int64_t end = beg + q < len ? beg + q : len;
     const int2* pp = reinterpret_cast<const int2*>(path);
     F2 acc = {0.0f, 0.0f};
-    for (int64_t l0 = threadIdx.x; l0 < len; l0 += int64_t(kTotalThreads) * kCells) {
+    for (int64_t l0 = beg + threadIdx.x; l0 < end; l0 += int64_t(kTotalThreads) * kCells) {
         int2 cell[kCells];
         float w[kCells], c[kCells];
 #pragma unroll
         for (int u = 0; u < kCells; ++u) {
             const int64_t l = l0 + int64_t(u) * kTotalThreads;
-            cell[u] = l < len ? pp[l] : int2{0, 0};
-            w[u] = l < len ? step_weight(pp, l, cell[u]) : 0.0f;
+            cell[u] = l < end ? pp[l] : int2{0, 0};
+            w[u] = l < end ? step_weight(pp, l, cell[u]) : 0.0f;
         }
         if (d <= kRegD && d % 4 == 0) {
             // rows of whole 16-byte vectors (X and Y start 16-byte aligned)
@@ -128,23 +146,35 @@ __global__ __launch_bounds__(kTotalThreads) void path_total_kernel(const float* 
             acc.lo += e;
         }
     }
-    part[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = kTotalThreads / 2; s > 0; s >>= 1) {
-        if (int(threadIdx.x) < s) part[threadIdx.x] = f2_add(part[threadIdx.x], part[threadIdx.x + s]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *total = len > 0 ? part[0].hi + part[0].lo : __builtin_inff();
+    const F2 sum = block_sum(part, acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = sum;
+}
+
+// The kTotalBlocks pieces, added in a tree; +inf for an empty path.
+__global__ __launch_bounds__(kTotalThreads) void path_total_final_kernel(const F2* __restrict__ partial,
+                                                                         const int32_t* __restrict__ path_len,
+                                                                         float* total) {
+    static_assert(kTotalBlocks == kTotalThreads, "one piece per thread");
+    __shared__ F2 part[kTotalThreads];
+    const F2 sum = block_sum(part, partial[threadIdx.x]);
+    if (threadIdx.x == 0) *total = *path_len > 0 ? sum.hi + sum.lo : __builtin_inff();
 }
 
 }  // namespace
 }  // namespace pardtw
 
+extern "C" size_t pardtw_path_total_bytes(void) { return pardtw::kTotalBlocks * sizeof(pardtw::F2); }
+
 extern "C" pardtw_status pardtw_path_total(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
                                            const int32_t* path, const int32_t* path_len, float* total,
-                                           hipStream_t stream) {
-    if (!X || !Y || !path || !path_len || !total || !pardtw::valid_sizes(n, m) || d <= 0)
+                                           void* workspace, size_t workspace_bytes, hipStream_t stream) {
+    if (!X || !Y || !path || !path_len || !total || !workspace || !pardtw::valid_sizes(n, m) || d <= 0)
         return PARDTW_ERR_INVALID_ARG;
-    pardtw::path_total_kernel<<<1, pardtw::kTotalThreads, 0, stream>>>(X, Y, d, path, path_len, total);
+    if (reinterpret_cast<uintptr_t>(workspace) % 8 != 0) return PARDTW_ERR_INVALID_ARG;
+    if (workspace_bytes < pardtw_path_total_bytes()) return PARDTW_ERR_WORKSPACE;
+    pardtw::F2* partial = reinterpret_cast<pardtw::F2*>(workspace);
+    pardtw::path_total_kernel<<<pardtw::kTotalBlocks, pardtw::kTotalThreads, 0, stream>>>(X, Y, d, path, path_len,
+                                                                                          partial);
+    pardtw::path_total_final_kernel<<<1, pardtw::kTotalThreads, 0, stream>>>(partial, path_len, total);
     return pardtw::launch_status();
 }

@@ -67,10 +67,14 @@ _lib_dp_packed = _sig("pardtw_dp_packed", _E, [_P, _E, _I64, _I64, _P, _P, _P, _
 _lib_dp_fused_packed = _sig("pardtw_dp_fused_packed", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _SZ, _P])
 _lib_bt_packed = _sig("pardtw_backtrace_packed", _E, [_P, _I64, _I64, _P, _P, _P, _P])
 _lib_unpack2 = _sig("pardtw_bp2_unpack", _E, [_P, _I64, _I64, _P, _P])
+_lib_bt_par_bytes = _sig("pardtw_backtrace_parallel_bytes", _SZ, [_I64, _I64])
+_lib_bt_par = _sig("pardtw_backtrace_parallel", _E, [_P, _I64, _I64, _P, _P, _P, _P, _SZ, _P])
+_lib_bt_packed_par = _sig("pardtw_backtrace_packed_parallel", _E, [_P, _I64, _I64, _P, _P, _P, _P, _SZ, _P])
 _lib_ckpt_bytes = _sig("pardtw_ckpt_bytes", _SZ, [_I64, _I64, _I32])
 _lib_dp_ckpt = _sig("pardtw_dp_fused_ckpt", _E, [_P, _P, _I64, _I64, _I64, _I32, _P, _SZ, _P, _P, _P, _SZ, _P])
 _lib_ckpt_bt = _sig("pardtw_ckpt_backtrace", _E, [_P, _P, _I64, _I64, _I64, _I32, _P, _SZ, _P, _P, _P, _P])
-_lib_total = _sig("pardtw_path_total", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P])
+_lib_total = _sig("pardtw_path_total", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _SZ, _P])
+_lib_total_bytes = _sig("pardtw_path_total_bytes", _SZ, [])
 _lib_grad = _sig("pardtw_path_grad", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P])
 _lib_plan_create = _sig("pardtw_plan_create_ex", _E, [_I32, _P, _P, _I64, _E, _I32, ctypes.POINTER(_P)])
 _lib_plan_ws = _sig("pardtw_plan_workspace_bytes", _SZ, [_P])
@@ -190,16 +194,24 @@ def pardtw_dp_noalloc(C: torch.Tensor, n: int, m: int, bp: torch.Tensor, total: 
            "pardtw_dp_noalloc")
 
 
+def pardtw_path_total_bytes() -> int:
+    return int(_lib_total_bytes())
+
+
 def pardtw_path_total(X: torch.Tensor, Y: torch.Tensor, path: torch.Tensor, path_len: torch.Tensor,
-                      total: torch.Tensor, stream=None):
-    """The path's cost summed in two-float arithmetic (compensated total)."""
+                      total: torch.Tensor, workspace: Optional[torch.Tensor] = None, stream=None):
+    """The path's cost summed in two-float arithmetic (compensated total).
+    Without `workspace` one of pardtw_path_total_bytes() is allocated."""
     _dev_f32(X, "X"), _dev_f32(Y, "Y"), _dev_f32(total, "total")
     if path.dtype != torch.int32 or path_len.dtype != torch.int32:
         raise ValueError("path and path_len must be int32")
     n, d = X.shape
     m = Y.shape[0]
-    _check(_lib_total(_ptr(X), _ptr(Y), n, m, d, _ptr(path), _ptr(path_len), _ptr(total), _stream(stream)),
-           "pardtw_path_total")
+    if workspace is None:
+        workspace = torch.empty(pardtw_path_total_bytes(), dtype=torch.uint8, device=X.device)
+    ws_bytes = workspace.numel() * workspace.element_size()
+    _check(_lib_total(_ptr(X), _ptr(Y), n, m, d, _ptr(path), _ptr(path_len), _ptr(total), _ptr(workspace),
+                      ws_bytes, _stream(stream)), "pardtw_path_total")
 
 
 def pardtw_dp_fused(X: torch.Tensor, Y: torch.Tensor, bp: torch.Tensor, total: torch.Tensor, status: torch.Tensor,
@@ -299,6 +311,25 @@ def pardtw_backtrace_packed(bp2: torch.Tensor, n: int, m: int, status: torch.Ten
            "pardtw_backtrace_packed")
 
 
+def pardtw_backtrace_parallel_bytes(n: int, m: int) -> int:
+    return int(_lib_bt_par_bytes(n, m))
+
+
+def pardtw_backtrace_parallel(bp: torch.Tensor, n: int, m: int, status: torch.Tensor, path: torch.Tensor,
+                              path_len: torch.Tensor, workspace: torch.Tensor, stream=None, packed: bool = False):
+    """The split walk (the same path as pardtw_backtrace / pardtw_backtrace_packed);
+    `workspace` holds pardtw_backtrace_parallel_bytes(n, m) bytes, 16-byte aligned."""
+    if packed:
+        _check_bp2(bp, n, m)
+    if path.dtype != torch.int32 or path.numel() < 2 * min(n, m):
+        raise ValueError("path must be int32 with room for 2*min(n, m) entries")
+    ws_bytes = workspace.numel() * workspace.element_size()
+    fn, name = (_lib_bt_packed_par, "pardtw_backtrace_packed_parallel") if packed else \
+        (_lib_bt_par, "pardtw_backtrace_parallel")
+    _check(fn(_ptr(bp), n, m, _ptr(status), _ptr(path), _ptr(path_len), _ptr(workspace), ws_bytes,
+              _stream(stream)), name)
+
+
 def pardtw_bp2_unpack(bp2: torch.Tensor, n: int, m: int, out: Optional[torch.Tensor] = None, stream=None):
     if out is None:
         out = torch.empty((n, m), dtype=torch.int8, device=bp2.device)
@@ -344,15 +375,19 @@ class Workspace:
         self.ws = torch.zeros(pardtw_dp_workspace_bytes(n, m), dtype=torch.uint8, device=device)
         self.total = torch.empty(1, dtype=torch.float32, device=device)
         self.total_comp = torch.empty(1, dtype=torch.float32, device=device)  # pardtw_path_total's output
+        self.total_ws = torch.empty(pardtw_path_total_bytes(), dtype=torch.uint8, device=device)
         self.status = torch.empty(1, dtype=torch.int32, device=device)
         self.path = torch.empty((min(n, m), 2), dtype=torch.int32, device=device)
         self.path_len = torch.empty(1, dtype=torch.int32, device=device)
+        # the split backtrace's segments (8 B per row)
+        self.bt_ws = torch.empty(pardtw_backtrace_parallel_bytes(n, m), dtype=torch.uint8, device=device)
 
 
 def align_into(X: torch.Tensor, Y: torch.Tensor, w: Workspace, prec: int = PREC_F32, stream=None,
-               fused: bool = False):
+               fused: bool = False, serial_backtrace: bool = False):
     """cost -> dp -> backtrace on the given stream, results left in w (with
-    `fused`, the DP computes the costs itself and w.C is not used)."""
+    `fused`, the DP computes the costs itself and w.C is not used). The
+    backtrace is the split walk unless `serial_backtrace` (same path)."""
     n, m = X.shape[0], Y.shape[0]
     if w.ckpt_rows:
         if prec != PREC_F32:
@@ -373,7 +408,9 @@ def align_into(X: torch.Tensor, Y: torch.Tensor, w: Workspace, prec: int = PREC_
             pardtw_dp_packed(w.C, n, m, w.bp, w.total, w.status, w.ws, w.layout, stream)
         else:
             pardtw_dp(w.C, n, m, w.bp, w.total, w.status, w.ws, w.layout, stream)
-    if w.packed:
+    if not serial_backtrace:
+        pardtw_backtrace_parallel(w.bp, n, m, w.status, w.path, w.path_len, w.bt_ws, stream, packed=w.packed)
+    elif w.packed:
         pardtw_backtrace_packed(w.bp, n, m, w.status, w.path, w.path_len, stream)
     else:
         pardtw_backtrace(w.bp, n, m, w.status, w.path, w.path_len, stream)

@@ -82,3 +82,24 @@ def test_total_zero_frames_and_empty_path():
     # costs 0, 1 (zero frame), 0; weights 1, 3, 2
     assert _total(X, Y, path) == pytest.approx(3.0, abs=1e-6)
     assert np.isinf(_total(X, Y, np.empty((0, 2), np.int32)))
+
+
+def test_total_pieces_and_workspace():
+    """Paths shorter than, equal to and just past the 256 pieces, and the
+    workspace check: every piece boundary leaves the sum unchanged."""
+    rng = np.random.default_rng(21)
+    for L in (255, 256, 257, 513, 100000):
+        steps = rng.choice(3, size=L - 1, p=[0.6, 0.2, 0.2])
+        d = np.array([(1, 1), (1, 2), (2, 1)])[steps]
+        path = np.concatenate([[[0, 0]], np.cumsum(d, 0)]).astype(np.int32)
+        n, m = int(path[-1, 0]) + 1, int(path[-1, 1]) + 1
+        X, Y = synth.chroma_like(rng, n), synth.chroma_like(rng, m)
+        J = oracle.path_cost(X, Y, path)
+        assert abs(_total(X, Y, path) - J) <= 5e-7 * J
+    Xd = torch.ones((4, 12), dtype=torch.float32, device=DEV)
+    p = torch.zeros((4, 2), dtype=torch.int32, device=DEV)
+    plen = torch.ones(1, dtype=torch.int32, device=DEV)
+    out = torch.empty(1, dtype=torch.float32, device=DEV)
+    small = torch.empty(pd.pardtw_path_total_bytes() - 8, dtype=torch.uint8, device=DEV)
+    with pytest.raises(pd.PardtwError, match="ERR_WORKSPACE"):
+        pd.pardtw_path_total(Xd, Xd, p, plen, out, small)

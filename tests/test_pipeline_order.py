@@ -57,6 +57,10 @@ class Lib:
     def pardtw_backtrace_packed(self, bp, n, m, status, path, path_len, stream):
         self._call("bt_packed", bp.owner, stream)
 
+    def pardtw_backtrace_parallel(self, bp, n, m, status, path, path_len, ws, stream, packed):
+        assert ws.owner is bp.owner
+        self._call("bt_packed" if packed else "bt", bp.owner, stream)
+
     def pardtw_dp_fused_ckpt(self, X, Y, K, ckpt, total, status, ws, stream):
         self._call("dp", ckpt.owner, stream)
 
@@ -76,7 +80,7 @@ class Workspace:
     def __init__(self, name, packed=False):
         self.name = name
         self.packed = packed
-        for f in ("C", "bp", "ckpt", "total", "status", "ws", "path", "path_len"):
+        for f in ("C", "bp", "ckpt", "total", "status", "ws", "path", "path_len", "bt_ws"):
             setattr(self, f, Buf(self))
 
 
@@ -87,7 +91,8 @@ class Shape:
 @pytest.mark.parametrize("fused,K,packed", [(False, 0, False), (True, 0, False), (False, 64, False),
                                             (False, 0, True), (True, 0, True)])
 @pytest.mark.parametrize("nbuf,nbt", [(2, 1), (3, 2), (2, 2)])
-def test_pipelined_order(fused, K, packed, nbuf, nbt):
+@pytest.mark.parametrize("serial_walk", [False, True])
+def test_pipelined_order(fused, K, packed, nbuf, nbt, serial_walk):
     log = []
     steps = 9
     stream = Stream(log, "main")
@@ -95,7 +100,8 @@ def test_pipelined_order(fused, K, packed, nbuf, nbt):
     bufs = [Workspace(f"w{i}", packed) for i in range(nbuf)]
     dp_kind, bt_kind = ("dp_packed", "bt_packed") if packed else ("dp", "bt")
     evs = [[Event(log, (s, k)) for k in range(6)] for s in range(steps)]
-    bench.launch_pipelined(Lib(log), Shape(), Shape(), bufs, stream, (stream, bts), steps, fused, K, evs)
+    bench.launch_pipelined(Lib(log), Shape(), Shape(), bufs, stream, (stream, bts), steps, fused, K, evs,
+                           serial_walk=serial_walk)
 
     def pos(entry):
         return log.index(entry)
