@@ -625,7 +625,8 @@ def pair_roofline(args, n, m, dp_ms):
     with the fused cost). The dense all-cells figure is reported only under
     its own label. `traffic` is the counter-measured bytes of one launch when
     the counters were taken on this DP source."""
-    bpc = 1 if args.fused else DP_BYTES_PER_CELL
+    # 4 B of cost read (none when fused), 1 B of code written (2 bits packed)
+    bpc = (0 if args.fused else DP_BYTES_PER_CELL - 1) + (0.25 if args.packed else 1)
     bcells = band_cells(n, m)
     alg = bpc * bcells
     dp_achieved = alg / (dp_ms * 1e-3) / 1e9
@@ -634,7 +635,7 @@ def pair_roofline(args, n, m, dp_ms):
         try:
             tj = json.load(open(args.traffic_json))
             src = open(os.path.join(ROOT, "paper_2607_15478_amd", "csrc", "dp.hip"), "rb").read()
-            if (not args.fused and tj.get("workload") == args.workload
+            if (not args.fused and not args.packed and tj.get("workload") == args.workload
                     and tj.get("dp_source_sha256") == hashlib.sha256(src).hexdigest()):
                 traffic = tj.get("bytes_per_launch")
         except (OSError, ValueError):
@@ -642,8 +643,8 @@ def pair_roofline(args, n, m, dp_ms):
     dense = bpc * n * m / (dp_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(dp_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dp_achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "dp_kernel (fused cost)" if args.fused else "dp_kernel",
-                "algorithmic_bytes_per_launch": alg, "bytes_per_band_cell": bpc, "band_cells": bcells,
+                "kernel": "dp_kernel" + (" (fused cost)" if args.fused else "") + (" (packed codes)" if args.packed else ""),
+                "algorithmic_bytes_per_launch": int(alg), "bytes_per_band_cell": bpc, "band_cells": bcells,
                 "band_fraction": round(bcells / (n * m), 4), "kernel_ms": round(float(dp_ms), 4),
                 "dense_equivalent": {"note": "all n*m cells at the same bytes per cell; not the method's work",
                                      "GBps": round(dense, 1), "frac": round(dense / HBM_PEAK_GBS, 4)}}

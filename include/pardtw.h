@@ -166,8 +166,9 @@ pardtw_status pardtw_dp_ex(const float* C, pardtw_layout layout, int64_t n, int6
  * routine; on its first call on a device it looks up the array's device
  * address (hipGetSymbolAddress) with that device current.
  *   PARDTW_ERR_WORKSPACE when pardtw_dp_workspace_bytes(n, m) exceeds
- *   PARDTW_NOALLOC_SCRATCH_BYTES (about n*m <= 2.6e8 cells; 10000 x 12000
- *   fits, 50000 x 60000 does not).
+ *   PARDTW_NOALLOC_SCRATCH_BYTES (16 B per row of X for each of
+ *   min(ceil(m/64), 257) record columns: about n*m <= 2.6e8 cells up to 16448
+ *   columns, n <= 16300 beyond; 15000 x 15000 fits, 50000 x 60000 does not).
  * Every call on one GPU shares that GPU's array, which keeps the last call's
  * contents (boundary records tagged by a launch counter, so stale contents
  * are never mistaken for new ones): calls that overlap in time on one GPU,
