@@ -722,7 +722,9 @@ def run_batch(args):
     Xp, Yp = pd.pack(pairs, dev)
     res = {}
     for prec in ([pd.PREC_F32, pd.PREC_BF16] if d >= 64 else [pd.PREC_F32]):
-        plan = pd.Plan(ns, ms, d, prec, fused=args.fused and d <= 16 and prec == pd.PREC_F32)
+        # fused: FP32 costs for d <= 16, BF16-operand costs for d <= 128 (d % 8 == 0)
+        fusable = (d <= 16) if prec == pd.PREC_F32 else (d <= 128 and d % 8 == 0)
+        plan = pd.Plan(ns, ms, d, prec, fused=args.fused and fusable)
         buf = plan.buffers(dev)
         best = plan.autotune(Xp, Yp, buf, reps=2)
         for _ in range(args.warmup):

@@ -1,17 +1,18 @@
 // a4: backtrace of the optimal path (Sec. II-D keeps the full backtrace
 // matrix; the path is recovered from (N-1, M-1) once the sweep is done).
 //
-// The walk is serial, so it is built for latency on one workgroup:
+// A walk is serial, so it is built for latency on one workgroup:
 //
-// * Loaders (waves 1..kLoaders). Every step moves 1-2 rows and 1-2 columns, so
+// * Loaders (waves 1..L). Every step moves 1-2 rows and 1-2 columns, so
 //   from a cell (i, j) the path's cells in a column panel p satisfy
 //   ceil(dj/2) <= di <= 2 dj, which bounds the rows it can touch there. When
-//   the walker enters panel q it asks for panel q - (kSlots - 1); a loader
+//   the walker enters panel q it asks for panel q - (S - 1); a loader
 //   copies exactly those rows' 8-row groups (contiguous in the DP's backtrace
-//   layout) into a ring of LDS slots (slot = panel mod kSlots), compacting the
+//   layout) into a ring of S LDS slots (slot = panel mod S), compacting the
 //   codes to 2 bits on the way: a slot holds one 16-bit word per (group,
 //   column) with row r of the group in bits 2r..2r+1. Loader w serves every
-//   kLoaders-th request, so several requests are in flight at once.
+//   L-th request, so several requests are in flight at once. (S, L) is (8, 7)
+//   for a whole path, (4, 3) for a segment of the split walk below.
 // * Walker (wave 0). From the current cell (i, j), lane b holds column j - b
 //   and the codes of rows i-31..i in two registers (row i - a in bits
 //   30-2a..31-2a of the first for a < 16, of the second as a - 16 otherwise),
@@ -36,26 +37,38 @@
 namespace pardtw {
 namespace {
 
-constexpr int kSlots = 8;                    // LDS ring of column panels
-constexpr int kSlotGroups = 128;             // 8-row groups per slot
-constexpr int kSlotBytes = kSlotGroups * kPanel * 2;  // 16 KB of 2-bit codes
+// A walker's LDS ring: NS column panels (a power of two) of NG 8-row groups
+// each, filled by NL loader waves.
+template <int NS, int NG, int NL>
+struct WalkShape {
+    static constexpr int kS = NS, kG = NG, kL = NL;
+    static constexpr int kBytes = NG * kPanel * 2;  // 2-bit codes of one slot
+    static constexpr int kThr = kLanes * (1 + NL);
+};
+// The whole path on one workgroup: panels 7 ahead (at most 101 groups each), 128 KB.
+using WalkFull = WalkShape<8, 128, 7>;
+// A segment of the split walk: panels 3 ahead (at most 65 groups each), 35 KB,
+// so that four segment workgroups share a CU.
+using WalkSeg = WalkShape<4, 68, 3>;
+constexpr int kSlots = WalkFull::kS;
 constexpr int kGroupBytes = kLanes * kBpRows;          // 512 bytes per group in the DP's layout
-constexpr int kLoaders = 7;
-constexpr int kThreads = kLanes * (1 + kLoaders);
+constexpr int kThreads = WalkFull::kThr;
 constexpr int kUnitBytes = kLanes * 16;      // one 16-byte load per lane: 1 KB = two groups
 constexpr int kBatch = 16;                   // units in flight per loader wave
 
-struct BtShared {
-    uint8_t slot[kSlots][kSlotBytes];
-    int req_panel[kSlots];   // request ring (request r in entry r % kSlots)
-    int req_glo[kSlots];
-    int req_ng[kSlots];
-    int slot_glo[kSlots];    // first group held by each slot
+template <class W>
+struct BtSharedT {
+    uint8_t slot[W::kS][W::kBytes];
+    int req_panel[W::kS];   // request ring (request r in entry r % kS)
+    int req_glo[W::kS];
+    int req_ng[W::kS];
+    int slot_glo[W::kS];    // first group held by each slot
     int req_count;           // requests issued by the walker
-    int loaded[kSlots];      // requests completed per slot
+    int loaded[W::kS];      // requests completed per slot
     int done;                // walker finished
     int len;                 // cells on the path (0 on failure)
 };
+using BtShared = BtSharedT<WalkFull>;
 
 __device__ inline int lds_load_acquire(int* p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -64,7 +77,9 @@ __device__ inline void lds_store_release(int* p, int v) {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Rows of panel p that a path from (i, j) can touch, as 8-row groups.
+// Rows of panel p that a path from (i, j) can touch, as 8-row groups (at most
+// NG of them).
+template <int NG>
 __device__ inline void panel_groups(int i, int j, int p, int& glo, int& ng) {
     const int djmax = j - p * kPanel;
     const int djmin = max(0, j - (p * kPanel + kPanel - 1));
@@ -73,8 +88,8 @@ __device__ inline void panel_groups(int i, int j, int p, int& glo, int& ng) {
     const int rlo = max(0, i - 2 * djmax);
     const int rhi = max(0, i - (djmin + 1) / 2);
     glo = rlo / kBpRows;
-    // at most 101 groups for a panel kSlots - 1 = 7 panels ahead
-    ng = min(rhi / kBpRows - glo + 1, kSlotGroups);
+    // at most 101 groups for a panel 7 panels ahead, 65 for 3 ahead
+    ng = min(rhi / kBpRows - glo + 1, NG);
 }
 
 // Eight 2-bit codes (one byte each, values 0..3) to 16 bits.
@@ -96,16 +111,19 @@ __device__ inline uint32_t compact8(uint32_t lo, uint32_t hi) {
 // stop_row >= 0 the walk ends at the first cell on a row <= stop_row, which is
 // not written but returned in *exit; such a walk must stay at row >= 33 and
 // column >= 66 (the path's cells there do), else it fails.
-template <bool SEG = false>
-__device__ int walk(BtShared& sh, int i0, int j0, bool sub, int cap, int32_t* path, int stop_row = -1,
+template <bool SEG, class W>
+__device__ int walk(BtSharedT<W>& sh, int i0, int j0, bool sub, int cap, int32_t* path, int stop_row = -1,
                     int2* exit = nullptr) {
+    constexpr int kSlots = W::kS;
+    constexpr int kSlotBytes = W::kBytes;
+    constexpr int kSlotGroups = W::kG;
     const int lane = threadIdx.x;
     const int P = j0 / kPanel + 1;  // panels the walk can visit
     int i = i0, j = j0, len = 0;
     int nreq = 0;
     auto request = [&](int p) {
         int glo, ng;
-        panel_groups(i, j, p, glo, ng);
+        panel_groups<kSlotGroups>(i, j, p, glo, ng);
         const int e = nreq % kSlots;
         if (lane == 0) {
             sh.req_panel[e] = p;
@@ -260,10 +278,11 @@ __device__ int walk(BtShared& sh, int i0, int j0, bool sub, int cap, int32_t* pa
 // the codes of each (group, column) to 16 bits. With PACK the codes already are
 // 16 bits per (group, column) in HBM, in the slot's own order, so the
 // requested groups are copied as they are.
-template <bool PACK>
-__device__ void load_panels(BtShared& sh, const uint8_t* bp, int64_t G, int w) {
+template <bool PACK, class W>
+__device__ void load_panels(BtSharedT<W>& sh, const uint8_t* bp, int64_t G, int w) {
+    constexpr int kSlots = W::kS;
     const int lane = threadIdx.x & (kLanes - 1);
-    for (int r = w;; r += kLoaders) {
+    for (int r = w;; r += W::kL) {
         while (lds_load_acquire(&sh.req_count) <= r) {
             if (lds_load_acquire(&sh.done)) return;
             __builtin_amdgcn_s_sleep(2);
@@ -362,7 +381,7 @@ __device__ void backtrace_pair(BtShared& sh, const uint8_t* bp, int n, int j_end
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     if (wave == 0) {
-        const int len = walk(sh, n - 1, j_end, sub, cap, path);
+        const int len = walk<false>(sh, n - 1, j_end, sub, cap, path);
         if (tid == 0) {
             sh.len = len;
             lds_store_release(&sh.done, 1);
@@ -428,11 +447,13 @@ __device__ inline int seg_guess_col(int i, int n, int m) {
 
 // One segment walk by the whole workgroup (walker wave 0, loader waves
 // 1..kLoaders); the result goes to info_out and, for every thread, to `res`.
+using SegShared = BtSharedT<WalkSeg>;
+
 template <bool PACK>
-__device__ SegInfo walk_segment(BtShared& sh, SegInfo& res, const SegArgs& a, int s, int si, int sj,
+__device__ SegInfo walk_segment(SegShared& sh, SegInfo& res, const SegArgs& a, int s, int si, int sj,
                                 SegInfo* info_out) {
     const int tid = threadIdx.x;
-    if (tid < kSlots) sh.loaded[tid] = 0;
+    if (tid < WalkSeg::kS) sh.loaded[tid] = 0;
     if (tid == 0) {
         sh.req_count = 0;
         sh.done = 0;
@@ -463,14 +484,9 @@ __device__ SegInfo walk_segment(BtShared& sh, SegInfo& res, const SegArgs& a, in
     return res;
 }
 
-// One round: workgroup s walks segment s.
+// One round for segment s.
 template <bool PACK>
-__global__ __launch_bounds__(kThreads) void seg_round_kernel(SegArgs a, const int32_t* __restrict__ status,
-                                                             int round) {
-    __shared__ BtShared sh;
-    __shared__ SegInfo res;
-    if (*status != PARDTW_PAIR_OK) return;
-    const int s = blockIdx.x;
+__device__ void seg_round_body(SegShared& sh, SegInfo& res, const SegArgs& a, int s, int round) {
     const SegInfo* prev = a.info + (round & 1 ? 0 : a.S);
     SegInfo* cur = a.info + (round & 1 ? a.S : 0);
     int si, sj;
@@ -499,18 +515,11 @@ __global__ __launch_bounds__(kThreads) void seg_round_kernel(SegArgs a, const in
 // Check from the last segment down, walk again what started elsewhere, take
 // the offsets and the length. `fin` is the half the last round wrote.
 template <bool PACK>
-__global__ __launch_bounds__(kThreads) void seg_finish_kernel(SegArgs a, const int32_t* __restrict__ status, int fin,
-                                                              int cap, int32_t* path_len) {
-    __shared__ BtShared sh;
-    __shared__ SegInfo res;
-    __shared__ SegInfo sinfo[kSegMaxCount];
+__device__ void seg_finish_body(SegShared& sh, SegInfo& res, SegInfo* sinfo, const SegArgs& a, int fin, int cap,
+                                int32_t* path_len) {
     const int tid = threadIdx.x;
-    if (*status != PARDTW_PAIR_OK) {
-        if (tid == 0) *path_len = 0;
-        return;
-    }
     SegInfo* info = a.info + fin * a.S;
-    for (int k = tid; k < a.S; k += kThreads) sinfo[k] = info[k];
+    for (int k = tid; k < a.S; k += WalkSeg::kThr) sinfo[k] = info[k];
     __syncthreads();
     int si = a.n - 1, sj = a.m - 1;
     for (int s = a.S - 1; s >= 0; --s) {
@@ -537,14 +546,96 @@ __global__ __launch_bounds__(kThreads) void seg_finish_kernel(SegArgs a, const i
     }
 }
 
-// Block s copies segment s, reversed, to its place in the path.
+// Copies segment s, reversed, to its place in the path.
+__device__ void seg_copy_body(const SegArgs& a, int s, int fin, int32_t* path) {
+    const SegInfo me = a.info[fin * a.S + s];
+    const int2* src = reinterpret_cast<const int2*>(a.cells + int64_t(s) * a.R * 2);
+    int2* dst = reinterpret_cast<int2*>(path) + me.off;
+    for (int k = threadIdx.x; k < me.len; k += blockDim.x) dst[me.len - 1 - k] = src[k];
+}
+
+// One pair: workgroup s walks segment s.
+template <bool PACK>
+__global__ __launch_bounds__(WalkSeg::kThr) void seg_round_kernel(SegArgs a, const int32_t* __restrict__ status,
+                                                                   int round) {
+    __shared__ SegShared sh;
+    __shared__ SegInfo res;
+    if (*status != PARDTW_PAIR_OK) return;
+    seg_round_body<PACK>(sh, res, a, blockIdx.x, round);
+}
+
+template <bool PACK>
+__global__ __launch_bounds__(WalkSeg::kThr) void seg_finish_kernel(SegArgs a, const int32_t* __restrict__ status,
+                                                                    int fin, int cap, int32_t* path_len) {
+    __shared__ SegShared sh;
+    __shared__ SegInfo res;
+    __shared__ SegInfo sinfo[kSegMaxCount];
+    if (*status != PARDTW_PAIR_OK) {
+        if (threadIdx.x == 0) *path_len = 0;
+        return;
+    }
+    seg_finish_body<PACK>(sh, res, sinfo, a, fin, cap, path_len);
+}
+
 __global__ __launch_bounds__(256) void seg_copy_kernel(SegArgs a, int fin, const int32_t* __restrict__ path_len,
                                                        int32_t* __restrict__ path) {
     if (*path_len <= 0) return;
-    const SegInfo me = a.info[fin * a.S + blockIdx.x];
-    const int2* src = reinterpret_cast<const int2*>(a.cells + int64_t(blockIdx.x) * a.R * 2);
-    int2* dst = reinterpret_cast<int2*>(path) + me.off;
-    for (int k = threadIdx.x; k < me.len; k += blockDim.x) dst[me.len - 1 - k] = src[k];
+    seg_copy_body(a, blockIdx.x, fin, path);
+}
+
+// Batched form: the pairs listed in `sp` are split (segment g belongs to
+// sp[seg_map[g]]); the others keep the one-workgroup walk.
+struct SegBatchArgs {
+    const BatchPair* pairs;
+    const SegPair* sp;
+    const int32_t* seg_map;
+    const uint8_t* bp;     // codes of the batch
+    const int32_t* status;
+    SegInfo* info;         // the split region: SegInfo entries, then cells
+    int32_t* cells;
+    int32_t* paths;
+    int32_t* path_len;
+};
+
+__device__ inline SegArgs seg_args_of(const SegBatchArgs& ba, const SegPair& sp) {
+    const BatchPair q = ba.pairs[sp.pair];
+    SegArgs a;
+    a.bp = ba.bp + q.bp_off;
+    a.n = int(q.n);
+    a.m = int(q.m);
+    a.R = sp.R;
+    a.S = sp.S;
+    a.info = ba.info + sp.info_off;
+    a.cells = ba.cells + sp.cells_off;
+    return a;
+}
+
+__global__ __launch_bounds__(WalkSeg::kThr) void seg_round_batch_kernel(SegBatchArgs ba, int round) {
+    __shared__ SegShared sh;
+    __shared__ SegInfo res;
+    const SegPair sp = ba.sp[ba.seg_map[blockIdx.x]];
+    if (ba.status[sp.pair] != PARDTW_PAIR_OK) return;
+    seg_round_body<false>(sh, res, seg_args_of(ba, sp), int(blockIdx.x) - sp.seg0, round);
+}
+
+__global__ __launch_bounds__(WalkSeg::kThr) void seg_finish_batch_kernel(SegBatchArgs ba, int fin) {
+    __shared__ SegShared sh;
+    __shared__ SegInfo res;
+    __shared__ SegInfo sinfo[kSegMaxCount];
+    const SegPair sp = ba.sp[blockIdx.x];
+    int32_t* plen = ba.path_len + sp.pair;
+    if (ba.status[sp.pair] != PARDTW_PAIR_OK) {
+        if (threadIdx.x == 0) *plen = 0;
+        return;
+    }
+    const BatchPair q = ba.pairs[sp.pair];
+    seg_finish_body<false>(sh, res, sinfo, seg_args_of(ba, sp), fin, int(q.n < q.m ? q.n : q.m), plen);
+}
+
+__global__ __launch_bounds__(256) void seg_copy_batch_kernel(SegBatchArgs ba, int fin) {
+    const SegPair sp = ba.sp[ba.seg_map[blockIdx.x]];
+    if (ba.path_len[sp.pair] <= 0) return;
+    seg_copy_body(seg_args_of(ba, sp), int(blockIdx.x) - sp.seg0, fin, ba.paths + 2 * ba.pairs[sp.pair].path_off);
 }
 
 __global__ __launch_bounds__(kThreads) void backtrace_kernel(const uint8_t* __restrict__ bp, int64_t n, int64_t m,
@@ -596,6 +687,7 @@ __global__ __launch_bounds__(kThreads) void backtrace_batch_kernel(const BatchPa
     __shared__ BtShared sh;
     const int b = blockIdx.x;
     const BatchPair q = pairs[b];
+    if (q.split) return;  // walked by the split kernels
     const bool ok = q.feasible && status[b] == PARDTW_PAIR_OK;
     backtrace_pair(sh, bpbase + q.bp_off, int(q.n), int(q.m - 1), false, ok, int(q.n < q.m ? q.n : q.m),
                    paths + 2 * q.path_off, path_len + b);
@@ -684,14 +776,41 @@ pardtw_status seg_backtrace(const uint8_t* bp, int64_t n, int64_t m, const int32
     }
     a.info = reinterpret_cast<SegInfo*>(ws);
     a.cells = reinterpret_cast<int32_t*>(a.info + 2 * a.S);
-    for (int r = 0; r < kSegRounds; ++r) seg_round_kernel<PACK><<<a.S, kThreads, 0, stream>>>(a, status, r);
+    for (int r = 0; r < kSegRounds; ++r) seg_round_kernel<PACK><<<a.S, WalkSeg::kThr, 0, stream>>>(a, status, r);
     const int fin = (kSegRounds - 1) & 1;
-    seg_finish_kernel<PACK><<<1, kThreads, 0, stream>>>(a, status, fin, int(n < m ? n : m), path_len);
+    seg_finish_kernel<PACK><<<1, WalkSeg::kThr, 0, stream>>>(a, status, fin, int(n < m ? n : m), path_len);
     seg_copy_kernel<<<a.S, 256, 0, stream>>>(a, fin, path_len, path);
     return launch_status();
 }
 
 }  // namespace
+
+void split_shape(int64_t n, int& R, int& S) { seg_shape(n, R, S); }
+
+size_t split_record_bytes() { return sizeof(SegInfo); }
+
+pardtw_status split_backtrace_batch_launch(const BatchPair* pairs, const SegPair* sp, int32_t nsplit,
+                                           const int32_t* seg_map, int32_t nseg, const uint8_t* bpbase,
+                                           const int32_t* status, void* records, int32_t* cells, int32_t* paths,
+                                           int32_t* path_len, hipStream_t stream) {
+    if (nsplit <= 0 || nseg <= 0) return PARDTW_OK;
+    SegBatchArgs ba;
+    ba.pairs = pairs;
+    ba.sp = sp;
+    ba.seg_map = seg_map;
+    ba.bp = bpbase;
+    ba.status = status;
+    ba.info = reinterpret_cast<SegInfo*>(records);
+    ba.cells = cells;
+    ba.paths = paths;
+    ba.path_len = path_len;
+    for (int r = 0; r < kSegRounds; ++r) seg_round_batch_kernel<<<nseg, WalkSeg::kThr, 0, stream>>>(ba, r);
+    const int fin = (kSegRounds - 1) & 1;
+    seg_finish_batch_kernel<<<nsplit, WalkSeg::kThr, 0, stream>>>(ba, fin);
+    seg_copy_batch_kernel<<<nseg, 256, 0, stream>>>(ba, fin);
+    return launch_status();
+}
+
 }  // namespace pardtw
 
 extern "C" size_t pardtw_backtrace_parallel_bytes(int64_t n, int64_t m) {

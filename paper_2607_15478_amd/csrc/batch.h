@@ -22,7 +22,18 @@ struct BatchPair {
     int32_t P;             // column panels
     int32_t feasible;      // some path exists (to (n-1, m-1), or to row n-1 for a fragment)
     int32_t band;          // cost groups written: 1 the DTW path band, 2 the subsequence band
-    int32_t pad;
+    int32_t split;         // 1: backtrace by the split walk (a SegPair lists it), 0: one workgroup
+};
+
+// A pair of a batch whose backtrace is the split walk of
+// pardtw_backtrace_parallel: its segments, and where their state lives in the
+// plan's split region (segment records, then cells).
+struct SegPair {
+    int32_t pair;       // index in the batch
+    int32_t R, S;       // rows per segment, segments
+    int32_t seg0;       // first segment in the batch numbering
+    int64_t info_off;   // first of its 2 S segment records
+    int64_t cells_off;  // first int32 of its S R cell pairs
 };
 
 // Work item of the persistent batched DP: panel group q of pair b.
@@ -41,11 +52,13 @@ pardtw_status cost_batch_launch(const BatchPair* pairs, const int32_t* tile_pair
 // DP (one header for the batch, records at each pair's rec_off).
 // With `sub` every pair is a fragment of Segmental DTW: the subsequence DP,
 // whose scores go to totals + b * m (fragments share m). With X (not null) the
-// costs are computed inside the DP from X_packed, Y_packed (d <= 16) and the
-// row norms at rxs (fused form; nw <= 4); otherwise they are read from Cbase.
+// costs are computed inside the DP from X_packed, Y_packed (fused form): FP32
+// with d <= 16 and the row norms at rxs (nw <= 4), or with `bf16` from BF16
+// operands with d <= 128, d % 8 == 0 (nw <= 2); otherwise they are read from
+// Cbase.
 pardtw_status dp_batch_launch(const BatchPair* pairs, const DpItem* items, int32_t nitems, int nw, int grid,
                               const float* Cbase, const float* X, const float* Y, int64_t d, const float* rxs,
-                              uint8_t* bpbase, float* totals, int32_t* status, void* dp_ws, bool sub,
+                              bool bf16, uint8_t* bpbase, float* totals, int32_t* status, void* dp_ws, bool sub,
                               hipStream_t stream);
 
 // Row norms of every feasible pair for the fused batched DP (rx_floats(n_b)
@@ -55,6 +68,17 @@ pardtw_status row_norms_batch_launch(const BatchPair* pairs, int32_t batch, cons
 
 pardtw_status backtrace_batch_launch(const BatchPair* pairs, int32_t batch, const uint8_t* bpbase,
                                      const int32_t* status, int32_t* paths, int32_t* path_len, hipStream_t stream);
+
+// Segments of the split walk for a pair of n rows: R rows each, S of them; a
+// pair is split when S > 2.
+void split_shape(int64_t n, int& R, int& S);
+size_t split_record_bytes();  // one segment record
+// The split pairs' walks (nseg segments over nsplit pairs; seg_map[g] is the
+// SegPair of segment g). Pairs with split == 0 are left to backtrace_batch_launch.
+pardtw_status split_backtrace_batch_launch(const BatchPair* pairs, const SegPair* sp, int32_t nsplit,
+                                           const int32_t* seg_map, int32_t nseg, const uint8_t* bpbase,
+                                           const int32_t* status, void* records, int32_t* cells, int32_t* paths,
+                                           int32_t* path_len, hipStream_t stream);
 
 pardtw_status grad_batch_launch(const BatchPair* pairs, int32_t batch, int64_t max_cap, int64_t d, const float* X,
                                 const float* Y, const int32_t* paths, const int32_t* path_len, const float* g,

@@ -68,11 +68,20 @@ struct pardtw_plan {
     int chosen = 0;
     size_t off_c = 0, off_bp = 0, off_dp = 0, ws_bytes = 0;
     int64_t path_capacity = 0, max_cap = 0, x_rows = 0, y_rows = 0;
+    // split backtraces of the long pairs: their segments and the workspace
+    // region of their segment records and cells
+    std::vector<pardtw::SegPair> segpairs;
+    std::vector<int32_t> seg_map;
+    pardtw::SegPair* segpairs_dev = nullptr;
+    int32_t* seg_map_dev = nullptr;
+    size_t off_split_rec = 0, off_split_cells = 0;
 
     ~pardtw_plan() {
         if (pairs_dev) (void)hipFree(pairs_dev);
         if (tile_pair_dev) (void)hipFree(tile_pair_dev);
         if (items_dev) (void)hipFree(items_dev);
+        if (segpairs_dev) (void)hipFree(segpairs_dev);
+        if (seg_map_dev) (void)hipFree(seg_map_dev);
     }
 };
 
@@ -119,13 +128,15 @@ pardtw_status run_dp(const pardtw_plan& pl, const Schedule& s, char* ws, const f
     }
     return pardtw::dp_batch_launch(pl.pairs_dev, pl.items_dev + s.items_at, s.nitems, s.nw, grid_for(pl, s),
                                    reinterpret_cast<const float*>(ws + pl.off_c), pl.fused ? X : nullptr, Y, pl.d,
-                                   reinterpret_cast<const float*>(ws + pl.off_rx),
+                                   reinterpret_cast<const float*>(ws + pl.off_rx), pl.prec == PARDTW_PREC_BF16,
                                    reinterpret_cast<uint8_t*>(ws + pl.off_bp), totals, status, ws + pl.off_dp, sub,
                                    stream);
 }
 
-// What precedes the DP: the cost GEMM, or for the fused form the row norms.
+// What precedes the DP: the cost GEMM, or for the FP32 fused form the row
+// norms (the BF16 fused form takes them from its row operands).
 pardtw_status run_front(const pardtw_plan& pl, const float* X, const float* Y, char* ws, hipStream_t stream) {
+    if (pl.fused && pl.prec == PARDTW_PREC_BF16) return PARDTW_OK;
     if (pl.fused)
         return pardtw::row_norms_batch_launch(pl.pairs_dev, pl.batch, X, pl.d, reinterpret_cast<float*>(ws + pl.off_rx),
                                               stream);
@@ -154,7 +165,7 @@ void place_pair(pardtw::BatchPair& q, int64_t n, int64_t m, bool feasible, int b
     q.P = int32_t(pardtw::num_panels(m));
     q.feasible = feasible ? 1 : 0;
     q.band = band;
-    q.pad = 0;
+    q.split = 0;
     q.c_off = int64_t(c_floats);
     q.bp_off = int64_t(bp_bytes);
     q.rec_off = int64_t(rec_bytes / sizeof(uint64_t));
@@ -193,7 +204,7 @@ pardtw_status finish_plan(pardtw_plan* pl, pardtw_plan** plan_out) {
     std::vector<pardtw::DpItem> all_items;
     const int nws[4] = {1, 2, 4, 8};
     for (int nw : nws) {
-        if (pl->fused && nw > 4) continue;
+        if (pl->fused && nw > (pl->prec == PARDTW_PREC_BF16 ? 2 : 4)) continue;
         for (int order = 0; order < 2; ++order) {
             const std::vector<pardtw::DpItem> it = make_items(*pl, nw, order);
             const int64_t at = int64_t(all_items.size());
@@ -201,10 +212,13 @@ pardtw_status finish_plan(pardtw_plan* pl, pardtw_plan** plan_out) {
             for (int gm = 1; gm <= 2; ++gm) pl->scheds.push_back({nw, order, gm, int32_t(it.size()), at});
         }
     }
-    // default: four panels per workgroup, breadth order, one workgroup per CU
+    // default: four panels per workgroup (two for BF16 fused), breadth order,
+    // one workgroup per CU
+    const int nw_default = pl->fused && pl->prec == PARDTW_PREC_BF16 ? 2 : 4;
     pl->chosen = 0;
     for (size_t s = 0; s < pl->scheds.size(); ++s)
-        if (pl->scheds[s].nw == 4 && pl->scheds[s].order == 0 && pl->scheds[s].grid_mul == 1) pl->chosen = int(s);
+        if (pl->scheds[s].nw == nw_default && pl->scheds[s].order == 0 && pl->scheds[s].grid_mul == 1)
+            pl->chosen = int(s);
     if (all_items.empty()) all_items.push_back({0, 0});
 
     bool ok = hipMalloc(&pl->pairs_dev, sizeof(pardtw::BatchPair) * batch) == hipSuccess &&
@@ -216,6 +230,14 @@ pardtw_status finish_plan(pardtw_plan* pl, pardtw_plan** plan_out) {
                          hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(pl->items_dev, all_items.data(), sizeof(pardtw::DpItem) * all_items.size(),
                          hipMemcpyHostToDevice) == hipSuccess;
+    if (ok && !pl->segpairs.empty()) {
+        ok = hipMalloc(&pl->segpairs_dev, sizeof(pardtw::SegPair) * pl->segpairs.size()) == hipSuccess &&
+             hipMalloc(&pl->seg_map_dev, sizeof(int32_t) * pl->seg_map.size()) == hipSuccess &&
+             hipMemcpy(pl->segpairs_dev, pl->segpairs.data(), sizeof(pardtw::SegPair) * pl->segpairs.size(),
+                       hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(pl->seg_map_dev, pl->seg_map.data(), sizeof(int32_t) * pl->seg_map.size(),
+                       hipMemcpyHostToDevice) == hipSuccess;
+    }
     if (!ok) {
         delete pl;
         return PARDTW_ERR_HIP;
@@ -228,10 +250,15 @@ pardtw_status finish_plan(pardtw_plan* pl, pardtw_plan** plan_out) {
 
 namespace {
 
-// The fused form computes FP32 costs from features with at most 16 entries.
+// The fused form computes FP32 costs from features with at most 16 entries,
+// or BF16-operand costs from features with at most 128 entries, a multiple of 8.
 pardtw_status check_flags(int32_t flags, int64_t d, pardtw_prec prec) {
     if (flags & ~int32_t(PARDTW_PLAN_FUSED_COST)) return PARDTW_ERR_INVALID_ARG;
-    if ((flags & PARDTW_PLAN_FUSED_COST) && (d > 16 || prec != PARDTW_PREC_F32)) return PARDTW_ERR_UNSUPPORTED;
+    if (flags & PARDTW_PLAN_FUSED_COST) {
+        const bool f32_ok = prec == PARDTW_PREC_F32 && d <= 16;
+        const bool bf16_ok = prec == PARDTW_PREC_BF16 && d <= 128 && d % 8 == 0;
+        if (!f32_ok && !bf16_ok) return PARDTW_ERR_UNSUPPORTED;
+    }
     return PARDTW_OK;
 }
 
@@ -290,7 +317,23 @@ extern "C" pardtw_status pardtw_plan_create_ex(int32_t batch, const int64_t* n_h
     pl->off_rx = 0;  // the fused form's row norms take the cost region's place
     pl->off_bp = align_up((pl->fused ? rx_total : c_floats) * sizeof(float));
     pl->off_dp = pl->off_bp + align_up(bp_bytes);
-    pl->ws_bytes = pl->off_dp + align_up(pardtw::dp_header_bytes() + rec_bytes);
+    // pairs of more than two segments get the split walk (pardtw_backtrace_parallel's)
+    int64_t nrec = 0, ncells = 0;
+    for (int b = 0; b < batch; ++b) {
+        pardtw::BatchPair& q = pl->pairs[b];
+        int R, S;
+        pardtw::split_shape(q.n, R, S);
+        if (!q.feasible || S <= 2) continue;
+        q.split = 1;
+        const int32_t idx = int32_t(pl->segpairs.size());
+        pl->segpairs.push_back({b, R, S, int32_t(pl->seg_map.size()), nrec, ncells});
+        pl->seg_map.insert(pl->seg_map.end(), size_t(S), idx);
+        nrec += 2 * int64_t(S);
+        ncells += int64_t(S) * R * 2;
+    }
+    pl->off_split_rec = pl->off_dp + align_up(pardtw::dp_header_bytes() + rec_bytes);
+    pl->off_split_cells = pl->off_split_rec + align_up(size_t(nrec) * pardtw::split_record_bytes());
+    pl->ws_bytes = pl->off_split_cells + align_up(size_t(ncells) * sizeof(int32_t));
     return finish_plan(pl, plan_out);
 }
 
@@ -338,9 +381,15 @@ extern "C" pardtw_status pardtw_align_batch(const pardtw_plan* plan, const float
     if (st != PARDTW_OK) return st;
     st = run_dp(*plan, plan->scheds[plan->chosen], ws, X_packed, Y_packed, totals, pair_status, stream);
     if (st != PARDTW_OK) return st;
-    return pardtw::backtrace_batch_launch(plan->pairs_dev, plan->batch,
-                                          reinterpret_cast<const uint8_t*>(ws + plan->off_bp), pair_status,
-                                          paths_packed, path_len, stream);
+    const uint8_t* bp = reinterpret_cast<const uint8_t*>(ws + plan->off_bp);
+    st = pardtw::backtrace_batch_launch(plan->pairs_dev, plan->batch, bp, pair_status, paths_packed, path_len,
+                                        stream);
+    if (st != PARDTW_OK) return st;
+    return pardtw::split_backtrace_batch_launch(plan->pairs_dev, plan->segpairs_dev, int32_t(plan->segpairs.size()),
+                                                plan->seg_map_dev, int32_t(plan->seg_map.size()), bp, pair_status,
+                                                ws + plan->off_split_rec,
+                                                reinterpret_cast<int32_t*>(ws + plan->off_split_cells),
+                                                paths_packed, path_len, stream);
 }
 
 extern "C" pardtw_status pardtw_plan_autotune(pardtw_plan* plan, const float* X_packed, const float* Y_packed,

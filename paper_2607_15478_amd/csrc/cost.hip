@@ -29,34 +29,9 @@
 namespace pardtw {
 namespace {
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
 constexpr int kTileM = 64;
 constexpr int kThreads = 256;
 constexpr int kTilesPerBlock = 8;  // row tiles swept by one workgroup
-
-// Eight consecutive features k0..k0+7 of one row (zeros past d), rounded to BF16.
-template <bool VEC>
-__device__ inline bf16x8 load8_bf16(const float* __restrict__ row, bool ok, int64_t k0, int64_t d, float& sq) {
-    float v[8];
-    if (VEC && ok && k0 + 8 <= d) {
-        const f32x4 a = *reinterpret_cast<const f32x4*>(row + k0);
-        const f32x4 b = *reinterpret_cast<const f32x4*>(row + k0 + 4);
-        v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
-        v[4] = b[0]; v[5] = b[1]; v[6] = b[2]; v[7] = b[3];
-    } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = (ok && k0 + e < d) ? row[k0 + e] : 0.0f;
-    }
-    bf16x8 out;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        out[e] = __bf16(v[e]);
-        const float r = float(out[e]);
-        sq = __builtin_fmaf(r, r, sq);
-    }
-    return out;
-}
 
 // Groups of panel p outside [lo, hi] are not written.
 struct GroupSpan {
@@ -237,19 +212,7 @@ __device__ __attribute__((always_inline)) inline void sweep_bf16_small(const flo
     const int64_t L = (d + 31) / 32 * 8;  // features per lane group, <= 32
     bf16x8 bv[4][4];
     float ry[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int64_t col = p * kPanel + b * 16 + (lane & 15);
-        const bool ok = col < m;
-        const float* yrow = Y + (ok ? col : 0) * d;
-        float sb = 0.0f;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            bv[b][s] = bf16x8{};
-            if (8 * s < L) bv[b][s] = load8_bf16<VEC>(yrow, ok, g * L + 8 * s, d, sb);
-        }
-        ry[b] = inv_from_sq(sum_groups(sb));
-    }
+    panel_operands_bf16<VEC>(Y, m, d, p, bv, ry);
     for (int u = 0; u < tiles; ++u) {
         const int64_t i0 = (t0 + u) * kTileM;
         if (i0 >= n) break;

@@ -17,6 +17,7 @@
 namespace pardtw {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 __device__ inline float sum_groups(float v) {
     // lanes l, l^16, l^32, l^48 hold the four quarters of one row / column
@@ -160,6 +161,63 @@ __device__ __attribute__((always_inline)) inline void costs_from_acc_rx(const f3
     for (int b = 0; b < 4; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[b][r] = 1.0f - (acc[b][r] * rx4[r]) * ry[b];
+}
+
+// ---- BF16 operands, d <= 128 (v_mfma_f32_16x16x32_bf16) ----------------------
+// Lane group g takes the features [g L, g L + L), L = ceil(d/32) * 8, eight per
+// MFMA step s (steps with 8 s >= L are not issued). The squares of the
+// BF16-rounded operands are summed in step and feature order; sum_groups adds
+// the four groups' sums.
+
+// Eight features rounded to BF16, their squares added to sq in order.
+__device__ __attribute__((always_inline)) inline bf16x8 cvt8_bf16(const float (&v)[8], float& sq) {
+    bf16x8 out;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        out[e] = __bf16(v[e]);
+        const float r = float(out[e]);
+        sq = __builtin_fmaf(r, r, sq);
+    }
+    return out;
+}
+
+// Eight consecutive features k0..k0+7 of one row (zeros past d), rounded to BF16.
+template <bool VEC>
+__device__ inline bf16x8 load8_bf16(const float* __restrict__ row, bool ok, int64_t k0, int64_t d, float& sq) {
+    float v[8];
+    if (VEC && ok && k0 + 8 <= d) {
+        const f32x4 a = *reinterpret_cast<const f32x4*>(row + k0);
+        const f32x4 b = *reinterpret_cast<const f32x4*>(row + k0 + 4);
+        v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
+        v[4] = b[0]; v[5] = b[1]; v[6] = b[2]; v[7] = b[3];
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = (ok && k0 + e < d) ? row[k0 + e] : 0.0f;
+    }
+    return cvt8_bf16(v, sq);
+}
+
+// The column operands of panel p and their inverse norms (zeros past m).
+template <bool VEC>
+__device__ __attribute__((always_inline)) inline void panel_operands_bf16(const float* __restrict__ Y, int64_t m,
+                                                                          int64_t d, int64_t p, bf16x8 (&bv)[4][4],
+                                                                          float (&ry)[4]) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4;
+    const int64_t L = (d + 31) / 32 * 8;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int64_t col = p * kPanel + b * 16 + (lane & 15);
+        const bool ok = col < m;
+        const float* yrow = Y + (ok ? col : 0) * d;
+        float sb = 0.0f;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            bv[b][s] = bf16x8{};
+            if (8 * s < L) bv[b][s] = load8_bf16<VEC>(yrow, ok, g * L + 8 * s, d, sb);
+        }
+        ry[b] = inv_from_sq(sum_groups(sb));
+    }
 }
 
 }  // namespace pardtw

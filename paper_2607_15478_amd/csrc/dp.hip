@@ -78,8 +78,14 @@ constexpr int kRecSlots = 257;   // record columns of one pair; the grid stays b
 // block of rows saved for the checkpointed backtrace.
 // kSrcPanelPk / kSrcFusedPk: panel or fused costs, codes packed 2 bits per
 // cell (one 16-bit word per column and 8-row group).
-enum CostSrc { kSrcRow = 0, kSrcPanel = 1, kSrcFused = 2, kSrcFusedCk = 3, kSrcPanelPk = 4, kSrcFusedPk = 5 };
-constexpr bool is_fused(int src) { return src == kSrcFused || src == kSrcFusedCk || src == kSrcFusedPk; }
+// kSrcFusedB: fused costs from BF16 operands (d <= 128, d % 8 == 0), those of
+// the cost GEMM's BF16 sweep; at most two compute waves per workgroup.
+enum CostSrc { kSrcRow = 0, kSrcPanel = 1, kSrcFused = 2, kSrcFusedCk = 3, kSrcPanelPk = 4, kSrcFusedPk = 5,
+               kSrcFusedB = 6 };
+constexpr bool is_fused(int src) {
+    return src == kSrcFused || src == kSrcFusedCk || src == kSrcFusedPk || src == kSrcFusedB;
+}
+constexpr int kMaxNWFusedB = 2;  // BF16 producers hold about 230 registers: two waves per SIMD
 constexpr bool is_packed(int src) { return src == kSrcPanelPk || src == kSrcFusedPk; }
 
 // Fused cost: per compute wave a ring of cost chunks in the panel layout
@@ -506,6 +512,106 @@ __device__ __attribute__((always_inline)) inline void cost_producer(const DpArgs
     }
 }
 
+// Producer of compute wave w (panel p) from BF16 operands (d <= 128, d % 8 ==
+// 0): the panel operands, row operands, MFMA steps and their order are those
+// of the cost GEMM's BF16 sweep (cost_slab.h), so the costs are the same
+// bits; the row norms come from the row operands, as there. Only the band's
+// slabs are visited. Each step issues the raw row features of the slab two
+// ahead into one of three rotating register sets (rows past n read row n-1,
+// which is zeroed after the load), then converts and computes its own slab.
+__device__ __attribute__((always_inline)) inline void cost_producer_bf16(const DpArgs& a, CostRing& cr, int w,
+                                                                         int p, bool sub) {
+    const int lane = threadIdx.x & 63;
+    const int g = lane >> 4;
+    const int G = int(a.G);
+    // the band's chunks, clamped to the rows (the subsequence bound runs past
+    // them): the consumer takes chunks up to G - 1 only, so a slab past them
+    // would wait for ring space forever
+    const int64_t lo = sub ? sub_group_lo(p, a.n, a.m) : band_group_lo(p, a.n, a.m);
+    const int64_t hi_raw = sub ? sub_group_hi(p, a.n, a.m) : band_group_hi(p, a.n, a.m);
+    const int64_t hi = hi_raw < G - 1 ? hi_raw : G - 1;
+    bf16x8 bv[4][4];
+    float ry[4];
+    panel_operands_bf16<true>(a.Y, a.m, a.d, p, bv, ry);
+    f32x4* ring = reinterpret_cast<f32x4*>(&cr.slot[w][0][0]);
+    for (int e = lane; e < kCRing * kChunk * kLanes / 4; e += kLanes) ring[e] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int64_t L = (a.d + 31) / 32 * 8;  // features per lane group
+    const int kq = lane >> 5, half = (lane >> 4) & 1, col = lane & 15;
+    int cons_seen = 0;
+    auto load_rows = [&](int s, f32x4 (&raw)[8]) {
+        const int64_t row = int64_t(16) * s + (lane & 15);
+        const float* xr = a.X + (row < a.n ? row : a.n - 1) * a.d;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t k0 = g * L + 8 * t;
+            const int64_t kc = k0 + 8 <= a.d ? k0 : a.d - 8;  // in the row (d >= 8)
+            raw[2 * t] = *reinterpret_cast<const f32x4*>(xr + kc);
+            raw[2 * t + 1] = *reinterpret_cast<const f32x4*>(xr + kc + 4);
+        }
+    };
+    auto compute = [&](int s, const f32x4 (&raw)[8], f32x4 (&v)[4]) {
+        const bool ok = int64_t(16) * s + (lane & 15) < a.n;
+        float sa = 0.0f;
+        bf16x8 av[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            av[t] = bf16x8{};
+            if (8 * t < L) {
+                const bool okk = ok && g * L + 8 * t < a.d;  // d % 8 == 0: all eight or none
+                float x[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) x[e] = okk ? raw[2 * t + (e >> 2)][e & 3] : 0.0f;
+                av[t] = cvt8_bf16(x, sa);
+            }
+        }
+        f32x4 acc[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (8 * t < L)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[t], bv[b][t], acc[b], 0, 0, 0);
+        costs_from_acc(acc, inv_from_sq(sum_groups(sa)), ry, v);
+    };
+    if (lo > hi) {
+        lds_put(&cr.prog[w], G);
+        return;
+    }
+    const int s0 = int(lo >> 1), s1 = int(hi >> 1);
+    f32x4 rA[8], rB[8], rC[8];
+    load_rows(s0, rA);
+    compiler_order();
+    load_rows(s0 + 1, rB);
+    compiler_order();
+    auto step = [&](int s, f32x4 (&cur)[8], f32x4 (&nxt)[8]) {
+        load_rows(s + 2, nxt);
+        const int k0 = 2 * s;
+        if (s <= s1) {
+            const int need = k0 + 2 - kCRing;  // the consumer has taken chunk k0 + 1 - kCRing out
+            while (cons_seen < need) {
+                cons_seen = lds_get(&cr.cons[w]);
+                if (cons_seen < need) __builtin_amdgcn_s_sleep(1);
+            }
+            f32x4 v[4];
+            compute(s, cur, v);
+            const int kk = k0 + kq;
+            if (kk < G) {
+                float* dst = &cr.slot[w][kk % kCRing][half * (kLanes * 4)];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) *reinterpret_cast<f32x4*>(dst + (b * 16 + col) * 4) = v[b];
+            }
+        }
+        compiler_order();
+        lds_put(&cr.prog[w], k0 + 2 < G ? k0 + 2 : G);
+    };
+    for (int s = s0; s <= s1; s += 3) {
+        step(s, rA, rC);
+        step(s + 1, rB, rA);
+        step(s + 2, rC, rB);
+    }
+}
+
 // Input helper: copies the boundary columns of panel pl (the last panel of the
 // previous group, computed by another workgroup) from the global records into
 // LDS ring 0. One poll reads kHelperWin chunks (16 records each, one per
@@ -639,7 +745,11 @@ __device__ __attribute__((always_inline)) inline void run_group(const DpArgs& a,
         if (p < a.P) compute_wave<SRC, SUB>(a, sh, cring, wave, p, p + 1 < a.P);
     } else if (is_fused(SRC) && wave >= NW + 2) {
         const int p = p0 + wave - (NW + 2);
-        if (p < a.P) cost_producer(a, *cring, wave - (NW + 2), p, SUB);
+        if constexpr (SRC == kSrcFusedB) {
+            if (p < a.P) cost_producer_bf16(a, *cring, wave - (NW + 2), p, SUB);
+        } else {
+            if (p < a.P) cost_producer(a, *cring, wave - (NW + 2), p, SUB);
+        }
     } else if (wave == NW) {
         if (p0 > 0) in_helper<SUB>(a, sh, p0 - 1, rec_column(a, q - 1, NW), rec_tag(a, q - 1, epoch));
         else inf_source(sh);
@@ -718,9 +828,9 @@ __device__ __attribute__((always_inline)) inline void dp_batch_body(const DpBatc
         const DpItem it = ba.items[t];
         const BatchPair q = ba.pairs[it.pair];
         DpArgs a;
-        a.C = SRC == kSrcFused ? nullptr : ba.C + q.c_off;
-        a.X = SRC == kSrcFused ? ba.X + q.x_off * ba.d : nullptr;
-        a.Y = SRC == kSrcFused ? ba.Y + q.y_off * ba.d : nullptr;
+        a.C = is_fused(SRC) ? nullptr : ba.C + q.c_off;
+        a.X = is_fused(SRC) ? ba.X + q.x_off * ba.d : nullptr;
+        a.Y = is_fused(SRC) ? ba.Y + q.y_off * ba.d : nullptr;
         a.rxs = SRC == kSrcFused ? ba.rxs + q.rx_off : nullptr;
         a.d = ba.d;
         a.bp = ba.bp + q.bp_off;
@@ -747,7 +857,7 @@ __device__ __attribute__((always_inline)) inline void dp_batch_body(const DpBatc
 template <int NW, int SRC, bool SUB>
 __global__ __launch_bounds__(kLanes * dp_waves(NW, SRC)) void dp_batch_kernel(DpBatchArgs ba) {
     __shared__ DpShared<NW> sh;
-    if constexpr (SRC == kSrcFused) {
+    if constexpr (is_fused(SRC)) {
         static_assert(NW <= kMaxNWFused, "fused workgroups hold at most kMaxNWFused compute waves");
         __shared__ CostRing cring;
         dp_batch_body<NW, SRC, SUB>(ba, sh, &cring);
@@ -819,9 +929,12 @@ void launch_batch_src(const DpBatchArgs& a, bool sub, int grid, hipStream_t stre
 }
 
 template <int NW>
-void launch_batch_nw(const DpBatchArgs& a, bool fused, bool sub, int grid, hipStream_t stream) {
+void launch_batch_nw(const DpBatchArgs& a, bool fused, bool bf16, bool sub, int grid, hipStream_t stream) {
     if (!fused) launch_batch_src<NW, kSrcPanel>(a, sub, grid, stream);
-    else if constexpr (NW <= kMaxNWFused) launch_batch_src<NW, kSrcFused>(a, sub, grid, stream);
+    else if constexpr (NW <= kMaxNWFusedB) {
+        if (bf16) launch_batch_src<NW, kSrcFusedB>(a, sub, grid, stream);
+        else launch_batch_src<NW, kSrcFused>(a, sub, grid, stream);
+    } else if constexpr (NW <= kMaxNWFused) launch_batch_src<NW, kSrcFused>(a, sub, grid, stream);
 }
 
 }  // namespace
@@ -848,10 +961,11 @@ size_t dp_workspace_bytes_impl(int64_t n, int64_t m) {
 
 pardtw_status dp_batch_launch(const BatchPair* pairs, const DpItem* items, int32_t nitems, int nw, int grid,
                               const float* Cbase, const float* X, const float* Y, int64_t d, const float* rxs,
-                              uint8_t* bpbase, float* totals, int32_t* status, void* dp_ws, bool sub,
+                              bool bf16, uint8_t* bpbase, float* totals, int32_t* status, void* dp_ws, bool sub,
                               hipStream_t stream) {
     const bool fused = X != nullptr;
-    if (fused && nw > kMaxNWFused) return PARDTW_ERR_UNSUPPORTED;
+    if (fused && nw > (bf16 ? kMaxNWFusedB : kMaxNWFused)) return PARDTW_ERR_UNSUPPORTED;
+    if (fused && bf16 && (d > 128 || d % 8 != 0)) return PARDTW_ERR_UNSUPPORTED;
     DpBatchArgs a;
     a.pairs = pairs;
     a.items = items;
@@ -870,10 +984,10 @@ pardtw_status dp_batch_launch(const BatchPair* pairs, const DpItem* items, int32
     if (nitems <= 0) return launch_status();
     if (grid > nitems) grid = nitems;
     switch (nw) {
-        case 1: launch_batch_nw<1>(a, fused, sub, grid, stream); break;
-        case 2: launch_batch_nw<2>(a, fused, sub, grid, stream); break;
-        case 4: launch_batch_nw<4>(a, fused, sub, grid, stream); break;
-        case 8: launch_batch_nw<8>(a, fused, sub, grid, stream); break;
+        case 1: launch_batch_nw<1>(a, fused, bf16, sub, grid, stream); break;
+        case 2: launch_batch_nw<2>(a, fused, bf16, sub, grid, stream); break;
+        case 4: launch_batch_nw<4>(a, fused, bf16, sub, grid, stream); break;
+        case 8: launch_batch_nw<8>(a, fused, bf16, sub, grid, stream); break;
         default: return PARDTW_ERR_UNSUPPORTED;
     }
     return launch_status();

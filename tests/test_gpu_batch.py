@@ -214,3 +214,26 @@ def test_fused_plan_bit_identical(mixed):
         pd.Plan([10], [10], 17, fused=True)
     with pytest.raises(pd.PardtwError):
         pd.Plan([10], [10], 12, pd.PREC_BF16, fused=True)
+
+
+def test_split_walks_of_long_pairs_equal_the_serial_walk():
+    """Pairs of more than 1024 rows are walked by the split walk inside the
+    batch. Uniform random frames make nearby optimal paths merge slowly, so
+    guessed segment starts miss and the final check walks segments again:
+    every path must still equal the one-workgroup walk's."""
+    rng = np.random.default_rng(23)
+    shapes = [(2500, 2700), (4100, 3500), (1025, 1500), (5000, 5000), (900, 1000), (3000, 2000)]
+    pairs = [(rng.random((n, 12), dtype=np.float32), rng.random((m, 12), dtype=np.float32)) for n, m in shapes]
+    plan = pd.Plan([n for n, _ in shapes], [m for _, m in shapes], 12)
+    Xp, Yp = pd.pack(pairs, DEV)
+    buf = plan.buffers(DEV)
+    plan.align(Xp, Yp, buf)
+    totals, status, plen, paths = _outputs(plan, buf)
+    for b, (x, y) in enumerate(pairs):
+        w = pd.Workspace(len(x), len(y), DEV)
+        pd.align_into(torch.from_numpy(x).to(DEV), torch.from_numpy(y).to(DEV), w, serial_backtrace=True)
+        torch.cuda.synchronize()
+        L = int(w.path_len.item())
+        assert L > 0 and plen[b] == L
+        assert np.array_equal(paths[b], w.path[:L].cpu().numpy())
+        assert np.float32(totals[b]) == np.float32(w.total.item())
