@@ -66,8 +66,7 @@ def parse():
     ap.add_argument("--variant", choices=["wsdtw", "nsdtw"], default="wsdtw", help="segmental workloads")
     ap.add_argument("--pipelined", action="store_true",
                     help="pair workloads: run each pair's backtrace on a second stream beside the next pair's "
-                         "cost and DP (default with --ckpt; otherwise each step's backtrace runs before the next "
-                         "step's cost)")
+                         "cost and DP (the default runs each step's backtrace before the next step's cost)")
     ap.add_argument("--serial", action="store_true",
                     help="pair workloads: the serial schedule (the default; overrides --pipelined)")
     ap.add_argument("--packed", action="store_true",
@@ -257,12 +256,13 @@ def cpu_baseline_batch(pairs, paths, totals, status, bf16=None, threads=8):
     return cpu, validation
 
 
-# FP32 vector work per recomputed cell in the checkpointed backtrace: three
-# FMAs and two mins of the recurrence, and 1 - (acc * rx) * ry of the cost
+# FP32 vector work per cell of the checkpointed sweep and of the backtrace's
+# recomputed windows: three FMAs and two mins of the recurrence, and
+# 1 - (acc * rx) * ry of the cost (whose dot product runs on MFMA)
 CKPT_FLOPS_PER_CELL = 3 * 2 + 2 + 3
-# one compute unit's share of the FP32 vector peak (157.3 TFLOP/s over 256 CUs):
-# the backtrace is one workgroup
-CU_FP32_PEAK_TFLOPS = 157.3 / 256
+FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector peak
+# one compute unit's share of it: the one-workgroup backtrace
+CU_FP32_PEAK_TFLOPS = FP32_PEAK_TFLOPS / 256
 
 
 def ckpt_window_ranges(ie, je, r0):
@@ -344,12 +344,11 @@ def main():
         calib = {"bytes_each_way": nb}
         del src, dst
 
-    # Serial schedule (the default for code matrices): cost, DP, split-walk
-    # backtrace and compensated total of one pair, then the next. The split
-    # walk takes about 0.1 ms at 50000 x 60000, so hiding it buys less than
-    # the CUs it would take from the next pair's DP.
-    # Pipelined schedule (--pipelined, and the default for checkpoints, whose
-    # backtrace is as long as a sweep): the
+    # Serial schedule (the default): cost, DP, split-walk backtrace and
+    # compensated total of one pair, then the next. The split walk takes about
+    # 0.1 ms at 50000 x 60000 (over checkpoints, a few ms at 600000 x 600000),
+    # so hiding it buys less than the CUs it would take from the next pair's DP.
+    # Pipelined schedule (--pipelined): the
     # cost and DP of each pair run on the launch stream, and the backtrace of
     # pair s (one workgroup) on a second stream beside the cost and DP of pair
     # s + 1. Pairs alternate between two workspaces; a workspace's codes are
@@ -363,7 +362,7 @@ def main():
     # Extra workspaces are taken only as far as free device memory allows
     # (a 600000 x 600000 checkpointed pair needs 101 GB each); with none the
     # run is serial.
-    pipelined = (args.pipelined or bool(K)) and not args.serial
+    pipelined = args.pipelined and not args.serial
     bufs = [w]
     if pipelined:
         per = sum(t.numel() * t.element_size() for t in (w.C, w.bp, w.ws, w.ckpt, w.path))
@@ -399,7 +398,10 @@ def main():
             e[1].record(stream)
             pd.pardtw_dp_fused_ckpt(Xd, Yd, K, w.ckpt, w.total, w.status, w.ws)
             e[2].record(stream)
-            pd.pardtw_ckpt_backtrace(Xd, Yd, K, w.ckpt, w.status, w.path, w.path_len)
+            if args.walk != "serial":
+                pd.pardtw_ckpt_backtrace_parallel(Xd, Yd, K, w.ckpt, w.status, w.path, w.path_len, w.bt_ws)
+            else:
+                pd.pardtw_ckpt_backtrace(Xd, Yd, K, w.ckpt, w.status, w.path, w.path_len)
             if comp:
                 pd.pardtw_path_total(Xd, Yd, w.path, w.path_len, w.total_comp, w.total_ws)
             e[3].record(stream)
@@ -524,7 +526,9 @@ def launch_pipelined(pd, Xd, Yd, bufs, stream, side, steps, fused, K, evs, after
         e[3].record(stream)
         s_bt.wait_event(e[3])
         e[4].record(s_bt)
-        if K:
+        if K and not serial_walk:
+            pd.pardtw_ckpt_backtrace_parallel(Xd, Yd, K, w.ckpt, w.status, w.path, w.path_len, w.bt_ws, stream=s_bt)
+        elif K:
             pd.pardtw_ckpt_backtrace(Xd, Yd, K, w.ckpt, w.status, w.path, w.path_len, stream=s_bt)
         elif not serial_walk:
             pd.pardtw_backtrace_parallel(w.bp, n, m, w.status, w.path, w.path_len, w.bt_ws, stream=s_bt,
@@ -655,19 +659,36 @@ def pair_roofline(args, n, m, dp_ms):
 
 
 def ckpt_result(args, X, Y, path, total, cells, ms_per_step, cost_ms, dp_ms, bt_ms, w):
-    """The bench line of the checkpointed path. Its dominant kernel is the
-    backtrace, one workgroup that recomputes the window cells block by block:
-    its roofline is one compute unit's FP32 vector peak."""
+    """The bench line of the checkpointed path. Both its kernels do FP32
+    vector work on cells (the sweep on the path band, the backtrace on its
+    recomputed windows), with no HBM traffic to speak of (no cost matrix, no
+    codes), so each is set against the FP32 vector peak: the whole chip's, or
+    one compute unit's share for the one-workgroup walk. `roofline` names the
+    longer of the two and carries the other."""
     from paper_2607_15478_amd import pardtw as pd
     n, m, d = X.shape[0], Y.shape[0], X.shape[1]
     K = args.ckpt
+    bcells = band_cells(n, m)
+    sweep_ach = bcells * CKPT_FLOPS_PER_CELL / (dp_ms * 1e-3) / 1e12
+    sweep = {"bound": "alu", "achieved": round(sweep_ach, 4), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+             "frac": round(sweep_ach / FP32_PEAK_TFLOPS, 4), "traffic": None,
+             "kernel": "dp_kernel (fused cost, checkpoints)", "band_cells": bcells,
+             "flops_per_cell": CKPT_FLOPS_PER_CELL, "kernel_ms": round(float(dp_ms), 4),
+             "note": "chain-bound: rows of a panel in sequence, panels in a staircase"}
     wcells = ckpt_window_cells(path, n, m, K)
-    achieved = wcells * CKPT_FLOPS_PER_CELL / (bt_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 5), "peak": round(CU_FP32_PEAK_TFLOPS, 4),
-                "unit": "TFLOP/s", "frac": round(achieved / CU_FP32_PEAK_TFLOPS, 4), "traffic": None,
-                "kernel": "ckpt_backtrace_kernel", "peak_scope": "one CU (the kernel is one workgroup)",
-                "window_cells_per_launch": wcells, "flops_per_cell": CKPT_FLOPS_PER_CELL,
-                "kernel_ms": round(float(bt_ms), 4)}
+    one_wg = args.walk == "serial"
+    bt_peak = CU_FP32_PEAK_TFLOPS if one_wg else FP32_PEAK_TFLOPS
+    bt_ach = wcells * CKPT_FLOPS_PER_CELL / (bt_ms * 1e-3) / 1e12
+    bt = {"bound": "alu", "achieved": round(bt_ach, 5), "peak": round(bt_peak, 4),
+          "unit": "TFLOP/s", "frac": round(bt_ach / bt_peak, 4), "traffic": None,
+          "kernel": "ckpt_backtrace_kernel" if one_wg else "ck_seg_round_kernel (split walk)",
+          "peak_scope": "one CU (the kernel is one workgroup)" if one_wg else "the chip",
+          "window_cells_per_launch": wcells, "flops_per_cell": CKPT_FLOPS_PER_CELL,
+          "kernel_ms": round(float(bt_ms), 4)}
+    if dp_ms >= bt_ms:
+        roofline = dict(sweep, backtrace=bt)
+    else:
+        roofline = dict(bt, sweep=sweep)
     comp_total = None if args.no_comp_total else float(w.total_comp.item())
     cpu, validation = None, None
     if not args.no_cpu:
@@ -690,6 +711,7 @@ def ckpt_result(args, X, Y, path, total, cells, ms_per_step, cost_ms, dp_ms, bt_
         "config": {"workload": args.workload, "n": n, "m": m, "d": d, "cells": cells,
                    "layout": "checkpointed", "rows_per_block": K,
                    "schedule": "serial: sweep and backtrace of one pair, then the next",
+                   "walk": "one workgroup" if args.walk == "serial" else "split",
                    "checkpoint_bytes": pd.pardtw_ckpt_bytes(n, m, K),
                    "device_bytes_per_pair": workspace_device_bytes(w),
                    "device_bytes_per_cell": round(workspace_device_bytes(w) / cells, 4),

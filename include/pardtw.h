@@ -304,6 +304,21 @@ pardtw_status pardtw_ckpt_backtrace(const float* X, const float* Y, int64_t n, i
                                     const int32_t* pair_status, int32_t* path, int32_t* path_len,
                                     hipStream_t stream);
 
+/* pardtw_ckpt_backtrace's path from a split walk over runs of blocks (the
+ * split walk of pardtw_backtrace_parallel: runs of R = K max(4, ceil(N / 256K))
+ * rows, each walked block by block by its own workgroup from a guessed start,
+ * then from where the run above ended, then checked from the last run down
+ * with a serial rewalk of any run that started elsewhere). Same arguments,
+ * plus workspace [device, >= pardtw_ckpt_backtrace_parallel_bytes(n, m,
+ * rows_per_block) bytes, 16-byte aligned; no initialisation needed]. Pairs of
+ * at most two runs take the one-workgroup walk. PARDTW_ERR_WORKSPACE if the
+ * workspace is too small. */
+size_t pardtw_ckpt_backtrace_parallel_bytes(int64_t n, int64_t m, int32_t rows_per_block);
+pardtw_status pardtw_ckpt_backtrace_parallel(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
+                                             int32_t rows_per_block, const float* ckpt, size_t ckpt_bytes,
+                                             const int32_t* pair_status, int32_t* path, int32_t* path_len,
+                                             void* workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* a6: gradient of g * J with the optimal path held fixed (the paper motivates
  * backpropagating through the optimal alignment path, Sec. I):
  *   J = sum over path cells (i,j) of w_ij * C[i,j], w = 1 at (0,0), else the

@@ -24,6 +24,7 @@
 // Work: the cones cover about 3/4 K^2 cells per block, about n K in all,
 // against n m for the sweep; memory: the checkpoints, 8 n m / K bytes.
 #include "dp_step.h"
+#include "split.h"
 #include "trace.h"
 
 namespace pardtw {
@@ -196,8 +197,9 @@ __device__ void window_wave(CkShared& sh, const WaveStart& st, int wave, int r0,
 // or reaches the origin, 32 rows at a time: lane b holds column j - b of rows
 // i-31 .. i, and the window trace resolves them at once. Rows above r0 (the
 // block before) are not traced: the cell the path enters there starts the
-// next block.
-__device__ void walk_block(const CkArgs& a, CkShared& sh, int r0, int plo, int cap) {
+// next block. The k-th cell of the walk goes to out[k] (`forward`) or to
+// out[cap - 1 - k].
+__device__ void walk_block(CkShared& sh, int r0, int plo, int cap, int32_t* out, bool forward) {
     const int lane = threadIdx.x & 63;
     int i = __builtin_amdgcn_readfirstlane(sh.ie);
     int j = __builtin_amdgcn_readfirstlane(sh.je);
@@ -251,9 +253,9 @@ __device__ void walk_block(const CkArgs& a, CkShared& sh, int r0, int plo, int c
         if (on != 0 && (lane != last || cnt == __builtin_popcountll(has))) {
             const int idx = int(__builtin_amdgcn_mbcnt_hi(uint32_t(has >> 32),
                                                           __builtin_amdgcn_mbcnt_lo(uint32_t(has), 0u)));
-            const int64_t pos = int64_t(cap) - 1 - (len + idx);
-            a.path[2 * pos] = i - __builtin_clz(on);
-            a.path[2 * pos + 1] = j - lane;
+            const int64_t pos = forward ? int64_t(len + idx) : int64_t(cap) - 1 - (len + idx);
+            out[2 * pos] = i - __builtin_clz(on);
+            out[2 * pos + 1] = j - lane;
         }
         len += cnt;
         i -= da;
@@ -268,29 +270,35 @@ __device__ void walk_block(const CkArgs& a, CkShared& sh, int r0, int plo, int c
     }
 }
 
-__global__ __launch_bounds__(kCkThreads) void ckpt_backtrace_kernel(CkArgs a) {
-    __shared__ CkShared sh;
+// Fills the boundary rings with +inf once per kernel (the blocks' windows
+// then keep them consistent).
+__device__ void ck_init(CkShared& sh) {
+    for (int e = threadIdx.x; e < kCkPanels * kCkGroups * 2 * kChunk; e += kCkThreads)
+        (&sh.ring[0][0][0][0])[e] = __builtin_inff();
+}
+
+// Walks the path from (i0, j0) block by block (each block's window recomputed
+// from its checkpoints, then traced) until it reaches the origin or, with
+// stop_row >= 0, a cell on a row <= stop_row, which goes to *ex (a segment of
+// the split walk; stop_row + 1 is a block's first row). Cells go to out as
+// walk_block writes them. Returns the number of cells, 0 if the walk failed
+// (or, with stop_row >= 0, reached the origin). Called by the whole workgroup.
+__device__ int ck_walk(const CkArgs& a, CkShared& sh, int i0, int j0, int stop_row, int32_t* out, bool forward,
+                       int cap, int2* ex) {
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int cap = int(a.n < a.m ? a.n : a.m);
-    if (*a.status != PARDTW_PAIR_OK) {
-        if (tid == 0) *a.path_len = 0;
-        return;
-    }
     if (tid == 0) {
-        sh.ie = int(a.n - 1);
-        sh.je = int(a.m - 1);
+        sh.ie = i0;
+        sh.je = j0;
         sh.len = 0;
         sh.fail = 0;
     }
-    for (int e = tid; e < kCkPanels * kCkGroups * 2 * kChunk; e += kCkThreads)
-        (&sh.ring[0][0][0][0])[e] = __builtin_inff();
     __syncthreads();
     constexpr int kXPer = kCkMaxRows * 16 / kCkThreads + 1;  // feature loads per thread
     for (;;) {
         const int ie = __builtin_amdgcn_readfirstlane(sh.ie);
         const int je = __builtin_amdgcn_readfirstlane(sh.je);
-        if (ie < 0) break;
+        if (ie < 0 || ie <= stop_row) break;
         const int r0 = ie - ie % a.K;
         const int A = ie - r0;
         const int nch = A / kChunk + 1;  // chunks holding rows r0 .. ie
@@ -327,11 +335,27 @@ __global__ __launch_bounds__(kCkThreads) void ckpt_backtrace_kernel(CkArgs a) {
         __syncthreads();
         if (active) window_wave(sh, st, wave, r0, ie, je, plo, nch);
         __syncthreads();
-        if (wave == 0) walk_block(a, sh, r0, plo, cap);
+        if (wave == 0) walk_block(sh, r0, plo, cap, out, forward);
         __syncthreads();
     }
+    const int ie = __builtin_amdgcn_readfirstlane(sh.ie);
+    const int je = __builtin_amdgcn_readfirstlane(sh.je);
+    const bool fail = sh.fail != 0 || (stop_row >= 0 && ie < 0);
+    if (ex) *ex = make_int2(ie, je);
+    return fail ? 0 : sh.len;
+}
+
+__global__ __launch_bounds__(kCkThreads) void ckpt_backtrace_kernel(CkArgs a) {
+    __shared__ CkShared sh;
+    const int tid = threadIdx.x;
+    const int cap = int(a.n < a.m ? a.n : a.m);
+    if (*a.status != PARDTW_PAIR_OK) {
+        if (tid == 0) *a.path_len = 0;
+        return;
+    }
+    ck_init(sh);
+    const int len = ck_walk(a, sh, int(a.n - 1), int(a.m - 1), -1, a.path, false, cap, nullptr);
     // the path was written backwards from entry cap-1: move it to the front
-    const int len = sh.fail ? 0 : sh.len;
     const int64_t base = int64_t(cap) - len;
     int2* pp = reinterpret_cast<int2*>(a.path);
     constexpr int kPer = 8;
@@ -353,6 +377,67 @@ __global__ __launch_bounds__(kCkThreads) void ckpt_backtrace_kernel(CkArgs a) {
     if (tid == 0) *a.path_len = len;
 }
 
+// ---- Split walk over the blocks (split.h) ------------------------------------
+// Segments are runs of whole blocks (R a multiple of K), each walked by one
+// workgroup with ck_walk from its start down to its first row.
+__device__ SegInfo ck_segment(const CkArgs& a, CkShared& sh, SegInfo& res, const SplitArgs& sp, int s, int si,
+                              int sj, SegInfo* out) {
+    int2 ex;
+    const int len = ck_walk(a, sh, si, sj, seg_stop_row(s, sp.R), sp.cells + int64_t(s) * sp.R * 2, true, sp.R, &ex);
+    if (threadIdx.x == 0) {
+        const SegInfo r = seg_info(si, sj, ex.x, ex.y, len);
+        *out = r;
+        res = r;
+    }
+    __syncthreads();
+    return res;
+}
+
+__global__ __launch_bounds__(kCkThreads) void ck_seg_round_kernel(CkArgs a, SplitArgs sp, int round) {
+    __shared__ CkShared sh;
+    __shared__ SegInfo res;
+    if (*a.status != PARDTW_PAIR_OK) return;
+    ck_init(sh);
+    split_round(sp, blockIdx.x, round, [&](int s, int si, int sj, SegInfo* out) {
+        return ck_segment(a, sh, res, sp, s, si, sj, out);
+    });
+}
+
+__global__ __launch_bounds__(kCkThreads) void ck_seg_finish_kernel(CkArgs a, SplitArgs sp, int fin) {
+    __shared__ CkShared sh;
+    __shared__ SegInfo res;
+    __shared__ SegInfo sinfo[kSegMaxCount];
+    if (*a.status != PARDTW_PAIR_OK) {
+        if (threadIdx.x == 0) *a.path_len = 0;
+        return;
+    }
+    ck_init(sh);
+    split_finish(sp, sinfo, fin, int(a.n < a.m ? a.n : a.m), a.path_len, [&](int s, int si, int sj, SegInfo* out) {
+        return ck_segment(a, sh, res, sp, s, si, sj, out);
+    });
+}
+
+__global__ __launch_bounds__(256) void ck_seg_copy_kernel(SplitArgs sp, int fin, const int32_t* __restrict__ path_len,
+                                                          int32_t* __restrict__ path) {
+    if (*path_len <= 0) return;
+    split_copy(sp, blockIdx.x, fin, path);
+}
+
+constexpr int kCkSegRounds = 3;
+
+// Segments of at least four blocks, at most kSegMaxCount of them.
+void ck_seg_shape(int64_t n, int K, int& R, int& S) {
+    const int64_t blocks = ceil_div(ceil_div(n, int64_t(kSegMaxCount)), int64_t(K));
+    R = int(K * (blocks > 4 ? blocks : 4));
+    S = int(ceil_div(n, int64_t(R)));
+}
+
+size_t ck_seg_bytes(int64_t n, int K) {
+    int R, S;
+    ck_seg_shape(n, K, R, S);
+    return size_t(2) * S * sizeof(SegInfo) + size_t(S) * R * 2 * sizeof(int32_t);
+}
+
 }  // namespace
 }  // namespace pardtw
 
@@ -361,6 +446,13 @@ extern "C" size_t pardtw_ckpt_bytes(int64_t n, int64_t m, int32_t rows_per_block
         rows_per_block % 16)
         return 0;
     return size_t(pardtw::ckpt_floats(n, m, rows_per_block)) * sizeof(float);
+}
+
+extern "C" size_t pardtw_ckpt_backtrace_parallel_bytes(int64_t n, int64_t m, int32_t rows_per_block) {
+    if (!pardtw::valid_sizes(n, m) || rows_per_block < 16 || rows_per_block > pardtw::kCkMaxRows ||
+        rows_per_block % 16)
+        return 0;
+    return pardtw::ck_seg_bytes(n, rows_per_block);
 }
 
 extern "C" pardtw_status pardtw_ckpt_backtrace(const float* X, const float* Y, int64_t n, int64_t m, int64_t d,
@@ -387,5 +479,50 @@ extern "C" pardtw_status pardtw_ckpt_backtrace(const float* X, const float* Y, i
     a.path = path;
     a.path_len = path_len;
     pardtw::ckpt_backtrace_kernel<<<1, pardtw::kCkThreads, 0, stream>>>(a);
+    return pardtw::launch_status();
+}
+
+extern "C" pardtw_status pardtw_ckpt_backtrace_parallel(const float* X, const float* Y, int64_t n, int64_t m,
+                                                        int64_t d, int32_t rows_per_block, const float* ckpt,
+                                                        size_t ckpt_bytes, const int32_t* pair_status, int32_t* path,
+                                                        int32_t* path_len, void* workspace, size_t workspace_bytes,
+                                                        hipStream_t stream) {
+    if (!X || !Y || !pair_status || !path || !path_len || !pardtw::valid_sizes(n, m) || d <= 0)
+        return PARDTW_ERR_INVALID_ARG;
+    if (d > 16) return PARDTW_ERR_UNSUPPORTED;
+    if (rows_per_block < 16 || rows_per_block > pardtw::kCkMaxRows || rows_per_block % 16)
+        return PARDTW_ERR_INVALID_ARG;
+    if (!workspace || reinterpret_cast<uintptr_t>(workspace) % 16 != 0 || reinterpret_cast<uintptr_t>(path) % 8 != 0)
+        return PARDTW_ERR_INVALID_ARG;
+    const int64_t floats = pardtw::ckpt_floats(n, m, rows_per_block);
+    if (floats > 0 && (!ckpt || ckpt_bytes < size_t(floats) * sizeof(float))) return PARDTW_ERR_WORKSPACE;
+    if (workspace_bytes < pardtw::ck_seg_bytes(n, rows_per_block)) return PARDTW_ERR_WORKSPACE;
+    pardtw::CkArgs a;
+    a.X = X;
+    a.Y = Y;
+    a.n = n;
+    a.m = m;
+    a.d = d;
+    a.K = rows_per_block;
+    a.ckpt = ckpt;
+    a.stride = pardtw::num_panels(m) * pardtw::kPanel;
+    a.status = pair_status;
+    a.path = path;
+    a.path_len = path_len;
+    pardtw::SplitArgs sp;
+    sp.n = int(n);
+    sp.m = int(m);
+    pardtw::ck_seg_shape(n, rows_per_block, sp.R, sp.S);
+    if (sp.S <= 2) {
+        pardtw::ckpt_backtrace_kernel<<<1, pardtw::kCkThreads, 0, stream>>>(a);
+        return pardtw::launch_status();
+    }
+    sp.info = reinterpret_cast<pardtw::SegInfo*>(workspace);
+    sp.cells = reinterpret_cast<int32_t*>(sp.info + 2 * sp.S);
+    for (int r = 0; r < pardtw::kCkSegRounds; ++r)
+        pardtw::ck_seg_round_kernel<<<sp.S, pardtw::kCkThreads, 0, stream>>>(a, sp, r);
+    const int fin = (pardtw::kCkSegRounds - 1) & 1;
+    pardtw::ck_seg_finish_kernel<<<1, pardtw::kCkThreads, 0, stream>>>(a, sp, fin);
+    pardtw::ck_seg_copy_kernel<<<sp.S, 256, 0, stream>>>(sp, fin, path_len, path);
     return pardtw::launch_status();
 }

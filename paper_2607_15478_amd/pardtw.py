@@ -73,6 +73,9 @@ _lib_bt_packed_par = _sig("pardtw_backtrace_packed_parallel", _E, [_P, _I64, _I6
 _lib_ckpt_bytes = _sig("pardtw_ckpt_bytes", _SZ, [_I64, _I64, _I32])
 _lib_dp_ckpt = _sig("pardtw_dp_fused_ckpt", _E, [_P, _P, _I64, _I64, _I64, _I32, _P, _SZ, _P, _P, _P, _SZ, _P])
 _lib_ckpt_bt = _sig("pardtw_ckpt_backtrace", _E, [_P, _P, _I64, _I64, _I64, _I32, _P, _SZ, _P, _P, _P, _P])
+_lib_ckpt_bt_par_bytes = _sig("pardtw_ckpt_backtrace_parallel_bytes", _SZ, [_I64, _I64, _I32])
+_lib_ckpt_bt_par = _sig("pardtw_ckpt_backtrace_parallel", _E,
+                        [_P, _P, _I64, _I64, _I64, _I32, _P, _SZ, _P, _P, _P, _P, _SZ, _P])
 _lib_total = _sig("pardtw_path_total", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _SZ, _P])
 _lib_total_bytes = _sig("pardtw_path_total_bytes", _SZ, [])
 _lib_grad = _sig("pardtw_path_grad", _E, [_P, _P, _I64, _I64, _I64, _P, _P, _P, _P, _P, _P])
@@ -261,6 +264,27 @@ def pardtw_ckpt_backtrace(X: torch.Tensor, Y: torch.Tensor, rows_per_block: int,
                         _ptr(status), _ptr(path), _ptr(path_len), _stream(stream)), "pardtw_ckpt_backtrace")
 
 
+def pardtw_ckpt_backtrace_parallel_bytes(n: int, m: int, rows_per_block: int) -> int:
+    return int(_lib_ckpt_bt_par_bytes(n, m, int(rows_per_block)))
+
+
+def pardtw_ckpt_backtrace_parallel(X: torch.Tensor, Y: torch.Tensor, rows_per_block: int, ckpt: torch.Tensor,
+                                   status: torch.Tensor, path: torch.Tensor, path_len: torch.Tensor,
+                                   workspace: torch.Tensor, stream=None):
+    """pardtw_ckpt_backtrace's path, split into runs of blocks walked at once
+    (workspace: pardtw_ckpt_backtrace_parallel_bytes(n, m, rows_per_block) bytes)."""
+    _dev_f32(X, "X"), _dev_f32(Y, "Y")
+    n, d = X.shape
+    m = Y.shape[0]
+    if path.dtype != torch.int32 or path.numel() < 2 * min(n, m):
+        raise ValueError("path must be int32 with room for 2*min(n, m) entries")
+    ck_bytes = ckpt.numel() * ckpt.element_size()
+    ws_bytes = workspace.numel() * workspace.element_size()
+    _check(_lib_ckpt_bt_par(_ptr(X), _ptr(Y), n, m, d, int(rows_per_block), _ptr(ckpt) if ck_bytes else None,
+                            ck_bytes, _ptr(status), _ptr(path), _ptr(path_len), _ptr(workspace), ws_bytes,
+                            _stream(stream)), "pardtw_ckpt_backtrace_parallel")
+
+
 def pardtw_backtrace(bp: torch.Tensor, n: int, m: int, status: torch.Tensor, path: torch.Tensor,
                      path_len: torch.Tensor, stream=None):
     if path.dtype != torch.int32 or path.numel() < 2 * min(n, m):
@@ -379,8 +403,9 @@ class Workspace:
         self.status = torch.empty(1, dtype=torch.int32, device=device)
         self.path = torch.empty((min(n, m), 2), dtype=torch.int32, device=device)
         self.path_len = torch.empty(1, dtype=torch.int32, device=device)
-        # the split backtrace's segments (8 B per row)
-        self.bt_ws = torch.empty(pardtw_backtrace_parallel_bytes(n, m), dtype=torch.uint8, device=device)
+        # the split backtrace's segments (8 B per row; with checkpoints, runs of blocks)
+        self.bt_ws = torch.empty(pardtw_ckpt_backtrace_parallel_bytes(n, m, self.ckpt_rows) if self.ckpt_rows
+                                 else pardtw_backtrace_parallel_bytes(n, m), dtype=torch.uint8, device=device)
 
 
 def align_into(X: torch.Tensor, Y: torch.Tensor, w: Workspace, prec: int = PREC_F32, stream=None,
@@ -393,7 +418,10 @@ def align_into(X: torch.Tensor, Y: torch.Tensor, w: Workspace, prec: int = PREC_
         if prec != PREC_F32:
             raise ValueError("the checkpointed DP computes FP32 costs")
         pardtw_dp_fused_ckpt(X, Y, w.ckpt_rows, w.ckpt, w.total, w.status, w.ws, stream)
-        pardtw_ckpt_backtrace(X, Y, w.ckpt_rows, w.ckpt, w.status, w.path, w.path_len, stream)
+        if serial_backtrace:
+            pardtw_ckpt_backtrace(X, Y, w.ckpt_rows, w.ckpt, w.status, w.path, w.path_len, stream)
+        else:
+            pardtw_ckpt_backtrace_parallel(X, Y, w.ckpt_rows, w.ckpt, w.status, w.path, w.path_len, w.bt_ws, stream)
         return w
     if fused:
         if prec != PREC_F32:

@@ -226,3 +226,54 @@ def test_ckpt_many_blocks(n, m, K):
     X, Y = synth.chroma_pair(n + 2 * m + K, n, m)
     Xd, Yd = torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV)
     _same(_ckpt(Xd, Yd, K)[:3], _full(Xd, Yd))
+
+
+def _ckpt_walks(Xd, Yd, K):
+    """(one-workgroup checkpointed walk, split walk) over the same checkpoints."""
+    n, m = Xd.shape[0], Yd.shape[0]
+    w = pd.Workspace(n, m, DEV, cost=False, ckpt_rows=K)
+    pd.pardtw_dp_fused_ckpt(Xd, Yd, K, w.ckpt, w.total, w.status, w.ws)
+    out = []
+    for par in (False, True):
+        w.path.fill_(-9)
+        w.path_len.fill_(-9)
+        if par:
+            ws = torch.full((pd.pardtw_ckpt_backtrace_parallel_bytes(n, m, K),), 0xEE, dtype=torch.uint8,
+                            device=DEV)
+            pd.pardtw_ckpt_backtrace_parallel(Xd, Yd, K, w.ckpt, w.status, w.path, w.path_len, ws)
+        else:
+            pd.pardtw_ckpt_backtrace(Xd, Yd, K, w.ckpt, w.status, w.path, w.path_len)
+        torch.cuda.synchronize()
+        L = int(w.path_len.item())
+        out.append(w.path[:L].cpu().numpy())
+    return out
+
+
+@pytest.mark.parametrize("n,m,K,kind", [(3000, 3300, 32, "random"), (5000, 4000, 16, "random"),
+                                        (9000, 10000, 64, "chroma"), (2100, 2000, 16, "chroma"),
+                                        (1100, 1200, 64, "chroma")])
+def test_ckpt_split_walk_equals_one_workgroup(n, m, K, kind):
+    """The split walk over runs of blocks gives the one-workgroup walk's
+    path: on chroma pairs (guessed starts pay) and on uniform random frames
+    (optimal paths of nearby cells seldom merge, so runs are walked again)."""
+    rng = np.random.default_rng(n + K)
+    if kind == "random":
+        X = rng.random((n, 12), dtype=np.float32)
+        Y = rng.random((m, 12), dtype=np.float32)
+    else:
+        X, Y = synth.chroma_pair(n + m + K, n, m, 12, 0.8 * (m - 1) / (n - 1), 1.25 * (m - 1) / (n - 1))
+    Xd, Yd = torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV)
+    ser, par = _ckpt_walks(Xd, Yd, K)
+    assert len(ser) > 0 and np.array_equal(ser, par)
+    # and the code-matrix path
+    assert np.array_equal(par, _full(Xd, Yd)[2])
+
+
+def test_ckpt_split_walk_workspace_check():
+    X, Y = _features(61, 3000, 3100, 12)
+    Xd, Yd = torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV)
+    w = pd.Workspace(3000, 3100, DEV, cost=False, ckpt_rows=32)
+    pd.pardtw_dp_fused_ckpt(Xd, Yd, 32, w.ckpt, w.total, w.status, w.ws)
+    small = torch.empty(pd.pardtw_ckpt_backtrace_parallel_bytes(3000, 3100, 32) - 16, dtype=torch.uint8, device=DEV)
+    with pytest.raises(pd.PardtwError, match="ERR_WORKSPACE"):
+        pd.pardtw_ckpt_backtrace_parallel(Xd, Yd, 32, w.ckpt, w.status, w.path, w.path_len, small)

@@ -70,6 +70,10 @@ class Lib:
     def pardtw_ckpt_backtrace(self, X, Y, K, ckpt, status, path, path_len, stream):
         self._call("bt", ckpt.owner, stream)
 
+    def pardtw_ckpt_backtrace_parallel(self, X, Y, K, ckpt, status, path, path_len, ws, stream):
+        assert ws.owner is ckpt.owner
+        self._call("bt", ckpt.owner, stream)
+
 
 class Buf:
     def __init__(self, owner):
