@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--packed", action="store_true",
                     help="pair workloads: codes packed 2 bits per cell (pardtw_dp_packed / pardtw_dp_fused_packed "
                          "and pardtw_backtrace_packed), a memory mode")
+    ap.add_argument("--graph", action="store_true",
+                    help="pair workloads, serial schedule: capture one step as a hipGraph and time its replays "
+                         "(stage times from eager steps before the timed region)")
     ap.add_argument("--walk", choices=["auto", "split", "serial"], default="auto",
                     help="pair workloads: the backtrace, split walk (pardtw_backtrace_parallel, many workgroups) "
                          "or one-workgroup walk (pardtw_backtrace); the same path. auto: split in the serial "
@@ -387,39 +390,39 @@ def main():
         return run_pair_pipelined(args, X, Y, Xd, Yd, bufs, stream, side, cells, calib)
 
     comp = not args.no_comp_total
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        e = evs[s]
-        e[0].record(stream)
+
+    def one_step(e):
+        """One pass of the hot path; e: four events around its stages, or None."""
+        def rec(k):
+            if e is not None:
+                e[k].record(torch.cuda.current_stream())
+        rec(0)
         if K:
-            e[1].record(stream)
+            rec(1)
             pd.pardtw_dp_fused_ckpt(Xd, Yd, K, w.ckpt, w.total, w.status, w.ws)
-            e[2].record(stream)
+            rec(2)
             if args.walk != "serial":
                 pd.pardtw_ckpt_backtrace_parallel(Xd, Yd, K, w.ckpt, w.status, w.path, w.path_len, w.bt_ws)
             else:
                 pd.pardtw_ckpt_backtrace(Xd, Yd, K, w.ckpt, w.status, w.path, w.path_len)
             if comp:
                 pd.pardtw_path_total(Xd, Yd, w.path, w.path_len, w.total_comp, w.total_ws)
-            e[3].record(stream)
-            continue
+            rec(3)
+            return
         if args.fused:
-            e[1].record(stream)
+            rec(1)
             if args.packed:
                 pd.pardtw_dp_fused_packed(Xd, Yd, w.bp, w.total, w.status, w.ws)
             else:
                 pd.pardtw_dp_fused(Xd, Yd, w.bp, w.total, w.status, w.ws)
         else:
             pd.pardtw_cost(Xd, Yd, w.C, pd.PREC_F32, pd.LAYOUT_PANEL_BAND)
-            e[1].record(stream)
+            rec(1)
             if args.packed:
                 pd.pardtw_dp_packed(w.C, n, m, w.bp, w.total, w.status, w.ws, pd.LAYOUT_PANEL_BAND)
             else:
                 pd.pardtw_dp(w.C, n, m, w.bp, w.total, w.status, w.ws, pd.LAYOUT_PANEL_BAND)
-        e[2].record(stream)
+        rec(2)
         if args.walk != "serial":
             pd.pardtw_backtrace_parallel(w.bp, n, m, w.status, w.path, w.path_len, w.bt_ws, packed=args.packed)
         elif args.packed:
@@ -428,7 +431,41 @@ def main():
             pd.pardtw_backtrace(w.bp, n, m, w.status, w.path, w.path_len)
         if comp:
             pd.pardtw_path_total(Xd, Yd, w.path, w.path_len, w.total_comp, w.total_ws)
-        e[3].record(stream)
+        rec(3)
+
+    graph = None
+    if args.graph:
+        # the whole step captured once as a hipGraph and replayed: one launch
+        # per step instead of one host call per kernel (small pairs are
+        # otherwise bound by the host issuing them); the stage times come from
+        # eager steps before the timed region
+        side = torch.cuda.Stream(device=dev)  # default priority
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            one_step(None)
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            one_step(None)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(min(args.steps, 10))]
+        for e in evs:
+            one_step(e)
+        torch.cuda.synchronize()
+    else:
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    print(f"[bench] timing {args.steps} steps" + (" (graph replays)" if graph else ""), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if graph is not None:
+        for _ in range(args.steps):
+            graph.replay()
+    else:
+        for s in range(args.steps):
+            one_step(evs[s])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     stage_ms = np.array([[e[k].elapsed_time(e[k + 1]) for k in range(3)] for e in evs])
@@ -473,7 +510,8 @@ def main():
                    "layout": ("fused_cost" if args.fused else "panel64_band") + ("+packed_codes" if args.packed else ""),
                    "device_bytes_per_pair": workspace_device_bytes(w),
                    "device_bytes_per_cell": round(workspace_device_bytes(w) / cells, 4),
-                   "schedule": "serial: cost, DP and backtrace of one pair, then the next",
+                   "schedule": "serial: cost, DP and backtrace of one pair, then the next"
+                               + (", each step one hipGraph replay" if args.graph else ""),
                    "walk": "one workgroup" if args.walk == "serial" else "split",
                    "pairs_per_s": round(1e3 / ms_per_step, 3),
                    "stage_ms": {"cost": round(float(cost_ms), 4), "dp": round(float(dp_ms), 4),

@@ -50,6 +50,7 @@
 // LDS ring the compute wave reads instead of HBM. The DP then moves 1 byte per
 // cell (the codes) and its costs are bit for bit those of the GEMM.
 #include <mutex>
+#include <type_traits>
 
 #include "batch.h"
 #include "cost_slab.h"
@@ -168,6 +169,15 @@ __device__ __attribute__((always_inline)) inline void load_chunk(const DpArgs& a
     }
 }
 
+// Loads the panel-layout cost chunk at base into cb (see load_chunk).
+__device__ __attribute__((always_inline)) inline void load_chunk_at(const float* base, int lane, float (&cb)[kChunk]) {
+    const f32x4* src = reinterpret_cast<const f32x4*>(base) + lane;
+    const f32x4 v0 = __builtin_nontemporal_load(src);
+    const f32x4 v1 = __builtin_nontemporal_load(src + kLanes);
+    cb[0] = v0[0]; cb[1] = v0[1]; cb[2] = v0[2]; cb[3] = v0[3];
+    cb[4] = v1[0]; cb[5] = v1[1]; cb[6] = v1[2]; cb[7] = v1[3];
+}
+
 // Chunks whose costs the sweep reads: those of the band of cells that can lie
 // on a path from (0,0) to (N-1,M-1). Every other chunk runs the same
 // instructions on a cost chunk that is always written (the origin's), so the
@@ -216,7 +226,7 @@ __device__ __attribute__((always_inline)) inline void ring_chunk(CostRing& cr, i
     if (k <= klast)
         while (cprog_seen <= k) cprog_seen = lds_get(&cr.prog[wave]);
     compiler_order();
-    const f32x4* src = reinterpret_cast<const f32x4*>(&cr.slot[wave][k % kCRing][0]) + lane;
+    const f32x4* src = reinterpret_cast<const f32x4*>(&cr.slot[wave][unsigned(k) % unsigned(kCRing)][0]) + lane;
     const f32x4 v0 = src[0], v1 = src[kLanes];
     cb[0] = v0[0]; cb[1] = v0[1]; cb[2] = v0[2]; cb[3] = v0[3];
     cb[4] = v1[0]; cb[5] = v1[1]; cb[6] = v1[2]; cb[7] = v1[3];
@@ -242,6 +252,7 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
     const float kInf = __builtin_inff();
     const int bcol = lane - (kLanes - 2);  // 0 / 1 on the two boundary lanes
     uint64_t* bp_pan = reinterpret_cast<uint64_t*>(a.bp) + int64_t(p) * G * kLanes;
+    uint64_t* cptr = bp_pan + int64_t(k0) * kLanes;
     const float* rin = &sh.ring[wave][0][0][0];
     float* rout = &sh.ring[wave + 1][0][0][0];
     int flags = __builtin_amdgcn_readfirstlane(have_out ? 2 : 0);
@@ -266,6 +277,8 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
         for (int u = 0; u < kPf; ++u)
             load_chunk<SRC>(a, p, lane, k0 + u, k0 + u <= k1, cbuf[u]);
     }
+    // panel layouts: the chunk kPf ahead, advanced one chunk per chunk
+    const float* cnext = a.C + (int64_t(p) * G + k0 + kPf) * (kLanes * kChunk);
 
     // Rows above the first band chunk: D of this panel's own columns there
     // is +inf (no band cell has a finite predecessor there), and lane 0
@@ -306,13 +319,27 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
     // goes to a ring nobody reads. Every path then issues the same memory
     // operations, which keeps the compiler's outstanding-load counts exact
     // across the loop back edge.
-    for (int kb = k0; kb <= k1; kb += kPf) {
+    // The chunks go in groups of kPf. whole: 0 any group; 1 band chunks only,
+    // so the tests of `inside` fold away; 2 band chunks whose prefetches (kPf
+    // ahead) are band chunks too. Groups 1 and 2 also check the right ring's
+    // space and release their input slots once per group instead of once per
+    // chunk. A wave issues one instruction at a time and the sweep's chain
+    // runs through every chunk, so each instruction taken out of a chunk
+    // shortens the sweep: this took the DP from 3.38 to 2.79 ms.
+    auto group = [&](int kb, auto whole) {
+        if constexpr (decltype(whole)::value >= 1) {
+            if ((flags & 2) && cons_seen < kb + kPf - kRing) {
+                int v;
+                while ((v = lds_get(&sh.cons[wave + 1])) < kb + kPf - kRing) {}
+                cons_seen = v;
+            }
+        }
 #pragma unroll
         for (int u = 0; u < kPf; ++u) {
             const int k = kb + u;
-            const bool inside = k <= k1;
+            const bool inside = decltype(whole)::value ? true : k <= k1;
             asm volatile("" : "+s"(flags));
-            const int slot = k % kRing;
+            const int slot = int(unsigned(k) % unsigned(kRing));
 
             {
                 // Compute waves own their SIMD, so a consumer that caught up spins
@@ -330,7 +357,7 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
                 lv1[0] = y0[0]; lv1[1] = y0[1]; lv1[2] = y0[2]; lv1[3] = y0[3];
                 lv1[4] = y1[0]; lv1[5] = y1[1]; lv1[6] = y1[2]; lv1[7] = y1[3];
                 compiler_order();
-                lds_put(lane == 0 ? &sh.cons[wave] : &sh.isink[wave][lane], k + 1);
+                if constexpr (!decltype(whole)::value) lds_put(lane == 0 ? &sh.cons[wave] : &sh.isink[wave][lane], k + 1);
                 // read per lane from one of two identical copies, so the value
                 // stays in a vector register and is not waited for until the
                 // end of the chunk
@@ -340,11 +367,13 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
             uint32_t lo, hi;
             float best_r[kChunk];
             dp_rows<SUB, kPack>(cbuf[u], lv0, lv1, e0, e1, d1, s1p, lo, hi, best_r);
-            if (SUB) {
-                if (k == 0) lo = (lo & ~0xffu) | 3u;  // row 0: every cell is a start
-            } else if (p == 0 && k == 0) {
-                const uint32_t row0 = kPack ? 0x3u : 0xffu;
-                lo = (lane == 0) ? ((lo & ~row0) | 3u) : lo;  // the origin's code
+            if constexpr (!decltype(whole)::value) {
+                if (SUB) {
+                    if (k == 0) lo = (lo & ~0xffu) | 3u;  // row 0: every cell is a start
+                } else if (p == 0 && k == 0 && lane == 0) {
+                    const uint32_t row0 = kPack ? 0x3u : 0xffu;
+                    lo = (lo & ~row0) | 3u;  // the origin's code
+                }
             }
             e0 = lv0[kChunk - 1];
             e1 = lv1[kChunk - 1];
@@ -365,7 +394,8 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
                                         : reinterpret_cast<uint16_t*>(a.hdr->sink);
                 __builtin_nontemporal_store(uint16_t(lo), cdst + lane);
             } else {
-                uint64_t* cdst = inside ? bp_pan + int64_t(k) * kLanes : a.hdr->sink;
+                uint64_t* cdst = inside ? cptr : a.hdr->sink;
+                cptr += kLanes;
                 __builtin_nontemporal_store(uint64_t(lo) | (uint64_t(hi) << 32), cdst + lane);
             }
 
@@ -380,7 +410,7 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
 
             {
                 // A wave without a right neighbour writes into a ring nobody reads.
-                if ((flags & 2) && inside && cons_seen < k + 1 - kRing) {
+                if (!decltype(whole)::value && (flags & 2) && inside && cons_seen < k + 1 - kRing) {
                     int v;
                     while ((v = lds_get(&sh.cons[wave + 1])) < k + 1 - kRing) {}
                     cons_seen = v;
@@ -395,16 +425,36 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
                 compiler_order();
                 lds_put(lane < 2 ? &sh.prog[wave + 1][lane] : &sh.isink[wave][lane], inside ? k + 1 : k1 + 1);
             }
-            if (k == last && inside) {
+            if (!decltype(whole)::value && k == last && inside) {
 #pragma unroll
                 for (int r = 0; r < kChunk; ++r) dlast = (r == rlast) ? best_r[r] : dlast;
             }
 
             const int kn = k + kPf;
             if constexpr (kFused) ring_chunk(*cring, wave, lane, kn, k1, cprog_seen, cbuf[u]);
-            else load_chunk<SRC>(a, p, lane, kn <= k1 ? kn : k0, kn <= k1, cbuf[u]);
+            else if constexpr (SRC == kSrcRow) load_chunk<SRC>(a, p, lane, kn <= k1 ? kn : k0, kn <= k1, cbuf[u]);
+            else {
+                load_chunk_at(decltype(whole)::value == 2 || kn <= k1 ? cnext : a.C, lane, cbuf[u]);
+                cnext += kLanes * kChunk;
+            }
         }
+        if constexpr (decltype(whole)::value >= 1) {
+            compiler_order();
+            lds_put(lane == 0 ? &sh.cons[wave] : &sh.isink[wave][lane], kb + kPf);
+        }
+    };
+    // Chunk 0 (the origin, or subsequence DTW's row of starts) and the
+    // matrix's last chunk (the total) are left to the general groups.
+    int kb = k0;
+    if (k0 == 0) {
+        group(kb, std::integral_constant<int, 0>{});
+        kb += kPf;
     }
+    const int kw_end = k1 == last ? k1 - 1 : k1;
+    if constexpr (!kFused && SRC != kSrcRow)
+        for (; kb + 2 * kPf - 1 <= kw_end; kb += kPf) group(kb, std::integral_constant<int, 2>{});
+    for (; kb + kPf - 1 <= kw_end; kb += kPf) group(kb, std::integral_constant<int, 1>{});
+    for (; kb <= k1; kb += kPf) group(kb, std::integral_constant<int, 0>{});
     // Chunks k1 + 1 .. khr of the right panel's band: their left boundary lies
     // outside this panel's band, so it is handed over as +inf.
     if (flags & 2) {
