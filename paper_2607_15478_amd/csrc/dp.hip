@@ -255,6 +255,9 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
     uint64_t* cptr = bp_pan + int64_t(k0) * kLanes;
     const float* rin = &sh.ring[wave][0][0][0];
     float* rout = &sh.ring[wave + 1][0][0][0];
+    // a boundary lane's column in the output ring (slot 0); other lanes write
+    // to their sink
+    float* wbase = bcol >= 0 ? rout + bcol * kChunk : reinterpret_cast<float*>(&sh.fsink[wave][lane][0]);
     int flags = __builtin_amdgcn_readfirstlane(have_out ? 2 : 0);
     // chunks before kin are never read: release their ring slots at once
     if (lane == 0) lds_put(&sh.cons[wave], kin);
@@ -405,7 +408,8 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
             __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
             {
                 const int pv0 = __builtin_amdgcn_readfirstlane(pv);
-                prog_seen = pv0 > prog_seen ? pv0 : prog_seen;
+                // the counter only grows, and pv was read after every earlier read of it
+                prog_seen = pv0;
             }
 
             {
@@ -417,7 +421,7 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
                 }
                 compiler_order();
                 {
-                    f32x4* dst = (bcol >= 0 && inside) ? reinterpret_cast<f32x4*>(rout + (slot * 2 + bcol) * kChunk)
+                    f32x4* dst = (bcol >= 0 && inside) ? reinterpret_cast<f32x4*>(wbase + slot * 2 * kChunk)
                                                        : &sh.fsink[wave][lane][0];
                     dst[0] = f32x4{best_r[0], best_r[1], best_r[2], best_r[3]};
                     dst[1] = f32x4{best_r[4], best_r[5], best_r[6], best_r[7]};
