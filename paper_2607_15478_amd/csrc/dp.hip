@@ -72,6 +72,10 @@ constexpr int kPfRow = 4;        // the same for the row-major layout (8 loads p
 constexpr int kHelperWin = 4;   // chunks polled per helper round trip (one record per lane)
 constexpr int kMaxNWFused = 4;   // fused workgroups: NW compute + NW producer + 2 helper waves
 constexpr int kCRing = 8;        // fused cost ring depth, in chunks (2 KB each)
+constexpr int kPfFused = 4;      // fused cost chunks read ahead of the one computed
+// the consumer releases ring slots once per group of kPfFused chunks, kPfFused
+// chunks behind its reads, and the producer writes two chunks at a time
+static_assert(kCRing >= kPfFused + 2, "fused cost ring too shallow for the read-ahead");
 constexpr int kRecSlots = 257;   // record columns of one pair; the grid stays below it
 
 // Where the DP's costs come from.
@@ -222,7 +226,8 @@ __device__ inline int first_input_chunk(int p, int64_t n, int64_t m, int64_t G) 
 // Chunk k's costs from the fused ring into cb, once the producer has them
 // (chunks past the end read a slot without waiting; their values are unused).
 __device__ __attribute__((always_inline)) inline void ring_chunk(CostRing& cr, int wave, int lane, int k, int klast,
-                                                                 int& cprog_seen, float (&cb)[kChunk]) {
+                                                                 int& cprog_seen, float (&cb)[kChunk],
+                                                                 bool release = true) {
     if (k <= klast)
         while (cprog_seen <= k) cprog_seen = lds_get(&cr.prog[wave]);
     compiler_order();
@@ -232,7 +237,7 @@ __device__ __attribute__((always_inline)) inline void ring_chunk(CostRing& cr, i
     cb[4] = v1[0]; cb[5] = v1[1]; cb[6] = v1[2]; cb[7] = v1[3];
     compiler_order();
     // the slot is free once read (LDS operations of a wave complete in order)
-    lds_put(&cr.cons[wave], k + 1);
+    if (release) lds_put(&cr.cons[wave], k + 1);
 }
 
 template <int SRC, bool SUB, class Sh>
@@ -269,12 +274,13 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
     int ck_next = kCk ? (ck_q + 1) * a.ck_chunks - 1 : 0;
     const int ck_q0 = ck_q;
     constexpr bool kPack = is_packed(SRC);
-    constexpr int kPf = kFused ? 1 : SRC == kSrcRow ? kPfRow : kPfPanel;
+    constexpr int kPf = kFused ? kPfFused : SRC == kSrcRow ? kPfRow : kPfPanel;
     float cbuf[kPf][kChunk];
-    int cprog_seen = 0;
+    int cprog_seen = 0, cpv = 0;
     if constexpr (kFused) {
         if (lane == 0) lds_put(&cring->cons[wave], k0);
-        ring_chunk(*cring, wave, lane, k0, k1, cprog_seen, cbuf[0]);
+#pragma unroll
+        for (int u = 0; u < kPf; ++u) ring_chunk(*cring, wave, lane, k0 + u, k1, cprog_seen, cbuf[u]);
     } else {
 #pragma unroll
         for (int u = 0; u < kPf; ++u)
@@ -365,6 +371,8 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
                 // stays in a vector register and is not waited for until the
                 // end of the chunk
                 pv = lds_get(&sh.prog[wave][lane & 1]);
+                // the same for the cost producer's counter
+                if constexpr (kFused) cpv = lds_get(&cring->prog[wave]);
             }
 
             uint32_t lo, hi;
@@ -410,6 +418,7 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
                 const int pv0 = __builtin_amdgcn_readfirstlane(pv);
                 // the counter only grows, and pv was read after every earlier read of it
                 prog_seen = pv0;
+                if constexpr (kFused) cprog_seen = __builtin_amdgcn_readfirstlane(cpv);
             }
 
             {
@@ -435,7 +444,7 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
             }
 
             const int kn = k + kPf;
-            if constexpr (kFused) ring_chunk(*cring, wave, lane, kn, k1, cprog_seen, cbuf[u]);
+            if constexpr (kFused) ring_chunk(*cring, wave, lane, kn, k1, cprog_seen, cbuf[u], !decltype(whole)::value);
             else if constexpr (SRC == kSrcRow) load_chunk<SRC>(a, p, lane, kn <= k1 ? kn : k0, kn <= k1, cbuf[u]);
             else {
                 load_chunk_at(decltype(whole)::value == 2 || kn <= k1 ? cnext : a.C, lane, cbuf[u]);
@@ -445,6 +454,8 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
         if constexpr (decltype(whole)::value >= 1) {
             compiler_order();
             lds_put(lane == 0 ? &sh.cons[wave] : &sh.isink[wave][lane], kb + kPf);
+            // the cost slots of every chunk read so far
+            if constexpr (kFused) lds_put(&cring->cons[wave], kb + 2 * kPf);
         }
     };
     // Chunk 0 (the origin, or subsequence DTW's row of starts) and the
@@ -499,15 +510,18 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
 }
 
 // Producer of compute wave w (panel p) in the fused form: the panel's costs,
-// 16 rows (two chunks) at a time, into the wave's ring. Slabs without a band
-// chunk are not computed: the compute wave then reads whatever finite values
-// the slot holds (zeros at first), which only reach cells outside the band.
+// 16 rows (two chunks) at a time, into the wave's ring. Only the slabs that
+// hold a band chunk are visited; the compute wave reads whatever finite values
+// a slot holds for the other chunk of a slab (zeros at first), which only
+// reach cells outside the band.
 __device__ __attribute__((always_inline)) inline void cost_producer(const DpArgs& a, CostRing& cr, int w, int p,
                                                                     bool sub) {
     const int lane = threadIdx.x & 63;
     const int G = int(a.G);
-    int64_t lo = sub ? sub_group_lo(p, a.n, a.m) : band_group_lo(p, a.n, a.m);
-    const int64_t hi = sub ? sub_group_hi(p, a.n, a.m) : band_group_hi(p, a.n, a.m);
+    // the band's chunks, clamped to the rows (the subsequence bound runs past them)
+    const int64_t lo = sub ? sub_group_lo(p, a.n, a.m) : band_group_lo(p, a.n, a.m);
+    const int64_t hi_raw = sub ? sub_group_hi(p, a.n, a.m) : band_group_hi(p, a.n, a.m);
+    const int64_t hi = hi_raw < G - 1 ? hi_raw : G - 1;
     float bv[4][4], ry[4];
     panel_operands_f32_small(a.Y, a.m, a.d, p, bv, ry);
     f32x4* ring = reinterpret_cast<f32x4*>(&cr.slot[w][0][0]);
@@ -525,21 +539,26 @@ __device__ __attribute__((always_inline)) inline void cost_producer(const DpArgs
     // register with a load in flight is copied. Rows past n read the zero
     // padding of the row-norm area.
     const float* zeros = a.rxs + a.n;
+    if (lo > hi) {
+        lds_put(&cr.prog[w], G);
+        return;
+    }
+    const int s0 = int(lo >> 1), s1 = int(hi >> 1);
     float avA[4], avB[4], avC[4];
     f32x4 rxA, rxB, rxC;
     // (issued in slab order, as the loop issues them, so that the compiler's
     // load counts agree on both ways into the loop)
-    slab_rows_f32_small_ahead(a.X, zeros, a.n, a.d, 0, avA);
-    rxA = rx_base[0];
+    slab_rows_f32_small_ahead(a.X, zeros, a.n, a.d, int64_t(16) * s0, avA);
+    rxA = rx_base[4 * s0];
     compiler_order();
-    slab_rows_f32_small_ahead(a.X, zeros, a.n, a.d, 16, avB);
-    rxB = rx_base[4];
+    slab_rows_f32_small_ahead(a.X, zeros, a.n, a.d, int64_t(16) * (s0 + 1), avB);
+    rxB = rx_base[4 * (s0 + 1)];
     compiler_order();
     auto step = [&](int s, float (&av)[4], f32x4& rx, float (&av_next)[4], f32x4& rx_next) {
         slab_rows_f32_small_ahead(a.X, zeros, a.n, a.d, int64_t(16) * (s + 2), av_next);
         rx_next = rx_base[4 * (s + 2)];
         const int k0 = 2 * s;
-        if (k0 <= hi && k0 + 1 >= lo) {
+        if (s <= s1) {
             const int need = k0 + 2 - kCRing;  // the consumer has taken chunk k0 + 1 - kCRing out
             while (cons_seen < need) {
                 cons_seen = lds_get(&cr.cons[w]);
@@ -558,8 +577,7 @@ __device__ __attribute__((always_inline)) inline void cost_producer(const DpArgs
         compiler_order();
         lds_put(&cr.prog[w], k0 + 2 < G ? k0 + 2 : G);
     };
-    const int slabs = int(ceil_div(G, 2));
-    for (int s = 0; s < slabs; s += 3) {
+    for (int s = s0; s <= s1; s += 3) {
         step(s, avA, rxA, avC, rxC);
         step(s + 1, avB, rxB, avA, rxA);
         step(s + 2, avC, rxC, avB, rxB);
