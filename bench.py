@@ -62,7 +62,12 @@ def parse():
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "dp_traffic.json"))
     ap.add_argument("--nfrag", type=int, default=32, help="segmental workloads: fragments of sequence A")
     ap.add_argument("--fused", action="store_true",
-                    help="the DP computes the costs itself (no cost matrix; FP32, d <= 16)")
+                    help="the DP computes the costs itself (no cost matrix; FP32 d <= 16, or BF16 operands "
+                         "d <= 128 for batches). Batch and segmental workloads use it by default for FP32 "
+                         "d <= 16, where it is the faster form")
+    ap.add_argument("--materialised", action="store_true",
+                    help="batch and segmental workloads: the cost GEMM writes the cost matrix and the DP reads "
+                         "it (the default for pairs)")
     ap.add_argument("--variant", choices=["wsdtw", "nsdtw"], default="wsdtw", help="segmental workloads")
     ap.add_argument("--pipelined", action="store_true",
                     help="pair workloads: run each pair's backtrace on a second stream beside the next pair's "
@@ -85,6 +90,8 @@ def parse():
                          "backtrace (no code matrix; K a multiple of 16 in [16, 256])")
     ap.add_argument("--no-comp-total", action="store_true",
                     help="pair workloads: skip the compensated path total (pardtw_path_total) after each backtrace")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="segmental workloads: skip the deviation from the exact DTW path")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (HBM counter calibration)")
     return ap.parse_args()
@@ -784,7 +791,9 @@ def run_batch(args):
     for prec in ([pd.PREC_F32, pd.PREC_BF16] if d >= 64 else [pd.PREC_F32]):
         # fused: FP32 costs for d <= 16, BF16-operand costs for d <= 128 (d % 8 == 0)
         fusable = (d <= 16) if prec == pd.PREC_F32 else (d <= 128 and d % 8 == 0)
-        plan = pd.Plan(ns, ms, d, prec, fused=args.fused and fusable)
+        # FP32 d <= 16 fuses by default (faster on the batches); BF16 on request
+        want = args.fused or (prec == pd.PREC_F32 and not args.materialised)
+        plan = pd.Plan(ns, ms, d, prec, fused=want and fusable)
         buf = plan.buffers(dev)
         best = plan.autotune(Xp, Yp, buf, reps=2)
         for _ in range(args.warmup):
@@ -808,6 +817,7 @@ def run_batch(args):
         torch.cuda.synchronize()
         ms_graph = e0.elapsed_time(e1) / args.steps
         res[prec] = dict(plan=plan, buf=buf, ms=ms_graph, tuned_dp_ms=best, sched=plan.schedule(),
+                         fused=bool(want and fusable),
                          totals=buf["totals"].cpu().numpy(), status=buf["status"].cpu().numpy(),
                          paths=[plan.path(buf, b).cpu().numpy() for b in range(len(pairs))])
         print(f"[bench] batch prec={prec} graph {ms_graph:.3f} ms, schedule {plan.schedule()}", file=sys.stderr,
@@ -884,14 +894,18 @@ def run_batch(args):
     if fwd_bwd is not None:
         out["config"]["forward_backward_graph_ms"] = round(fwd_bwd["graph_ms"], 4)
         out["config"]["backward_ms"] = round(fwd_bwd["grad_ms"], 4)
-    # the dominant kernel, the batched DP, on the pairs' path bands (tuned time)
+    # the dominant kernel, the batched DP, on the pairs' path bands (tuned
+    # time); with the fused cost it reads no costs, only writes its codes
     bcells = sum(band_cells(n, m) for n, m, f in zip(ns, ms, feas) if f)
     dp_ms = r32["tuned_dp_ms"]
-    ach = DP_BYTES_PER_CELL * bcells / (dp_ms * 1e-3) / 1e9
+    bpc = 1 if r32["fused"] else DP_BYTES_PER_CELL
+    ach = bpc * bcells / (dp_ms * 1e-3) / 1e9
+    out["config"]["fused_cost"] = r32["fused"]
     out["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "dp_batch_kernel",
-                       "algorithmic_bytes_per_launch": DP_BYTES_PER_CELL * bcells, "bytes_per_band_cell":
-                       DP_BYTES_PER_CELL, "band_cells": bcells, "kernel_ms": round(dp_ms, 4)}
+                       "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                       "kernel": "dp_batch_kernel (fused cost)" if r32["fused"] else "dp_batch_kernel",
+                       "algorithmic_bytes_per_launch": bpc * bcells, "bytes_per_band_cell": bpc,
+                       "band_cells": bcells, "kernel_ms": round(dp_ms, 4)}
     print(json.dumps(out), flush=True)
 
 
@@ -958,6 +972,29 @@ def cpu_baseline_grad(pairs, paths, fb):
     return cpu, {"max_abs_err_over_max_grad": float(worst), "within_1e-4": bool(worst <= 1e-4)}
 
 
+def path_rows_position(path, n: int) -> np.ndarray:
+    """For each row i < n of A, the mean column of B the path visits in that
+    row, linearly interpolated over rows it skips (a (2,1) step skips one) and
+    held constant before its first and after its last row."""
+    path = np.asarray(path, np.int64).reshape(-1, 2)
+    s, c = np.zeros(n), np.zeros(n)
+    np.add.at(s, path[:, 0], path[:, 1])
+    np.add.at(c, path[:, 0], 1)
+    have = c > 0
+    rows = np.arange(n)
+    return np.interp(rows, rows[have], s[have] / c[have])
+
+
+def path_deviation(path, ref_path, n: int) -> dict:
+    """Deviation in frames of `path` from `ref_path`, both over the n rows of
+    A: mean and max over rows i of |j(i) - j_ref(i)| (path_rows_position), and
+    the share of rows within 1 and 10 frames."""
+    dev = np.abs(path_rows_position(path, n) - path_rows_position(ref_path, n))
+    return {"mean_dev_frames": round(float(dev.mean()), 4), "max_dev_frames": round(float(dev.max()), 2),
+            "rows_within_1_frame": round(float((dev <= 1.0).mean()), 5),
+            "rows_within_10_frames": round(float((dev <= 10.0).mean()), 5)}
+
+
 def cpu_baseline_segmental(A, B, starts, hop, variant, g_S, g_ends, g_total, sample_frags):
     """The oracle's subsequence DP timed on a bounded sample of fragments (their
     scores then checked against the GPU's), and the oracle's segment level run
@@ -1006,7 +1043,8 @@ def run_segmental(args):
     nf, variant = args.nfrag, (pd.WSDTW if args.variant == "wsdtw" else pd.NSDTW)
     cells = la * lb
     Ad, Bd = torch.from_numpy(A).to(dev), torch.from_numpy(B).to(dev)
-    plan = pd.SegPlan(la, lb, nf, d, pd.PREC_F32, variant, fused=args.fused)
+    fused = (args.fused or not args.materialised) and d <= 16
+    plan = pd.SegPlan(la, lb, nf, d, pd.PREC_F32, variant, fused=fused)
     buf = plan.buffers(dev)
     print(f"[bench] plan {nf} fragments, workspace {plan.workspace_bytes / 2**30:.1f} GiB; autotune",
           file=sys.stderr, flush=True)
@@ -1041,14 +1079,28 @@ def run_segmental(args):
     g_ends = buf["ends"].cpu().numpy().astype(np.int64)
     g_total = float(buf["total"].item())
     L = int(buf["path_len"].item())
-    bpc = 1 if args.fused else DP_BYTES_PER_CELL
+    seg_path = buf["path"][:L].cpu().numpy()
+    seg_status = int(buf["status"].item())
+    # Accuracy against exact DTW of the same pair (outside the timed region):
+    # the segmental path's deviation from the exact path, row by row of A.
+    accuracy = None
+    if not args.no_accuracy:
+        w = pd.Workspace(la, lb, "cuda", pd.LAYOUT_PANEL_BAND, cost=False, packed=True)
+        pd.align_into(Ad, Bd, w, fused=True)
+        torch.cuda.synchronize()
+        if int(w.status.item()) == pd.PAIR_OK:
+            exact = w.path[: int(w.path_len.item())].cpu().numpy()
+            accuracy = {"reference": "exact DTW path of the same pair (weights 2,3,3)",
+                        **path_deviation(seg_path, exact, la)}
+        del w
+    bpc = 1 if fused else DP_BYTES_PER_CELL
     # the method's work: each fragment's subsequence band (cells on some path
     # from its first row to its last)
     bcells = sum(subseq_band_cells(plan.starts[f + 1] - plan.starts[f], lb) for f in range(nf))
     dp_achieved = bpc * bcells / (dp_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(dp_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dp_achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "dp_batch_kernel (subsequence%s)" % (", fused cost" if args.fused else ""),
+                "kernel": "dp_batch_kernel (subsequence%s)" % (", fused cost" if fused else ""),
                 "algorithmic_bytes_per_launch": bpc * bcells, "bytes_per_band_cell": bpc, "band_cells": bcells,
                 "band_fraction": round(bcells / cells, 4), "kernel_ms": round(float(dp_ms), 4)}
     cpu, validation = None, None
@@ -1077,13 +1129,14 @@ def run_segmental(args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "algorithm": args.variant, "fragments": nf, "hop": plan.hop,
-                   "fused_cost": bool(args.fused), "workspace_gib": round(plan.workspace_bytes / 2**30, 2),
+                   "fused_cost": fused, "workspace_gib": round(plan.workspace_bytes / 2**30, 2),
                    "la": la, "lb": lb, "d": d, "cells": cells, "pairs_per_s": round(1e3 / ms, 3),
                    "wall_ms_per_step": round(wall, 4), "schedule": plan.schedule(), "tuned_dp_ms": round(dp_ms, 4),
-                   "status": int(buf["status"].item()), "path_len": L},
+                   "status": seg_status, "path_len": L},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "validation": validation,
+        "accuracy": accuracy,
     }
     print(json.dumps(out), flush=True)
 

@@ -42,3 +42,25 @@ def test_band_cells_of_the_long_pair():
     sys.path.insert(0, ROOT)
     import bench
     assert bench.band_cells(50000, 60000) == 933333334
+
+
+def test_path_deviation_by_hand():
+    """The segmental accuracy report: a path's B position per row of A (mean
+    over the row's cells, interpolated over skipped rows) and its deviation
+    from a reference path, on small paths worked out by hand."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import numpy as np
+    # rows 0..4; row 1 is skipped by a (2,1) step, row 3 holds two cells
+    p = np.array([[0, 0], [2, 1], [3, 2], [3, 3], [4, 4]])
+    np.testing.assert_allclose(bench.path_rows_position(p, 5), [0.0, 0.5, 1.0, 2.5, 4.0])
+    # rows before the first and after the last visited row hold their neighbour
+    q = np.array([[1, 3], [2, 5]])
+    np.testing.assert_allclose(bench.path_rows_position(q, 4), [3.0, 3.0, 5.0, 5.0])
+    ref = np.array([[0, 0], [1, 1], [2, 2], [3, 3], [4, 4]])
+    d = bench.path_deviation(p, ref, 5)
+    # |0-0|, |0.5-1|, |1-2|, |2.5-3|, |4-4|
+    assert d["mean_dev_frames"] == round((0 + 0.5 + 1 + 0.5 + 0) / 5, 4)
+    assert d["max_dev_frames"] == 1.0
+    assert d["rows_within_1_frame"] == 1.0
+    assert bench.path_deviation(ref, ref, 5)["mean_dev_frames"] == 0.0

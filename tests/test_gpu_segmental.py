@@ -456,3 +456,32 @@ def test_segplan_hop_and_fragments_are_the_oracles(la, nf):
     assert pd._lib_segplan_fstart(plan._h, nf + 1) == -1 and pd._lib_segplan_fstart(plan._h, -1) == -1
     pair_plan = pd.Plan([10], [12], 4)
     assert pd._lib_segplan_hop(pair_plan._h) == -1 and pd._lib_segplan_fstart(pair_plan._h, 0) == -1
+
+
+@pytest.mark.parametrize("nf", [1, 8, 32])
+def test_segmental_deviation_from_exact_dtw(nf):
+    """The accuracy report of the Segmental DTW bench: the deviation of the
+    segmental path from the exact DTW path of the same pair, per row of A.
+    Computed from the GPU's two paths it agrees with the same report on the
+    oracle's two paths (paths may differ only at declared near-ties)."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    la, lb = 2000, 2400
+    A, B = synth.chroma_pair(7, la, lb, 12, 0.7, 1.4)
+    Ad, Bd = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+    plan = pd.SegPlan(la, lb, nf, 12, pd.PREC_F32, pd.WSDTW)
+    buf = plan.buffers(DEV)
+    plan.align(Ad, Bd, buf)
+    w = pd.Workspace(la, lb, DEV)
+    pd.align_into(Ad, Bd, w)
+    torch.cuda.synchronize()
+    seg = buf["path"][: int(buf["path_len"].item())].cpu().numpy()
+    exact = w.path[: int(w.path_len.item())].cpu().numpy()
+    got = bench.path_deviation(seg, exact, la)
+    ref = bench.path_deviation(oracle.segmental(A, B, nf, pd.WSDTW)["path"], oracle.align(A, B)[1], la)
+    assert abs(got["mean_dev_frames"] - ref["mean_dev_frames"]) <= 0.01
+    assert abs(got["max_dev_frames"] - ref["max_dev_frames"]) <= 1.0
+    # on this tempo-warped copy both methods follow the warp closely
+    assert got["rows_within_10_frames"] == 1.0
