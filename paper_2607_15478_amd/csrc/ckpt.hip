@@ -142,7 +142,7 @@ __device__ void window_wave(CkShared& sh, const WaveStart& st, int wave, int r0,
             for (int t = 0; t < 4; ++t) av[t] = sh.xs[rs + (lane & 15)][4 * t + (lane >> 4)];
             const f32x4 rx4 = *reinterpret_cast<const f32x4*>(&sh.rx[rs + 4 * (lane >> 4)]);
             f32x4 acc[4], v[4];
-            slab_acc_f32_small(av, st.bv, acc);
+            slab_acc_f32_small(16, av, st.bv, acc);  // every step: the same sums (zeros past d)
             costs_from_acc_rx(acc, rx4, st.ry, v);
             float* dst = &sh.tr[wave][kq][half * (kLanes * 4)];
 #pragma unroll

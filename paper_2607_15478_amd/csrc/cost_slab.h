@@ -95,26 +95,31 @@ __device__ __attribute__((always_inline)) inline void slab_rows_f32_small_ahead(
     }
 }
 
-// Four MFMA steps over features 4t + g, whatever d <= 16: past d both operands
-// are zero and add nothing.
-__device__ __attribute__((always_inline)) inline void slab_acc_f32_small(const float (&av)[4], const float (&bv)[4][4],
-                                                                         f32x4 (&acc)[4]) {
+// MFMA steps over features 4t + g, d <= 16. Step t is issued only when
+// 4t < d: past d both operands are zero, so a skipped step would only have
+// added zeros (at most turning a -0 or denormal sum into +0, which gives the
+// same cost 1 - (acc rx) ry), and the costs are the same bits (d = 12 takes
+// three steps, not four). Pass 16 to run every step.
+__device__ __attribute__((always_inline)) inline void slab_acc_f32_small(int64_t d, const float (&av)[4],
+                                                                         const float (&bv)[4][4], f32x4 (&acc)[4]) {
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int t = 0; t < 4; ++t)
+        if (4 * t < d)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], bv[b][t], acc[b], 0, 0, 0);
+            for (int b = 0; b < 4; ++b) acc[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[t], bv[b][t], acc[b], 0, 0, 0);
 }
 
 // The slab's costs from its row operands and the panel operands.
-__device__ __attribute__((always_inline)) inline void slab_costs_from_rows(const float (&av)[4], const float (&bv)[4][4],
+__device__ __attribute__((always_inline)) inline void slab_costs_from_rows(int64_t d, const float (&av)[4],
+                                                                           const float (&bv)[4][4],
                                                                            const float (&ry)[4], f32x4 (&v)[4]) {
     float sa = 0.0f;
 #pragma unroll
     for (int t = 0; t < 4; ++t) sa = __builtin_fmaf(av[t], av[t], sa);
     f32x4 acc[4];
-    slab_acc_f32_small(av, bv, acc);
+    slab_acc_f32_small(d, av, bv, acc);
     costs_from_acc(acc, inv_from_sq(sum_groups(sa)), ry, v);
 }
 
@@ -125,7 +130,7 @@ __device__ __attribute__((always_inline)) inline void slab_costs_f32_small(const
                                                                            const float (&ry)[4], f32x4 (&v)[4]) {
     float av[4];
     slab_rows_f32_small(X, n, d, row0, av);
-    slab_costs_from_rows(av, bv, ry, v);
+    slab_costs_from_rows(d, av, bv, ry, v);
 }
 
 // The inverse norm of row i (d <= 16) as the slab computes it: lane group g

@@ -565,7 +565,7 @@ __device__ __attribute__((always_inline)) inline void cost_producer(const DpArgs
                 if (cons_seen < need) __builtin_amdgcn_s_sleep(1);
             }
             f32x4 acc[4], v[4];
-            slab_acc_f32_small(av, bv, acc);
+            slab_acc_f32_small(a.d, av, bv, acc);
             costs_from_acc_rx(acc, rx, ry, v);
             const int kk = k0 + kq;
             if (kk < G) {
