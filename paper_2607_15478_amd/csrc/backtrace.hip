@@ -397,6 +397,10 @@ __device__ void backtrace_pair(BtShared& sh, const uint8_t* bp, int n, int j_end
     if (tid == 0) *path_len = len;
 }
 
+// A subsequence end is usable when it is a column of the matrix that row 0
+// reaches at row n-1.
+__device__ inline bool sub_end_ok(int64_t n, int64_t m, int32_t e) { return e >= 0 && e < m && 2 * int64_t(e) >= n - 1; }
+
 // ---- Split walk (split.h) ----------------------------------------------------
 // The segments are walked by the walker above with a stop row, on the smaller
 // ring of WalkSeg.
@@ -422,7 +426,8 @@ __device__ SegInfo walk_segment(SegShared& sh, SegInfo& res, const SegArgs& a, i
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     if (wave == 0) {
         int2 ex = make_int2(-1, -1);
-        const int len = walk<true>(sh, si, sj, false, a.R, a.cells + int64_t(s) * a.R * 2, seg_stop_row(s, a.R), &ex);
+        const int len = walk<true>(sh, si, sj, a.sub != 0, a.R, a.cells + int64_t(s) * a.R * 2, seg_stop_row(s, a.R),
+                                   &ex);
         if (tid == 0) {
             const SegInfo r = seg_info(si, sj, ex.x, ex.y, len);
             *info_out = r;
@@ -483,13 +488,16 @@ __global__ __launch_bounds__(256) void seg_copy_kernel(SegArgs a, int fin, const
 }
 
 // Batched form: the pairs listed in `sp` are split (segment g belongs to
-// sp[seg_map[g]]); the others keep the one-workgroup walk.
+// sp[seg_map[g]]); the others keep the one-workgroup walk. With `ends` the
+// pairs are the fragments of a Segmental DTW plan, walked as subsequence
+// paths from (n-1, ends[pair]); otherwise DTW pairs with their `status`.
 struct SegBatchArgs {
     const BatchPair* pairs;
     const SegPair* sp;
     const int32_t* seg_map;
     const uint8_t* bp;     // codes of the batch
     const int32_t* status;
+    const int32_t* ends;
     SegInfo* info;         // the split region: SegInfo entries, then cells
     int32_t* cells;
     int32_t* paths;
@@ -502,6 +510,8 @@ __device__ inline SegArgs seg_args_of(const SegBatchArgs& ba, const SegPair& sp)
     a.bp = ba.bp + q.bp_off;
     a.n = int(q.n);
     a.m = int(q.m);
+    a.end = ba.ends ? ba.ends[sp.pair] : int(q.m - 1);
+    a.sub = ba.ends ? 1 : 0;
     a.R = sp.R;
     a.S = sp.S;
     a.info = ba.info + sp.info_off;
@@ -509,11 +519,18 @@ __device__ inline SegArgs seg_args_of(const SegBatchArgs& ba, const SegPair& sp)
     return a;
 }
 
+// Whether the pair has a path to walk: a DTW pair's status, a fragment's end.
+__device__ inline bool seg_pair_ok(const SegBatchArgs& ba, const SegPair& sp) {
+    if (!ba.ends) return ba.status[sp.pair] == PARDTW_PAIR_OK;
+    const BatchPair q = ba.pairs[sp.pair];
+    return q.feasible && sub_end_ok(q.n, q.m, ba.ends[sp.pair]);
+}
+
 __global__ __launch_bounds__(WalkSeg::kThr) void seg_round_batch_kernel(SegBatchArgs ba, int round) {
     __shared__ SegShared sh;
     __shared__ SegInfo res;
     const SegPair sp = ba.sp[ba.seg_map[blockIdx.x]];
-    if (ba.status[sp.pair] != PARDTW_PAIR_OK) return;
+    if (!seg_pair_ok(ba, sp)) return;
     seg_round_body<false>(sh, res, seg_args_of(ba, sp), int(blockIdx.x) - sp.seg0, round);
 }
 
@@ -523,12 +540,14 @@ __global__ __launch_bounds__(WalkSeg::kThr) void seg_finish_batch_kernel(SegBatc
     __shared__ SegInfo sinfo[kSegMaxCount];
     const SegPair sp = ba.sp[blockIdx.x];
     int32_t* plen = ba.path_len + sp.pair;
-    if (ba.status[sp.pair] != PARDTW_PAIR_OK) {
+    if (!seg_pair_ok(ba, sp)) {
         if (threadIdx.x == 0) *plen = 0;
         return;
     }
     const BatchPair q = ba.pairs[sp.pair];
-    seg_finish_body<false>(sh, res, sinfo, seg_args_of(ba, sp), fin, int(q.n < q.m ? q.n : q.m), plen);
+    // a subsequence path has one cell per row at most, a DTW path min(n, m)
+    const int cap = ba.ends ? int(q.n) : int(q.n < q.m ? q.n : q.m);
+    seg_finish_body<false>(sh, res, sinfo, seg_args_of(ba, sp), fin, cap, plen);
 }
 
 __global__ __launch_bounds__(256) void seg_copy_batch_kernel(SegBatchArgs ba, int fin) {
@@ -552,10 +571,6 @@ __global__ __launch_bounds__(kThreads) void backtrace_packed_kernel(const uint8_
                          path_len);
 }
 
-// A subsequence end is usable when it is a column of the matrix that row 0
-// reaches at row n-1.
-__device__ inline bool sub_end_ok(int64_t n, int64_t m, int32_t e) { return e >= 0 && e < m && 2 * int64_t(e) >= n - 1; }
-
 __global__ __launch_bounds__(kThreads) void subseq_backtrace_kernel(const uint8_t* __restrict__ bp, int64_t n,
                                                                     int64_t m, const int32_t* __restrict__ end_col,
                                                                     int32_t* path, int32_t* path_len) {
@@ -573,6 +588,7 @@ __global__ __launch_bounds__(kThreads) void subseq_backtrace_batch_kernel(const 
     __shared__ BtShared sh;
     const int b = blockIdx.x;
     const BatchPair q = pairs[b];
+    if (q.split) return;  // walked by the split kernels
     const int32_t e = ends[b];
     backtrace_pair(sh, bpbase + q.bp_off, int(q.n), e, true, q.feasible && sub_end_ok(q.n, q.m, e), int(q.n),
                    paths + 2 * q.path_off, path_len + b);
@@ -665,6 +681,8 @@ pardtw_status seg_backtrace(const uint8_t* bp, int64_t n, int64_t m, const int32
     a.bp = bp;
     a.n = int(n);
     a.m = int(m);
+    a.end = int(m - 1);
+    a.sub = 0;
     seg_shape(n, a.R, a.S);
     if (a.S <= 2) {
         // a pair of at most 1024 rows: one workgroup walks it faster than
@@ -690,8 +708,8 @@ size_t split_record_bytes() { return sizeof(SegInfo); }
 
 pardtw_status split_backtrace_batch_launch(const BatchPair* pairs, const SegPair* sp, int32_t nsplit,
                                            const int32_t* seg_map, int32_t nseg, const uint8_t* bpbase,
-                                           const int32_t* status, void* records, int32_t* cells, int32_t* paths,
-                                           int32_t* path_len, hipStream_t stream) {
+                                           const int32_t* status, const int32_t* ends, void* records,
+                                           int32_t* cells, int32_t* paths, int32_t* path_len, hipStream_t stream) {
     if (nsplit <= 0 || nseg <= 0) return PARDTW_OK;
     SegBatchArgs ba;
     ba.pairs = pairs;
@@ -699,6 +717,7 @@ pardtw_status split_backtrace_batch_launch(const BatchPair* pairs, const SegPair
     ba.seg_map = seg_map;
     ba.bp = bpbase;
     ba.status = status;
+    ba.ends = ends;
     ba.info = reinterpret_cast<SegInfo*>(records);
     ba.cells = cells;
     ba.paths = paths;

@@ -74,17 +74,20 @@ pardtw_status backtrace_batch_launch(const BatchPair* pairs, int32_t batch, cons
 void split_shape(int64_t n, int& R, int& S);
 size_t split_record_bytes();  // one segment record
 // The split pairs' walks (nseg segments over nsplit pairs; seg_map[g] is the
-// SegPair of segment g). Pairs with split == 0 are left to backtrace_batch_launch.
+// SegPair of segment g). Pairs with split == 0 are left to backtrace_batch_launch
+// (DTW pairs, `ends` null, walked when status[pair] is OK) or to
+// subseq_backtrace_batch_launch (Segmental DTW fragments, walked from ends[pair]).
 pardtw_status split_backtrace_batch_launch(const BatchPair* pairs, const SegPair* sp, int32_t nsplit,
                                            const int32_t* seg_map, int32_t nseg, const uint8_t* bpbase,
-                                           const int32_t* status, void* records, int32_t* cells, int32_t* paths,
-                                           int32_t* path_len, hipStream_t stream);
+                                           const int32_t* status, const int32_t* ends, void* records,
+                                           int32_t* cells, int32_t* paths, int32_t* path_len, hipStream_t stream);
 
 pardtw_status grad_batch_launch(const BatchPair* pairs, int32_t batch, int64_t max_cap, int64_t d, const float* X,
                                 const float* Y, const int32_t* paths, const int32_t* path_len, const float* g,
                                 float* dX, int64_t dX_count, float* dY, int64_t dY_count, hipStream_t stream);
 
-// Fragment b walked from ends[b] to row 0 into its slot of n_b pairs at path_off.
+// Fragment b walked from ends[b] to row 0 into its slot of n_b pairs at path_off
+// (fragments with split set are left to split_backtrace_batch_launch).
 pardtw_status subseq_backtrace_batch_launch(const BatchPair* pairs, int32_t batch, const uint8_t* bpbase,
                                             const int32_t* ends, int32_t* paths, int32_t* path_len,
                                             hipStream_t stream);

@@ -387,7 +387,7 @@ extern "C" pardtw_status pardtw_align_batch(const pardtw_plan* plan, const float
     if (st != PARDTW_OK) return st;
     return pardtw::split_backtrace_batch_launch(plan->pairs_dev, plan->segpairs_dev, int32_t(plan->segpairs.size()),
                                                 plan->seg_map_dev, int32_t(plan->seg_map.size()), bp, pair_status,
-                                                ws + plan->off_split_rec,
+                                                nullptr, ws + plan->off_split_rec,
                                                 reinterpret_cast<int32_t*>(ws + plan->off_split_cells),
                                                 paths_packed, path_len, stream);
 }
@@ -510,7 +510,24 @@ extern "C" pardtw_status pardtw_segplan_create(int64_t la, int64_t lb, int32_t n
     pl->off_slots = pl->off_fstat + align_up(size_t(nfrag) * sizeof(int32_t));
     pl->off_flen = pl->off_slots + align_up(size_t(la) * 2 * sizeof(int32_t));
     pl->off_seg = pl->off_flen + align_up(size_t(nfrag) * sizeof(int32_t));
-    pl->ws_bytes = pl->off_seg + align_up(pardtw::segment_workspace_bytes_impl(nfrag, lb));
+    // fragments of more than two segments get the split walk, as subsequence
+    // paths from their ends
+    int64_t nrec = 0, ncells = 0;
+    for (int f = 0; f < nfrag; ++f) {
+        pardtw::BatchPair& q = pl->pairs[f];
+        int R, S;
+        pardtw::split_shape(q.n, R, S);
+        if (!q.feasible || S <= 2) continue;
+        q.split = 1;
+        const int32_t idx = int32_t(pl->segpairs.size());
+        pl->segpairs.push_back({f, R, S, int32_t(pl->seg_map.size()), nrec, ncells});
+        pl->seg_map.insert(pl->seg_map.end(), size_t(S), idx);
+        nrec += 2 * int64_t(S);
+        ncells += int64_t(S) * R * 2;
+    }
+    pl->off_split_rec = pl->off_seg + align_up(pardtw::segment_workspace_bytes_impl(nfrag, lb));
+    pl->off_split_cells = pl->off_split_rec + align_up(size_t(nrec) * pardtw::split_record_bytes());
+    pl->ws_bytes = pl->off_split_cells + align_up(size_t(ncells) * sizeof(int32_t));
     return finish_plan(pl, plan_out);
 }
 
@@ -561,9 +578,14 @@ extern "C" pardtw_status pardtw_segmental_align(const pardtw_plan* plan, const f
     if (st != PARDTW_OK) return st;
     int32_t* slots = reinterpret_cast<int32_t*>(ws + plan->off_slots);
     int32_t* flen = reinterpret_cast<int32_t*>(ws + plan->off_flen);
-    st = pardtw::subseq_backtrace_batch_launch(plan->pairs_dev, plan->batch,
-                                               reinterpret_cast<const uint8_t*>(ws + plan->off_bp), ends, slots,
-                                               flen, stream);
+    const uint8_t* bp = reinterpret_cast<const uint8_t*>(ws + plan->off_bp);
+    st = pardtw::subseq_backtrace_batch_launch(plan->pairs_dev, plan->batch, bp, ends, slots, flen, stream);
+    if (st != PARDTW_OK) return st;
+    st = pardtw::split_backtrace_batch_launch(plan->pairs_dev, plan->segpairs_dev, int32_t(plan->segpairs.size()),
+                                              plan->seg_map_dev, int32_t(plan->seg_map.size()), bp, nullptr, ends,
+                                              ws + plan->off_split_rec,
+                                              reinterpret_cast<int32_t*>(ws + plan->off_split_cells), slots, flen,
+                                              stream);
     if (st != PARDTW_OK) return st;
     return pardtw::segment_gather_launch(plan->pairs_dev, plan->batch, slots, flen, status, path, path_len, stream);
 }

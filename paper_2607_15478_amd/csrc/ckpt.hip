@@ -512,6 +512,8 @@ extern "C" pardtw_status pardtw_ckpt_backtrace_parallel(const float* X, const fl
     pardtw::SplitArgs sp;
     sp.n = int(n);
     sp.m = int(m);
+    sp.end = int(m - 1);
+    sp.sub = 0;
     pardtw::ck_seg_shape(n, rows_per_block, sp.R, sp.S);
     if (sp.S <= 2) {
         pardtw::ckpt_backtrace_kernel<<<1, pardtw::kCkThreads, 0, stream>>>(a);

@@ -3,12 +3,15 @@
 // matrix, or of its checkpointed form, gives the same path).
 //
 // Segment s of S holds the path's cells on rows (s R - 1, (s + 1) R - 1]
-// (segment 0 down to the origin). It starts at the first path cell on or
-// below its top row, which is where the segment above ends (a step moves at
-// most two rows, so every segment holds at least one cell).
-//   round 0: every segment walks from a guess on its top row (the diagonal
-//            through the corners, clamped to the band; the last segment from
-//            (n-1, m-1), exactly);
+// (segment 0 down to the origin, or for a subsequence path (Sec. II-B) down to
+// its start on row 0). It starts at the first path cell on or below its top
+// row, which is where the segment above ends (a step moves at most two rows,
+// so every segment holds at least one cell).
+//   round 0: every segment walks from a guess on its top row (DTW: the
+//            diagonal through the corners, clamped to the band; subsequence:
+//            the line of slope one into the end, clamped to the cells that
+//            row 0 reaches and that reach the end); the last segment starts
+//            exactly, at (n-1, m-1) or (n-1, end);
 //   round r: every segment walks again from where the segment above ended in
 //            round r - 1, unless it already started there;
 //   finish:  one workgroup checks, from the last segment down, that each
@@ -39,6 +42,8 @@ constexpr int kSegMaxCount = 256;  // segments of one walk at most
 
 struct SplitArgs {
     int n, m;
+    int end;  // the path's last column: m - 1 for DTW, the chosen end for a subsequence path
+    int sub;  // nonzero: a subsequence path, walked back to row 0
     int R, S;
     SegInfo* info;   // [2][S]: rounds alternate between the halves
     int32_t* cells;  // [S][R][2]: segment s's cells from its start backward
@@ -55,6 +60,20 @@ __device__ inline int seg_guess_col(int i, int n, int m) {
     const int64_t lo = lo1 > lo2 ? lo1 : lo2, hi = hi1 < hi2 ? hi1 : hi2;
     const int64_t c = jd < lo ? lo : jd > hi ? hi : jd;
     return int(c < 0 ? 0 : c > m - 1 ? m - 1 : c);
+}
+
+// A guess on row i for a subsequence path ending at (n-1, end): the line of
+// slope one into the end, clamped to the cells that row 0 reaches (at least
+// ceil(i/2) columns in) and that reach the end (1 to 2 columns per row).
+__device__ inline int seg_guess_col_sub(int i, int n, int end) {
+    const int64_t di = int64_t(n - 1 - i);
+    const int64_t lo1 = (i + 1) / 2, lo2 = int64_t(end) - 2 * di;
+    const int64_t hi = int64_t(end) - (di + 1) / 2;
+    const int64_t lo = lo1 > lo2 ? lo1 : lo2;
+    int64_t c = int64_t(end) - di;
+    c = c < lo ? lo : c;
+    c = c > hi ? hi : c;
+    return int(c < 0 ? 0 : c > end ? end : c);
 }
 
 __device__ inline SegInfo seg_info(int si, int sj, int ei, int ej, int len) {
@@ -79,10 +98,10 @@ __device__ void split_round(const SplitArgs& a, int s, int round, Walk&& walk) {
     int si, sj;
     if (s == a.S - 1) {
         si = a.n - 1;
-        sj = a.m - 1;
+        sj = a.end;
     } else if (round == 0) {
         si = (s + 1) * a.R - 1;
-        sj = seg_guess_col(si, a.n, a.m);
+        sj = a.sub ? seg_guess_col_sub(si, a.n, a.end) : seg_guess_col(si, a.n, a.m);
     } else {
         const SegInfo up = prev[s + 1];
         si = up.ei;
@@ -107,7 +126,7 @@ __device__ void split_finish(const SplitArgs& a, SegInfo* sinfo, int fin, int ca
     SegInfo* info = a.info + fin * a.S;
     for (int k = tid; k < a.S; k += int(blockDim.x)) sinfo[k] = info[k];
     __syncthreads();
-    int si = a.n - 1, sj = a.m - 1;
+    int si = a.n - 1, sj = a.end;
     for (int s = a.S - 1; s >= 0; --s) {
         SegInfo me = sinfo[s];
         if (me.si != si || me.sj != sj || me.len <= 0) {

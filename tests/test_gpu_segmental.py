@@ -485,3 +485,33 @@ def test_segmental_deviation_from_exact_dtw(nf):
     assert abs(got["max_dev_frames"] - ref["max_dev_frames"]) <= 1.0
     # on this tempo-warped copy both methods follow the warp closely
     assert got["rows_within_10_frames"] == 1.0
+
+
+@pytest.mark.parametrize("fused", [False, True])
+@pytest.mark.parametrize("la,lb,nf", [(5000, 6000, 1), (3000, 3600, 2), (6000, 5000, 3), (4100, 9000, 2)])
+def test_segmental_split_walk_equals_one_workgroup_walk(la, lb, nf, fused):
+    """Fragments of more than two 512-row segments are walked by the split
+    walk (many workgroups, then an exact check). Each fragment's path equals,
+    cell for cell, the one-workgroup subsequence walk over the same codes:
+    the fragment's costs from the cost GEMM (the plan's, bit for bit), its
+    subsequence DP and pardtw_subseq_backtrace from the plan's end."""
+    (A, B), _ = _pair(la + nf, la, lb)
+    Ad, Bd = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+    plan = pd.SegPlan(la, lb, nf, 12, pd.PREC_F32, pd.WSDTW, fused)
+    buf = plan.buffers(DEV)
+    plan.align(Ad, Bd, buf)
+    torch.cuda.synchronize()
+    assert int(buf["status"].item()) == pd.PAIR_OK
+    ends = buf["ends"].cpu().numpy()
+    path = buf["path"][: int(buf["path_len"].item())].cpu().numpy()
+    starts = plan.starts
+    for f in range(nf):
+        r0, r1 = starts[f], starts[f + 1]
+        n_f = r1 - r0
+        C = torch.empty(pd.pardtw_cost_elems(n_f, lb, pd.LAYOUT_ROW), dtype=torch.float32, device=DEV)
+        pd.pardtw_cost(Ad[r0:r1].contiguous(), Bd, C, pd.PREC_F32, pd.LAYOUT_ROW)
+        torch.cuda.synchronize()
+        _, status, _, bp = _gpu_subseq(C.cpu().numpy().reshape(n_f, lb))
+        ref = _gpu_subseq_path(bp, n_f, lb, int(ends[f]))
+        got = path[(path[:, 0] >= r0) & (path[:, 0] < r1)] - np.array([r0, 0])
+        assert len(ref) > 0 and np.array_equal(got, ref), f"fragment {f}"
