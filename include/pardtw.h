@@ -556,7 +556,8 @@ int64_t pardtw_segplan_fragment_start(const pardtw_plan* plan, int32_t f);
 /* Segmental DTW with one call: the cost GEMM of every fragment against B (only
  * the subsequence band), the subsequence DP of all fragments as one persistent
  * launch, the segment-level program, the fragments' backtraces (one workgroup
- * each) and their concatenation. No allocation, copy or synchronisation; it
+ * each, or the split walk of pardtw_backtrace_parallel for a fragment of more
+ * than 1024 rows; the same paths) and their concatenation. No allocation, copy or synchronisation; it
  * can be captured in a hipGraph.
  *   A [device, la*d FP32], B [device, lb*d FP32].
  *   total [device, 1 float], ends [device, nfrag int32], status [device, 1
