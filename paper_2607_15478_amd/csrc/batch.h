@@ -62,9 +62,9 @@ pardtw_status dp_batch_launch(const BatchPair* pairs, const DpItem* items, int32
                               hipStream_t stream);
 
 // Row norms of every feasible pair for the fused batched DP (rx_floats(n_b)
-// floats at rx_off each).
-pardtw_status row_norms_batch_launch(const BatchPair* pairs, int32_t batch, const float* X, int64_t d, float* rxs,
-                                     hipStream_t stream);
+// floats at rx_off each); max_n is the largest n_b.
+pardtw_status row_norms_batch_launch(const BatchPair* pairs, int32_t batch, int64_t max_n, const float* X,
+                                     int64_t d, float* rxs, hipStream_t stream);
 
 pardtw_status backtrace_batch_launch(const BatchPair* pairs, int32_t batch, const uint8_t* bpbase,
                                      const int32_t* status, int32_t* paths, int32_t* path_len, hipStream_t stream);

@@ -67,7 +67,7 @@ struct pardtw_plan {
     std::vector<Schedule> scheds;
     int chosen = 0;
     size_t off_c = 0, off_bp = 0, off_dp = 0, ws_bytes = 0;
-    int64_t path_capacity = 0, max_cap = 0, x_rows = 0, y_rows = 0;
+    int64_t path_capacity = 0, max_cap = 0, max_n = 0, x_rows = 0, y_rows = 0;
     // split backtraces of the long pairs: their segments and the workspace
     // region of their segment records and cells
     std::vector<pardtw::SegPair> segpairs;
@@ -138,8 +138,8 @@ pardtw_status run_dp(const pardtw_plan& pl, const Schedule& s, char* ws, const f
 pardtw_status run_front(const pardtw_plan& pl, const float* X, const float* Y, char* ws, hipStream_t stream) {
     if (pl.fused && pl.prec == PARDTW_PREC_BF16) return PARDTW_OK;
     if (pl.fused)
-        return pardtw::row_norms_batch_launch(pl.pairs_dev, pl.batch, X, pl.d, reinterpret_cast<float*>(ws + pl.off_rx),
-                                              stream);
+        return pardtw::row_norms_batch_launch(pl.pairs_dev, pl.batch, pl.max_n, X, pl.d,
+                                              reinterpret_cast<float*>(ws + pl.off_rx), stream);
     return pardtw::cost_batch_launch(pl.pairs_dev, pl.tile_pair_dev, pl.tiles, X, Y, pl.d, pl.prec,
                                      reinterpret_cast<float*>(ws + pl.off_c), stream);
 }
@@ -308,6 +308,7 @@ extern "C" pardtw_status pardtw_plan_create_ex(int32_t batch, const int64_t* n_h
         yr += m;
         po += cap;
         pl->max_cap = std::max(pl->max_cap, cap);
+        pl->max_n = std::max(pl->max_n, n);
     }
     pl->x_rows = xr;
     pl->y_rows = yr;
@@ -494,6 +495,7 @@ extern "C" pardtw_status pardtw_segplan_create(int64_t la, int64_t lb, int32_t n
         place_pair(q, r1 - r0, lb, pardtw::subseq_feasible(r1 - r0, lb), 2, pl->fused, c_floats, bp_bytes, rec_bytes,
                    rx_total, tiles);
         pl->max_cap = std::max(pl->max_cap, r1 - r0);
+        pl->max_n = std::max(pl->max_n, r1 - r0);
     }
     pl->x_rows = la;
     pl->y_rows = lb;

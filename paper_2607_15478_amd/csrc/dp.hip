@@ -938,13 +938,14 @@ __global__ __launch_bounds__(kLanes * dp_waves(NW, SRC)) void dp_batch_kernel(Dp
     }
 }
 
-// Row norms of pair b (block b) for the fused batched DP.
+// Row norms of pair b for the fused batched DP: blocks (b, y) for y <
+// gridDim.y share the pair's rows, so one long pair is not left to one block.
 __global__ void row_norms_batch_kernel(const BatchPair* __restrict__ pairs, const float* __restrict__ X, int64_t d,
                                        float* rxs) {
     const BatchPair q = pairs[blockIdx.x];
     if (!q.feasible) return;
     const int64_t len = rx_floats(q.n);
-    for (int64_t i = threadIdx.x; i < len; i += blockDim.x)
+    for (int64_t i = int64_t(blockIdx.y) * blockDim.x + threadIdx.x; i < len; i += int64_t(gridDim.y) * blockDim.x)
         rxs[q.rx_off + i] = row_inv_norm_f32_small(X + q.x_off * d, q.n, d, i);
 }
 
@@ -1065,10 +1066,12 @@ pardtw_status dp_batch_launch(const BatchPair* pairs, const DpItem* items, int32
     return launch_status();
 }
 
-pardtw_status row_norms_batch_launch(const BatchPair* pairs, int32_t batch, const float* X, int64_t d, float* rxs,
-                                     hipStream_t stream) {
+pardtw_status row_norms_batch_launch(const BatchPair* pairs, int32_t batch, int64_t max_n, const float* X,
+                                     int64_t d, float* rxs, hipStream_t stream) {
     if (batch <= 0) return PARDTW_OK;
-    row_norms_batch_kernel<<<unsigned(batch), 256, 0, stream>>>(pairs, X, d, rxs);
+    const int64_t per = ceil_div(rx_floats(max_n > 0 ? max_n : 1), int64_t(256));
+    const dim3 grid(unsigned(batch), unsigned(per < 64 ? per : 64));
+    row_norms_batch_kernel<<<grid, 256, 0, stream>>>(pairs, X, d, rxs);
     return launch_status();
 }
 
