@@ -257,7 +257,11 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
     const float kInf = __builtin_inff();
     const int bcol = lane - (kLanes - 2);  // 0 / 1 on the two boundary lanes
     uint64_t* bp_pan = reinterpret_cast<uint64_t*>(a.bp) + int64_t(p) * G * kLanes;
-    uint64_t* cptr = bp_pan + int64_t(k0) * kLanes;
+    // the code store of chunk k0, advanced one chunk per chunk (8 bytes per
+    // lane, or 2 with packed codes)
+    uint64_t* cptr = is_packed(SRC) ? reinterpret_cast<uint64_t*>(reinterpret_cast<uint16_t*>(a.bp) +
+                                                                   (int64_t(p) * G + k0) * kLanes)
+                                    : bp_pan + int64_t(k0) * kLanes;
     const float* rin = &sh.ring[wave][0][0][0];
     float* rout = &sh.ring[wave + 1][0][0][0];
     // a boundary lane's column in the output ring (slot 0); other lanes write
@@ -401,8 +405,8 @@ __device__ __attribute__((always_inline)) inline void compute_wave(const DpArgs&
                 }
             } else if constexpr (kPack) {
                 // one 16-bit word per lane: 128 bytes per chunk
-                uint16_t* cdst = inside ? reinterpret_cast<uint16_t*>(a.bp) + (int64_t(p) * G + k) * kLanes
-                                        : reinterpret_cast<uint16_t*>(a.hdr->sink);
+                uint16_t* cdst = inside ? reinterpret_cast<uint16_t*>(cptr) : reinterpret_cast<uint16_t*>(a.hdr->sink);
+                cptr = reinterpret_cast<uint64_t*>(reinterpret_cast<uint16_t*>(cptr) + kLanes);
                 __builtin_nontemporal_store(uint16_t(lo), cdst + lane);
             } else {
                 uint64_t* cdst = inside ? cptr : a.hdr->sink;

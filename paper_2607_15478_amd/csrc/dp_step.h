@@ -50,12 +50,21 @@ __device__ __attribute__((always_inline)) inline void dp_rows(const float (&cb)[
         const float best = __builtin_fminf(__builtin_fminf(c0, c1), c2);
         uint32_t code = (c1 == best) ? 1u : 2u;
         code = (c0 == best) ? 0u : code;
-        if (PACK) lo |= code << (2 * r);
-        else if (r < 4) lo |= code << (8 * r);
+        // packed: 2 bits per row, rows 4-7 gathered apart and joined after
+        // the loop, which keeps the OR chains short enough for the compiler
+        // to interleave the code selection with the row arithmetic
+        if (PACK) {
+            if (r < 4) lo |= code << (2 * r);
+            else hi |= code << (2 * r);
+        } else if (r < 4) lo |= code << (8 * r);
         else hi |= code << (8 * (r - 4));
         d1 = best;
         s1p = s1;
         best_r[r] = best;
+    }
+    if (PACK) {
+        lo |= hi;
+        hi = 0;
     }
 }
 
