@@ -488,13 +488,16 @@ def test_segmental_deviation_from_exact_dtw(nf):
 
 
 @pytest.mark.parametrize("fused", [False, True])
-@pytest.mark.parametrize("la,lb,nf", [(5000, 6000, 1), (3000, 3600, 2), (6000, 5000, 3), (4100, 9000, 2)])
+@pytest.mark.parametrize("la,lb,nf", [(5000, 6000, 1), (3000, 3600, 2), (6000, 5000, 3), (4100, 9000, 2),
+                                      (2049, 2400, 2)])
 def test_segmental_split_walk_equals_one_workgroup_walk(la, lb, nf, fused):
     """Fragments of more than two 512-row segments are walked by the split
     walk (many workgroups, then an exact check). Each fragment's path equals,
     cell for cell, the one-workgroup subsequence walk over the same codes:
     the fragment's costs from the cost GEMM (the plan's, bit for bit), its
-    subsequence DP and pardtw_subseq_backtrace from the plan's end."""
+    subsequence DP and pardtw_subseq_backtrace from the plan's end.
+    (2049 rows in two fragments: 1024 rows, walked by one workgroup, beside
+    1025, split.)"""
     (A, B), _ = _pair(la + nf, la, lb)
     Ad, Bd = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
     plan = pd.SegPlan(la, lb, nf, 12, pd.PREC_F32, pd.WSDTW, fused)
