@@ -959,6 +959,154 @@ __global__ void row_norms_batch_kernel(const BatchPair* __restrict__ pairs, cons
         rxs[q.rx_off + i] = row_inv_norm_f32_small(X + q.x_off * d, q.n, d, i);
 }
 
+// Segmental DTW with short fragments (at most kSweepRows rows, FP32 fused
+// costs, d <= 16): one wave sweeps a whole fragment, panel after panel from
+// the left, each panel's chunks top to bottom. A fragment of 100 rows spans
+// 13 chunks per panel, too few to pay for the handoffs and producer start-up
+// of the staircase sweep; here nothing is handed between waves. The
+// fragment's row operands and row norms stay in LDS for the whole sweep and
+// the next panel's column operands are loaded during the current one. The
+// costs, the row step and the codes are those of the fused batched DP (the
+// same slab code and row norms, the same dp_rows), so scores, codes and
+// statuses are bit for bit the same. All of the fragment's chunks are swept:
+// cells outside the subsequence band get exact values, which the band's
+// argument makes irrelevant.
+constexpr int kSweepRows = 256;
+
+struct alignas(16) SweepShared {
+    float xs[kSweepRows][16];           // row operands, zero past d and n
+    float rx[kSweepRows + 16];          // row inverse norms, zero padded
+    float bnd[2][2][kSweepRows];        // columns 64p-2 and 64p-1 of the panel to the left, double buffered
+    float cs[2][kChunk * kLanes];       // one slab's costs (two chunks) in the panel layout
+};
+
+struct FragSweepArgs {
+    const BatchPair* pairs;
+    const float* X;
+    const float* Y;
+    const float* rxs;
+    int64_t d;
+    uint8_t* bp;
+    float* totals;   // [fragment][m] scores
+    int32_t* status;
+};
+
+__global__ __launch_bounds__(kLanes) void frag_sweep_kernel(FragSweepArgs a) {
+    __shared__ SweepShared sh;
+    const int lane = threadIdx.x;
+    const int b = blockIdx.x;
+    const BatchPair q = a.pairs[b];
+    if (!q.feasible) return;  // scores and status set by the segment level's init
+    const int n = int(q.n), G = int(q.G), P = q.P;
+    const int64_t m = q.m, d = a.d;
+    const float* X = a.X + q.x_off * d;
+    const float* Y = a.Y + q.y_off * d;
+    const float* rxs = a.rxs + q.rx_off;
+    const float kInf = __builtin_inff();
+    // rows of the fragment (and zero padding up to a whole slab)
+    const int rows = ((G + 1) / 2) * 16;
+    for (int e = lane; e < rows * 16; e += kLanes) {
+        const int i = e >> 4, k = e & 15;
+        sh.xs[i][k] = (i < n && k < d) ? X[int64_t(i) * d + k] : 0.0f;
+    }
+    for (int i = lane; i < rows; i += kLanes) sh.rx[i] = i < n ? rxs[i] : 0.0f;
+    for (int i = lane; i < G * kChunk; i += kLanes) {
+        sh.bnd[0][0][i] = kInf;
+        sh.bnd[0][1][i] = kInf;
+    }
+    const int g = lane >> 4;
+    const int kq = lane >> 5, half = (lane >> 4) & 1, tcol = lane & 15;
+    const int bcol = lane - (kLanes - 2);  // 0 / 1 on the two boundary lanes
+    const int rlast = (n - 1) % kChunk;
+    // the first panel's column operands
+    float yn[4][4];
+    auto load_panel = [&](int p, float (&yv)[4][4]) {
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+            const int64_t col = int64_t(p) * kPanel + bb * 16 + (lane & 15);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int64_t k = 4 * t + g;
+                yv[bb][t] = (p < P && col < m && k < d) ? Y[col * d + k] : 0.0f;
+            }
+        }
+    };
+    load_panel(0, yn);
+    __syncthreads();
+    int cur = 0;
+    for (int p = 0; p < P; ++p) {
+        // this panel's column operands and norms, as panel_operands_f32_small
+        float bv[4][4], ry[4];
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+            float sq = 0.0f;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                bv[bb][t] = yn[bb][t];
+                sq = __builtin_fmaf(bv[bb][t], bv[bb][t], sq);
+            }
+            ry[bb] = inv_from_sq(sum_groups(sq));
+        }
+        load_panel(p + 1, yn);  // in flight during this panel
+        const int nxt = cur ^ 1;
+        float d1 = kInf, s1p = kInf, e0 = kInf, e1 = kInf, dlast = kInf;
+        for (int k = 0; k < G; k += 2) {
+            // the slab of chunks k and k + 1
+            {
+                float av[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) av[t] = sh.xs[8 * k + (lane & 15)][4 * t + g];
+                const f32x4 rx4 = *reinterpret_cast<const f32x4*>(&sh.rx[8 * k + 4 * g]);
+                f32x4 acc[4], v[4];
+                slab_acc_f32_small(d, av, bv, acc);
+                costs_from_acc_rx(acc, rx4, ry, v);
+                float* dst = &sh.cs[kq][half * (kLanes * 4)];
+#pragma unroll
+                for (int bb = 0; bb < 4; ++bb) *reinterpret_cast<f32x4*>(dst + (bb * 16 + tcol) * 4) = v[bb];
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int kk = k + u;
+                if (kk >= G) break;
+                float cb[kChunk], lv0[kChunk], lv1[kChunk];
+                {
+                    const f32x4* src = reinterpret_cast<const f32x4*>(&sh.cs[u][0]) + lane;
+                    const f32x4 c0 = src[0], c1 = src[kLanes];
+                    cb[0] = c0[0]; cb[1] = c0[1]; cb[2] = c0[2]; cb[3] = c0[3];
+                    cb[4] = c1[0]; cb[5] = c1[1]; cb[6] = c1[2]; cb[7] = c1[3];
+                }
+#pragma unroll
+                for (int r = 0; r < kChunk; ++r) {
+                    lv0[r] = sh.bnd[cur][0][kChunk * kk + r];
+                    lv1[r] = sh.bnd[cur][1][kChunk * kk + r];
+                }
+                // row 0 of the fragment: every cell a start, fma(2, C, -C) = C
+                if (kk == 0) s1p = -cb[0];
+                uint32_t lo, hi;
+                float best_r[kChunk];
+                dp_rows<true, false>(cb, lv0, lv1, e0, e1, d1, s1p, lo, hi, best_r);
+                if (kk == 0) lo = (lo & ~0xffu) | 3u;
+                e0 = lv0[kChunk - 1];
+                e1 = lv1[kChunk - 1];
+                uint64_t* cdst = reinterpret_cast<uint64_t*>(a.bp + q.bp_off) + (int64_t(p) * G + kk) * kLanes;
+                cdst[lane] = uint64_t(lo) | (uint64_t(hi) << 32);
+                if (bcol >= 0) {
+#pragma unroll
+                    for (int r = 0; r < kChunk; ++r) sh.bnd[nxt][bcol][kChunk * kk + r] = best_r[r];
+                }
+                if (kk == G - 1) {
+#pragma unroll
+                    for (int r = 0; r < kChunk; ++r) dlast = (r == rlast) ? best_r[r] : dlast;
+                }
+            }
+        }
+        const int64_t col = int64_t(p) * kPanel + lane;
+        if (col < m) a.totals[int64_t(b) * m + col] = dlast;
+        if (col == m - 1) a.status[b] = dlast == kInf ? PARDTW_PAIR_INFEASIBLE : PARDTW_PAIR_OK;
+        cur = nxt;
+    }
+}
+
 // Row inverse norms for the fused producers (zeros past n, up to len).
 __global__ void row_norms_kernel(const float* __restrict__ X, int64_t n, int64_t d, float* rxs, int64_t len) {
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < len; i += int64_t(gridDim.x) * blockDim.x)
@@ -1073,6 +1221,26 @@ pardtw_status dp_batch_launch(const BatchPair* pairs, const DpItem* items, int32
         case 8: launch_batch_nw<8>(a, fused, bf16, sub, grid, stream); break;
         default: return PARDTW_ERR_UNSUPPORTED;
     }
+    return launch_status();
+}
+
+int64_t frag_sweep_max_rows() { return kSweepRows; }
+
+pardtw_status frag_sweep_launch(const BatchPair* pairs, int32_t nfrag, int64_t max_n, const float* X,
+                                const float* Y, int64_t d, const float* rxs, uint8_t* bpbase, float* totals,
+                                int32_t* status, hipStream_t stream) {
+    if (nfrag <= 0) return PARDTW_OK;
+    if (max_n > kSweepRows || d > 16 || !X || !Y || !rxs) return PARDTW_ERR_UNSUPPORTED;
+    FragSweepArgs a;
+    a.pairs = pairs;
+    a.X = X;
+    a.Y = Y;
+    a.rxs = rxs;
+    a.d = d;
+    a.bp = bpbase;
+    a.totals = totals;
+    a.status = status;
+    frag_sweep_kernel<<<unsigned(nfrag), kLanes, 0, stream>>>(a);
     return launch_status();
 }
 

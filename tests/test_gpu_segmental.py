@@ -319,10 +319,16 @@ def test_segmental_infeasible_and_reuse():
         _check_segmental(A2, B2, 4, pd.WSDTW, plan, buf)
 
 
-def test_segmental_schedules_identical():
-    la, lb, nf = 1200, 2000, 6
-    (A, B), _ = _pair(12, la, lb)
-    plan = pd.SegPlan(la, lb, nf, 12)
+@pytest.mark.parametrize("la,lb,nf,fused", [(1200, 2000, 6, False), (1200, 2000, 6, True), (2500, 3000, 25, True),
+                                            (2000, 1500, 9, True)])
+def test_segmental_schedules_identical(la, lb, nf, fused):
+    """Every schedule of a plan gives the same scores, ends and path, bit for
+    bit. Fused plans of fragments of at most 256 rows include the schedule
+    of one wave per fragment (panels_per_workgroup 0)."""
+    (A, B), _ = _pair(12 + nf, la, lb)
+    plan = pd.SegPlan(la, lb, nf, 12, pd.PREC_F32, pd.WSDTW, fused)
+    if fused:
+        assert any(plan.schedule(s)["panels_per_workgroup"] == 0 for s in range(plan.num_schedules))
     buf = plan.buffers(DEV)
     Ad, Bd = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
     outs = []
