@@ -61,16 +61,17 @@ pardtw_status dp_batch_launch(const BatchPair* pairs, const DpItem* items, int32
                               bool bf16, uint8_t* bpbase, float* totals, int32_t* status, void* dp_ws, bool sub,
                               hipStream_t stream);
 
-// Row norms of every feasible pair for the fused batched DP (rx_floats(n_b)
-// floats at rx_off each); max_n is the largest n_b.
 // Segmental DTW fragments of at most frag_sweep_max_rows() rows (fused FP32
-// costs, d <= 16): one wave per fragment sweeps all of its panels, with the
-// batched DP's arithmetic (the same scores, codes and statuses).
+// costs, d <= 16): one workgroup per fragment sweeps all of its panels, its
+// `waves` waves (1, 2 or 4) taking them in turn, with the batched DP's
+// arithmetic (the same scores, codes and statuses).
 int64_t frag_sweep_max_rows();
-pardtw_status frag_sweep_launch(const BatchPair* pairs, int32_t nfrag, int64_t max_n, const float* X,
+pardtw_status frag_sweep_launch(const BatchPair* pairs, int32_t nfrag, int64_t max_n, int waves, const float* X,
                                 const float* Y, int64_t d, const float* rxs, uint8_t* bpbase, float* totals,
                                 int32_t* status, hipStream_t stream);
 
+// Row norms of every feasible pair for the fused batched DP (rx_floats(n_b)
+// floats at rx_off each); max_n is the largest n_b.
 pardtw_status row_norms_batch_launch(const BatchPair* pairs, int32_t batch, int64_t max_n, const float* X,
                                      int64_t d, float* rxs, hipStream_t stream);
 

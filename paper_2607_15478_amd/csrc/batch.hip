@@ -30,9 +30,9 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Schedule {
-    int nw;          // panels per workgroup; 0: one wave per fragment (frag_sweep_launch)
+    int nw;          // panels per workgroup; 0: one workgroup per fragment (frag_sweep_launch)
     int order;       // 0 breadth, 1 depth
-    int grid_mul;    // resident workgroups per CU, relative to the NW default
+    int grid_mul;    // resident workgroups per CU, relative to the NW default; nw 0: waves per fragment
     int32_t nitems;
     int64_t items_at;  // first item in the plan's item array
 };
@@ -128,7 +128,7 @@ pardtw_status run_dp(const pardtw_plan& pl, const Schedule& s, char* ws, const f
         status = reinterpret_cast<int32_t*>(ws + pl.off_fstat);
     }
     if (s.nw == 0)
-        return pardtw::frag_sweep_launch(pl.pairs_dev, int32_t(pl.batch), pl.max_n, X, Y, pl.d,
+        return pardtw::frag_sweep_launch(pl.pairs_dev, int32_t(pl.batch), pl.max_n, s.grid_mul, X, Y, pl.d,
                                          reinterpret_cast<const float*>(ws + pl.off_rx),
                                          reinterpret_cast<uint8_t*>(ws + pl.off_bp), totals, status, stream);
     return pardtw::dp_batch_launch(pl.pairs_dev, pl.items_dev + s.items_at, s.nitems, s.nw, grid_for(pl, s),
@@ -224,11 +224,12 @@ pardtw_status finish_plan(pardtw_plan* pl, pardtw_plan** plan_out) {
     for (size_t s = 0; s < pl->scheds.size(); ++s)
         if (pl->scheds[s].nw == nw_default && pl->scheds[s].order == 0 && pl->scheds[s].grid_mul == 1)
             pl->chosen = int(s);
-    // Segmental DTW with short fragments and fused FP32 costs: also one wave
-    // per fragment sweeping all of its panels (no handoffs between waves)
+    // Segmental DTW with short fragments and fused FP32 costs: also one
+    // workgroup per fragment sweeping all of its panels, with 1, 2 or 4 waves
+    // taking them in turn (no handoffs between workgroups)
     if (pl->mode == 1 && pl->fused && pl->prec == PARDTW_PREC_F32 && pl->d <= 16 &&
         pl->max_n <= pardtw::frag_sweep_max_rows())
-        pl->scheds.push_back({0, 0, 1, 0, 0});
+        for (int waves : {1, 2, 4}) pl->scheds.push_back({0, 0, waves, 0, 0});
     if (all_items.empty()) all_items.push_back({0, 0});
 
     bool ok = hipMalloc(&pl->pairs_dev, sizeof(pardtw::BatchPair) * batch) == hipSuccess &&
@@ -364,7 +365,7 @@ extern "C" pardtw_status pardtw_plan_schedule(const pardtw_plan* plan, int32_t i
     if (!plan || index < -1 || index >= int32_t(plan->scheds.size())) return PARDTW_ERR_INVALID_ARG;
     const Schedule& s = plan->scheds[index < 0 ? plan->chosen : index];
     if (panels_per_workgroup) *panels_per_workgroup = s.nw;
-    if (order) *order = s.order;
+    if (order) *order = s.nw == 0 ? s.grid_mul : s.order;
     if (workgroups) *workgroups = s.nw == 0 ? grid_for(*plan, s) : std::min(grid_for(*plan, s), std::max(s.nitems, 1));
     return PARDTW_OK;
 }

@@ -960,25 +960,37 @@ __global__ void row_norms_batch_kernel(const BatchPair* __restrict__ pairs, cons
 }
 
 // Segmental DTW with short fragments (at most kSweepRows rows, FP32 fused
-// costs, d <= 16): one wave sweeps a whole fragment, panel after panel from
-// the left, each panel's chunks top to bottom. A fragment of 100 rows spans
-// 13 chunks per panel, too few to pay for the handoffs and producer start-up
-// of the staircase sweep; here nothing is handed between waves. The
-// fragment's row operands and row norms stay in LDS for the whole sweep and
-// the next panel's column operands are loaded during the current one. The
-// costs, the row step and the codes are those of the fused batched DP (the
-// same slab code and row norms, the same dp_rows), so scores, codes and
-// statuses are bit for bit the same. All of the fragment's chunks are swept:
-// cells outside the subsequence band get exact values, which the band's
-// argument makes irrelevant.
+// costs, d <= 16): one workgroup sweeps a whole fragment, each panel's chunks
+// top to bottom. A fragment of 100 rows spans 13 chunks per panel, too few to
+// pay for the handoffs and producer start-up of the staircase sweep. The
+// workgroup's W waves take the panels in turn (wave w: panels w, w + W, ...),
+// so that several waves share each SIMD and hide each other's latency; the
+// two boundary columns of a panel pass to the next wave through LDS, chunk by
+// chunk, with a count of finished chunks per wave. The fragment's row
+// operands and norms stay in LDS for the whole sweep and each wave loads its
+// next panel's column operands during the current one. The costs, the row
+// step and the codes are those of the fused batched DP (the same slab code and
+// row norms, the same dp_rows), so scores, codes and statuses are bit for bit
+// the same. All of the fragment's chunks are swept: cells outside the
+// subsequence band get exact values, which the band's argument makes
+// irrelevant.
 constexpr int kSweepRows = 256;
 
-struct alignas(16) SweepShared {
-    float xs[kSweepRows][16];           // row operands, zero past d and n
-    float rx[kSweepRows + 16];          // row inverse norms, zero padded
-    float bnd[2][2][kSweepRows];        // columns 64p-2 and 64p-1 of the panel to the left, double buffered
-    float cs[2][kChunk * kLanes];       // one slab's costs (two chunks) in the panel layout
-};
+// LDS of one workgroup, sized at launch for R rows (the longest fragment's,
+// rounded up to a whole 16-row slab), in this order:
+//   cs   [W][2][kChunk * kLanes] each wave's slab costs (two chunks), panel layout
+//   xs   [R][16]                 row operands, zero past d and n
+//   rx   [R + 16]                row inverse norms, zero padded
+//   bnd  [slots][2][R]           columns 64p-2 and 64p-1 of the panel to the left;
+//                                slot w is written by wave w (one wave: two
+//                                slots, used in turn)
+//   done [W]                     chunks finished per wave
+constexpr int sweep_slots(int W) { return W == 1 ? 2 : W; }
+inline int sweep_rows(int64_t max_n) { return int((bp_groups(max_n) + 1) / 2) * 16; }
+constexpr size_t sweep_lds_bytes(int W, int R) {
+    return sizeof(float) * (size_t(W) * 2 * kChunk * kLanes + size_t(R) * 16 + R + 16 +
+                            size_t(sweep_slots(W)) * 2 * R) + sizeof(int) * W;
+}
 
 struct FragSweepArgs {
     const BatchPair* pairs;
@@ -989,11 +1001,26 @@ struct FragSweepArgs {
     uint8_t* bp;
     float* totals;   // [fragment][m] scores
     int32_t* status;
+    int R;           // rows of the LDS arrays
 };
 
-__global__ __launch_bounds__(kLanes) void frag_sweep_kernel(FragSweepArgs a) {
-    __shared__ SweepShared sh;
-    const int lane = threadIdx.x;
+// Slot reuse needs no flag of its own: wave w writes rows of chunk c of slot
+// w for panel p only after the wave before it finished chunk c of panel p-1,
+// which (around the ring of W waves) implies that wave w+1 finished chunk c of
+// panel p-W+1, the last reader of the slot's previous contents. A wave reads
+// only its own chunk's rows of a slot; the two rows above come in registers.
+template <int W>
+__global__ __launch_bounds__(kLanes * W, 3) void frag_sweep_kernel(FragSweepArgs a) {
+    extern __shared__ f32x4 sweep_lds[];
+    const int R = a.R;
+    float* const cs = reinterpret_cast<float*>(sweep_lds);
+    float* const xs = cs + W * 2 * kChunk * kLanes;
+    float* const rxl = xs + R * 16;
+    float* const bnd = rxl + R + 16;
+    int* const done_l = reinterpret_cast<int*>(bnd + sweep_slots(W) * 2 * R);
+    const int tid = threadIdx.x;
+    const int lane = tid & (kLanes - 1);
+    const int w = tid / kLanes;
     const int b = blockIdx.x;
     const BatchPair q = a.pairs[b];
     if (!q.feasible) return;  // scores and status set by the segment level's init
@@ -1005,15 +1032,18 @@ __global__ __launch_bounds__(kLanes) void frag_sweep_kernel(FragSweepArgs a) {
     const float kInf = __builtin_inff();
     // rows of the fragment (and zero padding up to a whole slab)
     const int rows = ((G + 1) / 2) * 16;
-    for (int e = lane; e < rows * 16; e += kLanes) {
+    for (int e = tid; e < rows * 16; e += kLanes * W) {
         const int i = e >> 4, k = e & 15;
-        sh.xs[i][k] = (i < n && k < d) ? X[int64_t(i) * d + k] : 0.0f;
+        xs[i * 16 + k] = (i < n && k < d) ? X[int64_t(i) * d + k] : 0.0f;
     }
-    for (int i = lane; i < rows; i += kLanes) sh.rx[i] = i < n ? rxs[i] : 0.0f;
-    for (int i = lane; i < G * kChunk; i += kLanes) {
-        sh.bnd[0][0][i] = kInf;
-        sh.bnd[0][1][i] = kInf;
+    for (int i = tid; i < rows; i += kLanes * W) rxl[i] = i < n ? rxs[i] : 0.0f;
+    // the slot that panel 0 reads: left of column 0 nothing is reachable
+    constexpr int kFirst = W == 1 ? 0 : W - 1;
+    for (int i = tid; i < G * kChunk; i += kLanes * W) {
+        bnd[(kFirst * 2 + 0) * R + i] = kInf;
+        bnd[(kFirst * 2 + 1) * R + i] = kInf;
     }
+    if (tid < W) done_l[tid] = 0;
     const int g = lane >> 4;
     const int kq = lane >> 5, half = (lane >> 4) & 1, tcol = lane & 15;
     const int bcol = lane - (kLanes - 2);  // 0 / 1 on the two boundary lanes
@@ -1031,10 +1061,11 @@ __global__ __launch_bounds__(kLanes) void frag_sweep_kernel(FragSweepArgs a) {
             }
         }
     };
-    load_panel(0, yn);
+    load_panel(w, yn);
     __syncthreads();
-    int cur = 0;
-    for (int p = 0; p < P; ++p) {
+    const int src = (w + W - 1) % W;  // the wave whose panels lie to the left of this wave's
+    int cur = kFirst, done = 0, seen = 0;
+    for (int p = w, kth = 0; p < P; p += W, ++kth) {
         // this panel's column operands and norms, as panel_operands_f32_small
         float bv[4][4], ry[4];
 #pragma unroll
@@ -1047,20 +1078,22 @@ __global__ __launch_bounds__(kLanes) void frag_sweep_kernel(FragSweepArgs a) {
             }
             ry[bb] = inv_from_sq(sum_groups(sq));
         }
-        load_panel(p + 1, yn);  // in flight during this panel
-        const int nxt = cur ^ 1;
+        load_panel(p + W, yn);  // in flight during this panel
+        const int put = W == 1 ? (cur ^ 1) : w;
+        // chunks the source wave has finished once panel p-1's chunk c is done
+        const int need0 = (w > 0 ? kth : kth - 1) * G + 1;
         float d1 = kInf, s1p = kInf, e0 = kInf, e1 = kInf, dlast = kInf;
         for (int k = 0; k < G; k += 2) {
             // the slab of chunks k and k + 1
             {
                 float av[4];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) av[t] = sh.xs[8 * k + (lane & 15)][4 * t + g];
-                const f32x4 rx4 = *reinterpret_cast<const f32x4*>(&sh.rx[8 * k + 4 * g]);
+                for (int t = 0; t < 4; ++t) av[t] = xs[(8 * k + (lane & 15)) * 16 + 4 * t + g];
+                const f32x4 rx4 = *reinterpret_cast<const f32x4*>(&rxl[8 * k + 4 * g]);
                 f32x4 acc[4], v[4];
                 slab_acc_f32_small(d, av, bv, acc);
                 costs_from_acc_rx(acc, rx4, ry, v);
-                float* dst = &sh.cs[kq][half * (kLanes * 4)];
+                float* dst = cs + (w * 2 + kq) * (kChunk * kLanes) + half * (kLanes * 4);
 #pragma unroll
                 for (int bb = 0; bb < 4; ++bb) *reinterpret_cast<f32x4*>(dst + (bb * 16 + tcol) * 4) = v[bb];
             }
@@ -1070,15 +1103,24 @@ __global__ __launch_bounds__(kLanes) void frag_sweep_kernel(FragSweepArgs a) {
                 if (kk >= G) break;
                 float cb[kChunk], lv0[kChunk], lv1[kChunk];
                 {
-                    const f32x4* src = reinterpret_cast<const f32x4*>(&sh.cs[u][0]) + lane;
-                    const f32x4 c0 = src[0], c1 = src[kLanes];
+                    const f32x4* s4 = reinterpret_cast<const f32x4*>(cs + (w * 2 + u) * (kChunk * kLanes)) + lane;
+                    const f32x4 c0 = s4[0], c1 = s4[kLanes];
                     cb[0] = c0[0]; cb[1] = c0[1]; cb[2] = c0[2]; cb[3] = c0[3];
                     cb[4] = c1[0]; cb[5] = c1[1]; cb[6] = c1[2]; cb[7] = c1[3];
                 }
+                if (W > 1 && p > 0) {
+                    const int need = need0 + kk;
+                    while (seen < need) {
+                        seen = lds_get(&done_l[src]);
+                        if (seen < need) __builtin_amdgcn_s_sleep(1);
+                    }
+                    compiler_order();
+                }
+                const int get = W == 1 ? cur : src;
 #pragma unroll
                 for (int r = 0; r < kChunk; ++r) {
-                    lv0[r] = sh.bnd[cur][0][kChunk * kk + r];
-                    lv1[r] = sh.bnd[cur][1][kChunk * kk + r];
+                    lv0[r] = bnd[(get * 2 + 0) * R + kChunk * kk + r];
+                    lv1[r] = bnd[(get * 2 + 1) * R + kChunk * kk + r];
                 }
                 // row 0 of the fragment: every cell a start, fma(2, C, -C) = C
                 if (kk == 0) s1p = -cb[0];
@@ -1092,7 +1134,12 @@ __global__ __launch_bounds__(kLanes) void frag_sweep_kernel(FragSweepArgs a) {
                 cdst[lane] = uint64_t(lo) | (uint64_t(hi) << 32);
                 if (bcol >= 0) {
 #pragma unroll
-                    for (int r = 0; r < kChunk; ++r) sh.bnd[nxt][bcol][kChunk * kk + r] = best_r[r];
+                    for (int r = 0; r < kChunk; ++r) bnd[(put * 2 + bcol) * R + kChunk * kk + r] = best_r[r];
+                }
+                if constexpr (W > 1) {
+                    compiler_order();
+                    ++done;
+                    if (lane == 0) lds_put(&done_l[w], done);
                 }
                 if (kk == G - 1) {
 #pragma unroll
@@ -1103,7 +1150,7 @@ __global__ __launch_bounds__(kLanes) void frag_sweep_kernel(FragSweepArgs a) {
         const int64_t col = int64_t(p) * kPanel + lane;
         if (col < m) a.totals[int64_t(b) * m + col] = dlast;
         if (col == m - 1) a.status[b] = dlast == kInf ? PARDTW_PAIR_INFEASIBLE : PARDTW_PAIR_OK;
-        cur = nxt;
+        cur = put;
     }
 }
 
@@ -1226,7 +1273,7 @@ pardtw_status dp_batch_launch(const BatchPair* pairs, const DpItem* items, int32
 
 int64_t frag_sweep_max_rows() { return kSweepRows; }
 
-pardtw_status frag_sweep_launch(const BatchPair* pairs, int32_t nfrag, int64_t max_n, const float* X,
+pardtw_status frag_sweep_launch(const BatchPair* pairs, int32_t nfrag, int64_t max_n, int waves, const float* X,
                                 const float* Y, int64_t d, const float* rxs, uint8_t* bpbase, float* totals,
                                 int32_t* status, hipStream_t stream) {
     if (nfrag <= 0) return PARDTW_OK;
@@ -1240,7 +1287,14 @@ pardtw_status frag_sweep_launch(const BatchPair* pairs, int32_t nfrag, int64_t m
     a.bp = bpbase;
     a.totals = totals;
     a.status = status;
-    frag_sweep_kernel<<<unsigned(nfrag), kLanes, 0, stream>>>(a);
+    a.R = sweep_rows(max_n);
+    const size_t lds = sweep_lds_bytes(waves, a.R);
+    switch (waves) {
+        case 1: frag_sweep_kernel<1><<<unsigned(nfrag), kLanes, lds, stream>>>(a); break;
+        case 2: frag_sweep_kernel<2><<<unsigned(nfrag), 2 * kLanes, lds, stream>>>(a); break;
+        case 4: frag_sweep_kernel<4><<<unsigned(nfrag), 4 * kLanes, lds, stream>>>(a); break;
+        default: return PARDTW_ERR_UNSUPPORTED;
+    }
     return launch_status();
 }
 

@@ -673,6 +673,8 @@ class SegPlan:
         nw, order, wg = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(_lib_plan_sched(self._h, int(index), ctypes.byref(nw), ctypes.byref(order), ctypes.byref(wg)),
                "pardtw_plan_schedule")
+        if nw.value == 0:  # one workgroup per fragment; `order` carries its waves
+            return dict(panels_per_workgroup=0, order="fragment", waves=order.value, workgroups=wg.value)
         return dict(panels_per_workgroup=nw.value, order=("breadth", "depth")[order.value], workgroups=wg.value)
 
     def select(self, index: int):

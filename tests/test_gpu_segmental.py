@@ -320,15 +320,20 @@ def test_segmental_infeasible_and_reuse():
 
 
 @pytest.mark.parametrize("la,lb,nf,fused", [(1200, 2000, 6, False), (1200, 2000, 6, True), (2500, 3000, 25, True),
-                                            (2000, 1500, 9, True)])
+                                            (2000, 1500, 9, True), (400, 60, 8, True), (900, 190, 30, True)])
 def test_segmental_schedules_identical(la, lb, nf, fused):
     """Every schedule of a plan gives the same scores, ends and path, bit for
-    bit. Fused plans of fragments of at most 256 rows include the schedule
-    of one wave per fragment (panels_per_workgroup 0)."""
+    bit. Fused plans of fragments of at most 256 rows include the schedules
+    of one workgroup per fragment (panels_per_workgroup 0) with 1, 2 and 4
+    waves taking its panels in turn, also with fewer panels than waves (60
+    and 190 columns: one and three panels)."""
     (A, B), _ = _pair(12 + nf, la, lb)
     plan = pd.SegPlan(la, lb, nf, 12, pd.PREC_F32, pd.WSDTW, fused)
     if fused:
-        assert any(plan.schedule(s)["panels_per_workgroup"] == 0 for s in range(plan.num_schedules))
+        sweeps = [plan.schedule(s) for s in range(plan.num_schedules)]
+        sweeps = [sc for sc in sweeps if sc["panels_per_workgroup"] == 0]
+        assert sorted(sc["waves"] for sc in sweeps) == [1, 2, 4]
+        assert all(sc["workgroups"] == nf for sc in sweeps)
     buf = plan.buffers(DEV)
     Ad, Bd = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
     outs = []
