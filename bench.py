@@ -1100,7 +1100,9 @@ def run_segmental(args):
     dp_achieved = bpc * bcells / (dp_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(dp_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dp_achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "dp_batch_kernel (subsequence%s)" % (", fused cost" if fused else ""),
+                "kernel": ("frag_sweep_kernel (%d waves per fragment)" % plan.schedule()["waves"]
+                           if plan.schedule()["panels_per_workgroup"] == 0 else
+                           "dp_batch_kernel (subsequence%s)" % (", fused cost" if fused else "")),
                 "algorithmic_bytes_per_launch": bpc * bcells, "bytes_per_band_cell": bpc, "band_cells": bcells,
                 "band_fraction": round(bcells / cells, 4), "kernel_ms": round(float(dp_ms), 4)}
     cpu, validation = None, None

@@ -407,8 +407,13 @@ pardtw_status pardtw_align_batch(const pardtw_plan* plan, const float* X_packed,
 /* Schedules of the batched DP: panels per workgroup (1, 2, 4, 8), item order
  * (0 = breadth: group 0 of every pair by decreasing size, then group 1, ...;
  * 1 = depth: all groups of the largest pair first) and resident workgroups.
- * Every schedule computes bit-identical results; only the speed differs.
- * pardtw_plan_schedule describes schedule `index` (-1 = the selected one). */
+ * A Segmental DTW plan with PARDTW_PLAN_FUSED_COST, FP32, d <= 16 and
+ * fragments of at most 256 rows also has the fragment sweep: panels per
+ * workgroup 0, one workgroup per fragment (`workgroups` = nfrag) whose waves
+ * take the fragment's panels in turn; `order` then gives those waves (1, 2
+ * or 4). Every schedule computes bit-identical results; only the speed
+ * differs. pardtw_plan_schedule describes schedule `index` (-1 = the selected
+ * one). */
 int32_t pardtw_plan_num_schedules(const pardtw_plan* plan);
 pardtw_status pardtw_plan_schedule(const pardtw_plan* plan, int32_t index, int32_t* panels_per_workgroup,
                                    int32_t* order, int32_t* workgroups);
