@@ -182,8 +182,12 @@ def _gpu_segment(S: np.ndarray, hop: int, variant: int):
     return float(total.item()), ends.cpu().numpy().astype(np.int64), int(status.item())
 
 
+# Blocks of rows hand over through LDS while hop < 2048 columns and through
+# records otherwise (hop 5000, 9000, 20000); 37 and 1000 rows end on a
+# partial block; hop >= m leaves no column.
 SEG_CASES = [(1, 1, 1), (1, 5000, 3), (2, 7, 2), (3, 2047, 1), (3, 2049, 700), (5, 6000, 40), (32, 20000, 781),
-             (17, 4096, 1), (600, 40, 1), (40, 9000, 100)]
+             (17, 4096, 1), (600, 40, 1), (40, 9000, 100), (6, 30000, 5000), (5, 40000, 9000), (3, 60000, 20000),
+             (37, 3000, 50), (1000, 2000, 1), (9, 16000, 1790), (3, 700, 700), (2, 500, 900)]
 
 
 @pytest.mark.parametrize("variant", [pd.NSDTW, pd.WSDTW])
@@ -204,7 +208,8 @@ def test_segment_ends_integer_bit_exact(nf, m, hop, variant):
         assert g_status == pd.PAIR_INFEASIBLE and np.isinf(g_total) and np.all(g_ends == -1)
 
 
-@pytest.mark.parametrize("nf,m,hop", [(8, 3000, 100), (32, 60000, 781), (100, 5000, 20)])
+@pytest.mark.parametrize("nf,m,hop", [(8, 3000, 100), (32, 60000, 781), (100, 5000, 20), (6, 30000, 5000),
+                                      (9, 16000, 1790), (37, 3000, 50), (1000, 2000, 1)])
 def test_segment_ends_random_scores(nf, m, hop):
     rng = np.random.default_rng(nf + m)
     S = rng.uniform(0.0, 50.0, size=(nf, m)).astype(np.float32)
