@@ -338,11 +338,36 @@ __device__ __attribute__((always_inline)) inline void sweep(const float* __restr
     }
 }
 
+// Rows swept by one workgroup.
+constexpr int64_t kBlockRows = int64_t(kTileM) * kTilesPerBlock;
+
+// With a band, block (p, y) takes the y-th block of rows from the one holding
+// the panel's first band group, so the grid's height is the widest band in
+// blocks rather than all of n (about a third of the blocks for a 5:6 pair).
 template <bool BF16, bool PANEL, bool VEC>
 __global__ __launch_bounds__(kThreads) void cost_kernel(const float* __restrict__ X, const float* __restrict__ Y,
                                                         int64_t n, int64_t m, int64_t d, float* __restrict__ C,
                                                         int band) {
-    sweep<BF16, PANEL, VEC>(X, Y, n, m, d, C, blockIdx.x, int64_t(blockIdx.y) * kTilesPerBlock, band);
+    const int64_t p = blockIdx.x;
+    int64_t rb = blockIdx.y;
+    if (band != 0) rb += group_span(band, p, n, m).lo * kBpRows / kBlockRows;
+    sweep<BF16, PANEL, VEC>(X, Y, n, m, d, C, p, rb * kTilesPerBlock, band);
+}
+
+// The grid height for a band: the most blocks of rows that one panel's band
+// groups span (at least 1).
+int64_t band_grid_rows(int band, int64_t n, int64_t m) {
+    int64_t rows = 1;
+    const int64_t last = (n - 1) / kBpRows;
+    for (int64_t p = 0; p < num_panels(m); ++p) {
+        const int64_t lo = band == 1 ? band_group_lo(p, n, m) : sub_group_lo(p, n, m);
+        int64_t hi = band == 1 ? band_group_hi(p, n, m) : sub_group_hi(p, n, m);
+        if (hi > last) hi = last;
+        if (lo > hi) continue;
+        const int64_t span = hi * kBpRows / kBlockRows - lo * kBpRows / kBlockRows + 1;
+        if (span > rows) rows = span;
+    }
+    return rows;
 }
 
 // Batched form: block t is block t of the batch's numbering; tile_pair[t]
@@ -393,11 +418,11 @@ pardtw_status cost_batch_launch(const BatchPair* pairs, const int32_t* tile_pair
 
 pardtw_status cost_launch(const float* X, const float* Y, int64_t n, int64_t m, int64_t d, pardtw_prec prec,
                           pardtw_layout layout, float* C, hipStream_t stream) {
-    const int64_t rows_blk = ceil_div(ceil_div(n, kTileM), kTilesPerBlock);
+    const int band = layout == PARDTW_LAYOUT_PANEL_BAND ? 1 : layout == PARDTW_LAYOUT_PANEL_SUBSEQ_BAND ? 2 : 0;
+    const int64_t rows_blk = band != 0 ? band_grid_rows(band, n, m) : ceil_div(ceil_div(n, kTileM), kTilesPerBlock);
     if (rows_blk > 65535 || num_panels(m) > 0x7fffffff) return PARDTW_ERR_UNSUPPORTED;
     dim3 grid(unsigned(num_panels(m)), unsigned(rows_blk));
     const bool panel = layout != PARDTW_LAYOUT_ROW;
-    const int band = layout == PARDTW_LAYOUT_PANEL_BAND ? 1 : layout == PARDTW_LAYOUT_PANEL_SUBSEQ_BAND ? 2 : 0;
     const bool vec = vec_ok(X, Y, d);
     if (prec == PARDTW_PREC_F32 && vec && d % 16 == 0) {
         if (panel) cost_kernel<false, true, true><<<grid, kThreads, 0, stream>>>(X, Y, n, m, d, C, band);

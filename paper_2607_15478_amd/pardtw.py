@@ -484,10 +484,12 @@ class Plan:
             yo += ms[b]
             po += min(ns[b], ms[b])
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib_plan_destroy):
+        # the destroy call is bound here: at interpreter exit the module's
+        # globals may already be gone when the last plan is collected
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            _lib_plan_destroy(h)
+            _destroy(h)
             self._h = None
 
     def buffers(self, device="cuda"):
@@ -627,10 +629,12 @@ class SegPlan:
         self.starts = [int(_lib_segplan_fstart(h, f)) for f in range(self.nfrag + 1)]
         self.hop = int(_lib_segplan_hop(h))
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib_plan_destroy):
+        # the destroy call is bound here: at interpreter exit the module's
+        # globals may already be gone when the last plan is collected
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            _lib_plan_destroy(h)
+            _destroy(h)
             self._h = None
 
     def buffers(self, device="cuda"):

@@ -150,8 +150,13 @@ def test_cost_bf16_against_oracle_on_rounded_inputs(n, m, d):
                                         (1000, 1999, 12, pd.PREC_F32), (1999, 1000, 12, pd.PREC_F32),
                                         (3000, 2000, 12, pd.PREC_F32), (130, 1000, 12, pd.PREC_F32),
                                         (1000, 1300, 128, pd.PREC_F32), (1300, 1000, 32, pd.PREC_F32),
-                                        (1000, 1300, 128, pd.PREC_BF16)])
+                                        (1000, 1300, 128, pd.PREC_BF16), (6000, 7000, 12, pd.PREC_F32),
+                                        (7000, 3600, 12, pd.PREC_F32), (3600, 7000, 12, pd.PREC_F32)])
 def test_cost_band_layout_writes_exactly_the_band_groups(n, m, d, prec):
+    """The band layout holds the full panel layout's values bit for bit in
+    every band group and leaves the others untouched; the larger shapes put
+    the panels' first band groups in many different 512-row blocks, where the
+    launch starts each panel's blocks."""
     rng = np.random.default_rng(n * 7 + m + d)
     X = rng.normal(size=(n, d)).astype(np.float32)
     Y = rng.normal(size=(m, d)).astype(np.float32)
@@ -261,3 +266,26 @@ def test_align_10k_against_oracle():
     parity.check_total(g_total, J)
     ties = parity.audit_path(g_path, BP, lambda cells: oracle.probe(cells, X=X, Y=Y)[0])
     print(f"10k x 12k: total {g_total} oracle {J} declared ties {ties}")
+
+
+@pytest.mark.parametrize("n,m", [(333, 2100), (1500, 4000), (3000, 3100), (700, 9000), (2600, 1400)])
+def test_cost_subseq_band_layout_writes_exactly_the_band_groups(n, m):
+    """The subsequence band layout holds the full panel layout's values bit
+    for bit in every group of the subsequence band (a cell that row 0 reaches
+    and a cell that reaches row n-1, enumerated cell by cell) and leaves the
+    others untouched, also where the panels' first band groups lie in
+    different 512-row blocks."""
+    rng = np.random.default_rng(n + 11 * m)
+    X = rng.normal(size=(n, 12)).astype(np.float32)
+    Y = rng.normal(size=(m, 12)).astype(np.float32)
+    Xd, Yd = torch.from_numpy(X).to(DEV), torch.from_numpy(Y).to(DEV)
+    full = torch.empty(pd.pardtw_cost_elems(n, m, pd.LAYOUT_PANEL), dtype=torch.float32, device=DEV)
+    pd.pardtw_cost(Xd, Yd, full, pd.PREC_F32, pd.LAYOUT_PANEL)
+    part = torch.full((pd.pardtw_cost_elems(n, m, pd.LAYOUT_PANEL_SUBSEQ_BAND),), float("nan"), device=DEV)
+    pd.pardtw_cost(Xd, Yd, part, pd.PREC_F32, pd.LAYOUT_PANEL_SUBSEQ_BAND)
+    P, G = -(-m // 64), -(-n // 8)
+    f = full.cpu().numpy().reshape(P, G, 512)
+    g = part.cpu().numpy().reshape(P, G, 512)
+    band = parity.subseq_band_groups(n, m)
+    assert np.array_equal(f[band], g[band])
+    assert np.all(np.isnan(g[~band]))
