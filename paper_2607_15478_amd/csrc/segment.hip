@@ -51,11 +51,27 @@ struct VI {
 };
 __device__ inline VI later_if_less(VI earlier, VI later) { return later.v < earlier.v ? later : earlier; }
 
-__device__ inline VI shfl_up_vi(VI x, int d) {
+// Lanes of the wave `x` moved by a DPP pattern; lanes that the pattern (or
+// the row mask RM) leaves without a source receive the identity (+inf, -1).
+template <int CTRL, int RM>
+__device__ inline VI dpp_vi(VI x) {
     VI y;
-    y.v = __shfl_up(x.v, d, 64);
-    y.i = __shfl_up(x.i, d, 64);
+    y.v = __int_as_float(__builtin_amdgcn_update_dpp(int(0x7f800000), __float_as_int(x.v), CTRL, RM, 0xf, false));
+    y.i = __builtin_amdgcn_update_dpp(-1, x.i, CTRL, RM, 0xf, false);
     return y;
+}
+
+// Inclusive scan of (value, first index) over the 64 lanes: shifts by 1, 2, 4
+// and 8 within each row of 16 lanes, then each row takes the total of the rows
+// before it (row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2 and 3).
+__device__ inline VI wave_scan_vi(VI x) {
+    x = later_if_less(dpp_vi<0x111, 0xf>(x), x);
+    x = later_if_less(dpp_vi<0x112, 0xf>(x), x);
+    x = later_if_less(dpp_vi<0x114, 0xf>(x), x);
+    x = later_if_less(dpp_vi<0x118, 0xf>(x), x);
+    x = later_if_less(dpp_vi<0x142, 0xa>(x), x);
+    x = later_if_less(dpp_vi<0x143, 0xc>(x), x);
+    return x;
 }
 
 // One workgroup scans a block of up to kSegRows consecutive rows, tile by tile:
@@ -165,15 +181,10 @@ __global__ __launch_bounds__(kSegThreads) void segment_scan_kernel(SegArgs a, in
                     run = later_if_less(run, VI{t[e], int32_t(j0 + e)});
                     loc[e] = run;
                 }
-                // exclusive scan over the wave's lanes
-                VI inc = run;
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const VI up = shfl_up_vi(inc, d);
-                    if (lane >= d) inc = later_if_less(up, inc);
-                }
-                VI before = shfl_up_vi(inc, 1);
-                if (lane == 0) before = VI{kInf, -1};
+                // exclusive scan over the wave's lanes (wave_shr:1 of the
+                // inclusive one; lane 0 gets the identity)
+                const VI inc = wave_scan_vi(run);
+                const VI before = dpp_vi<0x138, 0xf>(inc);
                 if (lane == 63) wave_tot[wave] = inc;
                 __syncthreads();
                 VI pre = carry[0];
