@@ -667,6 +667,38 @@ def run_pair_pipelined(args, X, Y, Xd, Yd, bufs, stream, side, cells, calib):
     print(json.dumps(out), flush=True)
 
 
+_COPY = {}
+
+
+def copy_bandwidth():
+    """Bandwidth of a plain device-to-device copy (torch copy_, 1 GiB each
+    way, larger than the 256 MB Infinity Cache), bytes read + written per
+    second, measured once per process beside the datasheet peak; None when
+    less than 3 GiB of device memory is free."""
+    import torch
+    if "v" not in _COPY:
+        free, _ = torch.cuda.mem_get_info()
+        nb = 1 << 30
+        if free < 3 * nb:
+            _COPY["v"] = None
+        else:
+            src = torch.empty(nb // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(10):
+                dst.copy_(src)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 10
+            _COPY["v"] = {"GBps": round(2 * nb / (ms * 1e-3) / 1e9, 1), "bytes_each_way": nb, "ms": round(ms, 4)}
+            del src, dst
+            torch.cuda.empty_cache()
+    return _COPY["v"]
+
+
 def pair_roofline(args, n, m, dp_ms):
     """The DP kernel against the HBM peak. Algorithmic bytes are those of the
     method's own work, the path band (cells on some path from (0,0) to
@@ -700,6 +732,7 @@ def pair_roofline(args, n, m, dp_ms):
     if traffic:
         roofline["traffic_over_algorithmic"] = round(traffic / alg, 3)
         roofline["moved_GBps"] = round(traffic / (dp_ms * 1e-3) / 1e9, 1)
+    roofline["measured_copy"] = copy_bandwidth()
     return roofline
 
 
@@ -905,7 +938,7 @@ def run_batch(args):
                        "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
                        "kernel": "dp_batch_kernel (fused cost)" if r32["fused"] else "dp_batch_kernel",
                        "algorithmic_bytes_per_launch": bpc * bcells, "bytes_per_band_cell": bpc,
-                       "band_cells": bcells, "kernel_ms": round(dp_ms, 4)}
+                       "band_cells": bcells, "kernel_ms": round(dp_ms, 4), "measured_copy": copy_bandwidth()}
     print(json.dumps(out), flush=True)
 
 
@@ -1104,7 +1137,8 @@ def run_segmental(args):
                            if plan.schedule()["panels_per_workgroup"] == 0 else
                            "dp_batch_kernel (subsequence%s)" % (", fused cost" if fused else "")),
                 "algorithmic_bytes_per_launch": bpc * bcells, "bytes_per_band_cell": bpc, "band_cells": bcells,
-                "band_fraction": round(bcells / cells, 4), "kernel_ms": round(float(dp_ms), 4)}
+                "band_fraction": round(bcells / cells, 4), "kernel_ms": round(float(dp_ms), 4),
+                "measured_copy": copy_bandwidth()}
     cpu, validation = None, None
     if not args.no_cpu:
         # a bounded sample: up to three fragments, at most 3e9 cells (about 15 s on one core)
