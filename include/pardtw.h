@@ -407,8 +407,10 @@ pardtw_status pardtw_align_batch(const pardtw_plan* plan, const float* X_packed,
 /* Schedules of the batched DP: panels per workgroup (1, 2, 4, 8), item order
  * (0 = breadth: group 0 of every pair by decreasing size, then group 1, ...;
  * 1 = depth: all groups of the largest pair first) and resident workgroups.
- * A Segmental DTW plan with PARDTW_PLAN_FUSED_COST, FP32, d <= 16 and
- * fragments of at most 256 rows also has the fragment sweep: panels per
+ * A Segmental DTW plan's staircase schedules use breadth order only (its
+ * fragments differ in length by one row at most, so depth order would run
+ * them one after another). With PARDTW_PLAN_FUSED_COST, FP32, d <= 16 and
+ * fragments of at most 256 rows it also has the fragment sweep: panels per
  * workgroup 0, one workgroup per fragment (`workgroups` = nfrag) whose waves
  * take the fragment's panels in turn; `order` then gives those waves (1, 2
  * or 4). Every schedule computes bit-identical results; only the speed

@@ -205,12 +205,16 @@ pardtw_status finish_plan(pardtw_plan* pl, pardtw_plan** plan_out) {
     }
 
     // candidate schedules and their work lists (fused workgroups hold at most
-    // four compute waves)
+    // four compute waves). Segmental DTW fragments differ by one row at most,
+    // so depth order would run them nearly one after another (hundreds of
+    // times slower at 1000 fragments) and with one fragment it equals
+    // breadth order: those plans try breadth order only.
     std::vector<pardtw::DpItem> all_items;
     const int nws[4] = {1, 2, 4, 8};
+    const int orders = pl->mode == 1 ? 1 : 2;
     for (int nw : nws) {
         if (pl->fused && nw > (pl->prec == PARDTW_PREC_BF16 ? 2 : 4)) continue;
-        for (int order = 0; order < 2; ++order) {
+        for (int order = 0; order < orders; ++order) {
             const std::vector<pardtw::DpItem> it = make_items(*pl, nw, order);
             const int64_t at = int64_t(all_items.size());
             all_items.insert(all_items.end(), it.begin(), it.end());
