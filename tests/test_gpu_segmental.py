@@ -398,6 +398,39 @@ def test_segmental_full_size_sampled():
         assert np.all(parity.step_codes(seg) >= 0)
 
 
+@pytest.mark.slow
+def test_segmental_fragment_sweep_full_size():
+    """100000 x 100000 with 1000 fragments of 100 rows, on the fragment sweep
+    with four waves per fragment (the schedule the autotuner picks there):
+    three sampled fragments' scores against the oracle, and scores, ends,
+    total and path bit for bit those of the staircase schedule."""
+    A, B = synth.make_workload("segmental_100000x100000_d12")
+    la, lb, nf = A.shape[0], B.shape[0], 1000
+    plan = pd.SegPlan(la, lb, nf, A.shape[1], pd.PREC_F32, pd.WSDTW, True)
+    scheds = [plan.schedule(k) for k in range(plan.num_schedules)]
+    sweep = [k for k, sc in enumerate(scheds) if sc["panels_per_workgroup"] == 0 and sc["waves"] == 4]
+    stair = [k for k, sc in enumerate(scheds) if sc["panels_per_workgroup"] == 4]
+    assert sweep and stair
+    buf = plan.buffers(DEV)
+    Ad, Bd = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+    outs = []
+    for k in (sweep[0], stair[0]):
+        plan.select(k)
+        plan.align(Ad, Bd, buf)
+        torch.cuda.synchronize()
+        L = int(buf["path_len"].item())
+        outs.append((float(buf["total"].item()), buf["ends"].cpu().numpy(), buf["path"][:L].cpu().numpy(),
+                     _scores_of_plan(plan, buf), int(buf["status"].item())))
+    sw, st = outs
+    assert sw[4] == st[4] == pd.PAIR_OK
+    assert sw[0] == st[0] and np.array_equal(sw[1], st[1]) and np.array_equal(sw[2], st[2])
+    assert np.array_equal(sw[3], st[3])
+    starts = plan.starts
+    for f in (0, 500, 999):
+        S, _ = oracle.subseq_features(A[starts[f]:starts[f + 1]], B)
+        _check_scores(sw[3][f], S)
+
+
 @pytest.mark.parametrize("variant", [pd.NSDTW, pd.WSDTW])
 @pytest.mark.parametrize("la,lb,nf", [(1000, 1200, 4), (2000, 2400, 16), (777, 3000, 3), (500, 100, 2)])
 def test_segmental_fused_plan_bit_identical(la, lb, nf, variant):
